@@ -1,0 +1,148 @@
+"""Linear amplification matrices of the FD-LBM and MRT D2Q9 schemes (von Neumann analysis).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section 1-b: a plane wave of small amplitude, Phi = (drho, J_x, J_y) * p^i q^j with
+p = exp(i k_x), q = exp(i k_y), is multiplied by the amplification matrix H after one
+step (Phi^{n+1} = H Phi^n); the roots z of det(H - z Id) = 0 give Gamma = -log z.
+Section 2 interprets the shear root as Gamma = nu_0 k^2 + nu_2 k^4 ("hyperviscosity" nu_2),
+and solves the full cubic numerically up to k = pi for linear stability.
+
+Here H is assembled numerically about the rest state rho = 1, J = 0:
+  FD-LBM:  H = P(k) diag(exp(-i k.e_k)) M^{-1} L(k), where L(k) maps Phi to the
+           linearised post-collision moments (the theta terms keep only their linear
+           parts, the finite differences become their Fourier symbols) and P(k) takes
+           the conserved moments of the propagated populations;
+  MRT:     H = diag(exp(-i k.e_k)) M^{-1} (I - S + S Q) M on the 9 populations, with Q
+           the linearised equilibrium map and S the relaxation rates.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .matrix_form import E, M, MINV, STENCILS
+
+
+def derivative_symbols(kx, ky, stencil):
+    """Fourier symbols (Dx, Dy) of the section-2 finite differences: sum_o w_o exp(i k.o)."""
+    dx = sum(w * np.exp(1j * (kx * ox + ky * oy)) for ox, oy, w in STENCILS[stencil])
+    dy = sum(w * np.exp(1j * (ky * ox + kx * oy)) for ox, oy, w in STENCILS[stencil])
+    return dx, dy
+
+
+def _propagation(kx, ky):
+    return np.diag(np.exp(-1j * (kx * E[:, 0] + ky * E[:, 1])))
+
+
+def fd_symbol(kx, ky, *, s_xx, s_e=1.0, stencil=3):
+    """3x3 amplification matrix of the FD-LBM step acting on (drho, Jx, Jy)."""
+    Dx, Dy = derivative_symbols(kx, ky, stencil)
+    ce, cxx = 1 - 1 / s_e, 1 - 1 / s_xx
+    L = np.zeros((9, 3), dtype=complex)
+    L[0, 0] = 1
+    L[1, 1] = 1
+    L[2, 2] = 1
+    # E* = -2 rho + (1 - 1/s_e) * 2 (Dx Jx + Dy Jy)
+    L[3, 0] = -2
+    L[3, 1] = ce * 2 * Dx
+    L[3, 2] = ce * 2 * Dy
+    # XX* = (1 - 1/s_xx) * 2/3 (Dx Jx - Dy Jy)
+    L[4, 1] = cxx * 2 / 3 * Dx
+    L[4, 2] = -cxx * 2 / 3 * Dy
+    # XY* = (1 - 1/s_xx) * 1/3 (Dx Jy + Dy Jx)
+    L[5, 1] = cxx / 3 * Dy
+    L[5, 2] = cxx / 3 * Dx
+    L[6, 1] = -1
+    L[7, 2] = -1
+    L[8, 0] = 1
+    P = M[:3]
+    return P @ _propagation(kx, ky) @ MINV @ L
+
+
+def mrt_symbol(kx, ky, *, s_xx, s_e=1.0, s_q, s_eps=1.0):
+    """9x9 amplification matrix of the MRT step acting on the populations."""
+    S = np.diag([0, 0, 0, s_e, s_xx, s_xx, s_q, s_q, s_eps]).astype(float)
+    Q = np.zeros((9, 9))
+    Q[0, 0] = Q[1, 1] = Q[2, 2] = 1
+    Q[3, 0] = -2
+    Q[6, 1] = -1
+    Q[7, 2] = -1
+    Q[8, 0] = 1
+    C = MINV @ (np.eye(9) - S + S @ Q) @ M
+    return _propagation(kx, ky) @ C
+
+
+def _moments3(scheme, v):
+    return v if scheme == "fd" else M[:3] @ v
+
+
+def shear_gamma(kx, ky, scheme="fd", **params):
+    """Gamma = -log z of the transverse (shear) root at wave vector (kx, ky)."""
+    H = fd_symbol(kx, ky, **params) if scheme == "fd" else mrt_symbol(kx, ky, **params)
+    z, V = np.linalg.eig(H)
+    k = math.hypot(kx, ky)
+    tx, ty = -ky / k, kx / k
+    best, score = None, -1.0
+    for i in _hydrodynamic_roots(z):
+        m = _moments3(scheme, V[:, i])
+        norm = np.linalg.norm(m)
+        if norm < 1e-12:
+            continue
+        s = abs(m[1] * tx + m[2] * ty) / norm
+        if s > score:
+            best, score = i, s
+    return -np.log(z[best])
+
+
+def _hydrodynamic_roots(z):
+    """Indices of the three roots of largest modulus (the slow, hydrodynamic modes; the
+    other MRT roots decay within a few steps)."""
+    return list(np.argsort(-np.abs(z))[:3])
+
+
+def sound_gammas(kx, ky, scheme="fd", **params):
+    """Gamma of the two acoustic roots (the hydrodynamic roots other than the shear one)."""
+    H = fd_symbol(kx, ky, **params) if scheme == "fd" else mrt_symbol(kx, ky, **params)
+    z, V = np.linalg.eig(H)
+    k = math.hypot(kx, ky)
+    nx_, ny_ = kx / k, ky / k
+    out = []
+    for i in _hydrodynamic_roots(z):
+        m = _moments3(scheme, V[:, i])
+        norm = np.linalg.norm(m)
+        if norm < 1e-12:
+            continue
+        longit = abs(m[0]) + abs(m[1] * nx_ + m[2] * ny_)
+        if longit / norm > 0.5:
+            out.append(-np.log(z[i]))
+    return sorted(out, key=lambda g: g.imag)
+
+
+def nu_of_k(k, angle, scheme="fd", **params):
+    """k-dependent shear viscosity Re(Gamma)/k^2 along direction `angle` (radians)."""
+    g = shear_gamma(k * math.cos(angle), k * math.sin(angle), scheme, **params)
+    return g.real / (k * k)
+
+
+def hyperviscosity(angle, scheme="fd", ks=(0.02, 0.04, 0.06, 0.08, 0.1, 0.12), **params):
+    """(nu_0, nu_2) from a least-squares fit nu(k) = nu_0 + nu_2 k^2 + nu_4 k^4 + nu_6 k^6."""
+    ks = np.asarray(ks, dtype=float)
+    nus = np.array([nu_of_k(k, angle, scheme, **params) for k in ks])
+    A = np.stack([np.ones_like(ks), ks ** 2, ks ** 4, ks ** 6], axis=1)
+    coef, *_ = np.linalg.lstsq(A, nus, rcond=None)
+    return coef[0], coef[1]
+
+
+def max_amplification(scheme="fd", n=64, **params):
+    """max |z| over a grid of wave vectors in [-pi, pi]^2 (linear stability map)."""
+    ks = np.linspace(-math.pi, math.pi, n)
+    worst = 0.0
+    for kx in ks:
+        for ky in ks:
+            if kx == 0 and ky == 0:
+                continue
+            H = fd_symbol(kx, ky, **params) if scheme == "fd" else mrt_symbol(kx, ky, **params)
+            worst = max(worst, float(np.max(np.abs(np.linalg.eigvals(H)))))
+    return worst

@@ -1,0 +1,445 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values printed in the
+paper (Table 1, the quartic rate of section 3-b), closed forms of sections 1-a and 2
+(transport coefficients, Galilean factor, hyperviscosity), exact invariants (mass and
+momentum conservation, fixed points), a special case that reduces to the textbook BGK
+scheme, the independently written linear symbol, and a second independent rendering of
+the same steps.  No GPU is used.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import matrix_form as MF
+from oracle import symbol as S
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def fourier_coeff(field, mx, my):
+    ny, nx = field.shape
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    return np.sum(field * np.exp(-2j * np.pi * (mx * x / nx + my * y / ny)))
+
+
+# ---------------------------------------------------------------- section 1: moments ----
+
+def test_velocity_set_is_d2q9():
+    ex, ey = O.velocities()
+    assert sorted(zip(ex.tolist(), ey.tolist())) == sorted((a, b) for a in (-1, 0, 1) for b in (-1, 0, 1))
+    assert (ex[0], ey[0]) == (0, 0)
+
+
+def test_moment_matrix_rows_are_the_physical_moments():
+    """Section 1 names the rows: density, mass fluxes, energy, stresses, energy fluxes,
+    square of energy.  As polynomials of the velocity e they are 1, e_x, e_y, 3|e|^2-4,
+    e_x^2-e_y^2, e_x e_y, (3|e|^2-5)e, (9|e|^4-21|e|^2+8)/2; the printed energy, stress,
+    energy-flux and eps rows are exactly these, which fixes the order of the velocities."""
+    M = O.moment_matrix()
+    ex, ey = (v.astype(float) for v in O.velocities())
+    e2 = ex * ex + ey * ey
+    expect = np.array([np.ones(9), ex, ey, 3 * e2 - 4, ex * ex - ey * ey, ex * ey,
+                       (3 * e2 - 5) * ex, (3 * e2 - 5) * ey, (9 * e2 * e2 - 21 * e2 + 8) / 2])
+    assert np.array_equal(M, expect)
+    # rows printed in the section-1 table that carry no sign ambiguity
+    assert M[3].tolist() == [-4, -1, -1, -1, -1, 2, 2, 2, 2]
+    assert M[4].tolist() == [0, 1, -1, 1, -1, 0, 0, 0, 0]
+    assert M[5].tolist() == [0, 0, 0, 0, 0, 1, -1, 1, -1]
+    assert M[6].tolist() == [0, -2, 0, 2, 0, 1, -1, -1, 1]
+    assert M[7].tolist() == [0, 0, -2, 0, 2, 1, 1, -1, -1]
+    assert M[8].tolist() == [4, -2, -2, -2, -2, 1, 1, 1, 1]
+
+
+def test_moment_matrix_is_orthogonal_and_inverse_is_exact():
+    M = O.moment_matrix()
+    assert np.array_equal(M @ M.T, np.diag([9.0, 6, 6, 36, 4, 4, 12, 12, 36]))
+    assert np.allclose(O.inverse_moment_matrix() @ M, np.eye(9), atol=1e-15, rtol=0)
+    assert np.allclose(O.inverse_moment_matrix(), np.linalg.inv(M), atol=1e-15, rtol=0)
+
+
+def test_equilibrium_populations_are_the_textbook_polynomial():
+    """M^{-1} m^eq with the section 1-a equilibria is the usual D2Q9 polynomial
+    w_k [rho + 3 e.J + 9/2 (e.J)^2/rho - 3/2 |J|^2/rho]."""
+    w = O.inverse_moment_matrix() @ np.array([1.0, 0, 0, -2, 0, 0, 0, 0, 1])
+    assert np.allclose(w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, atol=1e-16, rtol=0)
+    r, x, y = W.random_state(7, 5, seed=11, amp=0.05)
+    df = O.mrt_init(r, x, y)
+    f = df + w[:, None, None]
+    ex, ey = O.velocities()
+    wt = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    rho = 1.0 + r
+    for k in range(9):
+        ej = ex[k] * x + ey[k] * y
+        fk = wt[k] * (rho + 3 * ej + 4.5 * ej * ej / rho - 1.5 * (x * x + y * y) / rho)
+        assert np.max(np.abs(f[k] - fk)) < 2e-16
+
+
+# ------------------------------------------------- section 2: finite differences ----
+
+@pytest.mark.parametrize("stencil", [3, 5, 9])
+def test_finite_differences_exact_on_quadratics(stencil):
+    n = 16
+    y, x = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="ij")
+    f = 0.3 + 0.7 * x - 1.1 * y + 0.05 * x * x - 0.02 * y * y + 0.03 * x * y
+    dfx = 0.7 + 0.1 * x + 0.03 * y
+    dfy = -1.1 - 0.04 * y + 0.03 * x
+    inner = (slice(3, n - 3), slice(3, n - 3))
+    gx, gy = O.derivative(f, stencil, 0), O.derivative(f, stencil, 1)
+    assert np.max(np.abs(gx[inner] - dfx[inner])) < 1e-13
+    assert np.max(np.abs(gy[inner] - dfy[inner])) < 1e-13
+
+
+@pytest.mark.parametrize("stencil,err", [(3, 1.0), (5, -0.5), (9, 1.0)])
+def test_finite_difference_error_on_cubics(stencil, err):
+    """Section 2 leading errors: 3 points +h^2 f'''/6, 5 points -h^2 f'''/12 (so the
+    5-point formula is second order by design); the 9-point formula reduces to the
+    3-point one on a function of x alone.  With f = x^3 (f''' = 6) the errors are
+    +1, -1/2 and +1 exactly; the same holds along y."""
+    n = 16
+    y, x = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="ij")
+    inner = (slice(3, n - 3), slice(3, n - 3))
+    gx = O.derivative(x ** 3, stencil, 0)
+    gy = O.derivative(y ** 3, stencil, 1)
+    assert np.max(np.abs(gx[inner] - (3 * x * x + err)[inner])) < 1e-11
+    assert np.max(np.abs(gy[inner] - (3 * y * y + err)[inner])) < 1e-11
+
+
+# ----------------------------------------------------- invariants of both schemes ----
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "fd9", "mrt"])
+def test_uniform_states_are_fixed_points(scheme):
+    shape = (6, 7)
+    r, x, y = (np.full(shape, v) for v in (0.01, 0.03, -0.02))
+    if scheme == "mrt":
+        out = O.mrt_moments(O.mrt_run(O.mrt_init(r, x, y), 10, s_xx=1.6, s_e=1.3, s_q=1.1, s_eps=1.2))
+    else:
+        out = O.fd_run(r, x, y, 10, s_xx=1.6, s_e=1.3, stencil=int(scheme[2]))
+    for a, b in zip(out, (r, x, y)):
+        assert np.max(np.abs(a - b)) < 1e-16
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+def test_mass_and_momentum_conserved_on_periodic_grids(scheme):
+    """rho and J are the conserved moments (section 1) and propagation permutes the
+    populations (eq. 2): totals are invariant; a uniform force adds exactly F per node and
+    per step to the total momentum (Strang splitting, J* = J + F)."""
+    r, x, y = W.random_state(24, 20, seed=3, amp=0.02)
+    n, steps = r.size, 200
+    for fx, fy in ((0.0, 0.0), (1e-5, -3e-6)):
+        if scheme == "mrt":
+            out = O.mrt_moments(O.mrt_run(O.mrt_init(r, x, y), steps, s_xx=1.5, s_q=1.2, fx=fx, fy=fy))
+        else:
+            out = O.fd_run(r, x, y, steps, s_xx=1.5, stencil=int(scheme[2]), fx=fx, fy=fy)
+        assert abs(out[0].sum() - r.sum()) < 1e-13
+        assert abs(out[1].sum() - x.sum() - steps * n * fx) < 1e-12
+        assert abs(out[2].sum() - y.sum() - steps * n * fy) < 1e-12
+
+
+# ------------------------------------------------------------- two oracles agree ----
+
+@pytest.mark.parametrize("stencil", [3, 5, 9])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("force", [0.0, 2e-4])
+def test_c_oracle_equals_matrix_form(stencil, walls, force):
+    r, x, y = W.random_state(13, 11, seed=5, amp=0.03)
+    kw = dict(s_xx=1.7, s_e=1.25, stencil=stencil, walls=walls, fx=force, fy=-0.5 * force)
+    a = O.fd_run(r, x, y, 8, **kw)
+    b = MF.fd_run(r, x, y, 8, **kw)
+    for u, v in zip(a, b):
+        assert np.max(np.abs(u - v)) < 1e-16
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_mrt_c_oracle_equals_matrix_form(walls):
+    r, x, y = W.random_state(13, 11, seed=6, amp=0.03)
+    df = O.mrt_init(r, x, y)
+    assert np.max(np.abs(df - MF.mrt_init(r, x, y))) < 1e-17
+    kw = dict(s_xx=1.7, s_e=1.25, s_q=1.1, s_eps=1.35, walls=walls, fx=1e-4, fy=2e-5)
+    a = O.mrt_run(df, 8, **kw)
+    b = MF.mrt_run(df, 8, **kw)
+    assert np.max(np.abs(a - b)) < 1e-16
+
+
+# ----------------------------------------------- exact special case: BGK, tau = 1 ----
+
+def test_unit_rates_reduce_to_textbook_bgk():
+    """With every rate equal to 1 the post-collision populations are the equilibrium ones
+    for both schemes (the theta terms carry the factor 1 - 1/s = 0): FD-LBM (3 or 5 points)
+    and MRT must both equal textbook BGK with tau = 1, f(x, t+1) = f^eq(x - e_k, t)."""
+    r, x, y = W.random_state(10, 9, seed=8, amp=0.03)
+    ex, ey = O.velocities()
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    br, bx, by = r.copy(), x.copy(), y.copy()
+    for _ in range(20):
+        rho = 1.0 + br
+        nr, nx_, ny_ = np.zeros_like(br), np.zeros_like(br), np.zeros_like(br)
+        for k in range(9):
+            ej = ex[k] * bx + ey[k] * by
+            fk = w[k] * (rho + 3 * ej + 4.5 * ej * ej / rho - 1.5 * (bx * bx + by * by) / rho) - w[k]
+            fk = np.roll(fk, shift=(ey[k], ex[k]), axis=(0, 1))
+            nr += fk
+            nx_ += ex[k] * fk
+            ny_ += ey[k] * fk
+        br, bx, by = nr, nx_, ny_
+    for stencil in (3, 5):
+        out = O.fd_run(r, x, y, 20, s_xx=1.0, s_e=1.0, stencil=stencil)
+        for u, v in zip(out, (br, bx, by)):
+            assert np.max(np.abs(u - v)) < 1e-15
+    out = O.mrt_moments(O.mrt_run(O.mrt_init(r, x, y), 20, s_xx=1.0, s_e=1.0, s_q=1.0, s_eps=1.0))
+    for u, v in zip(out, (br, bx, by)):
+        assert np.max(np.abs(u - v)) < 1e-15
+
+
+# --------------------------------------------------- linear symbol vs the paper ----
+
+def test_symbol_reproduces_table1():
+    g = json.load(open(os.path.join(GOLD, "table1_hyperviscosity.json")))
+    for stencil, vals in g["nu2"].items():
+        for ang, printed in zip(g["angles_deg"], vals):
+            _, nu2 = S.hyperviscosity(math.radians(ang), s_xx=g["s_xx"], s_e=1.0, stencil=int(stencil))
+            digits = len(repr(printed).split(".")[1])
+            assert abs(nu2 - printed) <= 0.5 * 10.0 ** (-digits) + 1e-7, (stencil, ang, nu2, printed)
+
+
+@pytest.mark.parametrize("s_xx", [1.2, 1.5, 1.85])
+@pytest.mark.parametrize("s_e", [1.0, 1.4])
+def test_symbol_transport_coefficients(s_xx, s_e):
+    """Section 1-a / section 2: nu = (1/s_xx - 1/2)/3, c_s = 1/sqrt(3), and the sound
+    root damps as (nu + zeta)/2 k^2 with zeta = (1/s_e - 1/2)/3."""
+    nu, zeta = (1 / s_xx - 0.5) / 3, (1 / s_e - 0.5) / 3
+    for stencil in (3, 5):
+        nu0, _ = S.hyperviscosity(0.3, s_xx=s_xx, s_e=s_e, stencil=stencil)
+        assert abs(nu0 - nu) < 1e-9
+        k = 1e-3
+        gs = S.sound_gammas(k * math.cos(0.4), k * math.sin(0.4), s_xx=s_xx, s_e=s_e, stencil=stencil)
+        assert len(gs) == 2
+        for g in gs:
+            assert abs(abs(g.imag) / k - 1 / math.sqrt(3)) < 1e-6
+            assert abs(g.real / k ** 2 - (nu + zeta) / 2) < 1e-5
+    g = json.load(open(os.path.join(GOLD, "closed_forms.json")))
+    assert abs(1 / math.sqrt(3) - g["c_s"]) < 1e-15
+
+
+@pytest.mark.parametrize("s_xx", [1.85, 1.5, 1.2])
+def test_hyperviscosity_closed_forms(s_xx):
+    """Section 2 closed forms, with the angular term entering with a plus sign
+    (the printed minus contradicts Table 1: at 45 degrees it would give 0.0558 for the
+    3-point stencil instead of the tabulated 0.01867), and the 9-point form written with
+    the prefactors that reduce to the 3-point one on the x axis."""
+    s = 1 / s_xx - 0.5
+    for deg in (0.0, 26.6, 30.0, 45.0):
+        c2 = math.cos(math.radians(deg)) ** 2
+        ang = c2 - c2 * c2
+        forms = {3: (2 * s - 3) * (2 * s - 1) / 72 + (8 * s - 3) / 36 * ang,
+                 5: s * (2 * s - 1) / 36 + s / 18 * ang,
+                 9: (2 * s - 3) * (2 * s - 1) / 72 + (20 * s - 9) / 36 * ang}
+        for stencil, val in forms.items():
+            _, nu2 = S.hyperviscosity(math.radians(deg), s_xx=s_xx, stencil=stencil)
+            assert abs(nu2 - val) < 2e-6, (stencil, deg, nu2, val)
+
+
+def test_quartic_condition_and_optimized_viscosity():
+    """Section 3-b: (1/s_xx - 1/2)(1/s_q - 1/2) = 1/6 makes the D2Q9 hyperviscosity
+    isotropic; at nu = 1/sqrt(108) it gives s_q = 0.9282 (printed) and a vanishing
+    hyperviscosity, while s_q = 1.3 (the non-optimised run) is anisotropic."""
+    g = json.load(open(os.path.join(GOLD, "closed_forms.json")))
+    nu = 1 / math.sqrt(108)
+    assert abs(nu - g["quartic_nu"]) < 1e-15
+    s_xx = O.rate_from_viscosity(nu)
+    s_q = O.quartic_s_q(s_xx)
+    assert abs(s_q - g["quartic_s_q_printed"]) < 0.5e-4
+    assert abs((1 / s_xx - 0.5) * (1 / s_q - 0.5) - 1 / 6) < 1e-14
+    angles = [0.0, math.radians(26.6), math.pi / 4]
+    nu2 = [S.hyperviscosity(a, "mrt", s_xx=s_xx, s_q=s_q)[1] for a in angles]
+    assert max(abs(v) for v in nu2) < 1e-6
+    for nu_b in (0.05, 0.02):
+        sb = O.rate_from_viscosity(nu_b)
+        v = [S.hyperviscosity(a, "mrt", s_xx=sb, s_q=O.quartic_s_q(sb))[1] for a in angles]
+        assert max(v) - min(v) < 1e-6 and abs(v[0]) > 1e-4
+    v = [S.hyperviscosity(a, "mrt", s_xx=s_xx, s_q=g["non_optimized_s_q_printed"])[1] for a in angles]
+    assert max(v) - min(v) > 1e-3
+
+
+def test_nine_point_stencil_unstable_on_the_diagonal():
+    """Section 3-a: the 9-point stencil is linearly unstable in the {1,1} direction, which
+    the 3- and 5-point stencils (with s_e = 1) are not."""
+    s_xx = O.rate_from_viscosity(0.01)
+    ks = np.linspace(0.05, math.pi, 80)
+
+    def worst(stencil, direction):
+        d = np.array(direction) / np.linalg.norm(direction)
+        return max(np.max(np.abs(np.linalg.eigvals(S.fd_symbol(k * d[0], k * d[1], s_xx=s_xx, stencil=stencil))))
+                   for k in ks)
+
+    assert worst(9, (1, 1)) > 1.001
+    for stencil in (3, 5):
+        for direction in ((1, 0), (2, 1), (1, 1)):
+            assert worst(stencil, direction) <= 1.0 + 1e-12
+
+
+# ------------------------------------- the oracle's linear response equals H(k)^n ----
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("mode", [(1, 0), (2, 1), (1, 1), (3, 2)])
+def test_oracle_linear_response_equals_symbol_power(stencil, mode):
+    n, steps = 32, 40
+    rng = np.random.default_rng(100 + stencil)
+    phi0 = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) * 1e-9
+    kx, ky = 2 * math.pi * mode[0] / n, 2 * math.pi * mode[1] / n
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    wave = np.exp(1j * (kx * x + ky * y))
+    fields = [np.real(p * wave) for p in phi0]
+    kw = dict(s_xx=1.6, s_e=1.1, stencil=stencil)
+    out = O.fd_run(*fields, steps, **kw)
+    got = np.array([fourier_coeff(f, *mode) for f in out]) * 2 / n ** 2
+    expect = np.linalg.matrix_power(S.fd_symbol(kx, ky, **kw), steps) @ phi0
+    assert np.max(np.abs(got - expect)) < 1e-6 * np.max(np.abs(expect))
+
+
+@pytest.mark.parametrize("mode", [(1, 0), (2, 1), (1, 1)])
+def test_mrt_linear_response_equals_symbol_power(mode):
+    n, steps = 32, 40
+    rng = np.random.default_rng(7)
+    phi0 = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) * 1e-9
+    kx, ky = 2 * math.pi * mode[0] / n, 2 * math.pi * mode[1] / n
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    wave = np.exp(1j * (kx * x + ky * y))
+    df0 = O.mrt_init(*[np.real(p * wave) for p in phi0])
+    kw = dict(s_xx=1.6, s_e=1.1, s_q=1.2, s_eps=1.3)
+    df = O.mrt_run(df0, steps, **kw)
+    f0 = np.array([fourier_coeff(f, *mode) for f in df0])
+    got = np.array([fourier_coeff(f, *mode) for f in df])
+    expect = np.linalg.matrix_power(S.mrt_symbol(kx, ky, **kw), steps) @ f0
+    assert np.max(np.abs(got - expect)) < 1e-6 * np.max(np.abs(expect))
+
+
+# ------------------------------------------- shear wave 64 x 64 (section 3-a) ----
+
+def _fit_rate(series, t0, t1):
+    t = np.arange(t0, t1 + 1)
+    return -np.polyfit(t, np.log(series[t0:t1 + 1]), 1)[0]
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+def test_shear_wave_64_decays_at_nu_k2(scheme):
+    """A(t) = <J(t), J(0)> / <J(0), J(0)> decays as exp(-Gamma t) with Gamma = nu k^2 up
+    to the hyperviscosity term; the decay rate equals the symbol's shear root."""
+    nu = 0.02
+    s_xx = O.rate_from_viscosity(nu)
+    s_q = O.quartic_s_q(s_xx)
+    r, x, y = W.shear_wave_y(64, 64, 0.01, 1)
+    k = 2 * math.pi / 64
+    norm = np.sum(x * x)
+    A = [1.0]
+    if scheme == "mrt":
+        state = O.mrt_init(r, x, y)
+        for _ in range(1000):
+            state = O.mrt_run(state, 1, s_xx=s_xx, s_q=s_q)
+            A.append(np.sum(O.mrt_moments(state)[1] * x) / norm)
+        mass = O.mrt_moments(state)[0].sum()
+        g_sym = S.shear_gamma(0.0, k, "mrt", s_xx=s_xx, s_q=s_q).real
+        tol = 1e-5
+    else:
+        st = int(scheme[2])
+        state = (r, x, y)
+        for _ in range(100):
+            state = O.fd_run(*state, 10, s_xx=s_xx, stencil=st)
+            A.extend([np.nan] * 9 + [np.sum(state[1] * x) / norm])
+        mass = state[0].sum()
+        g_sym = S.shear_gamma(0.0, k, s_xx=s_xx, stencil=st).real
+        tol = 1e-6
+    A = np.array(A)
+    t = np.arange(100, 1001, 10)
+    gamma = -np.polyfit(t, np.log(A[t]), 1)[0]
+    assert abs(gamma / g_sym - 1) < tol
+    _, nu2 = S.hyperviscosity(math.pi / 2, "mrt" if scheme == "mrt" else "fd", s_xx=s_xx,
+                              **({"s_q": s_q} if scheme == "mrt" else {"stencil": int(scheme[2])}))
+    assert abs(gamma / k ** 2 - nu) <= abs(nu2) * k * k * 1.01 + 1e-7
+    assert abs(mass) < 1e-13
+
+
+# ----------------------------------------- Galilean factor (sections 1-a and 2) ----
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+@pytest.mark.parametrize("direction", [(1, 0), (0, 1), (1, 1), (1, -1)])
+def test_galilean_shear_viscosity(scheme, direction):
+    """A shear wave whose wave vector is parallel to a uniform velocity V is damped with
+    nu_eff = nu (1 - 3 V^2), for D2Q9 (section 1-a) and for FD-LBM (section 2).  Along an
+    axis the factor comes from the cubic terms of theta_XY, along a diagonal from those of
+    theta_XX, so the four directions pin every velocity-cubic term of both."""
+    nu = 0.05
+    s_xx = O.rate_from_viscosity(nu)
+    if direction == (1, 0):
+        nx, ny, T1, T2 = 128, 4, 200, 1200
+    elif direction == (0, 1):
+        nx, ny, T1, T2 = 4, 128, 200, 1200
+    else:
+        nx, ny, T1, T2 = 48, 48, 100, 500
+    k = 2 * math.pi * math.hypot(direction[0] / nx, direction[1] / ny)
+    t = np.array([-direction[1], direction[0]]) / math.hypot(*direction)
+    rates = {}
+    for V in (0.0, 0.1, 0.2):
+        r, x, y = W.shear_wave(nx, ny, 1e-6, direction[0], direction[1], V=V)
+        if scheme == "mrt":
+            s_q = O.quartic_s_q(s_xx)
+            d1 = O.mrt_run(O.mrt_init(r, x, y), T1, s_xx=s_xx, s_q=s_q)
+            d2 = O.mrt_run(d1, T2 - T1, s_xx=s_xx, s_q=s_q)
+            m1, m2 = O.mrt_moments(d1), O.mrt_moments(d2)
+        else:
+            st = int(scheme[2])
+            m1 = O.fd_run(r, x, y, T1, s_xx=s_xx, stencil=st)
+            m2 = O.fd_run(*m1, T2 - T1, s_xx=s_xx, stencil=st)
+        a1 = abs(fourier_coeff(t[0] * m1[1] + t[1] * m1[2], *direction))
+        a2 = abs(fourier_coeff(t[0] * m2[1] + t[1] * m2[2], *direction))
+        rates[V] = math.log(a1 / a2) / (T2 - T1) / k ** 2
+    for V in (0.1, 0.2):
+        assert abs(rates[V] / rates[0.0] - (1 - 3 * V * V)) < 1.5e-3, (V, rates)
+
+
+# ----------------------------------------------------- Poiseuille (section 3-c) ----
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+def test_poiseuille_profile_and_wall_location(scheme):
+    """Channel of 15 fluid rows between walls at y = -1/2 and 14 + 1/2, driven by a uniform
+    force; the steady profile is a parabola whose zeros sit at the walls to within a few
+    hundredths of a node (halfway bounce-back gives xi_m = 0.5, section 3-c), and which
+    converges to the analytic parabola as the channel widens."""
+    nu = 1 / math.sqrt(108)
+    s_xx = O.rate_from_viscosity(nu)
+    errs = []
+    for ny in (15, 30):
+        r, x, y, F = W.poiseuille_profile(4, ny, nu, 0.05)
+        exact = x[:, 0].copy()
+        if scheme == "mrt":
+            d = O.mrt_run(O.mrt_init(r, x, y), 6000, s_xx=s_xx, s_q=O.quartic_s_q(s_xx), walls=True, fx=F)
+            u = O.mrt_moments(d)[1][:, 0] + F / 2
+        else:
+            out = O.fd_run(r, x, y, 6000, s_xx=s_xx, stencil=int(scheme[2]), walls=True, fx=F)
+            u = out[1][:, 0] + F / 2
+        yy = np.arange(ny)
+        c = np.polyfit(yy, u, 2)
+        lo, hi = np.sort(np.roots(c).real)
+        assert abs(lo + 0.5) < 0.02 and abs(hi - (ny - 0.5)) < 0.02, (ny, lo, hi)
+        errs.append(np.linalg.norm(u - exact) / np.linalg.norm(exact))
+    assert errs[0] < 1e-2 and errs[1] < errs[0]
+
+
+# -------------------------------------------------- instability is detectable ----
+
+def test_unstable_stencil_grows_and_stable_ones_decay():
+    """The 9-point stencil at nu = 0.01 amplifies noise (its symbol has |z| > 1 on the
+    diagonal); the same state decays with the 3-point stencil.  This is the growth that
+    the nonfinite / max|J| diagnostics of the GPU path must flag."""
+    s_xx = O.rate_from_viscosity(0.01)
+    r, x, y = W.random_state(24, 24, seed=9, amp=1e-6)
+    bad = O.fd_run(r, x, y, 3000, s_xx=s_xx, stencil=9)
+    good = O.fd_run(r, x, y, 3000, s_xx=s_xx, stencil=3)
+    j0 = np.max(np.abs(x))
+    assert not np.all(np.isfinite(bad[1])) or np.max(np.abs(bad[1])) > 10 * j0
+    assert np.max(np.abs(good[1])) < j0

@@ -1,0 +1,137 @@
+"""Seeded synthetic inputs shared by the oracle-side tests, the GPU tests and the bench.
+
+This module only draws numbers and lays them out; it holds none of the scheme's
+arithmetic (no equilibria, no finite differences, no relaxation).  Both the CPU
+oracle and the HIP path receive the arrays built here as plain inputs.
+
+Every field is a float64 array of shape (ny, nx) with x fastest, i.e. element
+[j, i] is node (x=i, y=j).  The stored state of a node is the deviation from the
+rest state: drho = rho - 1, jx, jy (momentum components).
+
+Workloads (the paper measures only synthetic flows, section 3):
+  * plane shear waves (section 3-a), optionally carried by a uniform velocity V;
+  * band-limited random Fourier fields ("Stokes modes" / decaying flow);
+  * the steady Poiseuille channel profile (section 3-c);
+  * a seeded family of independent shear-wave instances of uneven sizes.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "shear_wave",
+    "shear_wave_y",
+    "fourier_field",
+    "stokes_modes_256",
+    "decaying_flow",
+    "poiseuille_profile",
+    "batch_instances",
+    "random_state",
+]
+
+
+def shear_wave(nx, ny, amp, mx, my, V=0.0):
+    """Transverse plane wave of integer wave numbers (mx, my) (section 3-a).
+
+    k = 2*pi*(mx/nx, my/ny); the velocity amplitude A(0)=amp is carried by the
+    direction perpendicular to k, and an optional uniform velocity V is added
+    parallel to k:
+        rho = 1,  jx = -amp*ky/|k| cos(k.x) + V kx/|k|,  jy = amp*kx/|k| cos(k.x) + V ky/|k|.
+    (The printed initial condition repeats k_x in the phase; the phase is k.x.)
+    """
+    kx = 2.0 * math.pi * mx / nx
+    ky = 2.0 * math.pi * my / ny
+    k = math.hypot(kx, ky)
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    phase = np.cos(kx * x + ky * y)
+    drho = np.zeros((ny, nx))
+    jx = -amp * (ky / k) * phase + V * kx / k
+    jy = amp * (kx / k) * phase + V * ky / k
+    return drho, jx, jy
+
+
+def shear_wave_y(nx, ny, amp=0.01, m=1):
+    """jx(y) = amp*sin(2*pi*m*y/ny), rho = 1, jy = 0 (the 64x64 shear-wave case)."""
+    y = np.arange(ny, dtype=np.float64)
+    col = amp * np.sin(2.0 * math.pi * m * y / ny)
+    jx = np.repeat(col[:, None], nx, axis=1)
+    return np.zeros((ny, nx)), jx, np.zeros((ny, nx))
+
+
+def fourier_field(nx, ny, kmax, rng, row_chunk=2048):
+    """Real field made of every Fourier mode 0 < |k| <= kmax (integer wave numbers).
+
+    The coefficients are iid complex Gaussians, i.e. the spectrum of white noise
+    with every mode outside the band (and the mean) removed.  The sum is
+    evaluated as Re(Ey @ C @ Ex^T) so that an 8192^2 field needs no full FFT.
+    The result is not normalised.
+    """
+    ks = np.arange(-kmax, kmax + 1)
+    KY, KX = np.meshgrid(ks, ks, indexing="ij")
+    mask = (KX * KX + KY * KY <= kmax * kmax) & ((KX != 0) | (KY != 0))
+    c = (rng.standard_normal(KX.shape) + 1j * rng.standard_normal(KX.shape)) * mask
+    ex = np.exp(2j * math.pi * np.outer(np.arange(nx), ks) / nx)  # (nx, nk)
+    ey = np.exp(2j * math.pi * np.outer(np.arange(ny), ks) / ny)  # (ny, nk)
+    a = ey @ c  # (ny, nk)
+    out = np.empty((ny, nx))
+    exr, exi = ex.real.T.copy(), ex.imag.T.copy()
+    for j0 in range(0, ny, row_chunk):
+        j1 = min(ny, j0 + row_chunk)
+        out[j0:j1] = a[j0:j1].real @ exr - a[j0:j1].imag @ exi
+    return out
+
+
+def stokes_modes_256(seed=2, n=256, kmax=8, rms=1e-3):
+    """Band-limited random state: each of (drho, jx, jy) holds the modes 0<|k|<=kmax
+    and is rescaled to the given RMS."""
+    rng = np.random.default_rng(seed)
+    fields = []
+    for _ in range(3):
+        f = fourier_field(n, n, kmax, rng)
+        fields.append(f * (rms / np.sqrt(np.mean(f * f))))
+    return tuple(fields)
+
+
+def decaying_flow(n=8192, seed=4, kmax=32, amp=0.02, ny=None):
+    """Large decaying flow: per field, random modes 0<|k|<=kmax scaled to max|field|=amp."""
+    ny = n if ny is None else ny
+    rng = np.random.default_rng(seed)
+    fields = []
+    for _ in range(3):
+        f = fourier_field(n, ny, kmax, rng)
+        fields.append(f * (amp / np.max(np.abs(f))))
+    return tuple(fields)
+
+
+def poiseuille_profile(nx, ny, nu, u_c=0.05):
+    """Channel with walls at y=-1/2 and y=ny-1/2 (x periodic), centre-line speed u_c.
+
+    Returns (drho, jx, jy, force_x): the parabola u(y) = F/(2 nu) (y+1/2)(ny-1/2-y),
+    with the body force F = 8 nu u_c / ny^2 that sustains it.
+    """
+    F = 8.0 * nu * u_c / (ny * ny)
+    y = np.arange(ny, dtype=np.float64)
+    u = F / (2.0 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    jx = np.repeat(u[:, None], nx, axis=1)
+    return np.zeros((ny, nx)), jx, np.zeros((ny, nx)), F
+
+
+def batch_instances(count=512, seed=5, nmin=32, nmax=1024, numin=0.005, numax=0.1, mmax=4):
+    """Independent shear-wave instances of uneven size and viscosity.
+
+    N ~ U{nmin..nmax}, nu ~ U[numin, numax], m ~ U{1..mmax}; each instance starts
+    from jx = 0.01 sin(2 pi m y / N), drho = jy = 0 on an N x N periodic grid.
+    """
+    rng = np.random.default_rng(seed)
+    n = rng.integers(nmin, nmax + 1, size=count)
+    nu = rng.uniform(numin, numax, size=count)
+    m = rng.integers(1, mmax + 1, size=count)
+    return [dict(n=int(n[i]), nu=float(nu[i]), m=int(m[i]), amp=0.01) for i in range(count)]
+
+
+def random_state(nx, ny, seed, amp=1e-2):
+    """Uniform white noise of amplitude amp in each field (small parity cases)."""
+    rng = np.random.default_rng(seed)
+    return tuple(amp * (2.0 * rng.random((ny, nx)) - 1.0) for _ in range(3))
