@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Throughput of the FD-LBM D2Q9 step on one MI355X, with the MRT D2Q9 step beside it.
+
+Workload: the 8192 x 8192 periodic decaying flow (random Fourier modes 0<|k|<=32 per field,
+max |field| = 0.02, seed 4), FD-LBM with 3-point finite differences, nu = 0.02, s_e = 1,
+FP32 storage and arithmetic.  One step is one FD-LBM time step of the whole grid; the
+timed region also runs the FP64 diagnostics reduction every 100 steps.
+
+Prints ONE JSON line: value = FD-LBM FP32 MLUPS (million lattice-node updates per
+second), the HBM roofline of the step kernel (algorithmic bytes: 3 FP32 words read and 3
+written per node), the CPU oracle timed on a bounded band of the same workload, the
+relative L2 error of each GPU dtype against that oracle band, and the same measurements
+for the MRT step, the FP64 and FP16-storage FD-LBM steps and the 5-point stencil.
+
+    python bench.py [--steps K] [--warmup W] [--n 8192] [--no-compare] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM peak, FD-LBM vs MRT D2Q9 at 8192² FP32 (err vs FP64 oracle)"
+HBM_PEAK_GBS = 8000.0
+NU = 0.02
+DIAG_EVERY = 100
+COUNTERS = os.path.join(ROOT, "profiles", "fd3_f32_8192_counters.json")
+KERNEL_SOURCES = ["paper_1803_00437_amd/csrc/fd_sweep.hip", "paper_1803_00437_amd/csrc/fdlbm_device.hpp"]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_node(scheme, dtype):
+    words = 3 if scheme == "fd" else 9
+    return 2 * words * {"f64": 8, "f32": 4, "f16": 2}[dtype]
+
+
+def run_case(F, torch, init, n, scheme, dtype, stencil, steps, warmup, kernel, with_diag):
+    s_xx = F.fdlbm_rate_from_viscosity(NU)
+    kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel)
+    if scheme == "fd":
+        kw["stencil"] = stencil
+    else:
+        kw["quartic"] = True
+    sim = F.FdLbm(n, n, **kw)
+    sim.set_state(*init)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    # kernel-only region, timed with HIP events on the library's stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    e1.synchronize()
+    kernel_ms = e0.elapsed_time(e1) / steps
+    # whole-step region (steps + periodic diagnostics), wall clock between synchronisations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(DIAG_EVERY, steps - done)
+        sim.step(k)
+        done += k
+        if with_diag:
+            sim.diagnostics()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    diag = sim.diagnostics()
+    sim.close()
+    nodes = n * n
+    return {
+        "ms_per_step": wall_ms,
+        "kernel_ms": kernel_ms,
+        "mlups": nodes / (wall_ms * 1e3),
+        "kernel_mlups": nodes / (kernel_ms * 1e3),
+        "alg_gbs": bytes_per_node(scheme, dtype) * nodes / (kernel_ms * 1e6),
+        "nonfinite": diag["nonfinite"],
+    }
+
+
+def band_errors(F, O, init, n, s_steps, rows, cases, threads):
+    """Relative L2 error of each GPU case after s_steps over a band of rows, against the
+    FP64 oracle run on that band alone (a band of rows +- the domain of dependence
+    s_steps * (h + 1) rows, periodic in y, whose contaminated edges are discarded)."""
+    import numpy as np
+
+    y0 = n // 3
+    out = {}
+    oracle_time = None
+    O.num_threads(threads)
+    s_xx = F.fdlbm_rate_from_viscosity(NU)
+    refs = {}
+    for scheme, stencil in sorted({(c[0], c[2]) for c in cases}):
+        m = s_steps * ((2 if stencil == 3 else 3) if scheme == "fd" else 1)
+        sl = slice(y0 - m, y0 + rows + m)
+        band = tuple(np.ascontiguousarray(a[sl]) for a in init)
+        t0 = time.perf_counter()
+        if scheme == "fd":
+            res = O.fd_run(*band, s_steps, s_xx=s_xx, s_e=1.0, stencil=stencil)
+        else:
+            res = O.mrt_moments(O.mrt_run(O.mrt_init(*band), s_steps, s_xx=s_xx, s_q=O.quartic_s_q(s_xx)))
+        dt = time.perf_counter() - t0
+        if scheme == "fd" and stencil == 3:
+            oracle_time = (band[0].size * s_steps, dt)
+        refs[(scheme, stencil)] = tuple(a[m:m + rows] for a in res)
+    for scheme, dtype, stencil in cases:
+        kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0)
+        kw.update({"stencil": stencil} if scheme == "fd" else {"quartic": True})
+        sim = F.FdLbm(n, n, **kw)
+        sim.set_state(*init)
+        sim.step(s_steps)
+        got = sim.get_state()
+        sim.close()
+        want = refs[(scheme, stencil)]
+        num = sum(float(np.sum((g[y0:y0 + rows] - w) ** 2)) for g, w in zip(got, want))
+        den = sum(float(np.sum(w * w)) for w in want)
+        out[f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"] = math.sqrt(num / den)
+    return out, oracle_time
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "reference", "sweep"])
+    ap.add_argument("--no-compare", action="store_true", help="skip MRT / FP64 / FP16 / 5-point lines")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error bands")
+    ap.add_argument("--err-steps", type=int, default=12)
+    ap.add_argument("--err-rows", type=int, default=512)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the FD-LBM path of this "
+              "library has no multi-GPU build; see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1803_00437_amd as F
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    F.load_library()
+    n = args.n
+    t0 = time.perf_counter()
+    init = W.decaying_flow(n=n, seed=4, kmax=32, amp=0.02)
+    print(f"# input {n}x{n} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    main_case = run_case(F, torch, init, n, "fd", "f32", 3, args.steps, args.warmup, args.kernel, True)
+    print(f"# fd3 f32: {main_case}", file=sys.stderr, flush=True)
+
+    compare = {}
+    if not args.no_compare:
+        short = max(100, args.steps // 4)
+        for scheme, dtype, stencil in (("mrt", "f32", 0), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5),
+                                       ("mrt", "f64", 0)):
+            key = f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"
+            compare[key] = run_case(F, torch, init, n, scheme, dtype, stencil, short, 10, args.kernel, False)
+            print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
+
+    cpu = None
+    errors = None
+    if not args.no_cpu:
+        import oracle as O
+
+        threads = min(os.cpu_count() or 1, 16)
+        cases = [("fd", "f32", 3), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5), ("mrt", "f32", 0),
+                 ("mrt", "f64", 0)]
+        errors, (updates, secs) = band_errors(F, O, init, n, args.err_steps, args.err_rows, cases, threads)
+        print(f"# errors vs oracle: {errors}", file=sys.stderr, flush=True)
+        cpu = {
+            "value": updates / secs / 1e6,
+            "unit": "MLUPS",
+            "cores": O.num_threads(0),
+            "kind": "oracle",
+            "sample": f"FP64 CPU oracle, FD-LBM 3-point, {args.err_steps} steps on a {n} x "
+                      f"{args.err_rows + 2 * 2 * args.err_steps}-row band of the {n}x{n} decaying flow "
+                      f"({updates / 1e6:.1f} M node updates in {secs:.1f} s)",
+        }
+
+    counters = None
+    if os.path.exists(COUNTERS):
+        with open(COUNTERS) as f:
+            c = json.load(f)
+        if c.get("kernel_source_sha") == kernel_source_sha() and c.get("n") == n:
+            counters = c
+    ms = main_case["ms_per_step"]
+    kernel_ms = main_case["kernel_ms"]
+    achieved = main_case["alg_gbs"]
+    line = {
+        "metric": METRIC,
+        "value": round(main_case["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n}x{n} periodic decaying flow, random Fourier modes 0<|k|<=32, max|field|=0.02, seed 4; "
+                        f"FD-LBM D2Q9 3-point finite differences, nu={NU}, s_e=1, FP32; FP64 diagnostics every "
+                        f"{DIAG_EVERY} steps",
+            "nx": n, "ny": n, "stencil": 3, "kernel": args.kernel,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (round(counters["hbm_bytes_per_launch"] / (kernel_ms * 1e6), 1) if counters else None),
+            "traffic_bytes_per_launch": (counters["hbm_bytes_per_launch"] if counters else None),
+            "kernel_ms": round(kernel_ms, 5),
+            "alg_bytes_per_launch": bytes_per_node("fd", "f32") * n * n,
+        },
+        "cpu_baseline": cpu,
+        "err_vs_oracle": errors,
+        "compare": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in compare.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * fdlbm.h -- C ABI of the MI355X (gfx950) library for the FD-LBM D2Q9 time step and the
+ * MRT D2Q9 stream-collide step of Dubois, Lallemand, Obrecht and Tekitek, "Lattice
+ * Boltzmann model approximated with finite difference expressions" (Computers & Fluids
+ * 155, 2017; arXiv 1803.00437).
+ *
+ * Conventions shared by every entry point
+ *   - Grid nx * ny, node (x=i, y=j) at linear index j*nx + i (x fastest).  x is always
+ *     periodic.  y is periodic (FDLBM_BC_PERIODIC) or closed by two walls parallel to Ox
+ *     at y = -1/2 and y = ny - 1/2 (FDLBM_BC_WALLS_Y; the channel of section 3-c with the
+ *     wall half-way between the last fluid node and the first node outside).
+ *   - The state is stored as deviations from the rest state rho = 1, J = 0: three planes
+ *     drho = rho - 1, jx, jy (FD-LBM) or nine population planes f_k - w_k (MRT), in the
+ *     storage dtype, plane after plane, each plane nx*ny elements with no padding.
+ *   - Velocity order of the populations (section 1): e_0 = (0,0), e_1..e_4 = (1,0), (0,1),
+ *     (-1,0), (0,-1), e_5..e_8 = (1,1), (-1,1), (-1,-1), (1,-1).
+ *   - Device buffers are owned by the caller (allocated e.g. by PyTorch) and must stay
+ *     valid until fdlbm_destroy.  The library never allocates or frees device memory.
+ *   - All work is issued on the HIP stream given at creation (NULL = the default stream).
+ *     Steps return without synchronising; fdlbm_get_state, fdlbm_get_populations,
+ *     fdlbm_diagnostics and fdlbm_mode_projection synchronise that stream.
+ *   - A context is used by one host thread at a time.
+ *   - Every function returns FDLBM_OK (0) or a negative code; no C++ exception crosses the
+ *     ABI.  After FDLBM_EDEVICE, fdlbm_last_error() returns the HIP error text.
+ */
+#ifndef FDLBM_H
+#define FDLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDLBM_OK 0
+#define FDLBM_EINVAL (-1)    /* invalid parameter, NULL pointer, or call on the wrong scheme */
+#define FDLBM_ENOMEM (-2)    /* a caller buffer is smaller than fdlbm_workspace_bytes requires */
+#define FDLBM_EDEVICE (-3)   /* a HIP runtime call failed */
+#define FDLBM_EUNSTABLE (-4) /* the periodic check found a non-finite value in the state */
+
+enum { FDLBM_SCHEME_FD = 0, FDLBM_SCHEME_MRT = 1 };
+enum { FDLBM_BC_PERIODIC = 0, FDLBM_BC_WALLS_Y = 1 };
+/* Storage dtype of the state.  F64: FP64 storage and arithmetic.  F32: FP32 storage and
+ * arithmetic.  F16DEV: FP16 storage of the deviations (drho, jx, jy), FP32 arithmetic
+ * (FD-LBM only).  Diagnostics are always reduced in FP64. */
+enum { FDLBM_F64 = 0, FDLBM_F32 = 1, FDLBM_F16DEV = 2 };
+/* FD-LBM kernel selection: AUTO picks the fused sweep kernel. */
+enum { FDLBM_KERNEL_AUTO = 0, FDLBM_KERNEL_REFERENCE = 1, FDLBM_KERNEL_SWEEP = 2 };
+
+typedef struct fdlbm_params {
+    int32_t nx, ny;     /* grid; FD-LBM: nx >= 8; walls: ny >= 4; periodic y: ny >= 8      */
+    int32_t scheme;     /* FDLBM_SCHEME_FD or FDLBM_SCHEME_MRT                               */
+    int32_t stencil;    /* FD-LBM finite differences of section 2: 3 or 5 points           */
+    int32_t bc;         /* FDLBM_BC_PERIODIC or FDLBM_BC_WALLS_Y                            */
+    int32_t dtype;      /* FDLBM_F64, FDLBM_F32, FDLBM_F16DEV                               */
+    /* Relaxation rates, each in (0, 2).  Section 1-a: nu = (1/s_xx - 1/2)/3,
+     * zeta = (1/s_e - 1/2)/3.  FD-LBM uses s_xx and s_e (its q and eps moments sit at
+     * equilibrium, section 2); MRT uses all four.                                            */
+    double s_xx, s_e, s_q, s_eps;
+    int32_t quartic;    /* MRT: nonzero replaces s_q by the value that satisfies
+                         * (1/s_xx - 1/2)(1/s_q - 1/2) = 1/6 (section 3-b)                   */
+    double force_x, force_y; /* uniform body force per node and step, Strang-split (section 1) */
+    int32_t kernel;     /* FDLBM_KERNEL_*                                                     */
+    int32_t tile_rows;  /* sweep kernel: rows per column strip (0 = choose); tuning knob      */
+    int32_t check_every;/* > 0: fdlbm_step / mrt_step scan the state for non-finite values
+                         * every check_every steps and return FDLBM_EUNSTABLE if one is found
+                         * (this synchronises the stream at each check)                       */
+    int32_t reserved;
+} fdlbm_params;
+
+typedef struct fdlbm_diag {
+    double mass;       /* sum of drho over all nodes (total mass minus nx*ny)              */
+    double mom_x;      /* sum of jx                                                         */
+    double mom_y;      /* sum of jy                                                         */
+    double kin_energy; /* 1/2 sum |J|^2 / rho                                               */
+    double max_abs_j;  /* max |J|                                                           */
+    double proj_num;   /* sum J . J0 (0 when no mode was set)                               */
+    double proj_den;   /* sum J0 . J0                                                       */
+    int64_t nonfinite; /* number of nodes with a NaN or Inf in drho, jx or jy              */
+} fdlbm_diag;
+
+typedef struct fdlbm_ctx fdlbm_ctx;
+
+/* Sizes of the caller-owned device buffers for these parameters: each of the two state
+ * buffers (ping-pong) needs *state_bytes, the scratch buffer *scratch_bytes.  Returns
+ * FDLBM_EINVAL for parameters fdlbm_create would reject. */
+int fdlbm_workspace_bytes(const fdlbm_params *p, size_t *state_bytes, size_t *scratch_bytes);
+
+/* Validate p, bind the caller's device buffers (state_a, state_b: state_bytes each;
+ * scratch: scratch_bytes; all 256-byte aligned) and the HIP stream (hipStream_t, may be
+ * NULL), and return a context in *out.  The state is zero (rest) until set. */
+int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scratch, size_t scratch_bytes,
+                 void *hip_stream, fdlbm_ctx **out);
+
+/* Upload a state from host FP64 arrays of nx*ny values each (drho = rho - 1, jx, jy),
+ * converting to the storage dtype on the device.  MRT: the populations become
+ * f^eq(rho, J) of section 1-a (the initial state of an MRT run).  Resets the step count. */
+int fdlbm_set_state(fdlbm_ctx *c, const double *drho, const double *jx, const double *jy);
+
+/* Download the current (drho, jx, jy) into host FP64 arrays.  MRT: the conserved moments
+ * of the populations.  With a body force the physical momentum is J + F/2 (Strang). */
+int fdlbm_get_state(fdlbm_ctx *c, double *drho, double *jx, double *jy);
+
+/* MRT only: upload / download the nine population planes (f_k - w_k), host FP64,
+ * 9*nx*ny values, plane k at offset k*nx*ny.  get/set round-trips exactly in FP64. */
+int fdlbm_set_populations(fdlbm_ctx *c, const double *df);
+int fdlbm_get_populations(fdlbm_ctx *c, double *df);
+
+/* Advance the FD-LBM state by nsteps time steps (section 2): finite differences of the
+ * stored (rho, J), theta terms, post-collision moments, f* = M^{-1} m*, propagation
+ * (eq. 2), new (rho, J).  Asynchronous.  FDLBM_EINVAL if the context is MRT. */
+int fdlbm_step(fdlbm_ctx *c, int64_t nsteps);
+
+/* Advance the MRT populations by nsteps stream-collide steps (section 1, eqs. 1-2) with
+ * halfway bounce-back on walls.  Asynchronous.  FDLBM_EINVAL if the context is FD-LBM. */
+int mrt_step(fdlbm_ctx *c, int64_t nsteps);
+
+/* FP64 reduction over the current state (section 3-a diagnostics): totals, kinetic
+ * energy, max |J|, non-finite count and, if a mode was set, sum J.J0.  Synchronises. */
+int fdlbm_diagnostics(fdlbm_ctx *c, fdlbm_diag *out);
+
+/* Store a reference velocity field J0 (host FP64, nx*ny each) in the scratch buffer for
+ * the correlation A(t) = <J(t), J0> / <J0, J0> of section 3-a. */
+int fdlbm_set_mode(fdlbm_ctx *c, const double *j0x, const double *j0y);
+
+/* A(t) for the current state (FDLBM_EINVAL if no mode was set).  Synchronises. */
+int fdlbm_mode_projection(fdlbm_ctx *c, double *out);
+
+/* Number of steps taken since the last set_state / set_populations. */
+int64_t fdlbm_step_count(const fdlbm_ctx *c);
+
+/* Release the context.  Frees nothing the caller owns. */
+void fdlbm_destroy(fdlbm_ctx *c);
+
+/* Static text for a return code, and the last HIP error text of this thread. */
+const char *fdlbm_strerror(int code);
+const char *fdlbm_last_error(void);
+
+/* The transport-coefficient map of section 1-a: s = 1 / (1/2 + 3 nu). */
+double fdlbm_rate_from_viscosity(double nu);
+/* The quartic rate of section 3-b: s_q with (1/s_xx - 1/2)(1/s_q - 1/2) = 1/6. */
+double fdlbm_quartic_s_q(double s_xx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDLBM_H */

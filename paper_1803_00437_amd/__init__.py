@@ -1,0 +1,290 @@
+"""MI355X (gfx950) FD-LBM and MRT D2Q9 steps -- thin Python binding of libfdlbm.so.
+
+The binding only marshals arguments: every step of the computation runs in the HIP
+kernels of ``csrc/``, behind the C ABI declared in ``include/fdlbm.h``.  PyTorch is used
+to allocate the caller-owned device buffers and to supply the HIP stream.
+
+Module-level functions carry the C names (``fdlbm_create``, ``fdlbm_step``, ``mrt_step``,
+``fdlbm_diagnostics`` ...); :class:`FdLbm` owns the buffers of one simulation.
+
+There is no fallback: if ``_build/libfdlbm.so`` is missing, importing the binding's entry
+points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libfdlbm.so")
+
+FDLBM_OK, FDLBM_EINVAL, FDLBM_ENOMEM, FDLBM_EDEVICE, FDLBM_EUNSTABLE = 0, -1, -2, -3, -4
+SCHEME = {"fd": 0, "mrt": 1}
+BC = {"periodic": 0, "walls": 1}
+DTYPE = {"f64": 0, "f32": 1, "f16": 2}
+KERNEL = {"auto": 0, "reference": 1, "sweep": 2}
+
+EXPORTED = (
+    "fdlbm_workspace_bytes", "fdlbm_create", "fdlbm_set_state", "fdlbm_get_state",
+    "fdlbm_set_populations", "fdlbm_get_populations", "fdlbm_step", "mrt_step",
+    "fdlbm_diagnostics", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
+    "fdlbm_destroy", "fdlbm_strerror", "fdlbm_last_error", "fdlbm_rate_from_viscosity",
+    "fdlbm_quartic_s_q",
+)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("scheme", ctypes.c_int32),
+        ("stencil", ctypes.c_int32), ("bc", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("s_xx", ctypes.c_double), ("s_e", ctypes.c_double), ("s_q", ctypes.c_double),
+        ("s_eps", ctypes.c_double), ("quartic", ctypes.c_int32),
+        ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
+        ("kernel", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double),
+        ("kin_energy", ctypes.c_double), ("max_abs_j", ctypes.c_double),
+        ("proj_num", ctypes.c_double), ("proj_den", ctypes.c_double), ("nonfinite", ctypes.c_int64),
+    ]
+
+
+class FdlbmError(RuntimeError):
+    def __init__(self, code, what):
+        lib = _lib_or_none()
+        msg = lib.fdlbm_strerror(code).decode() if lib else str(code)
+        if code == FDLBM_EDEVICE and lib:
+            msg += ": " + lib.fdlbm_last_error().decode()
+        super().__init__(f"{what}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def _lib_or_none():
+    return _LIB
+
+
+def load_library(path=LIB_PATH):
+    """Load libfdlbm.so and declare its signatures.  Raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1803_00437_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int64
+    P = ctypes.POINTER(Params)
+    sig = {
+        "fdlbm_workspace_bytes": (i32, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "fdlbm_create": (i32, [P, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "fdlbm_set_state": (i32, [vp, dp, dp, dp]),
+        "fdlbm_get_state": (i32, [vp, dp, dp, dp]),
+        "fdlbm_set_populations": (i32, [vp, dp]),
+        "fdlbm_get_populations": (i32, [vp, dp]),
+        "fdlbm_step": (i32, [vp, i64]),
+        "mrt_step": (i32, [vp, i64]),
+        "fdlbm_diagnostics": (i32, [vp, ctypes.POINTER(Diag)]),
+        "fdlbm_set_mode": (i32, [vp, dp, dp]),
+        "fdlbm_mode_projection": (i32, [vp, dp]),
+        "fdlbm_step_count": (i64, [vp]),
+        "fdlbm_destroy": (None, [vp]),
+        "fdlbm_strerror": (ctypes.c_char_p, [i32]),
+        "fdlbm_last_error": (ctypes.c_char_p, []),
+        "fdlbm_rate_from_viscosity": (ctypes.c_double, [ctypes.c_double]),
+        "fdlbm_quartic_s_q": (ctypes.c_double, [ctypes.c_double]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != FDLBM_OK:
+        raise FdlbmError(rc, what)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ----------------------------------------------------------- C-named entry points ----
+
+def make_params(nx, ny, scheme="fd", stencil=3, bc="periodic", dtype="f32", s_xx=1.0, s_e=1.0,
+                s_q=1.0, s_eps=1.0, quartic=False, force=(0.0, 0.0), kernel="auto", tile_rows=0,
+                check_every=0):
+    return Params(int(nx), int(ny), SCHEME[scheme], int(stencil), BC[bc], DTYPE[dtype], float(s_xx),
+                  float(s_e), float(s_q), float(s_eps), int(bool(quartic)), float(force[0]),
+                  float(force[1]), KERNEL[kernel], int(tile_rows), int(check_every), 0)
+
+
+def fdlbm_workspace_bytes(params):
+    sb, cb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().fdlbm_workspace_bytes(ctypes.byref(params), ctypes.byref(sb), ctypes.byref(cb)),
+           "fdlbm_workspace_bytes")
+    return sb.value, cb.value
+
+
+def fdlbm_create(params, state_a, state_b, scratch, scratch_bytes, stream):
+    """Device pointers as ints; stream a hipStream_t handle as int (0 = default)."""
+    ctx = ctypes.c_void_p()
+    _check(load_library().fdlbm_create(ctypes.byref(params), state_a, state_b, scratch, scratch_bytes,
+                                       stream or None, ctypes.byref(ctx)), "fdlbm_create")
+    return ctx
+
+
+def fdlbm_set_state(ctx, drho, jx, jy):
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (drho, jx, jy)]
+    _check(load_library().fdlbm_set_state(ctx, *[_dptr(v) for v in a]), "fdlbm_set_state")
+
+
+def fdlbm_get_state(ctx, shape):
+    out = [np.empty(shape, dtype=np.float64) for _ in range(3)]
+    _check(load_library().fdlbm_get_state(ctx, *[_dptr(v) for v in out]), "fdlbm_get_state")
+    return tuple(out)
+
+
+def fdlbm_set_populations(ctx, df):
+    a = np.ascontiguousarray(df, dtype=np.float64)
+    _check(load_library().fdlbm_set_populations(ctx, _dptr(a)), "fdlbm_set_populations")
+
+
+def fdlbm_get_populations(ctx, shape):
+    out = np.empty((9,) + tuple(shape), dtype=np.float64)
+    _check(load_library().fdlbm_get_populations(ctx, _dptr(out)), "fdlbm_get_populations")
+    return out
+
+
+def fdlbm_step(ctx, nsteps):
+    _check(load_library().fdlbm_step(ctx, int(nsteps)), "fdlbm_step")
+
+
+def mrt_step(ctx, nsteps):
+    _check(load_library().mrt_step(ctx, int(nsteps)), "mrt_step")
+
+
+def fdlbm_diagnostics(ctx):
+    d = Diag()
+    _check(load_library().fdlbm_diagnostics(ctx, ctypes.byref(d)), "fdlbm_diagnostics")
+    return {f: getattr(d, f) for f, _ in Diag._fields_}
+
+
+def fdlbm_set_mode(ctx, j0x, j0y):
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (j0x, j0y)]
+    _check(load_library().fdlbm_set_mode(ctx, *[_dptr(v) for v in a]), "fdlbm_set_mode")
+
+
+def fdlbm_mode_projection(ctx):
+    out = ctypes.c_double()
+    _check(load_library().fdlbm_mode_projection(ctx, ctypes.byref(out)), "fdlbm_mode_projection")
+    return out.value
+
+
+def fdlbm_step_count(ctx):
+    return int(load_library().fdlbm_step_count(ctx))
+
+
+def fdlbm_destroy(ctx):
+    load_library().fdlbm_destroy(ctx)
+
+
+def fdlbm_rate_from_viscosity(nu):
+    return float(load_library().fdlbm_rate_from_viscosity(float(nu)))
+
+
+def fdlbm_quartic_s_q(s_xx):
+    return float(load_library().fdlbm_quartic_s_q(float(s_xx)))
+
+
+# ----------------------------------------------------------------- convenience ----
+
+@dataclass
+class Buffers:
+    state_a: object
+    state_b: object
+    scratch: object
+
+
+class FdLbm:
+    """One simulation: owns its torch device buffers and its library context.
+
+    Keyword arguments follow ``fdlbm_params`` (see include/fdlbm.h); ``dtype`` is one of
+    "f64", "f32", "f16" (FP16-stored deviations, FP32 arithmetic), ``bc`` "periodic" or
+    "walls", ``scheme`` "fd" or "mrt", ``kernel`` "auto", "reference" or "sweep".
+    """
+
+    def __init__(self, nx, ny, device="cuda", stream=None, **kw):
+        import torch
+
+        load_library()
+        self.nx, self.ny = int(nx), int(ny)
+        self.params = make_params(nx, ny, **kw)
+        self.scheme = kw.get("scheme", "fd")
+        sb, cb = fdlbm_workspace_bytes(self.params)
+        dev = torch.device(device)
+        self._torch = torch
+        self.buffers = Buffers(*(torch.empty(b, dtype=torch.uint8, device=dev) for b in (sb, sb, cb)))
+        for t in (self.buffers.state_a, self.buffers.state_b, self.buffers.scratch):
+            if t.data_ptr() % 256:
+                raise RuntimeError("torch returned a device buffer that is not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.ctx = fdlbm_create(self.params, self.buffers.state_a.data_ptr(), self.buffers.state_b.data_ptr(),
+                                self.buffers.scratch.data_ptr(), cb, self.stream.cuda_stream)
+        self.state_bytes, self.scratch_bytes = sb, cb
+
+    # state
+    def set_state(self, drho, jx, jy):
+        fdlbm_set_state(self.ctx, drho, jx, jy)
+
+    def get_state(self):
+        return fdlbm_get_state(self.ctx, (self.ny, self.nx))
+
+    def set_populations(self, df):
+        fdlbm_set_populations(self.ctx, df)
+
+    def get_populations(self):
+        return fdlbm_get_populations(self.ctx, (self.ny, self.nx))
+
+    # stepping
+    def step(self, nsteps=1):
+        if self.scheme == "mrt":
+            mrt_step(self.ctx, nsteps)
+        else:
+            fdlbm_step(self.ctx, nsteps)
+
+    @property
+    def steps(self):
+        return fdlbm_step_count(self.ctx)
+
+    # diagnostics
+    def diagnostics(self):
+        return fdlbm_diagnostics(self.ctx)
+
+    def set_mode(self, j0x, j0y):
+        fdlbm_set_mode(self.ctx, j0x, j0y)
+
+    def mode_projection(self):
+        return fdlbm_mode_projection(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            fdlbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

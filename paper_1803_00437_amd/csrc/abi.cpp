@@ -1,0 +1,340 @@
+// C ABI of the FD-LBM / MRT D2Q9 library (declarations and contracts in include/fdlbm.h).
+// Host code only: validation, scratch layout, stream-ordered launches of the kernels in
+// the other translation units, and FP64 host <-> device staging.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace fdlbm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int device_error(hipError_t e, const char *what)
+{
+    std::snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+    return FDLBM_EDEVICE;
+}
+
+#define HIPCHK(call, what)                                 \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return device_error(e_, what); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
+
+double quartic(double s_xx) { return 1.0 / (0.5 + 1.0 / (6.0 * (1.0 / s_xx - 0.5))); }
+
+struct Layout {
+    size_t partials, out, mode, staging, fstar, total;
+};
+
+FdArgs fd_args(const fdlbm_params &p)
+{
+    return FdArgs{p.nx, p.ny, p.stencil, p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, p.dtype, p.s_xx, p.s_e, p.force_x, p.force_y};
+}
+
+bool uses_reference(const fdlbm_params &p)
+{
+    if (p.scheme != FDLBM_SCHEME_FD) return false;
+    if (p.kernel == FDLBM_KERNEL_REFERENCE) return true;
+    return !fd_sweep_supported(fd_args(p));
+}
+
+int validate(const fdlbm_params *p)
+{
+    if (!p) return FDLBM_EINVAL;
+    if (p->scheme != FDLBM_SCHEME_FD && p->scheme != FDLBM_SCHEME_MRT) return FDLBM_EINVAL;
+    if (p->bc != FDLBM_BC_PERIODIC && p->bc != FDLBM_BC_WALLS_Y) return FDLBM_EINVAL;
+    if (p->nx < 8 || p->nx > (1 << 20)) return FDLBM_EINVAL;
+    if (p->ny < (p->bc == FDLBM_BC_WALLS_Y ? 4 : 8) || p->ny > (1 << 20)) return FDLBM_EINVAL;
+    if ((size_t)p->nx * (size_t)p->ny > (size_t(1) << 32)) return FDLBM_EINVAL;
+    if (!rate_ok(p->s_xx) || !rate_ok(p->s_e)) return FDLBM_EINVAL;
+    if (!std::isfinite(p->force_x) || !std::isfinite(p->force_y)) return FDLBM_EINVAL;
+    if (p->kernel < FDLBM_KERNEL_AUTO || p->kernel > FDLBM_KERNEL_SWEEP) return FDLBM_EINVAL;
+    if (p->tile_rows < 0 || p->check_every < 0) return FDLBM_EINVAL;
+    if (p->scheme == FDLBM_SCHEME_FD) {
+        if (p->stencil != 3 && p->stencil != 5) return FDLBM_EINVAL;  // the 9-point form is unstable on {1,1}
+        if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32 && p->dtype != FDLBM_F16DEV) return FDLBM_EINVAL;
+        if (p->kernel == FDLBM_KERNEL_SWEEP && !fd_sweep_supported(fd_args(*p))) return FDLBM_EINVAL;
+    } else {
+        if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32) return FDLBM_EINVAL;
+        if (!rate_ok(p->s_eps)) return FDLBM_EINVAL;
+        if (!p->quartic && !rate_ok(p->s_q)) return FDLBM_EINVAL;
+    }
+    return FDLBM_OK;
+}
+
+Layout layout(const fdlbm_params &p)
+{
+    const size_t n = (size_t)p.nx * (size_t)p.ny;
+    Layout L;
+    size_t off = 0;
+    L.partials = off;
+    off += align256(sizeof(double) * DIAG_BLOCKS * DIAG_SLOTS);
+    L.out = off;
+    off += align256(sizeof(double) * DIAG_SLOTS);
+    L.mode = off;
+    off += align256(sizeof(double) * 2 * n);
+    // staging (set/get) and the reference path's f* planes are never live at once
+    const size_t staging = align256(sizeof(double) * (p.scheme == FDLBM_SCHEME_MRT ? 9 : 3) * n);
+    const size_t fstar = uses_reference(p) ? align256(fd_reference_scratch_bytes(fd_args(p))) : 0;
+    L.staging = off;
+    L.fstar = off;
+    off += staging > fstar ? staging : fstar;
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct fdlbm_ctx {
+    fdlbm_params p;
+    double s_q;  // effective MRT s_q
+    int device;
+    char *buf[2];
+    int cur;
+    char *scratch;
+    Layout L;
+    hipStream_t stream;
+    int64_t steps;
+    bool mode_set;
+
+    size_t n() const { return (size_t)p.nx * (size_t)p.ny; }
+    double *sd(size_t off) const { return reinterpret_cast<double *>(scratch + off); }
+};
+
+extern "C" {
+
+int fdlbm_workspace_bytes(const fdlbm_params *p, size_t *state_bytes, size_t *scratch_bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    const size_t n = (size_t)p->nx * (size_t)p->ny;
+    if (state_bytes) *state_bytes = align256((p->scheme == FDLBM_SCHEME_MRT ? 9 : 3) * n * dtype_bytes(p->dtype));
+    if (scratch_bytes) *scratch_bytes = layout(*p).total;
+    return FDLBM_OK;
+}
+
+int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scratch, size_t scratch_bytes,
+                 void *hip_stream, fdlbm_ctx **out)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out || !state_a || !state_b || !scratch || state_a == state_b) return FDLBM_EINVAL;
+    if (((uintptr_t)state_a | (uintptr_t)state_b | (uintptr_t)scratch) & 255) return FDLBM_EINVAL;
+    Layout L = layout(*p);
+    if (scratch_bytes < L.total) return FDLBM_ENOMEM;
+    fdlbm_ctx *c = new (std::nothrow) fdlbm_ctx;
+    if (!c) return FDLBM_ENOMEM;
+    c->p = *p;
+    c->s_q = p->scheme == FDLBM_SCHEME_MRT && p->quartic ? quartic(p->s_xx) : p->s_q;
+    c->buf[0] = static_cast<char *>(state_a);
+    c->buf[1] = static_cast<char *>(state_b);
+    c->cur = 0;
+    c->scratch = static_cast<char *>(scratch);
+    c->L = L;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->steps = 0;
+    c->mode_set = false;
+    hipError_t e = hipGetDevice(&c->device);
+    size_t sb = 0;
+    fdlbm_workspace_bytes(p, &sb, nullptr);
+    if (e == hipSuccess) e = hipMemsetAsync(state_a, 0, sb, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(state_b, 0, sb, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return device_error(e, "fdlbm_create");
+    }
+    *out = c;
+    return FDLBM_OK;
+}
+
+void fdlbm_destroy(fdlbm_ctx *c) { delete c; }
+
+int64_t fdlbm_step_count(const fdlbm_ctx *c) { return c ? c->steps : -1; }
+
+int fdlbm_set_state(fdlbm_ctx *c, const double *drho, const double *jx, const double *jy)
+{
+    if (!c || !drho || !jx || !jy) return FDLBM_EINVAL;
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const size_t n = c->n(), nb = n * sizeof(double);
+    double *st = c->sd(c->L.staging);
+    HIPCHK(hipMemcpyAsync(st, drho, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
+    HIPCHK(hipMemcpyAsync(st + n, jx, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
+    HIPCHK(hipMemcpyAsync(st + 2 * n, jy, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
+    if (c->p.scheme == FDLBM_SCHEME_FD)
+        HIPCHK(launch_pack(c->p.dtype, st, c->buf[c->cur], 3 * n, c->stream), "pack");
+    else
+        HIPCHK(launch_mrt_init(c->p.dtype, st, st + n, st + 2 * n, c->buf[c->cur], n, c->stream), "mrt_init");
+    HIPCHK(hipStreamSynchronize(c->stream), "set_state");
+    c->steps = 0;
+    return FDLBM_OK;
+}
+
+int fdlbm_get_state(fdlbm_ctx *c, double *drho, double *jx, double *jy)
+{
+    if (!c || !drho || !jx || !jy) return FDLBM_EINVAL;
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const size_t n = c->n(), nb = n * sizeof(double);
+    double *st = c->sd(c->L.staging);
+    if (c->p.scheme == FDLBM_SCHEME_FD)
+        HIPCHK(launch_unpack(c->p.dtype, c->buf[c->cur], st, 3 * n, c->stream), "unpack");
+    else
+        HIPCHK(launch_mrt_moments(c->p.dtype, c->buf[c->cur], st, st + n, st + 2 * n, n, c->stream), "mrt_moments");
+    HIPCHK(hipMemcpyAsync(drho, st, nb, hipMemcpyDeviceToHost, c->stream), "get_state download");
+    HIPCHK(hipMemcpyAsync(jx, st + n, nb, hipMemcpyDeviceToHost, c->stream), "get_state download");
+    HIPCHK(hipMemcpyAsync(jy, st + 2 * n, nb, hipMemcpyDeviceToHost, c->stream), "get_state download");
+    HIPCHK(hipStreamSynchronize(c->stream), "get_state");
+    return FDLBM_OK;
+}
+
+int fdlbm_set_populations(fdlbm_ctx *c, const double *df)
+{
+    if (!c || !df || c->p.scheme != FDLBM_SCHEME_MRT) return FDLBM_EINVAL;
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const size_t n = c->n();
+    double *st = c->sd(c->L.staging);
+    HIPCHK(hipMemcpyAsync(st, df, 9 * n * sizeof(double), hipMemcpyHostToDevice, c->stream), "set_populations");
+    HIPCHK(launch_pack(c->p.dtype, st, c->buf[c->cur], 9 * n, c->stream), "pack");
+    HIPCHK(hipStreamSynchronize(c->stream), "set_populations");
+    c->steps = 0;
+    return FDLBM_OK;
+}
+
+int fdlbm_get_populations(fdlbm_ctx *c, double *df)
+{
+    if (!c || !df || c->p.scheme != FDLBM_SCHEME_MRT) return FDLBM_EINVAL;
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const size_t n = c->n();
+    double *st = c->sd(c->L.staging);
+    HIPCHK(launch_unpack(c->p.dtype, c->buf[c->cur], st, 9 * n, c->stream), "unpack");
+    HIPCHK(hipMemcpyAsync(df, st, 9 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "get_populations");
+    HIPCHK(hipStreamSynchronize(c->stream), "get_populations");
+    return FDLBM_OK;
+}
+
+static int run_diag(fdlbm_ctx *c, double out[DIAG_SLOTS])
+{
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const size_t n = c->n();
+    const double *m = c->mode_set ? c->sd(c->L.mode) : nullptr;
+    HIPCHK(launch_diag(c->p.scheme, c->p.dtype, c->buf[c->cur], n, m, m ? m + n : nullptr, c->sd(c->L.partials),
+                       c->sd(c->L.out), c->stream),
+           "diagnostics");
+    HIPCHK(hipMemcpyAsync(out, c->sd(c->L.out), DIAG_SLOTS * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+           "diagnostics download");
+    HIPCHK(hipStreamSynchronize(c->stream), "diagnostics");
+    return FDLBM_OK;
+}
+
+static int advance(fdlbm_ctx *c, int64_t nsteps)
+{
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const bool fd = c->p.scheme == FDLBM_SCHEME_FD;
+    const bool ref = uses_reference(c->p);
+    const FdArgs fa = fd_args(c->p);
+    const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
+                     c->p.s_eps, c->p.force_x, c->p.force_y};
+    for (int64_t s = 0; s < nsteps; ++s) {
+        void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
+        hipError_t e;
+        if (!fd)
+            e = launch_mrt(ma, src, dst, c->stream);
+        else if (ref)
+            e = launch_fd_reference(fa, src, dst, c->scratch + c->L.fstar, c->stream);
+        else
+            e = launch_fd_sweep(fa, c->p.tile_rows, src, dst, c->stream);
+        if (e != hipSuccess) return device_error(e, fd ? "fdlbm_step launch" : "mrt_step launch");
+        c->cur ^= 1;
+        ++c->steps;
+        if (c->p.check_every > 0 && c->steps % c->p.check_every == 0) {
+            double d[DIAG_SLOTS];
+            int rc = run_diag(c, d);
+            if (rc) return rc;
+            if (d[7] > 0) return FDLBM_EUNSTABLE;
+        }
+    }
+    return FDLBM_OK;
+}
+
+int fdlbm_step(fdlbm_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0 || c->p.scheme != FDLBM_SCHEME_FD) return FDLBM_EINVAL;
+    return advance(c, nsteps);
+}
+
+int mrt_step(fdlbm_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0 || c->p.scheme != FDLBM_SCHEME_MRT) return FDLBM_EINVAL;
+    return advance(c, nsteps);
+}
+
+int fdlbm_diagnostics(fdlbm_ctx *c, fdlbm_diag *out)
+{
+    if (!c || !out) return FDLBM_EINVAL;
+    double d[DIAG_SLOTS];
+    int rc = run_diag(c, d);
+    if (rc) return rc;
+    out->mass = d[0];
+    out->mom_x = d[1];
+    out->mom_y = d[2];
+    out->kin_energy = d[3];
+    out->max_abs_j = d[4];
+    out->proj_num = d[5];
+    out->proj_den = d[6];
+    out->nonfinite = (int64_t)d[7];
+    return FDLBM_OK;
+}
+
+int fdlbm_set_mode(fdlbm_ctx *c, const double *j0x, const double *j0y)
+{
+    if (!c || !j0x || !j0y) return FDLBM_EINVAL;
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const size_t n = c->n();
+    double *m = c->sd(c->L.mode);
+    HIPCHK(hipMemcpyAsync(m, j0x, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "set_mode");
+    HIPCHK(hipMemcpyAsync(m + n, j0y, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "set_mode");
+    HIPCHK(hipStreamSynchronize(c->stream), "set_mode");
+    c->mode_set = true;
+    return FDLBM_OK;
+}
+
+int fdlbm_mode_projection(fdlbm_ctx *c, double *out)
+{
+    if (!c || !out || !c->mode_set) return FDLBM_EINVAL;
+    double d[DIAG_SLOTS];
+    int rc = run_diag(c, d);
+    if (rc) return rc;
+    if (!(d[6] > 0)) return FDLBM_EINVAL;
+    *out = d[5] / d[6];
+    return FDLBM_OK;
+}
+
+const char *fdlbm_strerror(int code)
+{
+    switch (code) {
+    case FDLBM_OK: return "ok";
+    case FDLBM_EINVAL: return "invalid argument";
+    case FDLBM_ENOMEM: return "buffer smaller than fdlbm_workspace_bytes requires";
+    case FDLBM_EDEVICE: return "HIP runtime error (see fdlbm_last_error)";
+    case FDLBM_EUNSTABLE: return "non-finite value in the state";
+    default: return "unknown error";
+    }
+}
+
+const char *fdlbm_last_error(void) { return g_err; }
+
+double fdlbm_rate_from_viscosity(double nu) { return 1.0 / (0.5 + 3.0 * nu); }
+
+double fdlbm_quartic_s_q(double s_xx) { return quartic(s_xx); }
+
+}  // extern "C"

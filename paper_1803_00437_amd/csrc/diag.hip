@@ -1,0 +1,179 @@
+// FP64 diagnostics of a state and the conversions between host-staged FP64 planes and the
+// device storage dtype.
+//
+// The reduction is deterministic: a fixed grid of DIAG_BLOCKS blocks walks the nodes with
+// a grid-stride loop, each block reduces its threads in a fixed tree (wavefront shuffles,
+// then LDS) and writes one partial; a single block then reduces the partials in order.
+// Quantities (section 3-a uses the correlation A(t) = <J(t), J0>/<J0, J0>):
+//   [0] sum drho, [1] sum jx, [2] sum jy, [3] 1/2 sum |J|^2/rho, [4] max |J|,
+//   [5] sum J.J0, [6] sum J0.J0, [7] count of nodes with a non-finite field.
+#include "fdlbm_device.hpp"
+#include "internal.hpp"
+
+namespace fdlbm {
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Reduce DIAG_SLOTS values over the block; thread 0 returns the result in acc.
+__device__ void block_reduce(double (&acc)[DIAG_SLOTS])
+{
+    __shared__ double lds[TPB / 64][DIAG_SLOTS];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < DIAG_SLOTS; ++q) acc[q] = q == 4 ? wave_max(acc[q]) : wave_sum(acc[q]);
+    if (lane == 0)
+        for (int q = 0; q < DIAG_SLOTS; ++q) lds[wid][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < DIAG_SLOTS; ++q) {
+            double v = lds[0][q];
+            for (int w = 1; w < TPB / 64; ++w) v = q == 4 ? fmax(v, lds[w][q]) : v + lds[w][q];
+            acc[q] = v;
+        }
+    }
+}
+
+template <typename T, bool MRT>
+__global__ void __launch_bounds__(TPB) diag_partials(const T *__restrict__ st, size_t n, const double *__restrict__ j0x,
+                                                     const double *__restrict__ j0y, double *__restrict__ partials)
+{
+    double acc[DIAG_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t p = blockIdx.x * (size_t)TPB + threadIdx.x; p < n; p += (size_t)gridDim.x * TPB) {
+        double r, x, y;
+        if (MRT) {
+            double f[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) f[q] = double(Storage<T>::load(st[q * n + p]));
+            r = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
+            x = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+            y = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+        } else {
+            r = double(Storage<T>::load(st[p]));
+            x = double(Storage<T>::load(st[n + p]));
+            y = double(Storage<T>::load(st[2 * n + p]));
+        }
+        const bool finite = isfinite(r) && isfinite(x) && isfinite(y);
+        if (!finite) {
+            acc[7] += 1.0;
+            continue;
+        }
+        const double j2 = x * x + y * y;
+        acc[0] += r;
+        acc[1] += x;
+        acc[2] += y;
+        acc[3] += 0.5 * j2 / (1.0 + r);
+        acc[4] = fmax(acc[4], sqrt(j2));
+        if (j0x) {
+            const double ax = j0x[p], ay = j0y[p];
+            acc[5] += x * ax + y * ay;
+            acc[6] += ax * ax + ay * ay;
+        }
+    }
+    block_reduce(acc);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < DIAG_SLOTS; ++q) partials[blockIdx.x * DIAG_SLOTS + q] = acc[q];
+}
+
+__global__ void __launch_bounds__(TPB) diag_final(const double *__restrict__ partials, int nblocks,
+                                                  double *__restrict__ out)
+{
+    double acc[DIAG_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += TPB)
+        for (int q = 0; q < DIAG_SLOTS; ++q) {
+            const double v = partials[b * DIAG_SLOTS + q];
+            acc[q] = q == 4 ? fmax(acc[q], v) : acc[q] + v;
+        }
+    block_reduce(acc);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < DIAG_SLOTS; ++q) out[q] = acc[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) pack_kernel(const double *__restrict__ in, T *__restrict__ out, size_t count)
+{
+    for (size_t p = blockIdx.x * (size_t)TPB + threadIdx.x; p < count; p += (size_t)gridDim.x * TPB)
+        out[p] = Storage<T>::store(typename Storage<T>::C(in[p]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) unpack_kernel(const T *__restrict__ in, double *__restrict__ out, size_t count)
+{
+    for (size_t p = blockIdx.x * (size_t)TPB + threadIdx.x; p < count; p += (size_t)gridDim.x * TPB)
+        out[p] = double(Storage<T>::load(in[p]));
+}
+
+inline unsigned grid_for(size_t n)
+{
+    size_t b = (n + TPB - 1) / TPB;
+    return (unsigned)(b < 8192 ? (b == 0 ? 1 : b) : 8192);
+}
+
+template <typename T>
+hipError_t diag_run(bool mrt, const void *state, size_t n, const double *j0x, const double *j0y, double *partials,
+                    double *out, hipStream_t s)
+{
+    const T *st = static_cast<const T *>(state);
+    if (mrt)
+        hipLaunchKernelGGL((diag_partials<T, true>), DIAG_BLOCKS, TPB, 0, s, st, n, j0x, j0y, partials);
+    else
+        hipLaunchKernelGGL((diag_partials<T, false>), DIAG_BLOCKS, TPB, 0, s, st, n, j0x, j0y, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_final, 1, TPB, 0, s, partials, DIAG_BLOCKS, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_diag(int scheme, int dtype, const void *state, size_t n, const double *j0x, const double *j0y,
+                       double *partials, double *out, hipStream_t s)
+{
+    const bool mrt = scheme == FDLBM_SCHEME_MRT;
+    switch (dtype) {
+    case FDLBM_F64: return diag_run<double>(mrt, state, n, j0x, j0y, partials, out, s);
+    case FDLBM_F32: return diag_run<float>(mrt, state, n, j0x, j0y, partials, out, s);
+    default: return diag_run<__half>(mrt, state, n, j0x, j0y, partials, out, s);
+    }
+}
+
+hipError_t launch_pack(int dtype, const double *in, void *out, size_t count, hipStream_t s)
+{
+    switch (dtype) {
+    case FDLBM_F64: hipLaunchKernelGGL(pack_kernel<double>, grid_for(count), TPB, 0, s, in, (double *)out, count); break;
+    case FDLBM_F32: hipLaunchKernelGGL(pack_kernel<float>, grid_for(count), TPB, 0, s, in, (float *)out, count); break;
+    default: hipLaunchKernelGGL(pack_kernel<__half>, grid_for(count), TPB, 0, s, in, (__half *)out, count); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int dtype, const void *in, double *out, size_t count, hipStream_t s)
+{
+    switch (dtype) {
+    case FDLBM_F64:
+        hipLaunchKernelGGL(unpack_kernel<double>, grid_for(count), TPB, 0, s, (const double *)in, out, count);
+        break;
+    case FDLBM_F32:
+        hipLaunchKernelGGL(unpack_kernel<float>, grid_for(count), TPB, 0, s, (const float *)in, out, count);
+        break;
+    default:
+        hipLaunchKernelGGL(unpack_kernel<__half>, grid_for(count), TPB, 0, s, (const __half *)in, out, count);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fdlbm

@@ -1,0 +1,179 @@
+// FD-LBM step, reference path (two passes through a scratch buffer).
+//
+// Pass 1 computes, for every node that sends a population into the fluid, the nine
+// post-collision populations of section 2 and writes them to nine planes; pass 2 gathers
+// the propagated populations (eq. 2) into the new (drho, jx, jy).  It moves about four
+// times the bytes of the fused kernel and exists as the plain GPU rendering that the fused
+// kernel must match bit for bit; both use fd_node_fstar() and fd_gather().
+#include "fdlbm_device.hpp"
+#include "internal.hpp"
+
+namespace fdlbm {
+namespace {
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Value of (drho, J_a) at node (i, j) with the boundary rules: x periodic; y periodic, or,
+// with walls, a ghost node mirrors the fluid node at the same distance from the wall
+// (linear extrapolation with zero velocity on the wall: drho even, J odd).
+template <typename T, bool WALLS> struct View {
+    using C = typename Storage<T>::C;
+    const T *dr, *jx, *jy;
+    int nx, ny;
+    C hfx, hfy;
+    __device__ __forceinline__ void at(int i, int j, C &r, C &x, C &y) const
+    {
+        i = wrap(wrap(i, nx), nx);
+        C sgn = C(1);
+        if (WALLS) {
+            if (j < 0) { j = -1 - j; sgn = C(-1); }
+            else if (j >= ny) { j = 2 * ny - 1 - j; sgn = C(-1); }
+        } else {
+            j = wrap(wrap(j, ny), ny);
+        }
+        const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+        r = Storage<T>::load(dr[p]);
+        x = fmac(sgn, Storage<T>::load(jx[p]), hfx);
+        y = fmac(sgn, Storage<T>::load(jy[p]), hfy);
+    }
+};
+
+template <typename T, int ST, bool WALLS>
+__global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typename Storage<T>::C> k, int row0,
+                                                    int nrows, typename Storage<T>::C *__restrict__ fstar)
+{
+    using C = typename Storage<T>::C;
+    constexpr int H = Stencil<ST>::H;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rr = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= v.nx || rr >= nrows) return;
+    const int j = row0 + rr;
+
+    // values along the x and y axes through the node, offsets -2..2 (index o + 2)
+    C rX[5], xX[5], yX[5], rY[5], xY[5], yY[5];
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
+        if (o < -H || o > H) {
+            rX[o + 2] = xX[o + 2] = yX[o + 2] = rY[o + 2] = xY[o + 2] = yY[o + 2] = C(0);
+            continue;
+        }
+        v.at(i + o, j, rX[o + 2], xX[o + 2], yX[o + 2]);
+        v.at(i, j + o, rY[o + 2], xY[o + 2], yY[o + 2]);
+    }
+    using S = Stencil<ST>;
+    C d[10];
+    d[0] = S::diff(rX[0], rX[1], rX[3], rX[4]);
+    d[1] = S::diff(rY[0], rY[1], rY[3], rY[4]);
+    d[2] = S::diff(xX[0], xX[1], xX[3], xX[4]);
+    d[3] = S::diff(yY[0], yY[1], yY[3], yY[4]);
+    d[4] = S::diff(yX[0], yX[1], yX[3], yX[4]);
+    d[5] = S::diff(xY[0], xY[1], xY[3], xY[4]);
+    C P[5], Rx[5], Ry[5], Q[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        P[o] = xX[o] * xX[o];
+        Rx[o] = xX[o] * yX[o];
+        Ry[o] = xY[o] * yY[o];
+        Q[o] = yY[o] * yY[o];
+    }
+    d[6] = S::diff(P[0], P[1], P[3], P[4]);
+    d[7] = S::diff(Ry[0], Ry[1], Ry[3], Ry[4]);
+    d[8] = S::diff(Rx[0], Rx[1], Rx[3], Rx[4]);
+    d[9] = S::diff(Q[0], Q[1], Q[3], Q[4]);
+
+    C f[9];
+    fd_node_fstar<C>(rX[2], xX[2], yX[2], d, k, f);
+    const size_t plane = (size_t)nrows * (size_t)v.nx;
+    const size_t p = (size_t)rr * (size_t)v.nx + (size_t)i;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fstar[q * plane + p] = f[q];
+}
+
+template <typename T, bool WALLS>
+__global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::C *__restrict__ fstar, int nx, int ny,
+                                                     int row0, int nrows, T *__restrict__ odr, T *__restrict__ ojx,
+                                                     T *__restrict__ ojy)
+{
+    using C = typename Storage<T>::C;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const size_t plane = (size_t)nrows * (size_t)nx;
+    auto F = [&](int q, int di, int dj) -> C {
+        int ii = wrap(i + di, nx);
+        int jj = j + dj;
+        if (!WALLS) jj = wrap(jj, ny);
+        const int rr = jj - row0;  // walls: row0 = -1, so rows -1..ny map to 0..ny+1
+        return fstar[q * plane + (size_t)rr * (size_t)nx + (size_t)ii];
+    };
+    C r, x, y;
+    fd_gather<C>(F(0, 0, 0), F(1, -1, 0), F(3, 1, 0), F(2, 0, -1), F(5, -1, -1), F(6, 1, -1), F(4, 0, 1), F(7, 1, 1),
+                 F(8, -1, 1), r, x, y);
+    const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+    odr[p] = Storage<T>::store(r);
+    ojx[p] = Storage<T>::store(x);
+    ojy[p] = Storage<T>::store(y);
+}
+
+template <typename T> FdCoef<typename Storage<T>::C> make_coef(const FdArgs &a)
+{
+    using C = typename Storage<T>::C;
+    const double scale = a.stencil == 3 ? Stencil<3>::SCALE : Stencil<5>::SCALE;
+    FdCoef<C> k;
+    k.ke = C(scale * (1.0 - 1.0 / a.s_e));
+    k.kxx = C(scale * (1.0 - 1.0 / a.s_xx));
+    k.hfx = C(0.5 * a.fx);
+    k.hfy = C(0.5 * a.fy);
+    k.qfx = C(0.25 * a.fx);
+    k.qfy = C(0.25 * a.fy);
+    k.dfx = C(a.fx);
+    k.dfy = C(a.fy);
+    return k;
+}
+
+template <typename T, int ST, bool WALLS>
+hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
+{
+    using C = typename Storage<T>::C;
+    const size_t n = (size_t)a.nx * (size_t)a.ny;
+    const T *in = static_cast<const T *>(src);
+    T *out = static_cast<T *>(dst);
+    auto k = make_coef<T>(a);
+    View<T, WALLS> v{in, in + n, in + 2 * n, a.nx, a.ny, k.hfx, k.hfy};
+    const int row0 = WALLS ? -1 : 0, nrows = WALLS ? a.ny + 2 : a.ny;
+    dim3 blk(64, 4);
+    dim3 g1((a.nx + 63) / 64, (nrows + 3) / 4);
+    hipLaunchKernelGGL((fd_ref_fstar<T, ST, WALLS>), g1, blk, 0, s, v, k, row0, nrows, static_cast<C *>(fstar));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((a.nx + 63) / 64, (a.ny + 3) / 4);
+    hipLaunchKernelGGL((fd_ref_gather<T, WALLS>), g2, blk, 0, s, static_cast<const C *>(fstar), a.nx, a.ny, row0,
+                       nrows, out, out + n, out + 2 * n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_stencil(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
+{
+    if (a.stencil == 3) return a.walls ? run<T, 3, true>(a, src, dst, fstar, s) : run<T, 3, false>(a, src, dst, fstar, s);
+    return a.walls ? run<T, 5, true>(a, src, dst, fstar, s) : run<T, 5, false>(a, src, dst, fstar, s);
+}
+
+}  // namespace
+
+size_t fd_reference_scratch_bytes(const FdArgs &a)
+{
+    const size_t rows = (size_t)a.ny + (a.walls ? 2 : 0);
+    return 9 * rows * (size_t)a.nx * compute_bytes(a.dtype);
+}
+
+hipError_t launch_fd_reference(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
+{
+    switch (a.dtype) {
+    case FDLBM_F64: return dispatch_stencil<double>(a, src, dst, fstar, s);
+    case FDLBM_F32: return dispatch_stencil<float>(a, src, dst, fstar, s);
+    default: return dispatch_stencil<__half>(a, src, dst, fstar, s);
+    }
+}
+
+}  // namespace fdlbm

@@ -1,0 +1,148 @@
+// Device-side building blocks shared by the FD-LBM kernels: storage types, the per-node
+// reconstruction of the post-collision populations (section 2 of Dubois, Lallemand,
+// Obrecht, Tekitek) and the gather order of the propagation (section 1, eq. 2).
+//
+// Every kernel that advances an FD-LBM state calls fd_node_fstar() with the same inputs
+// in the same order, and sums the propagated populations in the order of fd_gather(), so
+// the reference and the fused kernels produce bit-identical states.  The library is
+// compiled with -ffp-contract=off; every fused multiply-add below is written out.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdlbm {
+
+// ------------------------------------------------------------------ storage types ----
+template <typename T> struct Storage;
+template <> struct Storage<double> {
+    using C = double;  // arithmetic type
+    static __device__ __forceinline__ double load(double v) { return v; }
+    static __device__ __forceinline__ double store(double v) { return v; }
+};
+template <> struct Storage<float> {
+    using C = float;
+    static __device__ __forceinline__ float load(float v) { return v; }
+    static __device__ __forceinline__ float store(float v) { return v; }
+};
+template <> struct Storage<__half> {
+    using C = float;
+    static __device__ __forceinline__ float load(__half v) { return __half2float(v); }
+    static __device__ __forceinline__ __half store(float v) { return __float2half_rn(v); }
+};
+
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// 1/rho.  FP32 uses the hardware reciprocal (1 ulp); FP64 the IEEE division.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Finite differences of section 2 in unscaled form.  With g(+-1), g(+-2) the values at the
+// neighbours along one axis:
+//   3 points: D = g(+1) - g(-1)                    (derivative = D / 2)
+//   5 points: D = 6 (g(+1) - g(-1)) - (g(+2) - g(-2))  (derivative = D / 8,
+//             i.e. 3/4 (g(+1) - g(-1)) - 1/8 (g(+2) - g(-2)))
+// The theta terms are linear in the derivatives, so the power-of-two scale is folded into
+// the relaxation factors, which is exact.
+template <int STENCIL> struct Stencil;
+template <> struct Stencil<3> {
+    static constexpr int H = 1;  // half width
+    static constexpr double SCALE = 0.5;
+    template <typename C> static __device__ __forceinline__ C diff(C m2, C m1, C p1, C p2) {
+        (void)m2; (void)p2;
+        return p1 - m1;
+    }
+};
+template <> struct Stencil<5> {
+    static constexpr int H = 2;
+    static constexpr double SCALE = 0.125;
+    template <typename C> static __device__ __forceinline__ C diff(C m2, C m1, C p1, C p2) {
+        return fmac(C(6), p1 - m1, -(p2 - m2));
+    }
+};
+
+// Per-step constants of the reconstruction.
+template <typename C> struct FdCoef {
+    C ke;     // SCALE * (1 - 1/s_e)   multiplies theta_E (unscaled derivatives)
+    C kxx;    // SCALE * (1 - 1/s_xx)  multiplies theta_XX and theta_XY
+    C hfx, hfy;  // F/2: J_a = J + F/2 (Strang splitting, section 1)
+    C qfx, qfy;  // F/4: axis populations carry (J_a + F/4)/3
+    C dfx, dfy;  // F  : diagonal populations carry (J_a + F)/12
+};
+
+// Inputs of one node: J_a = J + F/2 and the ten unscaled derivatives
+//   d[0] = D_x rho, d[1] = D_y rho, d[2] = D_x Jx, d[3] = D_y Jy, d[4] = D_x Jy,
+//   d[5] = D_y Jx, d[6] = D_x Jx^2, d[7] = D_y JxJy, d[8] = D_x JxJy, d[9] = D_y Jy^2.
+// Output: the nine post-collision populations as deviations f*_k - w_k.
+//
+// Section 2: theta_E, theta_XX, theta_XY (the defects of conservation at rho close to 1,
+// with v read as the stored momentum and the linear part of theta_XY as
+// (1/3)(d_x J_y + d_y J_x)); post-collision moments
+//   E = -2 rho + 3|J|^2/rho + (1 - 1/s_e) theta_E,  XX = (Jx^2 - Jy^2)/rho + (1 - 1/s_xx) theta_XX,
+//   XY = Jx Jy/rho + (1 - 1/s_xx) theta_XY,  q = -J,  eps = rho - 3|J|^2/rho;
+// then f* = M^{-1} m* written out per velocity (M^{-1} = M^T diag(1/9, 1/6, 1/6, 1/36,
+// 1/4, 1/4, 1/12, 1/12, 1/36), section 1), as deviations from the rest populations.
+template <typename C>
+__device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10], const FdCoef<C> &k, C (&f)[9])
+{
+    const C rx = d[0], ry = d[1], a = d[2], b = d[3], c = d[4], dd = d[5];
+    const C sA = d[6] + d[7];  // D_x Jx^2 + D_y JxJy
+    const C sB = d[8] + d[9];  // D_x JxJy + D_y Jy^2
+    const C p0 = jx * jx, q0 = jy * jy, r0 = jx * jy;
+    const C j2 = p0 + q0;
+
+    const C w = fmac(jx, rx, jy * ry);                               // J . grad rho
+    const C th_e = fmac(fmac(C(6), j2, C(2)), a + b, C(-2) * w);
+    const C g = fmac(jx, rx, -(jy * ry));                             // Jx rx - Jy ry
+    const C h = fmac(jx, sA, -(jy * sB));
+    const C th_xx = fmac(C(2.0 / 3.0), (a - b) - g, C(-2) * h);
+    const C g2 = fmac(jx, ry, jy * rx);                               // Jx ry + Jy rx
+    const C h2 = fmac(jx, sB, jy * sA);
+    const C th_xy = fmac(C(1.0 / 3.0), (c + dd) - g2, -h2);
+
+    const C rinv = recip(C(1) + dr);
+    const C K = j2 * rinv;
+    const C te = k.ke * th_e;                                         // (1 - 1/s_e) theta_E
+    const C XX = fmac(p0 - q0, rinv, k.kxx * th_xx);
+    const C XY = fmac(r0, rinv, k.kxx * th_xy);
+
+    // deviation populations (rest moments m0 = (1,0,0,-2,0,0,0,0,1) removed)
+    const C k12 = K * C(1.0 / 12.0);
+    const C A_ax = fmac(dr, C(1.0 / 9.0), fmac(te, C(-1.0 / 36.0), k12));
+    const C A_dg = fmac(dr, C(1.0 / 36.0), fmac(te, C(1.0 / 18.0), k12));
+    f[0] = fmac(dr, C(4.0 / 9.0), fmac(K, C(-2.0 / 3.0), te * C(-1.0 / 9.0)));
+    const C axp = fmac(XX, C(0.25), A_ax), axm = fmac(XX, C(-0.25), A_ax);
+    const C ux = (jx + k.qfx) * C(1.0 / 3.0), uy = (jy + k.qfy) * C(1.0 / 3.0);
+    f[1] = axp + ux;
+    f[3] = axp - ux;
+    f[2] = axm + uy;
+    f[4] = axm - uy;
+    const C dgp = fmac(XY, C(0.25), A_dg), dgm = fmac(XY, C(-0.25), A_dg);
+    const C vx = (jx + k.dfx) * C(1.0 / 12.0), vy = (jy + k.dfy) * C(1.0 / 12.0);
+    const C s = vx + vy, t = vy - vx;
+    f[5] = dgp + s;
+    f[7] = dgp - s;
+    f[6] = dgm + t;
+    f[8] = dgm - t;
+}
+
+// Gather after propagation (eq. 2): the new state at x sums f*_k(x - e_k).  Arguments are
+// the populations already fetched from their source nodes:
+//   c0 = f0(x), c1 = f1(x-ex), c3 = f3(x+ex)                        (same row)
+//   u2 = f2(x-ey), u5 = f5(x-ex-ey), u6 = f6(x+ex-ey)                (row below)
+//   d4 = f4(x+ey), d7 = f7(x+ex+ey), d8 = f8(x-ex+ey)                (row above)
+// Fixed summation order shared by every kernel.
+template <typename C>
+__device__ __forceinline__ void fd_gather(C c0, C c1, C c3, C u2, C u5, C u6, C d4, C d7, C d8, C &dr, C &jx, C &jy)
+{
+    const C cen = (c0 + c1) + c3, cenx = c1 - c3;
+    const C up = (u2 + u5) + u6, upx = u5 - u6;
+    const C dn = (d4 + d7) + d8, dnx = d8 - d7;
+    dr = (cen + up) + dn;
+    jx = (cenx + upx) + dnx;
+    jy = up - dn;
+}
+
+}  // namespace fdlbm

@@ -1,0 +1,56 @@
+// Host-side declarations shared between the C ABI (abi.cpp) and the kernel translation
+// units.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/fdlbm.h"
+
+namespace fdlbm {
+
+// Bytes of one stored value for a dtype.
+inline size_t dtype_bytes(int dtype) { return dtype == FDLBM_F64 ? 8 : dtype == FDLBM_F32 ? 4 : 2; }
+// Bytes of one arithmetic value (FP16 storage computes in FP32).
+inline size_t compute_bytes(int dtype) { return dtype == FDLBM_F64 ? 8 : 4; }
+
+// Geometry and coefficients of one FD-LBM step, as the kernels need them.
+struct FdArgs {
+    int nx, ny, stencil, walls, dtype;
+    double s_xx, s_e, fx, fy;
+};
+
+struct MrtArgs {
+    int nx, ny, walls, dtype;
+    double s_e, s_xx, s_q, s_eps, fx, fy;
+};
+
+// FD-LBM, reference path: pass 1 writes the nine f* planes (compute dtype) for every
+// node that sends a population into the fluid (ny + 2 rows with walls), pass 2 gathers.
+hipError_t launch_fd_reference(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s);
+size_t fd_reference_scratch_bytes(const FdArgs &a);
+
+// FD-LBM, fused sweep path: one kernel per step, no scratch.
+hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s);
+bool fd_sweep_supported(const FdArgs &a);
+
+// MRT D2Q9 stream-collide (push) step.
+hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);
+
+// Conversions between host-staged FP64 planes and device storage.
+hipError_t launch_pack(int dtype, const double *in, void *out, size_t count, hipStream_t s);
+hipError_t launch_unpack(int dtype, const void *in, double *out, size_t count, hipStream_t s);
+// MRT: populations f^eq(rho, J) from FP64 (drho, jx, jy) planes, and the conserved moments back.
+hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const double *jy, void *pop, size_t n,
+                           hipStream_t s);
+hipError_t launch_mrt_moments(int dtype, const void *pop, double *dr, double *jx, double *jy, size_t n,
+                              hipStream_t s);
+
+// FP64 diagnostics: totals, kinetic energy, max |J|, non-finite count and sum J.J0.
+constexpr int DIAG_BLOCKS = 1024;
+constexpr int DIAG_SLOTS = 8;  // doubles per block partial
+hipError_t launch_diag(int scheme, int dtype, const void *state, size_t n, const double *j0x, const double *j0y,
+                       double *partials, double *out, hipStream_t s);
+
+}  // namespace fdlbm

@@ -1,0 +1,219 @@
+// MRT D2Q9 stream-collide step (section 1, eqs. 1-2; equilibria and rates of the table
+// in section 1-a), the scheme the FD-LBM is compared against.
+//
+// Storage: nine planes of f_k - w_k (deviations from the rest populations).  One thread
+// per node: read its nine populations (coalesced), relax the non-conserved moments, and
+// push f*_k to x + e_k in the other buffer.  A population whose destination lies beyond a
+// wall returns to its own node with the opposite velocity (halfway bounce-back, which puts
+// the wall half-way between the last fluid row and the next one, section 3-c).
+// Algorithmic traffic: 9 values read + 9 written per node.
+#include "fdlbm_device.hpp"
+#include "internal.hpp"
+
+namespace fdlbm {
+namespace {
+
+template <typename C> struct MrtCoef {
+    C se, sxx, sq, seps;
+    C hfx, hfy, fx, fy;
+};
+
+// m = M f for the deviations (rows rho, Jx, Jy, E, XX, XY, qx, qy, eps of section 1).
+template <typename C> __device__ __forceinline__ void moments(const C (&f)[9], C (&m)[9])
+{
+    const C ax = (f[1] + f[2]) + (f[3] + f[4]);
+    const C dg = (f[5] + f[6]) + (f[7] + f[8]);
+    const C x13 = f[1] - f[3], y24 = f[2] - f[4];
+    const C dxp = (f[5] - f[6]) - (f[7] - f[8]);  // sum e_x over diagonals
+    const C dyp = (f[5] + f[6]) - (f[7] + f[8]);  // sum e_y over diagonals
+    m[0] = (f[0] + ax) + dg;
+    m[1] = x13 + dxp;
+    m[2] = y24 + dyp;
+    m[3] = fmac(C(-4), f[0], fmac(C(2), dg, -ax));
+    m[4] = (f[1] + f[3]) - (f[2] + f[4]);
+    m[5] = (f[5] + f[7]) - (f[6] + f[8]);
+    m[6] = fmac(C(-2), x13, dxp);
+    m[7] = fmac(C(-2), y24, dyp);
+    m[8] = fmac(C(4), f[0], fmac(C(-2), ax, dg));
+}
+
+// f = M^{-1} m, M^{-1} = M^T diag(1/9, 1/6, 1/6, 1/36, 1/4, 1/4, 1/12, 1/12, 1/36).
+template <typename C> __device__ __forceinline__ void populations(const C (&m)[9], C (&f)[9])
+{
+    const C r9 = m[0] * C(1.0 / 9.0);
+    const C e36 = m[3] * C(1.0 / 36.0), p36 = m[8] * C(1.0 / 36.0);
+    f[0] = fmac(C(-4), e36, fmac(C(4), p36, r9));
+    const C ax = fmac(C(-2), p36, r9 - e36);            // rho/9 - E/36 - eps/18
+    const C dg = fmac(C(2), e36, r9 + p36);             // rho/9 + E/18 + eps/36
+    const C xx = m[4] * C(0.25), xy = m[5] * C(0.25);
+    const C jx6 = m[1] * C(1.0 / 6.0), jy6 = m[2] * C(1.0 / 6.0);
+    const C qx6 = m[6] * C(1.0 / 6.0), qy6 = m[7] * C(1.0 / 6.0);
+    const C ux = jx6 - qx6, uy = jy6 - qy6;             // axis: J/6 - q/6 (M_q = -2e on axes)
+    const C vx = fmac(qx6, C(0.5), jx6), vy = fmac(qy6, C(0.5), jy6);  // diagonal: J/6 + q/12
+    f[1] = (ax + xx) + ux;
+    f[3] = (ax + xx) - ux;
+    f[2] = (ax - xx) + uy;
+    f[4] = (ax - xx) - uy;
+    f[5] = (dg + xy) + (vx + vy);
+    f[7] = (dg + xy) - (vx + vy);
+    f[6] = (dg - xy) + (vy - vx);
+    f[8] = (dg - xy) - (vy - vx);
+}
+
+// Equilibrium moments of section 1-a as deviations from the rest moments.
+template <typename C>
+__device__ __forceinline__ void equilibrium(C dr, C jx, C jy, C &E, C &XX, C &XY, C &qx, C &qy, C &eps)
+{
+    const C rinv = recip(C(1) + dr);
+    const C p = jx * jx, q = jy * jy;
+    const C K3 = C(3) * ((p + q) * rinv);
+    E = fmac(C(-2), dr, K3);
+    XX = (p - q) * rinv;
+    XY = (jx * jy) * rinv;
+    qx = -jx;
+    qy = -jy;
+    eps = dr - K3;
+}
+
+template <typename T, bool WALLS>
+__global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
+                                                  MrtCoef<typename Storage<T>::C> k)
+{
+    using C = typename Storage<T>::C;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const size_t n = (size_t)nx * (size_t)ny;
+    const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+    C f[9], m[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = Storage<T>::load(in[q * n + p]);
+    moments<C>(f, m);
+    // Strang splitting: half the force before the collision ...
+    const C jax = m[1] + k.hfx, jay = m[2] + k.hfy;
+    C E, XX, XY, qx, qy, eps;
+    equilibrium<C>(m[0], jax, jay, E, XX, XY, qx, qy, eps);
+    // eq. 1 for the non-conserved moments
+    m[3] = fmac(k.se, E - m[3], m[3]);
+    m[4] = fmac(k.sxx, XX - m[4], m[4]);
+    m[5] = fmac(k.sxx, XY - m[5], m[5]);
+    m[6] = fmac(k.sq, qx - m[6], m[6]);
+    m[7] = fmac(k.sq, qy - m[7], m[7]);
+    m[8] = fmac(k.seps, eps - m[8], m[8]);
+    // ... and the other half after it
+    m[1] = m[1] + k.fx;
+    m[2] = m[2] + k.fy;
+    populations<C>(m, f);
+    // propagation, eq. 2 (push)
+    const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
+    int jp = j + 1, jm = j - 1;
+    if (!WALLS) {
+        if (jp == ny) jp = 0;
+        if (jm < 0) jm = ny - 1;
+    }
+    const size_t row = (size_t)j * nx, rowp = (size_t)jp * nx, rowm = (size_t)jm * nx;
+    out[0 * n + p] = Storage<T>::store(f[0]);
+    out[1 * n + row + ip] = Storage<T>::store(f[1]);
+    out[3 * n + row + im] = Storage<T>::store(f[3]);
+    if (!WALLS || jp < ny) {
+        out[2 * n + rowp + i] = Storage<T>::store(f[2]);
+        out[5 * n + rowp + ip] = Storage<T>::store(f[5]);
+        out[6 * n + rowp + im] = Storage<T>::store(f[6]);
+    } else {  // bounce-back at the upper wall
+        out[4 * n + p] = Storage<T>::store(f[2]);
+        out[7 * n + p] = Storage<T>::store(f[5]);
+        out[8 * n + p] = Storage<T>::store(f[6]);
+    }
+    if (!WALLS || jm >= 0) {
+        out[4 * n + rowm + i] = Storage<T>::store(f[4]);
+        out[7 * n + rowm + im] = Storage<T>::store(f[7]);
+        out[8 * n + rowm + ip] = Storage<T>::store(f[8]);
+    } else {  // bounce-back at the lower wall
+        out[2 * n + p] = Storage<T>::store(f[4]);
+        out[5 * n + p] = Storage<T>::store(f[7]);
+        out[6 * n + p] = Storage<T>::store(f[8]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) mrt_init_kernel(const double *__restrict__ dr, const double *__restrict__ jx,
+                                                       const double *__restrict__ jy, T *__restrict__ pop, size_t n)
+{
+    using C = typename Storage<T>::C;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        C m[9], f[9];
+        m[0] = C(dr[p]);
+        m[1] = C(jx[p]);
+        m[2] = C(jy[p]);
+        equilibrium<C>(m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8]);
+        populations<C>(m, f);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) pop[q * n + p] = Storage<T>::store(f[q]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) mrt_moments_kernel(const T *__restrict__ pop, double *__restrict__ dr,
+                                                          double *__restrict__ jx, double *__restrict__ jy, size_t n)
+{
+    using C = typename Storage<T>::C;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        C f[9], m[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = Storage<T>::load(pop[q * n + p]);
+        moments<C>(f, m);
+        dr[p] = double(m[0]);
+        jx[p] = double(m[1]);
+        jy[p] = double(m[2]);
+    }
+}
+
+template <typename T> hipError_t run(const MrtArgs &a, const void *src, void *dst, hipStream_t s)
+{
+    using C = typename Storage<T>::C;
+    MrtCoef<C> k{C(a.s_e), C(a.s_xx), C(a.s_q), C(a.s_eps), C(0.5 * a.fx), C(0.5 * a.fy), C(a.fx), C(a.fy)};
+    dim3 blk(64, 4), grd((a.nx + 63) / 64, (a.ny + 3) / 4);
+    if (a.walls)
+        hipLaunchKernelGGL((mrt_kernel<T, true>), grd, blk, 0, s, static_cast<const T *>(src), static_cast<T *>(dst),
+                           a.nx, a.ny, k);
+    else
+        hipLaunchKernelGGL((mrt_kernel<T, false>), grd, blk, 0, s, static_cast<const T *>(src), static_cast<T *>(dst),
+                           a.nx, a.ny, k);
+    return hipGetLastError();
+}
+
+inline unsigned grid_for(size_t n)
+{
+    size_t b = (n + 255) / 256;
+    return (unsigned)(b < 8192 ? (b == 0 ? 1 : b) : 8192);
+}
+
+}  // namespace
+
+hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s)
+{
+    return a.dtype == FDLBM_F64 ? run<double>(a, src, dst, s) : run<float>(a, src, dst, s);
+}
+
+hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const double *jy, void *pop, size_t n,
+                           hipStream_t s)
+{
+    if (dtype == FDLBM_F64)
+        hipLaunchKernelGGL(mrt_init_kernel<double>, grid_for(n), 256, 0, s, dr, jx, jy, static_cast<double *>(pop), n);
+    else
+        hipLaunchKernelGGL(mrt_init_kernel<float>, grid_for(n), 256, 0, s, dr, jx, jy, static_cast<float *>(pop), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mrt_moments(int dtype, const void *pop, double *dr, double *jx, double *jy, size_t n, hipStream_t s)
+{
+    if (dtype == FDLBM_F64)
+        hipLaunchKernelGGL(mrt_moments_kernel<double>, grid_for(n), 256, 0, s, static_cast<const double *>(pop), dr,
+                           jx, jy, n);
+    else
+        hipLaunchKernelGGL(mrt_moments_kernel<float>, grid_for(n), 256, 0, s, static_cast<const float *>(pop), dr, jx,
+                           jy, n);
+    return hipGetLastError();
+}
+
+}  // namespace fdlbm

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every function that
+include/fdlbm.h declares, and rejects invalid parameters before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1803_00437_amd as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdlbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_loads_and_exports_every_declared_function():
+    lib = F.load_library()
+    names = declared_functions()
+    assert "fdlbm_step" in names and "mrt_step" in names and "fdlbm_diagnostics" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(F.EXPORTED) == names
+
+
+def test_params_struct_layout_matches_header():
+    # 6 int32, 4 doubles, int32 (+pad), 2 doubles, 4 int32
+    assert ctypes.sizeof(F.Params) == 6 * 4 + 4 * 8 + 8 + 2 * 8 + 4 * 4
+    assert ctypes.sizeof(F.Diag) == 8 * 8
+
+
+def good(**kw):
+    base = dict(nx=64, ny=48, scheme="fd", stencil=3, bc="periodic", dtype="f32", s_xx=1.5, s_e=1.0)
+    base.update(kw)
+    return F.make_params(**base)
+
+
+def test_workspace_bytes():
+    sb, cb = F.fdlbm_workspace_bytes(good())
+    assert sb >= 3 * 64 * 48 * 4 and sb % 256 == 0 and cb > 0
+    sb64, _ = F.fdlbm_workspace_bytes(good(dtype="f64"))
+    sb16, _ = F.fdlbm_workspace_bytes(good(dtype="f16"))
+    assert sb64 >= 3 * 64 * 48 * 8 and sb16 >= 3 * 64 * 48 * 2 and sb16 < sb
+    sbm, _ = F.fdlbm_workspace_bytes(good(scheme="mrt", s_q=1.2, s_eps=1.0))
+    assert sbm >= 9 * 64 * 48 * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=4), dict(ny=2), dict(ny=6), dict(stencil=9), dict(stencil=4), dict(s_xx=2.0), dict(s_xx=0.0),
+    dict(s_e=-1.0), dict(s_xx=float("nan")), dict(scheme="mrt", dtype="f16", s_q=1.0),
+    dict(scheme="mrt", s_q=2.5), dict(scheme="mrt", s_eps=0.0), dict(force=(float("inf"), 0.0)),
+])
+def test_invalid_parameters_are_rejected(bad):
+    with pytest.raises(F.FdlbmError) as e:
+        F.fdlbm_workspace_bytes(good(**bad))
+    assert e.value.code == F.FDLBM_EINVAL
+
+
+def test_walls_allow_small_ny_and_quartic_needs_no_s_q():
+    F.fdlbm_workspace_bytes(good(bc="walls", ny=4))
+    F.fdlbm_workspace_bytes(good(scheme="mrt", quartic=True, s_q=0.0))
+
+
+def test_create_rejects_bad_buffers_without_a_device():
+    lib = F.load_library()
+    p = good()
+    ctx = ctypes.c_void_p()
+    # NULL buffers, identical ping-pong buffers and misaligned buffers are refused before any HIP call
+    assert lib.fdlbm_create(ctypes.byref(p), None, None, None, 0, None, ctypes.byref(ctx)) == F.FDLBM_EINVAL
+    assert lib.fdlbm_create(ctypes.byref(p), 4096, 4096, 8192, 1 << 30, None, ctypes.byref(ctx)) == F.FDLBM_EINVAL
+    assert lib.fdlbm_create(ctypes.byref(p), 4100, 8192, 16384, 1 << 30, None, ctypes.byref(ctx)) == F.FDLBM_EINVAL
+    assert lib.fdlbm_create(ctypes.byref(p), 4096, 8192, 16384, 16, None, ctypes.byref(ctx)) == F.FDLBM_ENOMEM
+
+
+def test_null_context_is_rejected():
+    lib = F.load_library()
+    assert lib.fdlbm_step(None, 1) == F.FDLBM_EINVAL
+    assert lib.mrt_step(None, 1) == F.FDLBM_EINVAL
+    assert lib.fdlbm_step_count(None) == -1
+
+
+def test_rate_helpers_match_section_1a_and_3b():
+    assert abs(F.fdlbm_rate_from_viscosity(0.02) - 1 / (0.5 + 0.06)) < 1e-15
+    s_xx = F.fdlbm_rate_from_viscosity(1 / 108 ** 0.5)
+    s_q = F.fdlbm_quartic_s_q(s_xx)
+    assert abs((1 / s_xx - 0.5) * (1 / s_q - 0.5) - 1 / 6) < 1e-14
+    assert abs(s_q - 0.9282) < 0.5e-4
+
+
+def test_strerror():
+    lib = F.load_library()
+    for code in (0, -1, -2, -3, -4):
+        assert lib.fdlbm_strerror(code)

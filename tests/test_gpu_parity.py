@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (relative L2 over the stacked deviation fields drho, jx, jy):
+  FP64 storage and arithmetic  <= 1e-12
+  FP32 storage and arithmetic  <= 1e-5
+  FP16-stored deviations, FP32 arithmetic: measured, <= 5e-3 (see test_f16_storage_error)
+Grids are ragged (not multiples of the 64-wide wavefront or of the 4-row block) so that
+every kernel runs partial tiles and the periodic wrap in both directions.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1803_00437_amd as F
+
+    F.load_library()
+    return F
+
+
+def rel_l2(a, b):
+    num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(a, b))
+    den = sum(float(np.sum(y ** 2)) for y in b)
+    return math.sqrt(num / den)
+
+
+def fd_case(F, nx, ny, nsteps, *, stencil, dtype, walls, force, kernel="reference", s_xx=1.6, s_e=1.1, seed=21,
+            amp=0.02):
+    r, x, y = W.random_state(nx, ny, seed=seed, amp=amp)
+    sim = F.FdLbm(nx, ny, scheme="fd", stencil=stencil, bc="walls" if walls else "periodic", dtype=dtype,
+                  s_xx=s_xx, s_e=s_e, force=(force, -0.3 * force), kernel=kernel)
+    sim.set_state(r, x, y)
+    sim.step(nsteps)
+    got = sim.get_state()
+    sim.close()
+    want = O.fd_run(r, x, y, nsteps, s_xx=s_xx, s_e=s_e, stencil=stencil, walls=walls, fx=force, fy=-0.3 * force)
+    return got, want
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("force", [0.0, 1e-5])
+def test_fd_reference_kernel_matches_oracle(F, stencil, dtype, walls, force):
+    print(f"case fd reference stencil={stencil} dtype={dtype} walls={walls} force={force}", flush=True)
+    got, want = fd_case(F, 70, 45 if walls else 46, 60, stencil=stencil, dtype=dtype, walls=walls, force=force)
+    err = rel_l2(got, want)
+    print(f"  rel L2 = {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("force", [0.0, 1e-5])
+def test_mrt_matches_oracle(F, dtype, walls, force):
+    print(f"case mrt dtype={dtype} walls={walls} force={force}", flush=True)
+    nx, ny, n = 70, 45 if walls else 46, 60
+    r, x, y = W.random_state(nx, ny, seed=22, amp=0.02)
+    s_xx, s_e, s_eps = 1.6, 1.1, 1.3
+    sim = F.FdLbm(nx, ny, scheme="mrt", bc="walls" if walls else "periodic", dtype=dtype, s_xx=s_xx, s_e=s_e,
+                  s_eps=s_eps, quartic=True, force=(force, 0.5 * force))
+    sim.set_state(r, x, y)
+    sim.step(n)
+    got_pop = sim.get_populations()
+    got = sim.get_state()
+    sim.close()
+    df = O.mrt_run(O.mrt_init(r, x, y), n, s_xx=s_xx, s_e=s_e, s_q=O.quartic_s_q(s_xx), s_eps=s_eps, walls=walls,
+                   fx=force, fy=0.5 * force)
+    want = O.mrt_moments(df)
+    err = rel_l2(got, want)
+    err_pop = math.sqrt(float(np.sum((got_pop - df) ** 2)) / float(np.sum(df ** 2)))
+    print(f"  rel L2 moments = {err:.3e}, populations = {err_pop:.3e}")
+    assert err <= TOL[dtype] and err_pop <= TOL[dtype]
+
+
+def test_f16_storage_error(F):
+    """FP16 storage of (drho, jx, jy) with FP32 arithmetic: the error against the FP64
+    oracle is dominated by the storage rounding (2^-11 relative) and does not grow,
+    because the rounding noise sits at high wave numbers that the scheme damps."""
+    nx = ny = 128
+    r, x, y = W.decaying_flow(n=128, seed=4, kmax=16, amp=0.02)
+    errs = []
+    sim = F.FdLbm(nx, ny, stencil=3, dtype="f16", s_xx=O.rate_from_viscosity(0.02), s_e=1.0)
+    sim.set_state(r, x, y)
+    state = (r, x, y)
+    for _ in range(4):
+        sim.step(100)
+        state = O.fd_run(*state, 100, s_xx=O.rate_from_viscosity(0.02), s_e=1.0, stencil=3)
+        errs.append(rel_l2(sim.get_state(), state))
+    sim.close()
+    print("  f16 rel L2 after 100..400 steps:", ["%.2e" % e for e in errs])
+    assert max(errs) <= 5e-3
+    assert errs[-1] <= 2.0 * errs[0] + 1e-4
+
+
+@pytest.mark.parametrize("scheme,dtype", [("fd", "f64"), ("fd", "f32"), ("fd", "f16"), ("mrt", "f64"), ("mrt", "f32")])
+def test_diagnostics_match_host_sums(F, scheme, dtype):
+    nx, ny = 77, 53
+    r, x, y = W.random_state(nx, ny, seed=31, amp=0.05)
+    sim = F.FdLbm(nx, ny, scheme=scheme, dtype=dtype, s_xx=1.5, s_e=1.0, quartic=True)
+    sim.set_state(r, x, y)
+    r2, x2, y2 = sim.get_state()
+    sim.set_mode(x, y)
+    d = sim.diagnostics()
+    a = sim.mode_projection()
+    sim.close()
+    tol = 1e-12 if dtype == "f64" else 1e-9
+    j2 = x2 * x2 + y2 * y2
+    assert abs(d["mass"] - r2.sum()) <= tol * np.abs(r2).sum()
+    assert abs(d["mom_x"] - x2.sum()) <= tol * np.abs(x2).sum()
+    assert abs(d["mom_y"] - y2.sum()) <= tol * np.abs(y2).sum()
+    assert abs(d["kin_energy"] - 0.5 * np.sum(j2 / (1 + r2))) <= tol * np.sum(j2)
+    assert abs(d["max_abs_j"] - np.sqrt(j2.max())) <= 1e-6 * np.sqrt(j2.max())
+    assert d["nonfinite"] == 0
+    assert abs(a - np.sum(x2 * x + y2 * y) / np.sum(x * x + y * y)) < 1e-9
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+def test_shear_wave_64_fp64(F, scheme):
+    """The 64 x 64 shear wave jx = 0.01 sin(2 pi y / 64), nu = 0.02, 1000 steps in FP64:
+    A(t) from the device reduction equals the oracle's at every sampled step, and total
+    mass stays zero."""
+    nu = 0.02
+    s_xx = O.rate_from_viscosity(nu)
+    r, x, y = W.shear_wave_y(64, 64, 0.01, 1)
+    kw = dict(scheme="mrt", quartic=True) if scheme == "mrt" else dict(scheme="fd", stencil=int(scheme[2]))
+    sim = F.FdLbm(64, 64, dtype="f64", s_xx=s_xx, s_e=1.0, **kw)
+    sim.set_state(r, x, y)
+    sim.set_mode(x, y)
+    gpu_a = []
+    for _ in range(10):
+        sim.step(100)
+        gpu_a.append(sim.mode_projection())
+    d = sim.diagnostics()
+    sim.close()
+    if scheme == "mrt":
+        st = O.mrt_init(r, x, y)
+    else:
+        st = (r, x, y)
+    norm = np.sum(x * x)
+    for t in range(10):
+        if scheme == "mrt":
+            st = O.mrt_run(st, 100, s_xx=s_xx, s_q=O.quartic_s_q(s_xx))
+            jx = O.mrt_moments(st)[1]
+        else:
+            st = O.fd_run(*st, 100, s_xx=s_xx, stencil=int(scheme[2]))
+            jx = st[1]
+        want = np.sum(jx * x) / norm
+        assert abs(gpu_a[t] - want) < 1e-12, (t, gpu_a[t], want)
+    assert abs(d["mass"]) < 1e-13
+    assert 0.8 < gpu_a[-1] < 0.83
+
+
+def test_state_roundtrip(F):
+    nx, ny = 40, 24
+    r, x, y = W.random_state(nx, ny, seed=41, amp=0.03)
+    for dtype, cast in (("f64", np.float64), ("f32", np.float32), ("f16", np.float16)):
+        sim = F.FdLbm(nx, ny, dtype=dtype, s_xx=1.5)
+        sim.set_state(r, x, y)
+        got = sim.get_state()
+        assert sim.steps == 0
+        sim.step(0)
+        sim.close()
+        for g, w in zip(got, (r, x, y)):
+            assert np.array_equal(g, w.astype(cast).astype(np.float64))
+    sim = F.FdLbm(nx, ny, scheme="mrt", dtype="f64", s_xx=1.5, quartic=True)
+    df = np.random.default_rng(3).standard_normal((9, ny, nx)) * 1e-3
+    sim.set_populations(df)
+    assert np.array_equal(sim.get_populations(), df)
+    sim.close()
+
+
+def test_wrong_scheme_and_instability_are_reported(F):
+    nx, ny = 32, 32
+    sim = F.FdLbm(nx, ny, scheme="fd", dtype="f32", s_xx=1.5, check_every=5)
+    with pytest.raises(F.FdlbmError) as e:
+        F.mrt_step(sim.ctx, 1)
+    assert e.value.code == F.FDLBM_EINVAL
+    r, x, y = W.random_state(nx, ny, seed=1, amp=0.01)
+    x[3, 7] = np.nan  # host-side poison: the kernels propagate it like any value
+    sim.set_state(r, x, y)
+    with pytest.raises(F.FdlbmError) as e:
+        sim.step(10)
+    assert e.value.code == F.FDLBM_EUNSTABLE
+    assert sim.diagnostics()["nonfinite"] > 0
+    sim.close()
+    mrt = F.FdLbm(nx, ny, scheme="mrt", dtype="f32", s_xx=1.5, quartic=True)
+    with pytest.raises(F.FdlbmError) as e:
+        F.fdlbm_step(mrt.ctx, 1)
+    assert e.value.code == F.FDLBM_EINVAL
+    mrt.close()

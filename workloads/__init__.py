@@ -75,11 +75,12 @@ def fourier_field(nx, ny, kmax, rng, row_chunk=2048):
     ex = np.exp(2j * math.pi * np.outer(np.arange(nx), ks) / nx)  # (nx, nk)
     ey = np.exp(2j * math.pi * np.outer(np.arange(ny), ks) / ny)  # (ny, nk)
     a = ey @ c  # (ny, nk)
-    out = np.empty((ny, nx))
+    ar, ai = np.ascontiguousarray(a.real), np.ascontiguousarray(a.imag)
     exr, exi = ex.real.T.copy(), ex.imag.T.copy()
+    out = np.empty((ny, nx))
     for j0 in range(0, ny, row_chunk):
         j1 = min(ny, j0 + row_chunk)
-        out[j0:j1] = a[j0:j1].real @ exr - a[j0:j1].imag @ exi
+        out[j0:j1] = ar[j0:j1] @ exr - ai[j0:j1] @ exi
     return out
 
 
