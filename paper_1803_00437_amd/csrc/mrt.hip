@@ -152,19 +152,19 @@ __global__ void __launch_bounds__(256) mrt_init_kernel(const double *__restrict_
     }
 }
 
+// Conserved moments of the stored populations, summed in FP64 whatever the storage dtype.
 template <typename T>
 __global__ void __launch_bounds__(256) mrt_moments_kernel(const T *__restrict__ pop, double *__restrict__ dr,
                                                           double *__restrict__ jx, double *__restrict__ jy, size_t n)
 {
-    using C = typename Storage<T>::C;
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
-        C f[9], m[9];
+        double f[9], m[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = Storage<T>::load(pop[q * n + p]);
-        moments<C>(f, m);
-        dr[p] = double(m[0]);
-        jx[p] = double(m[1]);
-        jy[p] = double(m[2]);
+        for (int q = 0; q < 9; ++q) f[q] = double(Storage<T>::load(pop[q * n + p]));
+        moments<double>(f, m);
+        dr[p] = m[0];
+        jx[p] = m[1];
+        jy[p] = m[2];
     }
 }
 
