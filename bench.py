@@ -46,9 +46,11 @@ def bytes_per_node(scheme, dtype):
     return 2 * words * {"f64": 8, "f32": 4, "f16": 2}[dtype]
 
 
-def run_case(F, torch, init, n, scheme, dtype, stencil, steps, warmup, kernel, with_diag):
+def run_case(F, torch, init, n, scheme, dtype, stencil, steps, warmup, kernel, with_diag, tile_rows=0, lane_cols=0):
     s_xx = F.fdlbm_rate_from_viscosity(NU)
-    kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel)
+    kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel, tile_rows=tile_rows)
+    if scheme == "fd":
+        kw["lane_cols"] = lane_cols
     if scheme == "fd":
         kw["stencil"] = stencil
     else:
@@ -87,6 +89,25 @@ def run_case(F, torch, init, n, scheme, dtype, stencil, steps, warmup, kernel, w
         "alg_gbs": bytes_per_node(scheme, dtype) * nodes / (kernel_ms * 1e6),
         "nonfinite": diag["nonfinite"],
     }
+
+
+def measure_copy(F, torch, probe=False, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: the library's streaming copy of 1 GiB (read + write)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(5 if probe else 2):
+        F.fdlbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        F.fdlbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e6)
 
 
 def band_errors(F, O, init, n, s_steps, rows, cases, threads):
@@ -140,6 +161,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error bands")
     ap.add_argument("--err-steps", type=int, default=12)
     ap.add_argument("--err-rows", type=int, default=512)
+    ap.add_argument("--tile-rows", type=int, default=0, help="rows per wavefront strip of the sweep kernel (0 = default)")
+    ap.add_argument("--lane-cols", type=int, default=0, help="grid columns per lane of the sweep kernel (0 = default)")
+    ap.add_argument("--only", default=None, help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run the 1 GiB streaming copy a few more times (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -161,7 +187,21 @@ def main():
     init = W.decaying_flow(n=n, seed=4, kmax=32, amp=0.02)
     print(f"# input {n}x{n} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
-    main_case = run_case(F, torch, init, n, "fd", "f32", 3, args.steps, args.warmup, args.kernel, True)
+    copy_gbs = measure_copy(F, torch, probe=args.copy_probe)
+    print(f"# streaming copy (fdlbm_device_copy, 1 GiB): {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+
+    if args.only:
+        name, dtype = args.only.split("_")
+        scheme = "mrt" if name == "mrt" else "fd"
+        stencil = int(name[2]) if scheme == "fd" else 0
+        case = run_case(F, torch, init, n, scheme, dtype, stencil, args.steps, args.warmup, args.kernel, False,
+                        args.tile_rows, args.lane_cols)
+        print(json.dumps({"case": args.only, "tile_rows": args.tile_rows, "lane_cols": args.lane_cols, **case}),
+              flush=True)
+        return
+
+    main_case = run_case(F, torch, init, n, "fd", "f32", 3, args.steps, args.warmup, args.kernel, True,
+                         args.tile_rows, args.lane_cols)
     print(f"# fd3 f32: {main_case}", file=sys.stderr, flush=True)
 
     compare = {}
@@ -232,6 +272,9 @@ def main():
             "kernel_ms": round(kernel_ms, 5),
             "alg_bytes_per_launch": bytes_per_node("fd", "f32") * n * n,
         },
+        "hbm_copy": {"gbs": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+                     "kernel_frac_of_copy": round(achieved / copy_gbs, 4),
+                     "what": "fdlbm_device_copy of 1 GiB: read + write bytes / time"},
         "cpu_baseline": cpu,
         "err_vs_oracle": errors,
         "compare": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}

@@ -66,7 +66,8 @@ typedef struct fdlbm_params {
     int32_t check_every;/* > 0: fdlbm_step / mrt_step scan the state for non-finite values
                          * every check_every steps and return FDLBM_EUNSTABLE if one is found
                          * (this synchronises the stream at each check)                       */
-    int32_t reserved;
+    int32_t lane_cols;  /* sweep kernel: grid columns per lane, 0 (choose), 1 (FP64 3-point),
+                         * 2, or 4 (FP32 / FP16); nx must be a multiple; tuning knob          */
 } fdlbm_params;
 
 typedef struct fdlbm_diag {
@@ -132,6 +133,13 @@ int64_t fdlbm_step_count(const fdlbm_ctx *c);
 
 /* Release the context.  Frees nothing the caller owns. */
 void fdlbm_destroy(fdlbm_ctx *c);
+
+/* Measurement utility: a plain streaming copy of `bytes` (a multiple of 16; both device
+ * pointers 16-byte aligned) from src to dst, 16-byte accesses, issued asynchronously on
+ * the HIP stream (NULL = default).  It gives the achievable HBM bandwidth that the step
+ * kernels' algorithmic bandwidth is compared with, and a kernel of known traffic for
+ * calibrating hardware byte counters.  Not part of the method. */
+int fdlbm_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 /* Static text for a return code, and the last HIP error text of this thread. */
 const char *fdlbm_strerror(int code);

@@ -32,7 +32,7 @@ EXPORTED = (
     "fdlbm_set_populations", "fdlbm_get_populations", "fdlbm_step", "mrt_step",
     "fdlbm_diagnostics", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
     "fdlbm_destroy", "fdlbm_strerror", "fdlbm_last_error", "fdlbm_rate_from_viscosity",
-    "fdlbm_quartic_s_q",
+    "fdlbm_quartic_s_q", "fdlbm_device_copy",
 )
 
 
@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
         ("s_eps", ctypes.c_double), ("quartic", ctypes.c_int32),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
         ("kernel", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("lane_cols", ctypes.c_int32),
     ]
 
 
@@ -102,6 +102,7 @@ def load_library(path=LIB_PATH):
         "fdlbm_last_error": (ctypes.c_char_p, []),
         "fdlbm_rate_from_viscosity": (ctypes.c_double, [ctypes.c_double]),
         "fdlbm_quartic_s_q": (ctypes.c_double, [ctypes.c_double]),
+        "fdlbm_device_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -124,10 +125,10 @@ def _dptr(a):
 
 def make_params(nx, ny, scheme="fd", stencil=3, bc="periodic", dtype="f32", s_xx=1.0, s_e=1.0,
                 s_q=1.0, s_eps=1.0, quartic=False, force=(0.0, 0.0), kernel="auto", tile_rows=0,
-                check_every=0):
+                check_every=0, lane_cols=0):
     return Params(int(nx), int(ny), SCHEME[scheme], int(stencil), BC[bc], DTYPE[dtype], float(s_xx),
                   float(s_e), float(s_q), float(s_eps), int(bool(quartic)), float(force[0]),
-                  float(force[1]), KERNEL[kernel], int(tile_rows), int(check_every), 0)
+                  float(force[1]), KERNEL[kernel], int(tile_rows), int(check_every), int(lane_cols))
 
 
 def fdlbm_workspace_bytes(params):
@@ -206,6 +207,11 @@ def fdlbm_rate_from_viscosity(nu):
 
 def fdlbm_quartic_s_q(s_xx):
     return float(load_library().fdlbm_quartic_s_q(float(s_xx)))
+
+
+def fdlbm_device_copy(dst, src, nbytes, stream=0):
+    """Streaming copy of nbytes between device pointers (ints) on a HIP stream handle."""
+    _check(load_library().fdlbm_device_copy(dst, src, int(nbytes), stream or None), "fdlbm_device_copy")
 
 
 # ----------------------------------------------------------------- convenience ----

@@ -45,7 +45,7 @@ bool uses_reference(const fdlbm_params &p)
 {
     if (p.scheme != FDLBM_SCHEME_FD) return false;
     if (p.kernel == FDLBM_KERNEL_REFERENCE) return true;
-    return !fd_sweep_supported(fd_args(p));
+    return !fd_sweep_supported(fd_args(p), p.lane_cols);
 }
 
 int validate(const fdlbm_params *p)
@@ -63,7 +63,8 @@ int validate(const fdlbm_params *p)
     if (p->scheme == FDLBM_SCHEME_FD) {
         if (p->stencil != 3 && p->stencil != 5) return FDLBM_EINVAL;  // the 9-point form is unstable on {1,1}
         if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32 && p->dtype != FDLBM_F16DEV) return FDLBM_EINVAL;
-        if (p->kernel == FDLBM_KERNEL_SWEEP && !fd_sweep_supported(fd_args(*p))) return FDLBM_EINVAL;
+        if (p->lane_cols != 0 && p->lane_cols != 1 && p->lane_cols != 2 && p->lane_cols != 4) return FDLBM_EINVAL;
+        if (p->kernel == FDLBM_KERNEL_SWEEP && !fd_sweep_supported(fd_args(*p), p->lane_cols)) return FDLBM_EINVAL;
     } else {
         if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32) return FDLBM_EINVAL;
         if (!rate_ok(p->s_eps)) return FDLBM_EINVAL;
@@ -252,7 +253,7 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
         else if (ref)
             e = launch_fd_reference(fa, src, dst, c->scratch + c->L.fstar, c->stream);
         else
-            e = launch_fd_sweep(fa, c->p.tile_rows, src, dst, c->stream);
+            e = launch_fd_sweep(fa, c->p.tile_rows, c->p.lane_cols, src, dst, c->stream);
         if (e != hipSuccess) return device_error(e, fd ? "fdlbm_step launch" : "mrt_step launch");
         c->cur ^= 1;
         ++c->steps;
@@ -316,6 +317,13 @@ int fdlbm_mode_projection(fdlbm_ctx *c, double *out)
     if (rc) return rc;
     if (!(d[6] > 0)) return FDLBM_EINVAL;
     *out = d[5] / d[6];
+    return FDLBM_OK;
+}
+
+int fdlbm_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) & 15) return FDLBM_EINVAL;
+    HIPCHK(launch_device_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream)), "fdlbm_device_copy");
     return FDLBM_OK;
 }
 

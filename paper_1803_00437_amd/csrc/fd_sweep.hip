@@ -2,30 +2,42 @@
 // once (3 values per node each way), no scratch memory.
 //
 // Mapping (designed for CDNA4's 64-wide wavefronts):
-//   * a wavefront owns a strip of W = 64*CPL consecutive columns (CPL columns per lane,
-//     loaded and stored as one vector per field) and walks down R rows of the grid;
+//   * a block is WV wavefronts stacked in y over one strip of W = 64*CPL consecutive
+//     columns (CPL columns per lane, loaded and stored as one aligned vector per field);
+//     each wavefront sweeps its own R rows of the strip;
 //   * x-neighbours of a lane's outer columns come from the adjacent lanes through DPP
-//     whole-wave shifts (wave_shl:1 / wave_shr:1), so no LDS and no barrier is needed;
-//     the PAD outermost columns on each side of the strip only feed their neighbours, and
-//     strips overlap by 2*PAD columns;
-//   * y-neighbours live in a rolling window of 2h+1 input rows held in registers (h = 1
-//     for 3-point and 2 for 5-point differences); the row loop is unrolled by the window
-//     length so the window rotates by renaming, not by register moves;
+//     whole-wave shifts (wave_shl:1 / wave_shr:1), so no LDS and no barrier is needed
+//     along x.  A node update needs h+1 columns on each side (h = 1 for 3-point, 2 for
+//     5-point differences); neighbouring strips overlap by whole halo lanes so that every
+//     access stays aligned;
+//   * y-neighbours live in a rolling window of 2h+1 input rows held in registers, with the
+//     next row prefetched; the row loop is unrolled by the window length so that the
+//     window rotates by renaming, not by register moves;
 //   * the post-collision populations of a row are exchanged along x with the same DPP
-//     shifts and split into the parts that land on the row itself, on the row above and
-//     on the row below; the row below's output is complete once the current row is done.
+//     shifts and split into the parts landing on the row itself, the row above and the
+//     row below; the output row below the current one is then complete and is stored
+//     with a non-temporal hint (it is read again only at the next step);
+//   * the first and last output rows of a wavefront also need the populations sent by the
+//     rows just outside it.  Inside a block those rows belong to the neighbouring
+//     wavefronts, which publish their partial sums in LDS; after one barrier every
+//     wavefront finishes its two boundary rows.  Only the block's outermost wavefronts
+//     compute the populations of one extra row each;
+//   * blocks are dealt out row band after row band, so the resident blocks cover a compact
+//     block of rows: the halo rows a block shares with the bands above and below are then
+//     re-read from cache, and HBM sees a few long sequential streams;
+//   * all row bookkeeping is wave-uniform (scalar registers).
 // Per node the arithmetic is fd_node_fstar() and the summation order is fd_gather()'s, so
 // the result equals the reference path bit for bit.
 //
-// Walls (rows -1 .. -(h+1) and ny .. ny+h are ghosts): the mirror of section 3-c's
-// xi = 1/2 extrapolation is applied when a row is loaded (drho even, J odd).
+// Walls (rows -1 .. -(h+1) and ny .. ny+h are ghosts): the mirror of the xi = 1/2
+// extrapolation of section 3-c is applied as a row is loaded (drho even, J odd).
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
 
 namespace fdlbm {
 namespace {
 
-constexpr int WAVES_PER_BLOCK = 4;
+constexpr int WV = 4;  // wavefronts stacked per block
 
 // whole-wave lane shifts: shl gives lane i the value of lane i+1, shr the value of lane i-1
 constexpr int DPP_WAVE_SHL1 = 0x130;
@@ -45,110 +57,131 @@ template <int CTRL> __device__ __forceinline__ double lane_shift(double v)
 template <typename C> __device__ __forceinline__ C from_right(C v) { return lane_shift<DPP_WAVE_SHL1>(v); }
 template <typename C> __device__ __forceinline__ C from_left(C v) { return lane_shift<DPP_WAVE_SHR1>(v); }
 
-// CPL consecutive stored values as one memory access.
+// CPL consecutive stored values as one memory access (4, 8 or 16 bytes).
 template <typename T, int CPL> struct Group {
     T v[CPL];
 };
+template <int BYTES> struct Word;
+template <> struct Word<4> { using type = unsigned int; };
+template <> struct Word<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
+template <> struct Word<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
 
 template <typename T, int CPL> __device__ __forceinline__ Group<T, CPL> load_group(const T *p)
 {
     static_assert(sizeof(Group<T, CPL>) == sizeof(T) * CPL, "packed group");
-    return *reinterpret_cast<const Group<T, CPL> *>(p);
+    using Wd = typename Word<sizeof(T) * CPL>::type;
+    return __builtin_bit_cast(Group<T, CPL>, *reinterpret_cast<const Wd *>(p));
 }
-
 template <typename T, int CPL> __device__ __forceinline__ void store_group(T *p, const Group<T, CPL> &g)
 {
-    *reinterpret_cast<Group<T, CPL> *>(p) = g;
+    using Wd = typename Word<sizeof(T) * CPL>::type;
+    __builtin_nontemporal_store(__builtin_bit_cast(Wd, g), reinterpret_cast<Wd *>(p));
 }
+
+// Strip geometry: a strip loads W columns starting at s*S - P and stores the S = W - 2P
+// columns [s*S, s*S + S), where P = h+1 rounded up to whole lanes.
+template <int CPL, int H> struct Strip {
+    static constexpr int W = 64 * CPL;
+    static constexpr int P = ((H + 1 + CPL - 1) / CPL) * CPL;
+    static constexpr int S = W - 2 * P;
+};
 
 template <typename T> struct SweepArgs {
     const T *dr, *jx, *jy;
     T *odr, *ojx, *ojy;
-    int nx, ny, rows, strips_x, strips_y, ntiles;
+    int nx, ny, rows, strips_x, nbands, nblocks;
     FdCoef<typename Storage<T>::C> k;
 };
 
+// LDS slots per wavefront, each CPL x 64 values: the partial sums a wavefront publishes
+// for its neighbours, and the ones it keeps for its own first output row.
+enum { PUB_DN = 0, PUB_DNX, PUB_UP, PUB_UPX, OWN_CEN, OWN_CENX, OWN_DN, OWN_DNX, NSLOT };
+
 template <typename T, int CPL, int ST, bool WALLS>
-__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) fd_sweep_kernel(SweepArgs<T> a)
+__global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 {
     using C = typename Storage<T>::C;
     using S = Stencil<ST>;
     constexpr int H = S::H;
-    constexpr int NW = 2 * H + 1;                           // rows in the input window
-    constexpr int W = 64 * CPL;                             // columns per strip
-    constexpr int PAD = ((H + 1 + CPL - 1) / CPL) * CPL;    // halo columns per side
-    constexpr int SX = W - 2 * PAD;                         // output columns per strip
+    constexpr int NW = 2 * H + 1;  // rows in the input window
+    using G = Strip<CPL, H>;
     static_assert(CPL >= 2 || H == 1, "5-point differences need two columns per lane");
+    __shared__ C lds[WV][NSLOT][CPL][64];
 
     const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    if (tile >= a.ntiles) return;  // uniform over the wavefront
-    // consecutive tiles are stacked in y so that a wavefront's halo rows were just read
-    // by its neighbour
-    const int sx = tile / a.strips_y, sy = tile - sx * a.strips_y;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // blocks dealt out row band after row band (uniform over the block)
+    const int band = blockIdx.x / a.strips_x;
+    const int sx = blockIdx.x - band * a.strips_x;
     const int nx = a.nx, ny = a.ny;
-    const int xs = sx * SX - PAD + CPL * lane;              // first column of this lane (unwrapped)
-    const int col = ((xs % nx) + nx) % nx;                  // wrapped (x periodic)
-    const bool store_ok = lane >= PAD / CPL && lane < (W - PAD) / CPL && xs < nx;
-    const int ybeg = sy * a.rows;
-    const int yend = min(ybeg + a.rows, ny);
-    const int nf = yend - ybeg + 2;                         // rows whose f* is needed: ybeg-1 .. yend
-    const int row0 = ybeg - 1 - H;                          // first input row
+    const int xl = sx * G::S - G::P + CPL * lane;  // first column of this lane (unwrapped)
+    const int col = ((xl % nx) + nx) % nx;          // wrapped (x periodic)
+    const bool store_ok = CPL * lane >= G::P && CPL * lane < G::P + G::S && xl < nx;
 
-    // source row and sign for input row j (wave-uniform)
-    auto source = [&](int j, int &src, C &sgn) {
-        sgn = C(1);
+    // rows of this wavefront: R each; a single leftover row at the end of the band is
+    // absorbed by the wavefront below it, so every non-empty wavefront has >= 2 rows
+    // unless the whole band has one row
+    const int b0 = band * WV * a.rows, b1 = min(b0 + WV * a.rows, ny);
+    const int ybeg = b0 + wv * a.rows;
+    int yend = min(ybeg + a.rows, b1);
+    if (b1 - yend == 1) yend = b1;
+    const bool empty = ybeg >= b1 || (wv > 0 && b1 - ybeg == 1);
+    const bool bottom = wv == 0;  // computes f* of row ybeg - 1 itself
+    const bool top = yend == b1;  // computes f* of row yend itself
+    const int rb = bottom ? ybeg - 1 : ybeg;
+    const int re = top ? yend : yend - 1;
+    const int nf = empty ? 0 : re - rb + 1;  // rows whose f* this wavefront computes
+    const int row0 = rb - H;                 // first input row
+
+    // rolling window of input rows: drho, J_a = J + F/2 and the products Jx^2, JxJy, Jy^2
+    C w[6][NW][CPL];
+    Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
+    C ps = C(1);               // its sign (-1: ghost row beyond a wall)
+
+    auto fetch = [&](int j) {
+        int src = j;
+        C sgn = C(1);
         if (WALLS) {
             if (j < 0) { src = -1 - j; sgn = C(-1); }
             else if (j >= ny) { src = 2 * ny - 1 - j; sgn = C(-1); }
-            else src = j;
         } else {
-            src = ((j % ny) + ny) % ny;
+            src = j < 0 ? j + ny : (j >= ny ? j - ny : j);
         }
-    };
-
-    // rolling window of input rows; fields: 0 drho, 1 J_a,x, 2 J_a,y (J_a = J + F/2),
-    // 3 Jx^2, 4 JxJy, 5 Jy^2 (products of J_a)
-    C w[6][NW][CPL];
-    Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
-    C psg = C(1);              // its sign (-1 for a ghost row beyond a wall)
-
-    auto fetch = [&](int j) {
-        int src;
-        source(j, src, psg);
         const size_t off = (size_t)src * (size_t)nx + (size_t)col;
         pr = load_group<T, CPL>(a.dr + off);
         px = load_group<T, CPL>(a.jx + off);
         py = load_group<T, CPL>(a.jy + off);
+        ps = sgn;
     };
-    auto insert = [&](int slot) {
+    auto insert = [&](int wslot) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const C r = Storage<T>::load(pr.v[c]);
-            const C x = fmac(psg, Storage<T>::load(px.v[c]), a.k.hfx);
-            const C y = fmac(psg, Storage<T>::load(py.v[c]), a.k.hfy);
-            w[0][slot][c] = r;
-            w[1][slot][c] = x;
-            w[2][slot][c] = y;
-            w[3][slot][c] = x * x;
-            w[4][slot][c] = x * y;
-            w[5][slot][c] = y * y;
+            const C x = fmac(ps, Storage<T>::load(px.v[c]), a.k.hfx);
+            const C y = fmac(ps, Storage<T>::load(py.v[c]), a.k.hfy);
+            w[0][wslot][c] = Storage<T>::load(pr.v[c]);
+            w[1][wslot][c] = x;
+            w[2][wslot][c] = y;
+            w[3][wslot][c] = x * x;
+            w[4][wslot][c] = x * y;
+            w[5][wslot][c] = y * y;
         }
     };
-
-    // prologue: the first 2H input rows, and the prefetch of the next one
-#pragma unroll
-    for (int q = 0; q < 2 * H; ++q) {
-        fetch(row0 + q);
-        insert(q);
-    }
-    fetch(row0 + 2 * H);
 
     // partial sums carried between rows (order of fd_gather): A = cen(r-1) + up(r-2),
     // AX = cenx(r-1) + upx(r-2), UP = up(r-2); UPp, UPXp = up(r-1), upx(r-1)
     C A[CPL], AX[CPL], UP[CPL], UPp[CPL], UPXp[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) A[c] = AX[c] = UP[c] = UPp[c] = UPXp[c] = C(0);
+
+    if (nf > 0) {
+        // prologue: the first 2H input rows, then the prefetch of the next one
+#pragma unroll
+        for (int r = 0; r < 2 * H; ++r) {
+            fetch(row0 + r);
+            insert(r);
+        }
+        fetch(row0 + 2 * H);
+    }
 
     // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
     // y-derivative fields (drho, Jy, Jx, JxJy, Jy^2) -> d[1], d[3], d[5], d[7], d[9]
@@ -161,17 +194,17 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) fd_sweep_kernel(SweepArg
             const int it = it0 + ph;
             if (it >= nf) break;
             insert((ph + 2 * H) % NW);
-            if (it + 1 < nf) fetch(row0 + it + 1 + 2 * H);
+            if (it + 1 < nf) fetch(row0 + 2 * H + it + 1);
 
-            const int cen = (ph + H) % NW;  // slot of the row whose f* is computed
+            const int cs = (ph + H) % NW;  // window slot of the row whose f* is computed
             // x-neighbours of the lane's outer columns, from the adjacent lanes
             C xl1[5], xr1[5], xl2[5], xr2[5];
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                xl1[q] = from_left(w[XF[q]][cen][CPL - 1]);
-                xr1[q] = from_right(w[XF[q]][cen][0]);
-                xl2[q] = H == 2 ? from_left(w[XF[q]][cen][CPL - 2]) : C(0);
-                xr2[q] = H == 2 ? from_right(w[XF[q]][cen][1]) : C(0);
+                xl1[q] = from_left(w[XF[q]][cs][CPL - 1]);
+                xr1[q] = from_right(w[XF[q]][cs][0]);
+                xl2[q] = H == 2 ? from_left(w[XF[q]][cs][CPL >= 2 ? CPL - 2 : 0]) : C(0);
+                xr2[q] = H == 2 ? from_right(w[XF[q]][cs][CPL > 1 ? 1 : 0]) : C(0);
             }
             C f[CPL][9];
 #pragma unroll
@@ -180,19 +213,19 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) fd_sweep_kernel(SweepArg
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
                     const int fx = XF[q], fy = YF[q];
-                    const C m1 = c > 0 ? w[fx][cen][c > 0 ? c - 1 : 0] : xl1[q];
-                    const C p1 = c < CPL - 1 ? w[fx][cen][c < CPL - 1 ? c + 1 : 0] : xr1[q];
+                    const C m1 = c > 0 ? w[fx][cs][c > 0 ? c - 1 : 0] : xl1[q];
+                    const C p1 = c < CPL - 1 ? w[fx][cs][c < CPL - 1 ? c + 1 : 0] : xr1[q];
                     C m2 = C(0), p2 = C(0), ym2 = C(0), yp2 = C(0);
                     if (H == 2) {
-                        m2 = c >= 2 ? w[fx][cen][c >= 2 ? c - 2 : 0] : (c == 1 ? xl1[q] : xl2[q]);
-                        p2 = c + 2 < CPL ? w[fx][cen][c + 2 < CPL ? c + 2 : 0] : (c + 2 == CPL ? xr1[q] : xr2[q]);
+                        m2 = c >= 2 ? w[fx][cs][c >= 2 ? c - 2 : 0] : (c == 1 ? xl1[q] : xl2[q]);
+                        p2 = c + 2 < CPL ? w[fx][cs][c + 2 < CPL ? c + 2 : 0] : (c + 2 == CPL ? xr1[q] : xr2[q]);
                         ym2 = w[fy][ph % NW][c];
                         yp2 = w[fy][(ph + 2 * H) % NW][c];
                     }
                     d[2 * q] = S::diff(m2, m1, p1, p2);
                     d[2 * q + 1] = S::diff(ym2, w[fy][(ph + H - 1) % NW][c], w[fy][(ph + H + 1) % NW][c], yp2);
                 }
-                fd_node_fstar<C>(w[0][cen][c], w[1][cen][c], w[2][cen][c], d, a.k, f[c]);
+                fd_node_fstar<C>(w[0][cs][c], w[1][cs][c], w[2][cs][c], d, a.k, f[c]);
             }
             // populations moving along +x come from the column on the left, along -x from
             // the column on the right
@@ -208,45 +241,94 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) fd_sweep_kernel(SweepArg
                 const C c3 = c < CPL - 1 ? f[cr][3] : f3r;
                 const C u6 = c < CPL - 1 ? f[cr][6] : f6r;
                 const C d7 = c < CPL - 1 ? f[cr][7] : f7r;
-                const C cen_ = (f[c][0] + c1) + c3, cenx = c1 - c3;
+                const C cen = (f[c][0] + c1) + c3, cenx = c1 - c3;
                 const C up = (f[c][2] + u5) + u6, upx = u5 - u6;
-                const C dn = (f[c][4] + d7) + d8, dnx = d8 - d7;
+                const C dn = (f[c][4] + d8) + d7, dnx = d8 - d7;
+                if (!bottom && it == 0) {
+                    // f* of the first row: its downward part completes the last output row
+                    // of the wavefront below; its own row still lacks the part sent up by
+                    // that wavefront
+                    lds[wv][PUB_DN][c][lane] = dn;
+                    lds[wv][PUB_DNX][c][lane] = dnx;
+                    lds[wv][OWN_CEN][c][lane] = cen;
+                    lds[wv][OWN_CENX][c][lane] = cenx;
+                }
+                if (!bottom && it == 1) {
+                    lds[wv][OWN_DN][c][lane] = dn;
+                    lds[wv][OWN_DNX][c][lane] = dnx;
+                }
                 // output row r-1 = (cen(r-1) + up(r-2)) + dn(r)
                 gr.v[c] = Storage<T>::store(A[c] + dn);
                 gx.v[c] = Storage<T>::store(AX[c] + dnx);
                 gy.v[c] = Storage<T>::store(UP[c] - dn);
-                A[c] = cen_ + UPp[c];
+                A[c] = cen + UPp[c];
                 AX[c] = cenx + UPXp[c];
                 UP[c] = UPp[c];
                 UPp[c] = up;
                 UPXp[c] = upx;
             }
-            // the output row ybeg - 1 + it - 1 is complete once f* of ybeg - 1 + it is known
+            // output row rb + it - 1 is complete once f* of rows rb + it - 2 .. rb + it are known
             if (it >= 2 && store_ok) {
-                const size_t off = (size_t)(ybeg + it - 2) * (size_t)nx + (size_t)col;
+                const size_t off = (size_t)(rb + it - 1) * (size_t)nx + (size_t)col;
                 store_group<T, CPL>(a.odr + off, gr);
                 store_group<T, CPL>(a.ojx + off, gx);
                 store_group<T, CPL>(a.ojy + off, gy);
             }
         }
     }
+    if (!top && !empty) {
+        // the upward part of the last f* row completes the first output row of the
+        // wavefront above
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            lds[wv][PUB_UP][c][lane] = UPp[c];
+            lds[wv][PUB_UPX][c][lane] = UPXp[c];
+        }
+    }
+    __syncthreads();
+    if (empty) return;
+    if (!bottom) {
+        // first output row: (cen + up from the wavefront below) + dn
+        Group<T, CPL> gr, gx, gy;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const C up = lds[wv - 1][PUB_UP][c][lane], upx = lds[wv - 1][PUB_UPX][c][lane];
+            const C dn = lds[wv][OWN_DN][c][lane], dnx = lds[wv][OWN_DNX][c][lane];
+            gr.v[c] = Storage<T>::store((lds[wv][OWN_CEN][c][lane] + up) + dn);
+            gx.v[c] = Storage<T>::store((lds[wv][OWN_CENX][c][lane] + upx) + dnx);
+            gy.v[c] = Storage<T>::store(up - dn);
+        }
+        if (store_ok) {
+            const size_t off = (size_t)ybeg * (size_t)nx + (size_t)col;
+            store_group<T, CPL>(a.odr + off, gr);
+            store_group<T, CPL>(a.ojx + off, gx);
+            store_group<T, CPL>(a.ojy + off, gy);
+        }
+    }
+    if (!top) {
+        // last output row: (cen + up) carried + dn from the wavefront above
+        Group<T, CPL> gr, gx, gy;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const C dn = lds[wv + 1][PUB_DN][c][lane], dnx = lds[wv + 1][PUB_DNX][c][lane];
+            gr.v[c] = Storage<T>::store(A[c] + dn);
+            gx.v[c] = Storage<T>::store(AX[c] + dnx);
+            gy.v[c] = Storage<T>::store(UP[c] - dn);
+        }
+        if (store_ok) {
+            const size_t off = (size_t)(yend - 1) * (size_t)nx + (size_t)col;
+            store_group<T, CPL>(a.odr + off, gr);
+            store_group<T, CPL>(a.ojx + off, gx);
+            store_group<T, CPL>(a.ojy + off, gy);
+        }
+    }
 }
 
-template <typename T> constexpr int cols_per_lane() { return sizeof(T) == 8 ? 2 : 4; }
-
-template <typename T, int ST> int strip_cols()
-{
-    constexpr int CPL = cols_per_lane<T>();
-    constexpr int H = Stencil<ST>::H;
-    constexpr int PAD = ((H + 1 + CPL - 1) / CPL) * CPL;
-    return 64 * CPL - 2 * PAD;
-}
-
-template <typename T, int ST, bool WALLS>
+template <typename T, int CPL, int ST, bool WALLS>
 hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
     using C = typename Storage<T>::C;
-    constexpr int CPL = cols_per_lane<T>();
+    using G = Strip<CPL, Stencil<ST>::H>;
     const size_t n = (size_t)fa.nx * (size_t)fa.ny;
     SweepArgs<T> a;
     const T *in = static_cast<const T *>(src);
@@ -259,10 +341,11 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     a.ojy = out + 2 * n;
     a.nx = fa.nx;
     a.ny = fa.ny;
-    a.rows = tile_rows > 0 ? tile_rows : 64;
-    a.strips_x = (fa.nx + strip_cols<T, ST>() - 1) / strip_cols<T, ST>();
-    a.strips_y = (fa.ny + a.rows - 1) / a.rows;
-    a.ntiles = a.strips_x * a.strips_y;
+    a.strips_x = (fa.nx + G::S - 1) / G::S;
+    // rows per wavefront (>= 2, see the kernel); 8 measured best at 8192^2
+    a.rows = tile_rows >= 2 ? tile_rows : 8;
+    a.nbands = (fa.ny + WV * a.rows - 1) / (WV * a.rows);
+    a.nblocks = a.strips_x * a.nbands;
     const double scale = ST == 3 ? Stencil<3>::SCALE : Stencil<5>::SCALE;
     a.k.ke = C(scale * (1.0 - 1.0 / fa.s_e));
     a.k.kxx = C(scale * (1.0 - 1.0 / fa.s_xx));
@@ -272,33 +355,64 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     a.k.qfy = C(0.25 * fa.fy);
     a.k.dfx = C(fa.fx);
     a.k.dfy = C(fa.fy);
-    const int blocks = (a.ntiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS>), blocks, 64 * WAVES_PER_BLOCK, 0, s, a);
+    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS>), a.nblocks, 64 * WV, 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t dispatch(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s)
+template <typename T, int CPL>
+hipError_t dispatch_cpl(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
     if (a.stencil == 3)
-        return a.walls ? run<T, 3, true>(a, tile_rows, src, dst, s) : run<T, 3, false>(a, tile_rows, src, dst, s);
-    return a.walls ? run<T, 5, true>(a, tile_rows, src, dst, s) : run<T, 5, false>(a, tile_rows, src, dst, s);
+        return a.walls ? run<T, CPL, 3, true>(a, tile_rows, src, dst, s)
+                       : run<T, CPL, 3, false>(a, tile_rows, src, dst, s);
+    if constexpr (CPL >= 2)
+        return a.walls ? run<T, CPL, 5, true>(a, tile_rows, src, dst, s)
+                       : run<T, CPL, 5, false>(a, tile_rows, src, dst, s);
+    return hipErrorInvalidValue;
+}
+
+// Columns per lane (measured at 8192^2): FP32 4 (16-byte accesses), FP16 2 (4-byte
+// accesses, fewer live registers), FP64 2 (16-byte accesses).
+int choose_cpl(const FdArgs &a, int lane_cols)
+{
+    if (lane_cols > 0) return lane_cols;
+    return a.dtype == FDLBM_F32 ? 4 : 2;
+}
+
+template <typename T>
+hipError_t dispatch(const FdArgs &a, int tile_rows, int lane_cols, const void *src, void *dst, hipStream_t s)
+{
+    switch (choose_cpl(a, lane_cols)) {
+    case 1:
+        if constexpr (sizeof(T) == 8) return dispatch_cpl<T, 1>(a, tile_rows, src, dst, s);
+        return hipErrorInvalidValue;
+    case 2: return dispatch_cpl<T, 2>(a, tile_rows, src, dst, s);
+    case 4:
+        if constexpr (sizeof(T) != 8) return dispatch_cpl<T, 4>(a, tile_rows, src, dst, s);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-bool fd_sweep_supported(const FdArgs &a)
+bool fd_sweep_supported(const FdArgs &a, int lane_cols)
 {
-    const int cpl = a.dtype == FDLBM_F64 ? 2 : 4;
-    return a.nx % cpl == 0 && (a.stencil == 3 || a.stencil == 5);
+    const int cpl = choose_cpl(a, lane_cols);
+    const bool f64 = a.dtype == FDLBM_F64;
+    if (a.stencil != 3 && a.stencil != 5) return false;
+    if (cpl == 1) return f64 && a.stencil == 3;
+    if (cpl == 4 && f64) return false;
+    if (cpl != 2 && cpl != 4) return false;
+    return a.nx % cpl == 0;
 }
 
-hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s)
+hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, int lane_cols, const void *src, void *dst, hipStream_t s)
 {
     switch (a.dtype) {
-    case FDLBM_F64: return dispatch<double>(a, tile_rows, src, dst, s);
-    case FDLBM_F32: return dispatch<float>(a, tile_rows, src, dst, s);
-    default: return dispatch<__half>(a, tile_rows, src, dst, s);
+    case FDLBM_F64: return dispatch<double>(a, tile_rows, lane_cols, src, dst, s);
+    case FDLBM_F32: return dispatch<float>(a, tile_rows, lane_cols, src, dst, s);
+    default: return dispatch<__half>(a, tile_rows, lane_cols, src, dst, s);
     }
 }
 

@@ -133,13 +133,14 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
 //   c0 = f0(x), c1 = f1(x-ex), c3 = f3(x+ex)                        (same row)
 //   u2 = f2(x-ey), u5 = f5(x-ex-ey), u6 = f6(x+ex-ey)                (row below)
 //   d4 = f4(x+ey), d7 = f7(x+ex+ey), d8 = f8(x-ex+ey)                (row above)
-// Fixed summation order shared by every kernel.
+// Fixed summation order shared by every kernel: within each source row the value from the
+// left neighbour is added before the one from the right neighbour.
 template <typename C>
 __device__ __forceinline__ void fd_gather(C c0, C c1, C c3, C u2, C u5, C u6, C d4, C d7, C d8, C &dr, C &jx, C &jy)
 {
     const C cen = (c0 + c1) + c3, cenx = c1 - c3;
     const C up = (u2 + u5) + u6, upx = u5 - u6;
-    const C dn = (d4 + d7) + d8, dnx = d8 - d7;
+    const C dn = (d4 + d8) + d7, dnx = d8 - d7;
     dr = (cen + up) + dn;
     jx = (cenx + upx) + dnx;
     jy = up - dn;

@@ -31,9 +31,11 @@ struct MrtArgs {
 hipError_t launch_fd_reference(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s);
 size_t fd_reference_scratch_bytes(const FdArgs &a);
 
-// FD-LBM, fused sweep path: one kernel per step, no scratch.
-hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s);
-bool fd_sweep_supported(const FdArgs &a);
+// FD-LBM, fused sweep path: one kernel per step, no scratch.  tile_rows: rows per
+// wavefront strip (0 = fit every tile in one resident wave); lane_cols: columns per lane
+// (0 = default; 1 FP64 3-point only, 2, or 4 FP32/FP16 only).
+hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, int lane_cols, const void *src, void *dst, hipStream_t s);
+bool fd_sweep_supported(const FdArgs &a, int lane_cols);
 
 // MRT D2Q9 stream-collide (push) step.
 hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);
@@ -46,6 +48,9 @@ hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const 
                            hipStream_t s);
 hipError_t launch_mrt_moments(int dtype, const void *pop, double *dr, double *jx, double *jy, size_t n,
                               hipStream_t s);
+
+// Streaming device-to-device copy (bytes a multiple of 16, 16-byte aligned pointers).
+hipError_t launch_device_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // FP64 diagnostics: totals, kinetic energy, max |J|, non-finite count and sum J.J0.
 constexpr int DIAG_BLOCKS = 1024;

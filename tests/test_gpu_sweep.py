@@ -1,10 +1,12 @@
 """The fused sweep kernel against the reference kernel (bit for bit) and the oracle.
 
 Both kernels evaluate the same per-node arithmetic in the same order, so any difference
-is a data-movement error: a wrong lane shift, window slot, strip overlap, wrap or ghost
-row.  Shapes are chosen so that strips are partial in x (widths that are not multiples of
-the strip width), the grid can be narrower than one strip, row strips end early, and the
-tile height is varied (including heights smaller than the row window).
+is a data-movement error: a wrong lane shift, window slot, strip overlap, wrap, ghost row
+or a partial sum exchanged between the stacked wavefronts of a block.  Shapes are chosen
+so that strips are partial in x (widths that are not multiples of the strip width), the
+grid can be narrower than one strip, row bands end early (with a single leftover row
+absorbed by the wavefront below, or a band of one row), and the rows per wavefront vary
+(including fewer than the row window).
 """
 import math
 
@@ -40,18 +42,21 @@ def run(F, kernel, nx, ny, steps, init, **kw):
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("stencil", [3, 5])
 @pytest.mark.parametrize("walls", [False, True])
-@pytest.mark.parametrize("shape,tile_rows", [((296, 77), 0), ((8, 13), 5), ((520, 40), 3), ((252, 64), 16)])
-def test_sweep_equals_reference_bitwise(F, dtype, stencil, walls, shape, tile_rows):
+@pytest.mark.parametrize("shape,tile_rows", [((296, 77), 0), ((8, 13), 5), ((520, 40), 3), ((252, 64), 16),
+                                              ((24, 9), 2)])
+@pytest.mark.parametrize("wide", [False, True])
+def test_sweep_equals_reference_bitwise(F, dtype, stencil, walls, shape, tile_rows, wide):
     nx, ny = shape
-    if not walls and ny < 8:
-        pytest.skip("periodic grids need ny >= 8")
+    lane_cols = {"f64": (2, 1), "f32": (2, 4), "f16": (2, 4)}[dtype][int(wide)]
+    if lane_cols == 1 and stencil == 5:
+        lane_cols = 2
     print(f"case sweep-vs-reference dtype={dtype} stencil={stencil} walls={walls} shape={shape} "
-          f"tile_rows={tile_rows}", flush=True)
+          f"tile_rows={tile_rows} lane_cols={lane_cols}", flush=True)
     init = W.random_state(nx, ny, seed=nx + ny, amp=0.02)
     kw = dict(stencil=stencil, dtype=dtype, bc="walls" if walls else "periodic", s_xx=1.6, s_e=1.1,
               force=(2e-5, -1e-5) if walls else (0.0, 0.0))
     a = run(F, "reference", nx, ny, 9, init, **kw)
-    b = run(F, "sweep", nx, ny, 9, init, tile_rows=tile_rows, **kw)
+    b = run(F, "sweep", nx, ny, 9, init, tile_rows=tile_rows, lane_cols=lane_cols, **kw)
     for u, v in zip(a, b):
         assert np.array_equal(u, v), float(np.max(np.abs(u - v)))
 
