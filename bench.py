@@ -110,6 +110,42 @@ def measure_copy(F, torch, probe=False, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e6)
 
 
+def run_batch(F, torch, W, steps, per_instance_steps, every=10):
+    """The 512-instance shear-wave sweep: N ~ U{32..1024}, nu ~ U[0.005, 0.1], m ~ U{1..4},
+    FP32, 3-point differences; one launch per step for all instances with A(t) sampled every
+    `every` steps (graph-replayed), against one launch per instance per step."""
+    insts = W.batch_instances(512, seed=5)
+    specs = [(d["n"], d["n"], F.fdlbm_rate_from_viscosity(d["nu"]), 1.0) for d in insts]
+    b = F.FdLbmBatch(specs, dtype="f32", max_samples=(steps + 20) // every + 1)
+    for i, d in enumerate(insts):
+        b.set_state(i, *W.shear_wave_y(d["n"], d["n"], d["amp"], d["m"]))
+    nodes = sum(d["n"] * d["n"] for d in insts)
+    b.step(20, sample_every=every, use_graph=True)
+    b.stream.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps, sample_every=every, use_graph=True)
+    b.stream.synchronize()
+    graph_s = time.perf_counter() - t0
+    b.step_per_instance(4)
+    b.stream.synchronize()
+    t0 = time.perf_counter()
+    b.step_per_instance(per_instance_steps)
+    b.stream.synchronize()
+    single_s = time.perf_counter() - t0
+    nsamp = b.amplitudes().shape[1]
+    b.close()
+    return {
+        "instances": len(insts), "nodes": nodes, "sample_every": every, "samples": nsamp,
+        "graph_steps": steps, "graph_ms_per_step": round(graph_s * 1e3 / steps, 4),
+        "graph_instance_steps_per_s": round(len(insts) * steps / graph_s, 1),
+        "graph_mlups": round(nodes * steps / graph_s / 1e6, 1),
+        "per_instance_steps": per_instance_steps,
+        "per_instance_ms_per_step": round(single_s * 1e3 / per_instance_steps, 4),
+        "per_instance_instance_steps_per_s": round(len(insts) * per_instance_steps / single_s, 1),
+        "speedup": round((per_instance_steps and (single_s / per_instance_steps)) / (graph_s / steps), 3),
+    }
+
+
 def band_errors(F, O, init, n, s_steps, rows, cases, threads):
     """Relative L2 error of each GPU case after s_steps over a band of rows, against the
     FP64 oracle run on that band alone (a band of rows +- the domain of dependence
@@ -159,6 +195,8 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "reference", "sweep"])
     ap.add_argument("--no-compare", action="store_true", help="skip MRT / FP64 / FP16 / 5-point lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error bands")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch line")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--err-steps", type=int, default=12)
     ap.add_argument("--err-rows", type=int, default=512)
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wavefront strip of the sweep kernel (0 = default)")
@@ -212,6 +250,11 @@ def main():
             key = f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"
             compare[key] = run_case(F, torch, init, n, scheme, dtype, stencil, short, 10, args.kernel, False)
             print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
+
+    batch = None
+    if not args.no_batch:
+        batch = run_batch(F, torch, W, args.batch_steps, max(10, args.batch_steps // 4))
+        print(f"# batch: {batch}", file=sys.stderr, flush=True)
 
     cpu = None
     errors = None
@@ -277,6 +320,7 @@ def main():
                      "what": "fdlbm_device_copy of 1 GiB: read + write bytes / time"},
         "cpu_baseline": cpu,
         "err_vs_oracle": errors,
+        "batch_512": batch,
         "compare": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in compare.items()},
     }

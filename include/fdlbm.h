@@ -62,11 +62,11 @@ typedef struct fdlbm_params {
                          * (1/s_xx - 1/2)(1/s_q - 1/2) = 1/6 (section 3-b)                   */
     double force_x, force_y; /* uniform body force per node and step, Strang-split (section 1) */
     int32_t kernel;     /* FDLBM_KERNEL_*                                                     */
-    int32_t tile_rows;  /* sweep kernel: rows per column strip (0 = choose); tuning knob      */
+    int32_t tile_rows;  /* sweep kernel: rows per wavefront, >= 2 (0 or 1 = choose); tuning  */
     int32_t check_every;/* > 0: fdlbm_step / mrt_step scan the state for non-finite values
                          * every check_every steps and return FDLBM_EUNSTABLE if one is found
                          * (this synchronises the stream at each check)                       */
-    int32_t lane_cols;  /* sweep kernel: grid columns per lane, 0 (choose), 1 (FP64 3-point),
+    int32_t lane_cols;  /* sweep kernel: grid columns per lane, 0 (choose), 1 (3-point only),
                          * 2, or 4 (FP32 / FP16); nx must be a multiple; tuning knob          */
 } fdlbm_params;
 
@@ -144,6 +144,53 @@ int fdlbm_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream
 /* Static text for a return code, and the last HIP error text of this thread. */
 const char *fdlbm_strerror(int code);
 const char *fdlbm_last_error(void);
+
+/* ---------------------------------------------------------------------------------- */
+/* Batches: many independent periodic FD-LBM grids (3-point differences, no force) of   */
+/* different sizes and rates, advanced together.  Each instance evolves exactly as the   */
+/* same grid would in its own fdlbm_ctx (same bits).  Its correlation with its initial   */
+/* state, A(t) = <J(t), J0> / <J0, J0> (section 3-a), is reduced on the device in FP64    */
+/* every `sample_every` steps into a count x max_samples table.                           */
+/* ---------------------------------------------------------------------------------- */
+typedef struct fdlbm_instance {
+    int32_t nx, ny;    /* >= 8 each                                                    */
+    double s_xx, s_e;  /* rates in (0, 2)                                              */
+} fdlbm_instance;
+
+typedef struct fdlbm_batch fdlbm_batch;
+
+/* Sizes of the two caller-owned state buffers (each) and of the scratch buffer. */
+int fdlbm_batch_workspace_bytes(const fdlbm_instance *instances, int32_t count, int32_t dtype, int32_t max_samples,
+                                size_t *state_bytes, size_t *scratch_bytes);
+
+/* Lay out `count` instances (dtype FDLBM_F64 / F32 / F16DEV) in the caller's buffers
+ * (256-byte aligned), upload the tile tables and bind the HIP stream.  All states are
+ * zero until set.  A stream other than the default one is needed for graph replay. */
+int fdlbm_batch_create(const fdlbm_instance *instances, int32_t count, int32_t dtype, int32_t max_samples,
+                       void *state_a, void *state_b, void *scratch, size_t scratch_bytes, void *hip_stream,
+                       fdlbm_batch **out);
+
+/* Set / read instance i from host FP64 arrays (nx*ny each).  Setting a state also makes
+ * its momentum the reference J0 of instance i and clears the sample table. */
+int fdlbm_batch_set_state(fdlbm_batch *b, int32_t i, const double *drho, const double *jx, const double *jy);
+int fdlbm_batch_get_state(fdlbm_batch *b, int32_t i, double *drho, double *jx, double *jy);
+
+/* Advance every instance by nsteps (one launch per step for all instances).  With
+ * sample_every > 0 (nsteps must be a multiple), A(t) of every instance is recorded after
+ * each sample_every steps; with use_graph != 0 each chunk of sample_every steps plus its
+ * sample is captured once in a HIP graph and replayed.  Asynchronous. */
+int fdlbm_batch_step(fdlbm_batch *b, int64_t nsteps, int32_t sample_every, int32_t use_graph);
+
+/* The same steps with one launch per instance per step (the comparison path). */
+int fdlbm_batch_step_per_instance(fdlbm_batch *b, int64_t nsteps);
+
+/* Number of recorded samples in *nsamples and, if out != NULL, the count x max_samples
+ * table (row i: instance i; entries beyond *nsamples are undefined).  Synchronises. */
+int fdlbm_batch_amplitudes(fdlbm_batch *b, double *out, int32_t *nsamples);
+
+int64_t fdlbm_batch_step_count(const fdlbm_batch *b);
+void fdlbm_batch_destroy(fdlbm_batch *b);
+const char *fdlbm_batch_last_error(void);
 
 /* The transport-coefficient map of section 1-a: s = 1 / (1/2 + 3 nu). */
 double fdlbm_rate_from_viscosity(double nu);

@@ -33,6 +33,9 @@ EXPORTED = (
     "fdlbm_diagnostics", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
     "fdlbm_destroy", "fdlbm_strerror", "fdlbm_last_error", "fdlbm_rate_from_viscosity",
     "fdlbm_quartic_s_q", "fdlbm_device_copy",
+    "fdlbm_batch_workspace_bytes", "fdlbm_batch_create", "fdlbm_batch_set_state", "fdlbm_batch_get_state",
+    "fdlbm_batch_step", "fdlbm_batch_step_per_instance", "fdlbm_batch_amplitudes", "fdlbm_batch_step_count",
+    "fdlbm_batch_destroy", "fdlbm_batch_last_error",
 )
 
 
@@ -54,6 +57,10 @@ class Diag(ctypes.Structure):
         ("kin_energy", ctypes.c_double), ("max_abs_j", ctypes.c_double),
         ("proj_num", ctypes.c_double), ("proj_den", ctypes.c_double), ("nonfinite", ctypes.c_int64),
     ]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("s_xx", ctypes.c_double), ("s_e", ctypes.c_double)]
 
 
 class FdlbmError(RuntimeError):
@@ -103,6 +110,18 @@ def load_library(path=LIB_PATH):
         "fdlbm_rate_from_viscosity": (ctypes.c_double, [ctypes.c_double]),
         "fdlbm_quartic_s_q": (ctypes.c_double, [ctypes.c_double]),
         "fdlbm_device_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
+        "fdlbm_batch_workspace_bytes": (i32, [ctypes.POINTER(Instance), i32, i32, i32, ctypes.POINTER(ctypes.c_size_t),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+        "fdlbm_batch_create": (i32, [ctypes.POINTER(Instance), i32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp,
+                                     ctypes.POINTER(vp)]),
+        "fdlbm_batch_set_state": (i32, [vp, i32, dp, dp, dp]),
+        "fdlbm_batch_get_state": (i32, [vp, i32, dp, dp, dp]),
+        "fdlbm_batch_step": (i32, [vp, i64, i32, i32]),
+        "fdlbm_batch_step_per_instance": (i32, [vp, i64]),
+        "fdlbm_batch_amplitudes": (i32, [vp, dp, ctypes.POINTER(ctypes.c_int32)]),
+        "fdlbm_batch_step_count": (i64, [vp]),
+        "fdlbm_batch_destroy": (None, [vp]),
+        "fdlbm_batch_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -287,6 +306,95 @@ class FdLbm:
     def close(self):
         if getattr(self, "ctx", None) is not None:
             fdlbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------- batches ----
+
+def _instances(specs):
+    arr = (Instance * len(specs))()
+    for i, (nx, ny, s_xx, s_e) in enumerate(specs):
+        arr[i] = Instance(int(nx), int(ny), float(s_xx), float(s_e))
+    return arr
+
+
+def fdlbm_batch_workspace_bytes(specs, dtype="f32", max_samples=0):
+    arr = _instances(specs)
+    sb, cb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().fdlbm_batch_workspace_bytes(arr, len(specs), DTYPE[dtype], int(max_samples), ctypes.byref(sb),
+                                                      ctypes.byref(cb)), "fdlbm_batch_workspace_bytes")
+    return sb.value, cb.value
+
+
+class FdLbmBatch:
+    """Many independent periodic FD-LBM grids (3-point differences) advanced together.
+
+    specs: list of (nx, ny, s_xx, s_e).  Uses its own HIP stream (default priority), which
+    graph replay needs.
+    """
+
+    def __init__(self, specs, dtype="f32", max_samples=0, device="cuda"):
+        import torch
+
+        lib = load_library()
+        self.specs = [tuple(x) for x in specs]
+        self.count = len(self.specs)
+        self.max_samples = int(max_samples)
+        arr = _instances(self.specs)
+        sb, cb = fdlbm_batch_workspace_bytes(self.specs, dtype, max_samples)
+        dev = torch.device(device)
+        self._bufs = [torch.empty(b, dtype=torch.uint8, device=dev) for b in (sb, sb, cb)]
+        self.stream = torch.cuda.Stream(device=dev)
+        self.ctx = ctypes.c_void_p()
+        rc = lib.fdlbm_batch_create(arr, self.count, DTYPE[dtype], self.max_samples, self._bufs[0].data_ptr(),
+                                    self._bufs[1].data_ptr(), self._bufs[2].data_ptr(), cb, self.stream.cuda_stream,
+                                    ctypes.byref(self.ctx))
+        if rc != FDLBM_OK:
+            raise FdlbmError(rc, "fdlbm_batch_create: " + lib.fdlbm_batch_last_error().decode())
+        self.state_bytes, self.scratch_bytes = sb, cb
+
+    def _chk(self, rc, what):
+        if rc != FDLBM_OK:
+            raise FdlbmError(rc, what + ": " + load_library().fdlbm_batch_last_error().decode())
+
+    def set_state(self, i, drho, jx, jy):
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (drho, jx, jy)]
+        self._chk(load_library().fdlbm_batch_set_state(self.ctx, int(i), *[_dptr(v) for v in a]), "fdlbm_batch_set_state")
+
+    def get_state(self, i):
+        nx, ny = self.specs[i][0], self.specs[i][1]
+        out = [np.empty((ny, nx)) for _ in range(3)]
+        self._chk(load_library().fdlbm_batch_get_state(self.ctx, int(i), *[_dptr(v) for v in out]),
+                  "fdlbm_batch_get_state")
+        return tuple(out)
+
+    def step(self, nsteps, sample_every=0, use_graph=True):
+        self._chk(load_library().fdlbm_batch_step(self.ctx, int(nsteps), int(sample_every),
+                                                  int(bool(use_graph and sample_every > 0))), "fdlbm_batch_step")
+
+    def step_per_instance(self, nsteps):
+        self._chk(load_library().fdlbm_batch_step_per_instance(self.ctx, int(nsteps)), "fdlbm_batch_step_per_instance")
+
+    def amplitudes(self):
+        """(count, nsamples) array of A(t) samples."""
+        out = np.empty((self.count, max(self.max_samples, 1)))
+        n = ctypes.c_int32()
+        self._chk(load_library().fdlbm_batch_amplitudes(self.ctx, _dptr(out), ctypes.byref(n)), "fdlbm_batch_amplitudes")
+        return out[:, :n.value].copy()
+
+    @property
+    def steps(self):
+        return int(load_library().fdlbm_batch_step_count(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load_library().fdlbm_batch_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

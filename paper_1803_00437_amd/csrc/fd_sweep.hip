@@ -31,297 +31,24 @@
 //
 // Walls (rows -1 .. -(h+1) and ny .. ny+h are ghosts): the mirror of the xi = 1/2
 // extrapolation of section 3-c is applied as a row is loaded (drho even, J odd).
-#include "fdlbm_device.hpp"
+#include "fd_sweep_body.hpp"
 #include "internal.hpp"
 
 namespace fdlbm {
 namespace {
-
-constexpr int WV = 4;  // wavefronts stacked per block
-
-// whole-wave lane shifts: shl gives lane i the value of lane i+1, shr the value of lane i-1
-constexpr int DPP_WAVE_SHL1 = 0x130;
-constexpr int DPP_WAVE_SHR1 = 0x138;
-
-template <int CTRL> __device__ __forceinline__ float lane_shift(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
-}
-template <int CTRL> __device__ __forceinline__ double lane_shift(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-template <typename C> __device__ __forceinline__ C from_right(C v) { return lane_shift<DPP_WAVE_SHL1>(v); }
-template <typename C> __device__ __forceinline__ C from_left(C v) { return lane_shift<DPP_WAVE_SHR1>(v); }
-
-// CPL consecutive stored values as one memory access (4, 8 or 16 bytes).
-template <typename T, int CPL> struct Group {
-    T v[CPL];
-};
-template <int BYTES> struct Word;
-template <> struct Word<4> { using type = unsigned int; };
-template <> struct Word<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
-template <> struct Word<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
-
-template <typename T, int CPL> __device__ __forceinline__ Group<T, CPL> load_group(const T *p)
-{
-    static_assert(sizeof(Group<T, CPL>) == sizeof(T) * CPL, "packed group");
-    using Wd = typename Word<sizeof(T) * CPL>::type;
-    return __builtin_bit_cast(Group<T, CPL>, *reinterpret_cast<const Wd *>(p));
-}
-template <typename T, int CPL> __device__ __forceinline__ void store_group(T *p, const Group<T, CPL> &g)
-{
-    using Wd = typename Word<sizeof(T) * CPL>::type;
-    __builtin_nontemporal_store(__builtin_bit_cast(Wd, g), reinterpret_cast<Wd *>(p));
-}
-
-// Strip geometry: a strip loads W columns starting at s*S - P and stores the S = W - 2P
-// columns [s*S, s*S + S), where P = h+1 rounded up to whole lanes.
-template <int CPL, int H> struct Strip {
-    static constexpr int W = 64 * CPL;
-    static constexpr int P = ((H + 1 + CPL - 1) / CPL) * CPL;
-    static constexpr int S = W - 2 * P;
-};
+using namespace sweep;
 
 template <typename T> struct SweepArgs {
-    const T *dr, *jx, *jy;
-    T *odr, *ojx, *ojy;
-    int nx, ny, rows, strips_x, nbands, nblocks;
-    FdCoef<typename Storage<T>::C> k;
+    TileArgs<T> t;
+    int strips_x;
 };
-
-// LDS slots per wavefront, each CPL x 64 values: the partial sums a wavefront publishes
-// for its neighbours, and the ones it keeps for its own first output row.
-enum { PUB_DN = 0, PUB_DNX, PUB_UP, PUB_UPX, OWN_CEN, OWN_CENX, OWN_DN, OWN_DNX, NSLOT };
 
 template <typename T, int CPL, int ST, bool WALLS>
 __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 {
-    using C = typename Storage<T>::C;
-    using S = Stencil<ST>;
-    constexpr int H = S::H;
-    constexpr int NW = 2 * H + 1;  // rows in the input window
-    using G = Strip<CPL, H>;
-    static_assert(CPL >= 2 || H == 1, "5-point differences need two columns per lane");
-    __shared__ C lds[WV][NSLOT][CPL][64];
-
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // blocks dealt out row band after row band (uniform over the block)
+    // blocks dealt out row band after row band
     const int band = blockIdx.x / a.strips_x;
-    const int sx = blockIdx.x - band * a.strips_x;
-    const int nx = a.nx, ny = a.ny;
-    const int xl = sx * G::S - G::P + CPL * lane;  // first column of this lane (unwrapped)
-    const int col = ((xl % nx) + nx) % nx;          // wrapped (x periodic)
-    const bool store_ok = CPL * lane >= G::P && CPL * lane < G::P + G::S && xl < nx;
-
-    // rows of this wavefront: R each; a single leftover row at the end of the band is
-    // absorbed by the wavefront below it, so every non-empty wavefront has >= 2 rows
-    // unless the whole band has one row
-    const int b0 = band * WV * a.rows, b1 = min(b0 + WV * a.rows, ny);
-    const int ybeg = b0 + wv * a.rows;
-    int yend = min(ybeg + a.rows, b1);
-    if (b1 - yend == 1) yend = b1;
-    const bool empty = ybeg >= b1 || (wv > 0 && b1 - ybeg == 1);
-    const bool bottom = wv == 0;  // computes f* of row ybeg - 1 itself
-    const bool top = yend == b1;  // computes f* of row yend itself
-    const int rb = bottom ? ybeg - 1 : ybeg;
-    const int re = top ? yend : yend - 1;
-    const int nf = empty ? 0 : re - rb + 1;  // rows whose f* this wavefront computes
-    const int row0 = rb - H;                 // first input row
-
-    // rolling window of input rows: drho, J_a = J + F/2 and the products Jx^2, JxJy, Jy^2
-    C w[6][NW][CPL];
-    Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
-    C ps = C(1);               // its sign (-1: ghost row beyond a wall)
-
-    auto fetch = [&](int j) {
-        int src = j;
-        C sgn = C(1);
-        if (WALLS) {
-            if (j < 0) { src = -1 - j; sgn = C(-1); }
-            else if (j >= ny) { src = 2 * ny - 1 - j; sgn = C(-1); }
-        } else {
-            src = j < 0 ? j + ny : (j >= ny ? j - ny : j);
-        }
-        const size_t off = (size_t)src * (size_t)nx + (size_t)col;
-        pr = load_group<T, CPL>(a.dr + off);
-        px = load_group<T, CPL>(a.jx + off);
-        py = load_group<T, CPL>(a.jy + off);
-        ps = sgn;
-    };
-    auto insert = [&](int wslot) {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const C x = fmac(ps, Storage<T>::load(px.v[c]), a.k.hfx);
-            const C y = fmac(ps, Storage<T>::load(py.v[c]), a.k.hfy);
-            w[0][wslot][c] = Storage<T>::load(pr.v[c]);
-            w[1][wslot][c] = x;
-            w[2][wslot][c] = y;
-            w[3][wslot][c] = x * x;
-            w[4][wslot][c] = x * y;
-            w[5][wslot][c] = y * y;
-        }
-    };
-
-    // partial sums carried between rows (order of fd_gather): A = cen(r-1) + up(r-2),
-    // AX = cenx(r-1) + upx(r-2), UP = up(r-2); UPp, UPXp = up(r-1), upx(r-1)
-    C A[CPL], AX[CPL], UP[CPL], UPp[CPL], UPXp[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) A[c] = AX[c] = UP[c] = UPp[c] = UPXp[c] = C(0);
-
-    if (nf > 0) {
-        // prologue: the first 2H input rows, then the prefetch of the next one
-#pragma unroll
-        for (int r = 0; r < 2 * H; ++r) {
-            fetch(row0 + r);
-            insert(r);
-        }
-        fetch(row0 + 2 * H);
-    }
-
-    // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
-    // y-derivative fields (drho, Jy, Jx, JxJy, Jy^2) -> d[1], d[3], d[5], d[7], d[9]
-    constexpr int XF[5] = {0, 1, 2, 3, 4};
-    constexpr int YF[5] = {0, 2, 1, 4, 5};
-
-    for (int it0 = 0; it0 < nf; it0 += NW) {
-#pragma unroll
-        for (int ph = 0; ph < NW; ++ph) {
-            const int it = it0 + ph;
-            if (it >= nf) break;
-            insert((ph + 2 * H) % NW);
-            if (it + 1 < nf) fetch(row0 + 2 * H + it + 1);
-
-            const int cs = (ph + H) % NW;  // window slot of the row whose f* is computed
-            // x-neighbours of the lane's outer columns, from the adjacent lanes
-            C xl1[5], xr1[5], xl2[5], xr2[5];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                xl1[q] = from_left(w[XF[q]][cs][CPL - 1]);
-                xr1[q] = from_right(w[XF[q]][cs][0]);
-                xl2[q] = H == 2 ? from_left(w[XF[q]][cs][CPL >= 2 ? CPL - 2 : 0]) : C(0);
-                xr2[q] = H == 2 ? from_right(w[XF[q]][cs][CPL > 1 ? 1 : 0]) : C(0);
-            }
-            C f[CPL][9];
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                C d[10];
-#pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    const int fx = XF[q], fy = YF[q];
-                    const C m1 = c > 0 ? w[fx][cs][c > 0 ? c - 1 : 0] : xl1[q];
-                    const C p1 = c < CPL - 1 ? w[fx][cs][c < CPL - 1 ? c + 1 : 0] : xr1[q];
-                    C m2 = C(0), p2 = C(0), ym2 = C(0), yp2 = C(0);
-                    if (H == 2) {
-                        m2 = c >= 2 ? w[fx][cs][c >= 2 ? c - 2 : 0] : (c == 1 ? xl1[q] : xl2[q]);
-                        p2 = c + 2 < CPL ? w[fx][cs][c + 2 < CPL ? c + 2 : 0] : (c + 2 == CPL ? xr1[q] : xr2[q]);
-                        ym2 = w[fy][ph % NW][c];
-                        yp2 = w[fy][(ph + 2 * H) % NW][c];
-                    }
-                    d[2 * q] = S::diff(m2, m1, p1, p2);
-                    d[2 * q + 1] = S::diff(ym2, w[fy][(ph + H - 1) % NW][c], w[fy][(ph + H + 1) % NW][c], yp2);
-                }
-                fd_node_fstar<C>(w[0][cs][c], w[1][cs][c], w[2][cs][c], d, a.k, f[c]);
-            }
-            // populations moving along +x come from the column on the left, along -x from
-            // the column on the right
-            const C f1l = from_left(f[CPL - 1][1]), f5l = from_left(f[CPL - 1][5]), f8l = from_left(f[CPL - 1][8]);
-            const C f3r = from_right(f[0][3]), f6r = from_right(f[0][6]), f7r = from_right(f[0][7]);
-            Group<T, CPL> gr, gx, gy;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int cl = c > 0 ? c - 1 : 0, cr = c < CPL - 1 ? c + 1 : 0;
-                const C c1 = c > 0 ? f[cl][1] : f1l;
-                const C u5 = c > 0 ? f[cl][5] : f5l;
-                const C d8 = c > 0 ? f[cl][8] : f8l;
-                const C c3 = c < CPL - 1 ? f[cr][3] : f3r;
-                const C u6 = c < CPL - 1 ? f[cr][6] : f6r;
-                const C d7 = c < CPL - 1 ? f[cr][7] : f7r;
-                const C cen = (f[c][0] + c1) + c3, cenx = c1 - c3;
-                const C up = (f[c][2] + u5) + u6, upx = u5 - u6;
-                const C dn = (f[c][4] + d8) + d7, dnx = d8 - d7;
-                if (!bottom && it == 0) {
-                    // f* of the first row: its downward part completes the last output row
-                    // of the wavefront below; its own row still lacks the part sent up by
-                    // that wavefront
-                    lds[wv][PUB_DN][c][lane] = dn;
-                    lds[wv][PUB_DNX][c][lane] = dnx;
-                    lds[wv][OWN_CEN][c][lane] = cen;
-                    lds[wv][OWN_CENX][c][lane] = cenx;
-                }
-                if (!bottom && it == 1) {
-                    lds[wv][OWN_DN][c][lane] = dn;
-                    lds[wv][OWN_DNX][c][lane] = dnx;
-                }
-                // output row r-1 = (cen(r-1) + up(r-2)) + dn(r)
-                gr.v[c] = Storage<T>::store(A[c] + dn);
-                gx.v[c] = Storage<T>::store(AX[c] + dnx);
-                gy.v[c] = Storage<T>::store(UP[c] - dn);
-                A[c] = cen + UPp[c];
-                AX[c] = cenx + UPXp[c];
-                UP[c] = UPp[c];
-                UPp[c] = up;
-                UPXp[c] = upx;
-            }
-            // output row rb + it - 1 is complete once f* of rows rb + it - 2 .. rb + it are known
-            if (it >= 2 && store_ok) {
-                const size_t off = (size_t)(rb + it - 1) * (size_t)nx + (size_t)col;
-                store_group<T, CPL>(a.odr + off, gr);
-                store_group<T, CPL>(a.ojx + off, gx);
-                store_group<T, CPL>(a.ojy + off, gy);
-            }
-        }
-    }
-    if (!top && !empty) {
-        // the upward part of the last f* row completes the first output row of the
-        // wavefront above
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            lds[wv][PUB_UP][c][lane] = UPp[c];
-            lds[wv][PUB_UPX][c][lane] = UPXp[c];
-        }
-    }
-    __syncthreads();
-    if (empty) return;
-    if (!bottom) {
-        // first output row: (cen + up from the wavefront below) + dn
-        Group<T, CPL> gr, gx, gy;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const C up = lds[wv - 1][PUB_UP][c][lane], upx = lds[wv - 1][PUB_UPX][c][lane];
-            const C dn = lds[wv][OWN_DN][c][lane], dnx = lds[wv][OWN_DNX][c][lane];
-            gr.v[c] = Storage<T>::store((lds[wv][OWN_CEN][c][lane] + up) + dn);
-            gx.v[c] = Storage<T>::store((lds[wv][OWN_CENX][c][lane] + upx) + dnx);
-            gy.v[c] = Storage<T>::store(up - dn);
-        }
-        if (store_ok) {
-            const size_t off = (size_t)ybeg * (size_t)nx + (size_t)col;
-            store_group<T, CPL>(a.odr + off, gr);
-            store_group<T, CPL>(a.ojx + off, gx);
-            store_group<T, CPL>(a.ojy + off, gy);
-        }
-    }
-    if (!top) {
-        // last output row: (cen + up) carried + dn from the wavefront above
-        Group<T, CPL> gr, gx, gy;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const C dn = lds[wv + 1][PUB_DN][c][lane], dnx = lds[wv + 1][PUB_DNX][c][lane];
-            gr.v[c] = Storage<T>::store(A[c] + dn);
-            gx.v[c] = Storage<T>::store(AX[c] + dnx);
-            gy.v[c] = Storage<T>::store(UP[c] - dn);
-        }
-        if (store_ok) {
-            const size_t off = (size_t)(yend - 1) * (size_t)nx + (size_t)col;
-            store_group<T, CPL>(a.odr + off, gr);
-            store_group<T, CPL>(a.ojx + off, gx);
-            store_group<T, CPL>(a.ojy + off, gy);
-        }
-    }
+    sweep_tile<T, CPL, ST, WALLS>(a.t, band, blockIdx.x - band * a.strips_x);
 }
 
 template <typename T, int CPL, int ST, bool WALLS>
@@ -333,29 +60,20 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     SweepArgs<T> a;
     const T *in = static_cast<const T *>(src);
     T *out = static_cast<T *>(dst);
-    a.dr = in;
-    a.jx = in + n;
-    a.jy = in + 2 * n;
-    a.odr = out;
-    a.ojx = out + n;
-    a.ojy = out + 2 * n;
-    a.nx = fa.nx;
-    a.ny = fa.ny;
+    a.t.dr = in;
+    a.t.jx = in + n;
+    a.t.jy = in + 2 * n;
+    a.t.odr = out;
+    a.t.ojx = out + n;
+    a.t.ojy = out + 2 * n;
+    a.t.nx = fa.nx;
+    a.t.ny = fa.ny;
+    // rows per wavefront (>= 2, see the tile body); 8 measured best at 8192^2
+    a.t.rows = tile_rows >= 2 ? tile_rows : 8;
+    a.t.k = make_coef<C>(ST, fa.s_xx, fa.s_e, fa.fx, fa.fy);
     a.strips_x = (fa.nx + G::S - 1) / G::S;
-    // rows per wavefront (>= 2, see the kernel); 8 measured best at 8192^2
-    a.rows = tile_rows >= 2 ? tile_rows : 8;
-    a.nbands = (fa.ny + WV * a.rows - 1) / (WV * a.rows);
-    a.nblocks = a.strips_x * a.nbands;
-    const double scale = ST == 3 ? Stencil<3>::SCALE : Stencil<5>::SCALE;
-    a.k.ke = C(scale * (1.0 - 1.0 / fa.s_e));
-    a.k.kxx = C(scale * (1.0 - 1.0 / fa.s_xx));
-    a.k.hfx = C(0.5 * fa.fx);
-    a.k.hfy = C(0.5 * fa.fy);
-    a.k.qfx = C(0.25 * fa.fx);
-    a.k.qfy = C(0.25 * fa.fy);
-    a.k.dfx = C(fa.fx);
-    a.k.dfy = C(fa.fy);
-    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS>), a.nblocks, 64 * WV, 0, s, a);
+    const int nbands = (fa.ny + WV * a.t.rows - 1) / (WV * a.t.rows);
+    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS>), a.strips_x * nbands, 64 * WV, 0, s, a);
     return hipGetLastError();
 }
 
@@ -372,20 +90,21 @@ hipError_t dispatch_cpl(const FdArgs &a, int tile_rows, const void *src, void *d
 }
 
 // Columns per lane (measured at 8192^2): FP32 4 (16-byte accesses), FP16 2 (4-byte
-// accesses, fewer live registers), FP64 2 (16-byte accesses).
+// accesses, fewer live registers), FP64 2 (16-byte accesses); narrower when nx is not a
+// multiple (1 is available for 3-point differences only).
 int choose_cpl(const FdArgs &a, int lane_cols)
 {
     if (lane_cols > 0) return lane_cols;
-    return a.dtype == FDLBM_F32 ? 4 : 2;
+    int c = a.dtype == FDLBM_F32 ? 4 : 2;
+    while (c > 1 && a.nx % c) c /= 2;
+    return c;
 }
 
 template <typename T>
 hipError_t dispatch(const FdArgs &a, int tile_rows, int lane_cols, const void *src, void *dst, hipStream_t s)
 {
     switch (choose_cpl(a, lane_cols)) {
-    case 1:
-        if constexpr (sizeof(T) == 8) return dispatch_cpl<T, 1>(a, tile_rows, src, dst, s);
-        return hipErrorInvalidValue;
+    case 1: return dispatch_cpl<T, 1>(a, tile_rows, src, dst, s);
     case 2: return dispatch_cpl<T, 2>(a, tile_rows, src, dst, s);
     case 4:
         if constexpr (sizeof(T) != 8) return dispatch_cpl<T, 4>(a, tile_rows, src, dst, s);
@@ -401,7 +120,7 @@ bool fd_sweep_supported(const FdArgs &a, int lane_cols)
     const int cpl = choose_cpl(a, lane_cols);
     const bool f64 = a.dtype == FDLBM_F64;
     if (a.stencil != 3 && a.stencil != 5) return false;
-    if (cpl == 1) return f64 && a.stencil == 3;
+    if (cpl == 1) return a.stencil == 3;
     if (cpl == 4 && f64) return false;
     if (cpl != 2 && cpl != 4) return false;
     return a.nx % cpl == 0;

@@ -1,0 +1,322 @@
+// Body of the fused FD-LBM sweep: one block of WV stacked wavefronts updating one tile
+// (a strip of 64*CPL columns by WV*R rows) of one grid.  Shared by the single-grid kernel
+// (fd_sweep.hip) and the multi-instance kernel (fd_batch.hip), so that both produce the
+// same bits as the reference path.  See fd_sweep.hip for the mapping.
+#pragma once
+
+#include "fdlbm_device.hpp"
+
+namespace fdlbm {
+namespace sweep {
+
+
+constexpr int WV = 4;  // wavefronts stacked per block
+
+// whole-wave lane shifts: shl gives lane i the value of lane i+1, shr the value of lane i-1
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL> __device__ __forceinline__ float lane_shift(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double lane_shift(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename C> __device__ __forceinline__ C from_right(C v) { return lane_shift<DPP_WAVE_SHL1>(v); }
+template <typename C> __device__ __forceinline__ C from_left(C v) { return lane_shift<DPP_WAVE_SHR1>(v); }
+
+// CPL consecutive stored values as one memory access (2, 4, 8 or 16 bytes).
+template <typename T, int CPL> struct Group {
+    T v[CPL];
+};
+template <int BYTES> struct Word;
+template <> struct Word<2> { using type = unsigned short; };
+template <> struct Word<4> { using type = unsigned int; };
+template <> struct Word<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
+template <> struct Word<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+
+template <typename T, int CPL> __device__ __forceinline__ Group<T, CPL> load_group(const T *p)
+{
+    static_assert(sizeof(Group<T, CPL>) == sizeof(T) * CPL, "packed group");
+    using Wd = typename Word<sizeof(T) * CPL>::type;
+    return __builtin_bit_cast(Group<T, CPL>, *reinterpret_cast<const Wd *>(p));
+}
+template <typename T, int CPL> __device__ __forceinline__ void store_group(T *p, const Group<T, CPL> &g)
+{
+    using Wd = typename Word<sizeof(T) * CPL>::type;
+    __builtin_nontemporal_store(__builtin_bit_cast(Wd, g), reinterpret_cast<Wd *>(p));
+}
+
+// Strip geometry: a strip loads W columns starting at s*S - P and stores the S = W - 2P
+// columns [s*S, s*S + S), where P = h+1 rounded up to whole lanes.
+template <int CPL, int H> struct Strip {
+    static constexpr int W = 64 * CPL;
+    static constexpr int P = ((H + 1 + CPL - 1) / CPL) * CPL;
+    static constexpr int S = W - 2 * P;
+};
+
+// One grid as a tile sees it: input and output planes, size, rows per wavefront and the
+// reconstruction constants.
+template <typename T> struct TileArgs {
+    const T *dr, *jx, *jy;
+    T *odr, *ojx, *ojy;
+    int nx, ny, rows;
+    FdCoef<typename Storage<T>::C> k;
+};
+
+// LDS slots per wavefront, each CPL x 64 values: the partial sums a wavefront publishes
+// for its neighbours, and the ones it keeps for its own first output row.
+enum { PUB_DN = 0, PUB_DNX, PUB_UP, PUB_UPX, OWN_CEN, OWN_CENX, OWN_DN, OWN_DNX, NSLOT };
+
+// One tile: the block's WV wavefronts over column strip sx and row band `band` of one
+// grid.  Called by every wavefront of the block (it contains a block barrier).
+template <typename T, int CPL, int ST, bool WALLS>
+__device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int sx)
+{
+    using C = typename Storage<T>::C;
+    using S = Stencil<ST>;
+    constexpr int H = S::H;
+    constexpr int NW = 2 * H + 1;  // rows in the input window
+    using G = Strip<CPL, H>;
+    static_assert(CPL >= 2 || H == 1, "5-point differences need two columns per lane");
+    __shared__ C lds[WV][NSLOT][CPL][64];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nx = a.nx, ny = a.ny;
+    const int xl = sx * G::S - G::P + CPL * lane;  // first column of this lane (unwrapped)
+    const int col = ((xl % nx) + nx) % nx;          // wrapped (x periodic)
+    const bool store_ok = CPL * lane >= G::P && CPL * lane < G::P + G::S && xl < nx;
+
+    // rows of this wavefront: R each; a single leftover row at the end of the band is
+    // absorbed by the wavefront below it, so every non-empty wavefront has >= 2 rows
+    // unless the whole band has one row
+    const int b0 = band * WV * a.rows, b1 = min(b0 + WV * a.rows, ny);
+    const int ybeg = b0 + wv * a.rows;
+    int yend = min(ybeg + a.rows, b1);
+    if (b1 - yend == 1) yend = b1;
+    const bool empty = ybeg >= b1 || (wv > 0 && b1 - ybeg == 1);
+    const bool bottom = wv == 0;  // computes f* of row ybeg - 1 itself
+    const bool top = yend == b1;  // computes f* of row yend itself
+    const int rb = bottom ? ybeg - 1 : ybeg;
+    const int re = top ? yend : yend - 1;
+    const int nf = empty ? 0 : re - rb + 1;  // rows whose f* this wavefront computes
+    const int row0 = rb - H;                 // first input row
+
+    // rolling window of input rows: drho, J_a = J + F/2 and the products Jx^2, JxJy, Jy^2
+    C w[6][NW][CPL];
+    Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
+    C ps = C(1);               // its sign (-1: ghost row beyond a wall)
+
+    auto fetch = [&](int j) {
+        int src = j;
+        C sgn = C(1);
+        if (WALLS) {
+            if (j < 0) { src = -1 - j; sgn = C(-1); }
+            else if (j >= ny) { src = 2 * ny - 1 - j; sgn = C(-1); }
+        } else {
+            src = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+        }
+        const size_t off = (size_t)src * (size_t)nx + (size_t)col;
+        pr = load_group<T, CPL>(a.dr + off);
+        px = load_group<T, CPL>(a.jx + off);
+        py = load_group<T, CPL>(a.jy + off);
+        ps = sgn;
+    };
+    auto insert = [&](int wslot) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const C x = fmac(ps, Storage<T>::load(px.v[c]), a.k.hfx);
+            const C y = fmac(ps, Storage<T>::load(py.v[c]), a.k.hfy);
+            w[0][wslot][c] = Storage<T>::load(pr.v[c]);
+            w[1][wslot][c] = x;
+            w[2][wslot][c] = y;
+            w[3][wslot][c] = x * x;
+            w[4][wslot][c] = x * y;
+            w[5][wslot][c] = y * y;
+        }
+    };
+
+    // partial sums carried between rows (order of fd_gather): A = cen(r-1) + up(r-2),
+    // AX = cenx(r-1) + upx(r-2), UP = up(r-2); UPp, UPXp = up(r-1), upx(r-1)
+    C A[CPL], AX[CPL], UP[CPL], UPp[CPL], UPXp[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) A[c] = AX[c] = UP[c] = UPp[c] = UPXp[c] = C(0);
+
+    if (nf > 0) {
+        // prologue: the first 2H input rows, then the prefetch of the next one
+#pragma unroll
+        for (int r = 0; r < 2 * H; ++r) {
+            fetch(row0 + r);
+            insert(r);
+        }
+        fetch(row0 + 2 * H);
+    }
+
+    // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
+    // y-derivative fields (drho, Jy, Jx, JxJy, Jy^2) -> d[1], d[3], d[5], d[7], d[9]
+    constexpr int XF[5] = {0, 1, 2, 3, 4};
+    constexpr int YF[5] = {0, 2, 1, 4, 5};
+
+    for (int it0 = 0; it0 < nf; it0 += NW) {
+#pragma unroll
+        for (int ph = 0; ph < NW; ++ph) {
+            const int it = it0 + ph;
+            if (it >= nf) break;
+            insert((ph + 2 * H) % NW);
+            if (it + 1 < nf) fetch(row0 + 2 * H + it + 1);
+
+            const int cs = (ph + H) % NW;  // window slot of the row whose f* is computed
+            // x-neighbours of the lane's outer columns, from the adjacent lanes
+            C xl1[5], xr1[5], xl2[5], xr2[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                xl1[q] = from_left(w[XF[q]][cs][CPL - 1]);
+                xr1[q] = from_right(w[XF[q]][cs][0]);
+                xl2[q] = H == 2 ? from_left(w[XF[q]][cs][CPL >= 2 ? CPL - 2 : 0]) : C(0);
+                xr2[q] = H == 2 ? from_right(w[XF[q]][cs][CPL > 1 ? 1 : 0]) : C(0);
+            }
+            C f[CPL][9];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                C d[10];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const int fx = XF[q], fy = YF[q];
+                    const C m1 = c > 0 ? w[fx][cs][c > 0 ? c - 1 : 0] : xl1[q];
+                    const C p1 = c < CPL - 1 ? w[fx][cs][c < CPL - 1 ? c + 1 : 0] : xr1[q];
+                    C m2 = C(0), p2 = C(0), ym2 = C(0), yp2 = C(0);
+                    if (H == 2) {
+                        m2 = c >= 2 ? w[fx][cs][c >= 2 ? c - 2 : 0] : (c == 1 ? xl1[q] : xl2[q]);
+                        p2 = c + 2 < CPL ? w[fx][cs][c + 2 < CPL ? c + 2 : 0] : (c + 2 == CPL ? xr1[q] : xr2[q]);
+                        ym2 = w[fy][ph % NW][c];
+                        yp2 = w[fy][(ph + 2 * H) % NW][c];
+                    }
+                    d[2 * q] = S::diff(m2, m1, p1, p2);
+                    d[2 * q + 1] = S::diff(ym2, w[fy][(ph + H - 1) % NW][c], w[fy][(ph + H + 1) % NW][c], yp2);
+                }
+                fd_node_fstar<C>(w[0][cs][c], w[1][cs][c], w[2][cs][c], d, a.k, f[c]);
+            }
+            // populations moving along +x come from the column on the left, along -x from
+            // the column on the right
+            const C f1l = from_left(f[CPL - 1][1]), f5l = from_left(f[CPL - 1][5]), f8l = from_left(f[CPL - 1][8]);
+            const C f3r = from_right(f[0][3]), f6r = from_right(f[0][6]), f7r = from_right(f[0][7]);
+            Group<T, CPL> gr, gx, gy;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int cl = c > 0 ? c - 1 : 0, cr = c < CPL - 1 ? c + 1 : 0;
+                const C c1 = c > 0 ? f[cl][1] : f1l;
+                const C u5 = c > 0 ? f[cl][5] : f5l;
+                const C d8 = c > 0 ? f[cl][8] : f8l;
+                const C c3 = c < CPL - 1 ? f[cr][3] : f3r;
+                const C u6 = c < CPL - 1 ? f[cr][6] : f6r;
+                const C d7 = c < CPL - 1 ? f[cr][7] : f7r;
+                const C cen = (f[c][0] + c1) + c3, cenx = c1 - c3;
+                const C up = (f[c][2] + u5) + u6, upx = u5 - u6;
+                const C dn = (f[c][4] + d8) + d7, dnx = d8 - d7;
+                if (!bottom && it == 0) {
+                    // f* of the first row: its downward part completes the last output row
+                    // of the wavefront below; its own row still lacks the part sent up by
+                    // that wavefront
+                    lds[wv][PUB_DN][c][lane] = dn;
+                    lds[wv][PUB_DNX][c][lane] = dnx;
+                    lds[wv][OWN_CEN][c][lane] = cen;
+                    lds[wv][OWN_CENX][c][lane] = cenx;
+                }
+                if (!bottom && it == 1) {
+                    lds[wv][OWN_DN][c][lane] = dn;
+                    lds[wv][OWN_DNX][c][lane] = dnx;
+                }
+                // output row r-1 = (cen(r-1) + up(r-2)) + dn(r)
+                gr.v[c] = Storage<T>::store(A[c] + dn);
+                gx.v[c] = Storage<T>::store(AX[c] + dnx);
+                gy.v[c] = Storage<T>::store(UP[c] - dn);
+                A[c] = cen + UPp[c];
+                AX[c] = cenx + UPXp[c];
+                UP[c] = UPp[c];
+                UPp[c] = up;
+                UPXp[c] = upx;
+            }
+            // output row rb + it - 1 is complete once f* of rows rb + it - 2 .. rb + it are known
+            if (it >= 2 && store_ok) {
+                const size_t off = (size_t)(rb + it - 1) * (size_t)nx + (size_t)col;
+                store_group<T, CPL>(a.odr + off, gr);
+                store_group<T, CPL>(a.ojx + off, gx);
+                store_group<T, CPL>(a.ojy + off, gy);
+            }
+        }
+    }
+    if (!top && !empty) {
+        // the upward part of the last f* row completes the first output row of the
+        // wavefront above
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            lds[wv][PUB_UP][c][lane] = UPp[c];
+            lds[wv][PUB_UPX][c][lane] = UPXp[c];
+        }
+    }
+    __syncthreads();
+    if (empty) return;
+    if (!bottom) {
+        // first output row: (cen + up from the wavefront below) + dn
+        Group<T, CPL> gr, gx, gy;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const C up = lds[wv - 1][PUB_UP][c][lane], upx = lds[wv - 1][PUB_UPX][c][lane];
+            const C dn = lds[wv][OWN_DN][c][lane], dnx = lds[wv][OWN_DNX][c][lane];
+            gr.v[c] = Storage<T>::store((lds[wv][OWN_CEN][c][lane] + up) + dn);
+            gx.v[c] = Storage<T>::store((lds[wv][OWN_CENX][c][lane] + upx) + dnx);
+            gy.v[c] = Storage<T>::store(up - dn);
+        }
+        if (store_ok) {
+            const size_t off = (size_t)ybeg * (size_t)nx + (size_t)col;
+            store_group<T, CPL>(a.odr + off, gr);
+            store_group<T, CPL>(a.ojx + off, gx);
+            store_group<T, CPL>(a.ojy + off, gy);
+        }
+    }
+    if (!top) {
+        // last output row: (cen + up) carried + dn from the wavefront above
+        Group<T, CPL> gr, gx, gy;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const C dn = lds[wv + 1][PUB_DN][c][lane], dnx = lds[wv + 1][PUB_DNX][c][lane];
+            gr.v[c] = Storage<T>::store(A[c] + dn);
+            gx.v[c] = Storage<T>::store(AX[c] + dnx);
+            gy.v[c] = Storage<T>::store(UP[c] - dn);
+        }
+        if (store_ok) {
+            const size_t off = (size_t)(yend - 1) * (size_t)nx + (size_t)col;
+            store_group<T, CPL>(a.odr + off, gr);
+            store_group<T, CPL>(a.ojx + off, gx);
+            store_group<T, CPL>(a.ojy + off, gy);
+        }
+    }
+}
+
+
+// Host-side strip width of a (dtype, CPL, stencil) combination.
+template <int CPL, int H> constexpr int strip_stride() { return Strip<CPL, H>::S; }
+
+template <typename C> inline FdCoef<C> make_coef(int stencil, double s_xx, double s_e, double fx, double fy)
+{
+    const double scale = stencil == 3 ? Stencil<3>::SCALE : Stencil<5>::SCALE;
+    FdCoef<C> k;
+    k.ke = C(scale * (1.0 - 1.0 / s_e));
+    k.kxx = C(scale * (1.0 - 1.0 / s_xx));
+    k.hfx = C(0.5 * fx);
+    k.hfy = C(0.5 * fy);
+    k.qfx = C(0.25 * fx);
+    k.qfy = C(0.25 * fy);
+    k.dfx = C(fx);
+    k.dfy = C(fy);
+    return k;
+}
+
+}  // namespace sweep
+}  // namespace fdlbm

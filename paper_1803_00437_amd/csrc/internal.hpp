@@ -37,6 +37,37 @@ size_t fd_reference_scratch_bytes(const FdArgs &a);
 hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, int lane_cols, const void *src, void *dst, hipStream_t s);
 bool fd_sweep_supported(const FdArgs &a, int lane_cols);
 
+// Batch of independent periodic FD-LBM grids (3-point differences) -------------------
+constexpr int BATCH_CHUNK = 65536;  // nodes per block of the A(t) reduction
+struct BatchInstance {
+    size_t offset;       // element offset of the instance's drho plane in the state buffers
+    size_t mode_offset;  // element offset of its J0 planes (jx, jy) in the mode buffer
+    int nx, ny, strips_x, nbands;
+    int first_chunk, nchunks;
+    double ke, kxx;      // (1 - 1/s_e) / 2 and (1 - 1/s_xx) / 2 (3-point scale folded in)
+};
+struct BatchBlock {
+    int instance, tile;
+};
+struct BatchChunk {
+    int instance, chunk;
+};
+struct BatchLaunch {
+    int dtype, count, rows, nblocks, nchunks, max_samples;
+    const BatchInstance *inst;
+    const BatchBlock *blocks;
+    const BatchChunk *chunks;
+    const void *mode;
+    double *partials;
+    int *counter;
+    double *amps;
+};
+int batch_strip_stride();
+int batch_rows_per_block(int rows);
+hipError_t launch_batch_step(const BatchLaunch &L, const void *src, void *dst, hipStream_t s);
+hipError_t launch_batch_single(const BatchLaunch &L, int i, int nblocks, const void *src, void *dst, hipStream_t s);
+hipError_t launch_batch_sample(const BatchLaunch &L, const void *state, hipStream_t s);
+
 // MRT D2Q9 stream-collide (push) step.
 hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);
 

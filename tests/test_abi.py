@@ -96,3 +96,15 @@ def test_strerror():
     lib = F.load_library()
     for code in (0, -1, -2, -3, -4):
         assert lib.fdlbm_strerror(code)
+
+
+def test_batch_workspace_and_validation():
+    specs = [(33, 40, 1.6, 1.0), (64, 64, 1.2, 1.1)]
+    sb, cb = F.fdlbm_batch_workspace_bytes(specs, "f32", 10)
+    assert sb >= 3 * (33 * 40 + 64 * 64) * 4 and sb % 256 == 0 and cb > 0
+    for bad in ([(4, 40, 1.6, 1.0)], [(33, 40, 2.0, 1.0)], [(33, 40, 1.6, 0.0)]):
+        with pytest.raises(F.FdlbmError) as e:
+            F.fdlbm_batch_workspace_bytes(bad, "f32", 10)
+        assert e.value.code == F.FDLBM_EINVAL
+    with pytest.raises(F.FdlbmError):
+        F.fdlbm_batch_workspace_bytes(specs, "f32", -1)
