@@ -45,7 +45,10 @@ enum { FDLBM_BC_PERIODIC = 0, FDLBM_BC_WALLS_Y = 1 };
  * arithmetic.  F16DEV: FP16 storage of the deviations (drho, jx, jy), FP32 arithmetic
  * (FD-LBM only).  Diagnostics are always reduced in FP64. */
 enum { FDLBM_F64 = 0, FDLBM_F32 = 1, FDLBM_F16DEV = 2 };
-/* FD-LBM kernel selection: AUTO picks the fused sweep kernel. */
+/* Kernel selection.  AUTO picks the vectorised sweep kernels (FD-LBM: one fused pass per
+ * step; MRT: lane groups with DPP column shifts).  REFERENCE: the plain kernels (FD-LBM:
+ * post-collision planes then gather; MRT: one thread per node).  SWEEP: FD-LBM sweep
+ * kernel, rejected if the grid width does not allow it. */
 enum { FDLBM_KERNEL_AUTO = 0, FDLBM_KERNEL_REFERENCE = 1, FDLBM_KERNEL_SWEEP = 2 };
 
 typedef struct fdlbm_params {

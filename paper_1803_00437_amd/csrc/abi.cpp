@@ -244,7 +244,7 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
     const bool ref = uses_reference(c->p);
     const FdArgs fa = fd_args(c->p);
     const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
-                     c->p.s_eps, c->p.force_x, c->p.force_y};
+                     c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, c->p.tile_rows};
     for (int64_t s = 0; s < nsteps; ++s) {
         void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
         hipError_t e;

@@ -24,6 +24,7 @@ struct FdArgs {
 struct MrtArgs {
     int nx, ny, walls, dtype;
     double s_e, s_xx, s_q, s_eps, fx, fy;
+    int kernel, tile_rows;  // FDLBM_KERNEL_REFERENCE: one thread per node; else the vector sweep
 };
 
 // FD-LBM, reference path: pass 1 writes the nine f* planes (compute dtype) for every

@@ -7,6 +7,7 @@
 // wall returns to its own node with the opposite velocity (halfway bounce-back, which puts
 // the wall half-way between the last fluid row and the next one, section 3-c).
 // Algorithmic traffic: 9 values read + 9 written per node.
+#include "fd_sweep_body.hpp"
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
 
@@ -75,19 +76,12 @@ __device__ __forceinline__ void equilibrium(C dr, C jx, C jy, C &E, C &XX, C &XY
     eps = dr - K3;
 }
 
-template <typename T, bool WALLS>
-__global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
-                                                  MrtCoef<typename Storage<T>::C> k)
+// Collision of one node: moments, relaxation of the non-conserved ones toward the
+// equilibria (eq. 1) with the force split half before and half after (Strang), and the
+// post-collision populations.  Every MRT kernel calls this, so all of them agree bit for bit.
+template <typename C> __device__ __forceinline__ void collide(C (&f)[9], const MrtCoef<C> &k)
 {
-    using C = typename Storage<T>::C;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const size_t n = (size_t)nx * (size_t)ny;
-    const size_t p = (size_t)j * (size_t)nx + (size_t)i;
-    C f[9], m[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = Storage<T>::load(in[q * n + p]);
+    C m[9];
     moments<C>(f, m);
     // Strang splitting: half the force before the collision ...
     const C jax = m[1] + k.hfx, jay = m[2] + k.hfy;
@@ -104,6 +98,23 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
     m[1] = m[1] + k.fx;
     m[2] = m[2] + k.fy;
     populations<C>(m, f);
+}
+
+// Reference MRT step: one thread per node.
+template <typename T, bool WALLS>
+__global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
+                                                  MrtCoef<typename Storage<T>::C> k)
+{
+    using C = typename Storage<T>::C;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const size_t n = (size_t)nx * (size_t)ny;
+    const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+    C f[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = Storage<T>::load(in[q * n + p]);
+    collide<C>(f, k);
     // propagation, eq. 2 (push)
     const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
     int jp = j + 1, jm = j - 1;
@@ -132,6 +143,110 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
         out[2 * n + p] = Storage<T>::store(f[4]);
         out[5 * n + p] = Storage<T>::store(f[7]);
         out[6 * n + p] = Storage<T>::store(f[8]);
+    }
+}
+
+// Vectorised MRT step.  A wavefront owns 64*CPL consecutive columns (CPL per lane, one
+// aligned vector access per population plane) of R rows.  After the collision, the
+// populations moving along +x / -x are shifted by one column across lanes with DPP
+// whole-wave shifts, so every store is an aligned vector too; the outermost lane on each
+// side has no neighbour to take from and only feeds its neighbour, so strips overlap by
+// one lane on each side.  Populations moving along y go to the row above or below (or
+// bounce back at a wall).  Wavefronts are dealt out row band after row band.
+template <typename T, int CPL, bool WALLS>
+__global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
+                                                        int rows, int strips_x, int ntiles,
+                                                        MrtCoef<typename Storage<T>::C> k)
+{
+    using C = typename Storage<T>::C;
+    using namespace sweep;
+    constexpr int S = 64 * CPL - 2 * CPL;  // stored columns per strip
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= ntiles) return;  // uniform over the wavefront
+    const int band = tile / strips_x, sx = tile - band * strips_x;
+    const int xl = sx * S - CPL + CPL * lane;  // first column of this lane (unwrapped)
+    const int col = ((xl % nx) + nx) % nx;
+    const bool store_ok = lane >= 1 && lane <= 62 && xl < nx;
+    const size_t n = (size_t)nx * (size_t)ny;
+    const int y0 = band * rows, y1 = min(y0 + rows, ny);
+    for (int y = y0; y < y1; ++y) {
+        const size_t p = (size_t)y * (size_t)nx + (size_t)col;
+        C f[CPL][9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const Group<T, CPL> g = load_group<T, CPL>(in + q * n + p);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) f[c][q] = Storage<T>::load(g.v[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) collide<C>(f[c], k);
+        // destination rows (wave-uniform); with walls a population leaving the channel
+        // returns to its own node with the opposite velocity
+        int yp = y + 1, ym = y - 1;
+        const bool top_wall = WALLS && yp == ny, bottom_wall = WALLS && ym < 0;
+        if (!WALLS) {
+            if (yp == ny) yp = 0;
+            if (ym < 0) ym = ny - 1;
+        }
+        const size_t prow = (size_t)yp * (size_t)nx + (size_t)col, mrow = (size_t)ym * (size_t)nx + (size_t)col;
+        Group<T, CPL> g[9];
+        // velocities (0,0), (0,+1), (0,-1) keep their column
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            g[0].v[c] = Storage<T>::store(f[c][0]);
+            g[2].v[c] = Storage<T>::store(f[c][2]);
+            g[4].v[c] = Storage<T>::store(f[c][4]);
+        }
+        // +x movers (1, 5, 8) arrive from the column on the left, -x movers (3, 6, 7) from
+        // the column on the right
+        const int rq[3] = {1, 5, 8}, lq[3] = {3, 6, 7};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const C fl = from_left(f[CPL - 1][rq[t]]), fr = from_right(f[0][lq[t]]);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                g[rq[t]].v[c] = Storage<T>::store(c > 0 ? f[c > 0 ? c - 1 : 0][rq[t]] : fl);
+                g[lq[t]].v[c] = Storage<T>::store(c < CPL - 1 ? f[c < CPL - 1 ? c + 1 : 0][lq[t]] : fr);
+            }
+        }
+        if (!store_ok) continue;
+        store_group<T, CPL>(out + 0 * n + p, g[0]);
+        store_group<T, CPL>(out + 1 * n + p, g[1]);
+        store_group<T, CPL>(out + 3 * n + p, g[3]);
+        if (!top_wall) {
+            store_group<T, CPL>(out + 2 * n + prow, g[2]);
+            store_group<T, CPL>(out + 5 * n + prow, g[5]);
+            store_group<T, CPL>(out + 6 * n + prow, g[6]);
+        }
+        if (!bottom_wall) {
+            store_group<T, CPL>(out + 4 * n + mrow, g[4]);
+            store_group<T, CPL>(out + 7 * n + mrow, g[7]);
+            store_group<T, CPL>(out + 8 * n + mrow, g[8]);
+        }
+        if (top_wall || bottom_wall) {
+            // unshifted post-collision values of this row for the bounce-back
+            Group<T, CPL> b2, b5, b6, b4, b7, b8;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                b2.v[c] = Storage<T>::store(f[c][2]);
+                b5.v[c] = Storage<T>::store(f[c][5]);
+                b6.v[c] = Storage<T>::store(f[c][6]);
+                b4.v[c] = Storage<T>::store(f[c][4]);
+                b7.v[c] = Storage<T>::store(f[c][7]);
+                b8.v[c] = Storage<T>::store(f[c][8]);
+            }
+            if (top_wall) {
+                store_group<T, CPL>(out + 4 * n + p, b2);
+                store_group<T, CPL>(out + 7 * n + p, b5);
+                store_group<T, CPL>(out + 8 * n + p, b6);
+            }
+            if (bottom_wall) {
+                store_group<T, CPL>(out + 2 * n + p, b4);
+                store_group<T, CPL>(out + 5 * n + p, b7);
+                store_group<T, CPL>(out + 6 * n + p, b8);
+            }
+        }
     }
 }
 
@@ -168,10 +283,33 @@ __global__ void __launch_bounds__(256) mrt_moments_kernel(const T *__restrict__ 
     }
 }
 
+template <typename T, int CPL>
+hipError_t run_sweep(const MrtArgs &a, MrtCoef<typename Storage<T>::C> k, const void *src, void *dst, hipStream_t s)
+{
+    constexpr int S = 64 * CPL - 2 * CPL;
+    const int rows = a.tile_rows > 0 ? a.tile_rows : 4;  // 4 measured best at 8192^2
+    const int strips_x = (a.nx + S - 1) / S;
+    const int ntiles = strips_x * ((a.ny + rows - 1) / rows);
+    const int blocks = (ntiles + 3) / 4;
+    if (a.walls)
+        hipLaunchKernelGGL((mrt_sweep_kernel<T, CPL, true>), blocks, 256, 0, s, static_cast<const T *>(src),
+                           static_cast<T *>(dst), a.nx, a.ny, rows, strips_x, ntiles, k);
+    else
+        hipLaunchKernelGGL((mrt_sweep_kernel<T, CPL, false>), blocks, 256, 0, s, static_cast<const T *>(src),
+                           static_cast<T *>(dst), a.nx, a.ny, rows, strips_x, ntiles, k);
+    return hipGetLastError();
+}
+
 template <typename T> hipError_t run(const MrtArgs &a, const void *src, void *dst, hipStream_t s)
 {
     using C = typename Storage<T>::C;
     MrtCoef<C> k{C(a.s_e), C(a.s_xx), C(a.s_q), C(a.s_eps), C(0.5 * a.fx), C(0.5 * a.fy), C(a.fx), C(a.fy)};
+    if (a.kernel != FDLBM_KERNEL_REFERENCE) {
+        constexpr int CPL = sizeof(T) == 8 ? 2 : 4;
+        if (a.nx % CPL == 0) return run_sweep<T, CPL>(a, k, src, dst, s);
+        if (a.nx % 2 == 0) return run_sweep<T, 2>(a, k, src, dst, s);
+        return run_sweep<T, 1>(a, k, src, dst, s);
+    }
     dim3 blk(64, 4), grd((a.nx + 63) / 64, (a.ny + 3) / 4);
     if (a.walls)
         hipLaunchKernelGGL((mrt_kernel<T, true>), grd, blk, 0, s, static_cast<const T *>(src), static_cast<T *>(dst),
