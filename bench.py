@@ -15,7 +15,6 @@ for the MRT step, the FP64 and FP16-storage FD-LBM steps and the 5-point stencil
     python bench.py [--steps K] [--warmup W] [--n 8192] [--no-compare] [--no-cpu]
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -30,15 +29,13 @@ HBM_PEAK_GBS = 8000.0
 NU = 0.02
 DIAG_EVERY = 100
 COUNTERS = os.path.join(ROOT, "profiles", "fd3_f32_8192_counters.json")
-KERNEL_SOURCES = ["paper_1803_00437_amd/csrc/fd_sweep.hip", "paper_1803_00437_amd/csrc/fdlbm_device.hpp"]
 
 
 def kernel_source_sha():
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the FD step kernel's sources: counters taken on other sources are not reported."""
+    from paper_1803_00437_amd.profiling import FD_SOURCES, sources_sha
+
+    return sources_sha(FD_SOURCES, ROOT)
 
 
 def bytes_per_node(scheme, dtype):
@@ -46,16 +43,18 @@ def bytes_per_node(scheme, dtype):
     return 2 * words * {"f64": 8, "f32": 4, "f16": 2}[dtype]
 
 
-def run_case(F, torch, init, n, scheme, dtype, stencil, steps, warmup, kernel, with_diag, tile_rows=0, lane_cols=0):
-    s_xx = F.fdlbm_rate_from_viscosity(NU)
-    kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel, tile_rows=tile_rows)
+def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with_diag, tile_rows=0, lane_cols=0,
+             bc="periodic", nu=NU, force=(0.0, 0.0)):
+    ny, nx = init[0].shape
+    s_xx = F.fdlbm_rate_from_viscosity(nu)
+    kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel, tile_rows=tile_rows, bc=bc, force=force)
     if scheme == "fd":
         kw["lane_cols"] = lane_cols
     if scheme == "fd":
         kw["stencil"] = stencil
     else:
         kw["quartic"] = True
-    sim = F.FdLbm(n, n, **kw)
+    sim = F.FdLbm(nx, ny, **kw)
     sim.set_state(*init)
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -80,7 +79,7 @@ def run_case(F, torch, init, n, scheme, dtype, stencil, steps, warmup, kernel, w
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
     diag = sim.diagnostics()
     sim.close()
-    nodes = n * n
+    nodes = nx * ny
     return {
         "ms_per_step": wall_ms,
         "kernel_ms": kernel_ms,
@@ -232,13 +231,13 @@ def main():
         name, dtype = args.only.split("_")
         scheme = "mrt" if name == "mrt" else "fd"
         stencil = int(name[2]) if scheme == "fd" else 0
-        case = run_case(F, torch, init, n, scheme, dtype, stencil, args.steps, args.warmup, args.kernel, False,
+        case = run_case(F, torch, init, scheme, dtype, stencil, args.steps, args.warmup, args.kernel, False,
                         args.tile_rows, args.lane_cols)
         print(json.dumps({"case": args.only, "tile_rows": args.tile_rows, "lane_cols": args.lane_cols, **case}),
               flush=True)
         return
 
-    main_case = run_case(F, torch, init, n, "fd", "f32", 3, args.steps, args.warmup, args.kernel, True,
+    main_case = run_case(F, torch, init, "fd", "f32", 3, args.steps, args.warmup, args.kernel, True,
                          args.tile_rows, args.lane_cols)
     print(f"# fd3 f32: {main_case}", file=sys.stderr, flush=True)
 
@@ -248,8 +247,17 @@ def main():
         for scheme, dtype, stencil in (("mrt", "f32", 0), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5),
                                        ("mrt", "f64", 0)):
             key = f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"
-            compare[key] = run_case(F, torch, init, n, scheme, dtype, stencil, short, 10, args.kernel, False)
+            compare[key] = run_case(F, torch, init, scheme, dtype, stencil, short, 10, args.kernel, False)
             print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
+        # the 16384 x 1024 Poiseuille channel: walls at y = -1/2 and ny - 1/2, body force along x
+        nu_ch = 1.0 / math.sqrt(108.0)
+        r, x, y, fx = W.poiseuille_profile(16384, 1024, nu_ch, 0.05)
+        for scheme, stencil in (("fd", 3), ("mrt", 0)):
+            key = f"poiseuille_16384x1024_{scheme}{stencil if scheme == 'fd' else ''}_f32"
+            compare[key] = run_case(F, torch, (r, x, y), scheme, "f32", stencil, short, 10, args.kernel, False,
+                                    bc="walls", nu=nu_ch, force=(fx, 0.0))
+            print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
+        del r, x, y
 
     batch = None
     if not args.no_batch:

@@ -2,9 +2,10 @@
 //
 // Pass 1 computes, for every node that sends a population into the fluid, the nine
 // post-collision populations of section 2 and writes them to nine planes; pass 2 gathers
-// the propagated populations (eq. 2) into the new (drho, jx, jy).  It moves about four
-// times the bytes of the fused kernel and exists as the plain GPU rendering that the fused
-// kernel must match bit for bit; both use fd_node_fstar() and fd_gather().
+// the propagated populations (eq. 2) and adds their difference from the node's own to the
+// stored (drho, jx, jy).  It moves about four times the bytes of the fused kernel and
+// exists as the plain GPU rendering that the fused kernel must match bit for bit; both
+// use fd_node_fstar(), row_sum(), fd_partial() and fd_finish().
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
 
@@ -13,14 +14,13 @@ namespace {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Value of (drho, J_a) at node (i, j) with the boundary rules: x periodic; y periodic, or,
+// Value of (drho, J) at node (i, j) with the boundary rules: x periodic; y periodic, or,
 // with walls, a ghost node mirrors the fluid node at the same distance from the wall
 // (linear extrapolation with zero velocity on the wall: drho even, J odd).
 template <typename T, bool WALLS> struct View {
     using C = typename Storage<T>::C;
     const T *dr, *jx, *jy;
     int nx, ny;
-    C hfx, hfy;
     __device__ __forceinline__ void at(int i, int j, C &r, C &x, C &y) const
     {
         i = wrap(wrap(i, nx), nx);
@@ -33,8 +33,8 @@ template <typename T, bool WALLS> struct View {
         }
         const size_t p = (size_t)j * (size_t)nx + (size_t)i;
         r = Storage<T>::load(dr[p]);
-        x = fmac(sgn, Storage<T>::load(jx[p]), hfx);
-        y = fmac(sgn, Storage<T>::load(jy[p]), hfy);
+        x = sgn * Storage<T>::load(jx[p]);
+        y = sgn * Storage<T>::load(jy[p]);
     }
 };
 
@@ -68,13 +68,15 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
     d[3] = S::diff(yY[0], yY[1], yY[3], yY[4]);
     d[4] = S::diff(yX[0], yX[1], yX[3], yX[4]);
     d[5] = S::diff(xY[0], xY[1], xY[3], xY[4]);
+    // products of J_a = J + F/2
     C P[5], Rx[5], Ry[5], Q[5];
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
-        P[o] = xX[o] * xX[o];
-        Rx[o] = xX[o] * yX[o];
-        Ry[o] = xY[o] * yY[o];
-        Q[o] = yY[o] * yY[o];
+        const C ax = xX[o] + k.hfx, ay = yX[o] + k.hfy, bx = xY[o] + k.hfx, by = yY[o] + k.hfy;
+        P[o] = ax * ax;
+        Rx[o] = ax * ay;
+        Ry[o] = bx * by;
+        Q[o] = by * by;
     }
     d[6] = S::diff(P[0], P[1], P[3], P[4]);
     d[7] = S::diff(Ry[0], Ry[1], Ry[3], Ry[4]);
@@ -82,7 +84,7 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
     d[9] = S::diff(Q[0], Q[1], Q[3], Q[4]);
 
     C f[9];
-    fd_node_fstar<C>(rX[2], xX[2], yX[2], d, k, f);
+    fd_node_fstar<C>(rX[2], xX[2] + k.hfx, yX[2] + k.hfy, d, k, f);
     const size_t plane = (size_t)nrows * (size_t)v.nx;
     const size_t p = (size_t)rr * (size_t)v.nx + (size_t)i;
 #pragma unroll
@@ -90,9 +92,10 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
 }
 
 template <typename T, bool WALLS>
-__global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::C *__restrict__ fstar, int nx, int ny,
-                                                     int row0, int nrows, T *__restrict__ odr, T *__restrict__ ojx,
-                                                     T *__restrict__ ojy)
+__global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::C *__restrict__ fstar,
+                                                     const T *__restrict__ in, FdCoef<typename Storage<T>::C> k,
+                                                     int nx, int ny, int row0, int nrows, T *__restrict__ odr,
+                                                     T *__restrict__ ojx, T *__restrict__ ojy)
 {
     using C = typename Storage<T>::C;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -106,10 +109,18 @@ __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::
         const int rr = jj - row0;  // walls: row0 = -1, so rows -1..ny map to 0..ny+1
         return fstar[q * plane + (size_t)rr * (size_t)nx + (size_t)ii];
     };
-    C r, x, y;
-    fd_gather<C>(F(0, 0, 0), F(1, -1, 0), F(3, 1, 0), F(2, 0, -1), F(5, -1, -1), F(6, 1, -1), F(4, 0, 1), F(7, 1, 1),
-                 F(8, -1, 1), r, x, y);
+    // arriving minus own, per source row: same row, row below, row above
+    const C pc = row_sum(F(0, 0, 0), F(1, -1, 0), F(3, 1, 0)) - row_sum(F(0, 0, 0), F(1, 0, 0), F(3, 0, 0));
+    const C pcx = (F(1, -1, 0) - F(3, 1, 0)) - (F(1, 0, 0) - F(3, 0, 0));
+    const C pu = row_sum(F(2, 0, -1), F(5, -1, -1), F(6, 1, -1)) - row_sum(F(2, 0, 0), F(5, 0, 0), F(6, 0, 0));
+    const C pux = (F(5, -1, -1) - F(6, 1, -1)) - (F(5, 0, 0) - F(6, 0, 0));
+    const C pd = row_sum(F(4, 0, 1), F(8, -1, 1), F(7, 1, 1)) - row_sum(F(4, 0, 0), F(8, 0, 0), F(7, 0, 0));
+    const C pdx = (F(8, -1, 1) - F(7, 1, 1)) - (F(8, 0, 0) - F(7, 0, 0));
+    const size_t n = (size_t)nx * (size_t)ny;
     const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+    C r, x, y;
+    fd_finish<C>(fd_partial<C>(pc, pcx, pu, pux), pd, pdx, Storage<T>::load(in[p]), Storage<T>::load(in[n + p]),
+                 Storage<T>::load(in[2 * n + p]), k.dfx, k.dfy, r, x, y);
     odr[p] = Storage<T>::store(r);
     ojx[p] = Storage<T>::store(x);
     ojy[p] = Storage<T>::store(y);
@@ -139,7 +150,7 @@ hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStre
     const T *in = static_cast<const T *>(src);
     T *out = static_cast<T *>(dst);
     auto k = make_coef<T>(a);
-    View<T, WALLS> v{in, in + n, in + 2 * n, a.nx, a.ny, k.hfx, k.hfy};
+    View<T, WALLS> v{in, in + n, in + 2 * n, a.nx, a.ny};
     const int row0 = WALLS ? -1 : 0, nrows = WALLS ? a.ny + 2 : a.ny;
     dim3 blk(64, 4);
     dim3 g1((a.nx + 63) / 64, (nrows + 3) / 4);
@@ -147,8 +158,8 @@ hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStre
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g2((a.nx + 63) / 64, (a.ny + 3) / 4);
-    hipLaunchKernelGGL((fd_ref_gather<T, WALLS>), g2, blk, 0, s, static_cast<const C *>(fstar), a.nx, a.ny, row0,
-                       nrows, out, out + n, out + 2 * n);
+    hipLaunchKernelGGL((fd_ref_gather<T, WALLS>), g2, blk, 0, s, static_cast<const C *>(fstar), in, k, a.nx, a.ny,
+                       row0, nrows, out, out + n, out + 2 * n);
     return hipGetLastError();
 }
 

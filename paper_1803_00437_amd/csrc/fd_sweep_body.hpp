@@ -69,9 +69,11 @@ template <typename T> struct TileArgs {
     FdCoef<typename Storage<T>::C> k;
 };
 
-// LDS slots per wavefront, each CPL x 64 values: the partial sums a wavefront publishes
-// for its neighbours, and the ones it keeps for its own first output row.
-enum { PUB_DN = 0, PUB_DNX, PUB_UP, PUB_UPX, OWN_CEN, OWN_CENX, OWN_DN, OWN_DNX, NSLOT };
+// LDS slots per wavefront, each CPL x 64 values: the row sums a wavefront publishes for its
+// neighbours (populations its first f* row sends down, its last f* row sends up), and the
+// parts of its own first output row that it keeps until the barrier (same-row and
+// row-above differences, and its own upward row sum to subtract from what arrives).
+enum { PUB_DN = 0, PUB_DNX, PUB_UP, PUB_UPX, OWN_PC, OWN_PCX, OWN_LU, OWN_LUX, OWN_PD, OWN_PDX, NSLOT };
 
 // One tile: the block's WV wavefronts over column strip sx and row band `band` of one
 // grid.  Called by every wavefront of the block (it contains a block barrier).
@@ -108,8 +110,9 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     const int nf = empty ? 0 : re - rb + 1;  // rows whose f* this wavefront computes
     const int row0 = rb - H;                 // first input row
 
-    // rolling window of input rows: drho, J_a = J + F/2 and the products Jx^2, JxJy, Jy^2
-    C w[6][NW][CPL];
+    // rolling window of input rows: drho and J (sign-flipped on ghost rows); the products
+    // of J_a = J + F/2 are formed where the derivatives need them
+    C w[3][NW][CPL];
     Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
     C ps = C(1);               // its sign (-1: ghost row beyond a wall)
 
@@ -131,22 +134,22 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     auto insert = [&](int wslot) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const C x = fmac(ps, Storage<T>::load(px.v[c]), a.k.hfx);
-            const C y = fmac(ps, Storage<T>::load(py.v[c]), a.k.hfy);
             w[0][wslot][c] = Storage<T>::load(pr.v[c]);
-            w[1][wslot][c] = x;
-            w[2][wslot][c] = y;
-            w[3][wslot][c] = x * x;
-            w[4][wslot][c] = x * y;
-            w[5][wslot][c] = y * y;
+            w[1][wslot][c] = ps * Storage<T>::load(px.v[c]);
+            w[2][wslot][c] = ps * Storage<T>::load(py.v[c]);
         }
     };
 
-    // partial sums carried between rows (order of fd_gather): A = cen(r-1) + up(r-2),
-    // AX = cenx(r-1) + upx(r-2), UP = up(r-2); UPp, UPXp = up(r-1), upx(r-1)
-    C A[CPL], AX[CPL], UP[CPL], UPp[CPL], UPXp[CPL];
+    // carried between rows, when f* of row r is being computed: QP = fd_partial of output
+    // row r-1 (its same-row and row-below parts), LD, LDX = the own downward row sums of
+    // row r-1, UPp, UPXp = the row sums row r-1 sends up
+    FdPartial<C> QP[CPL];
+    C LD[CPL], LDX[CPL], UPp[CPL], UPXp[CPL];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) A[c] = AX[c] = UP[c] = UPp[c] = UPXp[c] = C(0);
+    for (int c = 0; c < CPL; ++c) {
+        QP[c].q = QP[c].qx = QP[c].pu = C(0);
+        LD[c] = LDX[c] = UPp[c] = UPXp[c] = C(0);
+    }
 
     if (nf > 0) {
         // prologue: the first 2H input rows, then the prefetch of the next one
@@ -160,8 +163,11 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
 
     // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
     // y-derivative fields (drho, Jy, Jx, JxJy, Jy^2) -> d[1], d[3], d[5], d[7], d[9]
-    constexpr int XF[5] = {0, 1, 2, 3, 4};
-    constexpr int YF[5] = {0, 2, 1, 4, 5};
+    // (products of J_a).  yfield(q, slot, c): y-derivative field q of a window row.
+    auto yfield = [&](int q, int slot, int c) -> C {
+        const C xa = w[1][slot][c] + a.k.hfx, ya = w[2][slot][c] + a.k.hfy;
+        return q == 0 ? w[0][slot][c] : q == 1 ? w[2][slot][c] : q == 2 ? w[1][slot][c] : q == 3 ? xa * ya : ya * ya;
+    };
 
     for (int it0 = 0; it0 < nf; it0 += NW) {
 #pragma unroll
@@ -172,14 +178,26 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
             if (it + 1 < nf) fetch(row0 + 2 * H + it + 1);
 
             const int cs = (ph + H) % NW;  // window slot of the row whose f* is computed
+            // x-derivative fields of this row, and the J_a of its nodes
+            C xf[5][CPL], jxa[CPL], jya[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                jxa[c] = w[1][cs][c] + a.k.hfx;
+                jya[c] = w[2][cs][c] + a.k.hfy;
+                xf[0][c] = w[0][cs][c];
+                xf[1][c] = w[1][cs][c];
+                xf[2][c] = w[2][cs][c];
+                xf[3][c] = jxa[c] * jxa[c];
+                xf[4][c] = jxa[c] * jya[c];
+            }
             // x-neighbours of the lane's outer columns, from the adjacent lanes
             C xl1[5], xr1[5], xl2[5], xr2[5];
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                xl1[q] = from_left(w[XF[q]][cs][CPL - 1]);
-                xr1[q] = from_right(w[XF[q]][cs][0]);
-                xl2[q] = H == 2 ? from_left(w[XF[q]][cs][CPL >= 2 ? CPL - 2 : 0]) : C(0);
-                xr2[q] = H == 2 ? from_right(w[XF[q]][cs][CPL > 1 ? 1 : 0]) : C(0);
+                xl1[q] = from_left(xf[q][CPL - 1]);
+                xr1[q] = from_right(xf[q][0]);
+                xl2[q] = H == 2 ? from_left(xf[q][CPL >= 2 ? CPL - 2 : 0]) : C(0);
+                xr2[q] = H == 2 ? from_right(xf[q][CPL > 1 ? 1 : 0]) : C(0);
             }
             C f[CPL][9];
 #pragma unroll
@@ -187,25 +205,25 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
                 C d[10];
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
-                    const int fx = XF[q], fy = YF[q];
-                    const C m1 = c > 0 ? w[fx][cs][c > 0 ? c - 1 : 0] : xl1[q];
-                    const C p1 = c < CPL - 1 ? w[fx][cs][c < CPL - 1 ? c + 1 : 0] : xr1[q];
+                    const C m1 = c > 0 ? xf[q][c > 0 ? c - 1 : 0] : xl1[q];
+                    const C p1 = c < CPL - 1 ? xf[q][c < CPL - 1 ? c + 1 : 0] : xr1[q];
                     C m2 = C(0), p2 = C(0), ym2 = C(0), yp2 = C(0);
                     if (H == 2) {
-                        m2 = c >= 2 ? w[fx][cs][c >= 2 ? c - 2 : 0] : (c == 1 ? xl1[q] : xl2[q]);
-                        p2 = c + 2 < CPL ? w[fx][cs][c + 2 < CPL ? c + 2 : 0] : (c + 2 == CPL ? xr1[q] : xr2[q]);
-                        ym2 = w[fy][ph % NW][c];
-                        yp2 = w[fy][(ph + 2 * H) % NW][c];
+                        m2 = c >= 2 ? xf[q][c >= 2 ? c - 2 : 0] : (c == 1 ? xl1[q] : xl2[q]);
+                        p2 = c + 2 < CPL ? xf[q][c + 2 < CPL ? c + 2 : 0] : (c + 2 == CPL ? xr1[q] : xr2[q]);
+                        ym2 = yfield(q, ph % NW, c);
+                        yp2 = yfield(q, (ph + 2 * H) % NW, c);
                     }
                     d[2 * q] = S::diff(m2, m1, p1, p2);
-                    d[2 * q + 1] = S::diff(ym2, w[fy][(ph + H - 1) % NW][c], w[fy][(ph + H + 1) % NW][c], yp2);
+                    d[2 * q + 1] = S::diff(ym2, yfield(q, (ph + H - 1) % NW, c), yfield(q, (ph + H + 1) % NW, c), yp2);
                 }
-                fd_node_fstar<C>(w[0][cs][c], w[1][cs][c], w[2][cs][c], d, a.k, f[c]);
+                fd_node_fstar<C>(w[0][cs][c], jxa[c], jya[c], d, a.k, f[c]);
             }
             // populations moving along +x come from the column on the left, along -x from
             // the column on the right
             const C f1l = from_left(f[CPL - 1][1]), f5l = from_left(f[CPL - 1][5]), f8l = from_left(f[CPL - 1][8]);
             const C f3r = from_right(f[0][3]), f6r = from_right(f[0][6]), f7r = from_right(f[0][7]);
+            const int os = (ph + H - 1) % NW;  // window slot of output row r - 1
             Group<T, CPL> gr, gx, gy;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
@@ -216,29 +234,39 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
                 const C c3 = c < CPL - 1 ? f[cr][3] : f3r;
                 const C u6 = c < CPL - 1 ? f[cr][6] : f6r;
                 const C d7 = c < CPL - 1 ? f[cr][7] : f7r;
-                const C cen = (f[c][0] + c1) + c3, cenx = c1 - c3;
-                const C up = (f[c][2] + u5) + u6, upx = u5 - u6;
-                const C dn = (f[c][4] + d8) + d7, dnx = d8 - d7;
+                // row sums arriving at row r from row r, at r + 1 (up) and at r - 1 (dn)
+                const C up = row_sum(f[c][2], u5, u6), upx = u5 - u6;
+                const C dn = row_sum(f[c][4], d8, d7), dnx = d8 - d7;
+                // the same groups of this node's own populations
+                const C lu = row_sum(f[c][2], f[c][5], f[c][6]), lux = f[c][5] - f[c][6];
+                const C ld = row_sum(f[c][4], f[c][8], f[c][7]), ldx = f[c][8] - f[c][7];
+                const C pc = row_sum(f[c][0], c1, c3) - row_sum(f[c][0], f[c][1], f[c][3]);
+                const C pcx = (c1 - c3) - (f[c][1] - f[c][3]);
+                const C pd = dn - LD[c], pdx = dnx - LDX[c];  // row-above part of row r - 1
                 if (!bottom && it == 0) {
-                    // f* of the first row: its downward part completes the last output row
-                    // of the wavefront below; its own row still lacks the part sent up by
+                    // f* of the first row: its downward sums complete the last output row
+                    // of the wavefront below; its own row still lacks the upward sums of
                     // that wavefront
                     lds[wv][PUB_DN][c][lane] = dn;
                     lds[wv][PUB_DNX][c][lane] = dnx;
-                    lds[wv][OWN_CEN][c][lane] = cen;
-                    lds[wv][OWN_CENX][c][lane] = cenx;
+                    lds[wv][OWN_PC][c][lane] = pc;
+                    lds[wv][OWN_PCX][c][lane] = pcx;
+                    lds[wv][OWN_LU][c][lane] = lu;
+                    lds[wv][OWN_LUX][c][lane] = lux;
                 }
                 if (!bottom && it == 1) {
-                    lds[wv][OWN_DN][c][lane] = dn;
-                    lds[wv][OWN_DNX][c][lane] = dnx;
+                    lds[wv][OWN_PD][c][lane] = pd;
+                    lds[wv][OWN_PDX][c][lane] = pdx;
                 }
-                // output row r-1 = (cen(r-1) + up(r-2)) + dn(r)
-                gr.v[c] = Storage<T>::store(A[c] + dn);
-                gx.v[c] = Storage<T>::store(AX[c] + dnx);
-                gy.v[c] = Storage<T>::store(UP[c] - dn);
-                A[c] = cen + UPp[c];
-                AX[c] = cenx + UPXp[c];
-                UP[c] = UPp[c];
+                // output row r - 1
+                C nr, nxv, nyv;
+                fd_finish<C>(QP[c], pd, pdx, w[0][os][c], w[1][os][c], w[2][os][c], a.k.dfx, a.k.dfy, nr, nxv, nyv);
+                gr.v[c] = Storage<T>::store(nr);
+                gx.v[c] = Storage<T>::store(nxv);
+                gy.v[c] = Storage<T>::store(nyv);
+                QP[c] = fd_partial<C>(pc, pcx, UPp[c] - lu, UPXp[c] - lux);
+                LD[c] = ld;
+                LDX[c] = ldx;
                 UPp[c] = up;
                 UPXp[c] = upx;
             }
@@ -251,8 +279,22 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
             }
         }
     }
+    // stored values of the two output rows completed after the barrier (interior rows)
+    Group<T, CPL> o0r, o0x, o0y, o1r, o1x, o1y;
+    if (!empty && !bottom) {
+        const size_t off = (size_t)ybeg * (size_t)nx + (size_t)col;
+        o0r = load_group<T, CPL>(a.dr + off);
+        o0x = load_group<T, CPL>(a.jx + off);
+        o0y = load_group<T, CPL>(a.jy + off);
+    }
+    if (!empty && !top) {
+        const size_t off = (size_t)(yend - 1) * (size_t)nx + (size_t)col;
+        o1r = load_group<T, CPL>(a.dr + off);
+        o1x = load_group<T, CPL>(a.jx + off);
+        o1y = load_group<T, CPL>(a.jy + off);
+    }
     if (!top && !empty) {
-        // the upward part of the last f* row completes the first output row of the
+        // the upward sums of the last f* row complete the first output row of the
         // wavefront above
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
@@ -263,15 +305,19 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     __syncthreads();
     if (empty) return;
     if (!bottom) {
-        // first output row: (cen + up from the wavefront below) + dn
+        // first output row: own same-row and row-above parts, upward sums from below
         Group<T, CPL> gr, gx, gy;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const C up = lds[wv - 1][PUB_UP][c][lane], upx = lds[wv - 1][PUB_UPX][c][lane];
-            const C dn = lds[wv][OWN_DN][c][lane], dnx = lds[wv][OWN_DNX][c][lane];
-            gr.v[c] = Storage<T>::store((lds[wv][OWN_CEN][c][lane] + up) + dn);
-            gx.v[c] = Storage<T>::store((lds[wv][OWN_CENX][c][lane] + upx) + dnx);
-            gy.v[c] = Storage<T>::store(up - dn);
+            const C pu = lds[wv - 1][PUB_UP][c][lane] - lds[wv][OWN_LU][c][lane];
+            const C pux = lds[wv - 1][PUB_UPX][c][lane] - lds[wv][OWN_LUX][c][lane];
+            C nr, nxv, nyv;
+            fd_finish<C>(fd_partial<C>(lds[wv][OWN_PC][c][lane], lds[wv][OWN_PCX][c][lane], pu, pux),
+                         lds[wv][OWN_PD][c][lane], lds[wv][OWN_PDX][c][lane], Storage<T>::load(o0r.v[c]),
+                         Storage<T>::load(o0x.v[c]), Storage<T>::load(o0y.v[c]), a.k.dfx, a.k.dfy, nr, nxv, nyv);
+            gr.v[c] = Storage<T>::store(nr);
+            gx.v[c] = Storage<T>::store(nxv);
+            gy.v[c] = Storage<T>::store(nyv);
         }
         if (store_ok) {
             const size_t off = (size_t)ybeg * (size_t)nx + (size_t)col;
@@ -281,14 +327,18 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
         }
     }
     if (!top) {
-        // last output row: (cen + up) carried + dn from the wavefront above
+        // last output row: carried parts + downward sums from the wavefront above
         Group<T, CPL> gr, gx, gy;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const C dn = lds[wv + 1][PUB_DN][c][lane], dnx = lds[wv + 1][PUB_DNX][c][lane];
-            gr.v[c] = Storage<T>::store(A[c] + dn);
-            gx.v[c] = Storage<T>::store(AX[c] + dnx);
-            gy.v[c] = Storage<T>::store(UP[c] - dn);
+            const C pd = lds[wv + 1][PUB_DN][c][lane] - LD[c];
+            const C pdx = lds[wv + 1][PUB_DNX][c][lane] - LDX[c];
+            C nr, nxv, nyv;
+            fd_finish<C>(QP[c], pd, pdx, Storage<T>::load(o1r.v[c]), Storage<T>::load(o1x.v[c]),
+                         Storage<T>::load(o1y.v[c]), a.k.dfx, a.k.dfy, nr, nxv, nyv);
+            gr.v[c] = Storage<T>::store(nr);
+            gx.v[c] = Storage<T>::store(nxv);
+            gy.v[c] = Storage<T>::store(nyv);
         }
         if (store_ok) {
             const size_t off = (size_t)(yend - 1) * (size_t)nx + (size_t)col;

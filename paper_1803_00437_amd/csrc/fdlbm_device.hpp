@@ -1,11 +1,12 @@
 // Device-side building blocks shared by the FD-LBM kernels: storage types, the per-node
 // reconstruction of the post-collision populations (section 2 of Dubois, Lallemand,
-// Obrecht, Tekitek) and the gather order of the propagation (section 1, eq. 2).
+// Obrecht, Tekitek) and the update order of the propagation (section 1, eq. 2).
 //
 // Every kernel that advances an FD-LBM state calls fd_node_fstar() with the same inputs
-// in the same order, and sums the propagated populations in the order of fd_gather(), so
-// the reference and the fused kernels produce bit-identical states.  The library is
-// compiled with -ffp-contract=off; every fused multiply-add below is written out.
+// in the same order, and forms the new state with row_sum(), fd_partial() and fd_finish()
+// in the same order, so the reference and the fused kernels produce bit-identical states.
+// The library is compiled with -ffp-contract=off; every fused multiply-add below is
+// written out.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -72,7 +73,8 @@ template <typename C> struct FdCoef {
     C dfx, dfy;  // F  : diagonal populations carry (J_a + F)/12
 };
 
-// Inputs of one node: J_a = J + F/2 and the ten unscaled derivatives
+// Inputs of one node: J_a = J + F/2 and the ten unscaled derivatives (of drho, of the
+// stored J and of the products of J_a)
 //   d[0] = D_x rho, d[1] = D_y rho, d[2] = D_x Jx, d[3] = D_y Jy, d[4] = D_x Jy,
 //   d[5] = D_y Jx, d[6] = D_x Jx^2, d[7] = D_y JxJy, d[8] = D_x JxJy, d[9] = D_y Jy^2.
 // Output: the nine post-collision populations as deviations f*_k - w_k.
@@ -128,22 +130,40 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
     f[8] = dgm - t;
 }
 
-// Gather after propagation (eq. 2): the new state at x sums f*_k(x - e_k).  Arguments are
-// the populations already fetched from their source nodes:
-//   c0 = f0(x), c1 = f1(x-ex), c3 = f3(x+ex)                        (same row)
-//   u2 = f2(x-ey), u5 = f5(x-ex-ey), u6 = f6(x+ex-ey)                (row below)
-//   d4 = f4(x+ey), d7 = f7(x+ex+ey), d8 = f8(x-ex+ey)                (row above)
-// Fixed summation order shared by every kernel: within each source row the value from the
-// left neighbour is added before the one from the right neighbour.
-template <typename C>
-__device__ __forceinline__ void fd_gather(C c0, C c1, C c3, C u2, C u5, C u6, C d4, C d7, C d8, C &dr, C &jx, C &jy)
+// Propagation (eq. 2) in increment form.  The new state at x sums f*_k(x - e_k); the
+// collision conserves mass and adds F to the momentum, so the node's own populations sum
+// to sum_k f*_k(x) = drho(x) and sum_k e_k f*_k(x) = J(x) + F, and
+//   drho' = drho + sum_k [f*_k(x - e_k) - f*_k(x)],   J' = J + F + sum_k e_k [f*_k(x - e_k) - f*_k(x)].
+// The populations are grouped by the row they come from:
+//   same row   f0(x), f1(x - ex), f3(x + ex)
+//   row below  f2(x - ey), f5(x - ex - ey), f6(x + ex - ey)
+//   row above  f4(x + ey), f8(x - ex + ey), f7(x + ex + ey)
+// Each group is summed (middle, from the left, from the right) and the same sum of the
+// node's own populations is subtracted; the three small differences are added to the
+// stored value last.  Summing the nine arriving populations directly rounds at the scale
+// of the field every step, and because the rounded weights 1/9, 1/36, 1/3, 1/12 do not add
+// up to exactly one in FP32, a slowly varying field then drifts by about 3e-8 per step.
+template <typename C> __device__ __forceinline__ C row_sum(C mid, C from_l, C from_r) { return (mid + from_l) + from_r; }
+
+// The update in two halves, so that a kernel which meets the three source rows at
+// different times forms exactly the same sums.  pc, pu, pd: (arriving - own) for drho from
+// the same row, the row below and the row above; pcx, pux, pdx the same for Jx (Jy takes
+// pu - pd).  fd_finish adds the row-above part, the body force (fx, fy) and the stored
+// state (odr, ojx, ojy).
+template <typename C> struct FdPartial {
+    C q, qx, pu;
+};
+template <typename C> __device__ __forceinline__ FdPartial<C> fd_partial(C pc, C pcx, C pu, C pux)
 {
-    const C cen = (c0 + c1) + c3, cenx = c1 - c3;
-    const C up = (u2 + u5) + u6, upx = u5 - u6;
-    const C dn = (d4 + d8) + d7, dnx = d8 - d7;
-    dr = (cen + up) + dn;
-    jx = (cenx + upx) + dnx;
-    jy = up - dn;
+    return FdPartial<C>{pc + pu, pcx + pux, pu};
+}
+template <typename C>
+__device__ __forceinline__ void fd_finish(const FdPartial<C> &a, C pd, C pdx, C odr, C ojx, C ojy, C fx, C fy, C &dr,
+                                          C &jx, C &jy)
+{
+    dr = odr + (a.q + pd);
+    jx = ojx + ((a.qx + pdx) + fx);
+    jy = ojy + ((a.pu - pd) + fy);
 }
 
 }  // namespace fdlbm

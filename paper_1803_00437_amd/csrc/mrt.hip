@@ -61,6 +61,31 @@ template <typename C> __device__ __forceinline__ void populations(const C (&m)[9
     f[8] = (dg - xy) - (vy - vx);
 }
 
+// f += M^{-1} d for a moment increment d that leaves the mass unchanged (d[0] is not read).
+// Adding the small change to the stored deviations, instead of rebuilding f from the
+// relaxed moments, keeps the FP32 rounding relative to the change rather than to f: in a
+// slow steady flow the rebuilt form's rounding biases every step the same way.
+template <typename C> __device__ __forceinline__ void add_increment(const C (&d)[9], C (&f)[9])
+{
+    const C e36 = d[3] * C(1.0 / 36.0), p36 = d[8] * C(1.0 / 36.0);
+    f[0] = f[0] + C(4) * (p36 - e36);
+    const C ax = -fmac(C(2), p36, e36);                 // -E/36 - eps/18
+    const C dg = fmac(C(2), e36, p36);                  // E/18 + eps/36
+    const C xx = d[4] * C(0.25), xy = d[5] * C(0.25);
+    const C jx6 = d[1] * C(1.0 / 6.0), jy6 = d[2] * C(1.0 / 6.0);
+    const C qx6 = d[6] * C(1.0 / 6.0), qy6 = d[7] * C(1.0 / 6.0);
+    const C ux = jx6 - qx6, uy = jy6 - qy6;
+    const C vx = fmac(qx6, C(0.5), jx6), vy = fmac(qy6, C(0.5), jy6);
+    f[1] = f[1] + ((ax + xx) + ux);
+    f[3] = f[3] + ((ax + xx) - ux);
+    f[2] = f[2] + ((ax - xx) + uy);
+    f[4] = f[4] + ((ax - xx) - uy);
+    f[5] = f[5] + ((dg + xy) + (vx + vy));
+    f[7] = f[7] + ((dg + xy) - (vx + vy));
+    f[6] = f[6] + ((dg - xy) + (vy - vx));
+    f[8] = f[8] + ((dg - xy) - (vy - vx));
+}
+
 // Equilibrium moments of section 1-a as deviations from the rest moments.
 template <typename C>
 __device__ __forceinline__ void equilibrium(C dr, C jx, C jy, C &E, C &XX, C &XY, C &qx, C &qy, C &eps)
@@ -78,7 +103,8 @@ __device__ __forceinline__ void equilibrium(C dr, C jx, C jy, C &E, C &XX, C &XY
 
 // Collision of one node: moments, relaxation of the non-conserved ones toward the
 // equilibria (eq. 1) with the force split half before and half after (Strang), and the
-// post-collision populations.  Every MRT kernel calls this, so all of them agree bit for bit.
+// post-collision populations f* = f + M^{-1} (m* - m).  Every MRT kernel calls this, so
+// all of them agree bit for bit.
 template <typename C> __device__ __forceinline__ void collide(C (&f)[9], const MrtCoef<C> &k)
 {
     C m[9];
@@ -87,17 +113,19 @@ template <typename C> __device__ __forceinline__ void collide(C (&f)[9], const M
     const C jax = m[1] + k.hfx, jay = m[2] + k.hfy;
     C E, XX, XY, qx, qy, eps;
     equilibrium<C>(m[0], jax, jay, E, XX, XY, qx, qy, eps);
-    // eq. 1 for the non-conserved moments
-    m[3] = fmac(k.se, E - m[3], m[3]);
-    m[4] = fmac(k.sxx, XX - m[4], m[4]);
-    m[5] = fmac(k.sxx, XY - m[5], m[5]);
-    m[6] = fmac(k.sq, qx - m[6], m[6]);
-    m[7] = fmac(k.sq, qy - m[7], m[7]);
-    m[8] = fmac(k.seps, eps - m[8], m[8]);
-    // ... and the other half after it
-    m[1] = m[1] + k.fx;
-    m[2] = m[2] + k.fy;
-    populations<C>(m, f);
+    C d[9];
+    d[0] = C(0);
+    // ... the whole force over the step (the other half after the collision) ...
+    d[1] = k.fx;
+    d[2] = k.fy;
+    // ... and eq. 1 for the non-conserved moments
+    d[3] = k.se * (E - m[3]);
+    d[4] = k.sxx * (XX - m[4]);
+    d[5] = k.sxx * (XY - m[5]);
+    d[6] = k.sq * (qx - m[6]);
+    d[7] = k.sq * (qy - m[7]);
+    d[8] = k.seps * (eps - m[8]);
+    add_increment<C>(d, f);
 }
 
 // Reference MRT step: one thread per node.

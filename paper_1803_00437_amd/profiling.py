@@ -1,15 +1,20 @@
-"""Summaries of rocprofv3 output for the library's kernels.
+"""rocprofv3 runs and summaries for the library's kernels on the bench workloads.
 
-    python -m paper_1803_00437_amd.profiling \\
-        --trace DIR [--fetch DIR --write DIR] --kernel fd_sweep_kernel<float \\
-        --copy-bytes 1073741824 --launch-alg-bytes 1610612736 --command "..." \\
+Collect every profile the bench relies on (kernel trace, then FETCH_SIZE and WRITE_SIZE
+counter passes of their own) and write one summary per kernel:
+
+    python -m paper_1803_00437_amd.profiling collect --raw OUT_DIR --out profiles
+
+Summarise an existing set of rocprofv3 directories (``--output-format csv``) for one kernel:
+
+    python -m paper_1803_00437_amd.profiling summarise --trace DIR [--fetch DIR --write DIR] \\
+        --kernel "fd_sweep_kernel<float, 4, 3, false>" --launch-alg-bytes 1610612736 \\
         --out profiles/NAME.md [--json profiles/NAME.json --sources a.hip b.hpp]
 
-DIR are rocprofv3 output directories written with ``--output-format csv``:
-``--kernel-trace --stats`` for the trace, ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` for
-the two counter runs.  The counters are scaled by what they read for the library's
-streaming copy kernel (``fdlbm_device_copy``), which reads and writes a known number of
-bytes; the scale factors are printed with the summary.
+The HBM counters are scaled by what they read for the library's streaming copy kernel
+(``fdlbm_device_copy``), which reads and writes a known number of bytes; the scale factors
+are printed with each summary.  This module never touches the GPU itself: rocprofv3 runs
+the bench as a child process.
 """
 from __future__ import annotations
 
@@ -19,7 +24,18 @@ import glob
 import hashlib
 import json
 import os
+import subprocess
+import sys
 from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = "paper_1803_00437_amd/csrc"
+FD_SOURCES = [f"{CSRC}/fd_sweep.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"]
+MRT_SOURCES = [f"{CSRC}/mrt.hip", f"{CSRC}/fdlbm_device.hpp"]
+COPY_BYTES = 1 << 30
+N = 8192
+CHANNEL = 16384 * 1024
+BATCH_NODES = 177708266  # sum of N^2 over the 512 shear-wave instances (sizes U{32..1024}, seed 5)
 
 
 def _csvs(d, suffix):
@@ -49,76 +65,169 @@ def pick(table, pattern):
     return hits[0]
 
 
-def sources_sha(paths):
+def sources_sha(paths, root=ROOT):
     h = hashlib.sha256()
     for p in paths:
-        with open(p, "rb") as f:
+        with open(os.path.join(root, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch")
-    ap.add_argument("--write")
-    ap.add_argument("--kernel", required=True, help="substring of the kernel name to summarise")
-    ap.add_argument("--copy-kernel", default="copy_kernel")
-    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
-    ap.add_argument("--launch-alg-bytes", type=int, required=True, help="algorithmic bytes moved per launch")
-    ap.add_argument("--command", default="")
-    ap.add_argument("--counter-command", default="")
-    ap.add_argument("--out", required=True)
-    ap.add_argument("--json")
-    ap.add_argument("--sources", nargs="*", default=[])
-    ap.add_argument("--n", type=int, default=8192)
-    args = ap.parse_args()
-
-    stats = kernel_stats(args.trace)
+def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=None, sources=(), command="",
+              counter_command="", workload="", n=N, copy_kernel="copy_kernel", copy_bytes=COPY_BYTES):
+    stats = kernel_stats(trace)
     names = {r["Name"]: r for r in stats}
-    kname = pick(names, args.kernel)
+    kname = pick(names, kernel)
     k = names[kname]
     avg_ns = float(k["AverageNs"])
-    lines = [f"# rocprofv3 summary: {args.kernel}", "",
-             f"Command (kernel trace): `{args.command}`", ""]
-    lines += ["| kernel | calls | average ns | min ns | max ns |", "|---|---|---|---|---|"]
-    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+    lines = [f"# rocprofv3 summary: `{kernel}`", ""]
+    if workload:
+        lines += [f"Workload: {workload}", ""]
+    lines += [f"Command (kernel trace): `{command}`", "",
+              "| kernel | calls | average ns | min ns | max ns |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
         lines.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['MinNs']} | {r['MaxNs']} |")
-    alg = args.launch_alg_bytes
-    lines += ["", f"Summarised kernel: `{kname}`", f"- average duration: {avg_ns:.0f} ns",
-              f"- algorithmic bytes per launch: {alg} ({alg / avg_ns:.1f} GB/s at the average duration)"]
-    out = {"kernel": kname, "avg_ns": avg_ns, "alg_bytes_per_launch": alg, "n": args.n}
-    if args.fetch and args.write:
-        fm, wm = counter_means(args.fetch), counter_means(args.write)
-        kf, kw = fm[pick(fm, args.kernel)], wm[pick(wm, args.kernel)]
-        cf, cw = fm[pick(fm, args.copy_kernel)], wm[pick(wm, args.copy_kernel)]
-        f_fetch = args.copy_bytes / 1024.0 / cf[1]
-        f_write = args.copy_bytes / 1024.0 / cw[1]
+    lines += ["", f"Summarised kernel: `{kname}`", f"- calls: {k['Calls']}", f"- average duration: {avg_ns:.0f} ns",
+              f"- algorithmic bytes per launch: {alg} ({alg / avg_ns:.1f} GB/s at the average duration, "
+              f"{alg / avg_ns / 8000:.3f} of 8 TB/s)"]
+    out = {"kernel": kname, "avg_ns": avg_ns, "calls": int(k["Calls"]), "alg_bytes_per_launch": alg, "n": n,
+           "alg_gbs": alg / avg_ns}
+    if fetch and write:
+        fm, wm = counter_means(fetch), counter_means(write)
+        kf, kw = fm[pick(fm, kernel)], wm[pick(wm, kernel)]
+        cf, cw = fm[pick(fm, copy_kernel)], wm[pick(wm, copy_kernel)]
+        f_fetch = copy_bytes / 1024.0 / cf[1]
+        f_write = copy_bytes / 1024.0 / cw[1]
         fetch_b = kf[1] * 1024 * f_fetch
         write_b = kw[1] * 1024 * f_write
-        lines += ["", f"Counter commands: `{args.counter_command}`", "",
+        lines += ["", f"Counter commands: `{counter_command}`", "",
                   "| counter | copy kernel KiB/dispatch | scale (known bytes / counter) | kernel KiB/dispatch | kernel bytes (scaled) |",
                   "|---|---|---|---|---|",
                   f"| FETCH_SIZE | {cf[1]:.1f} | {f_fetch:.4f} | {kf[1]:.1f} | {fetch_b:.4g} |",
                   f"| WRITE_SIZE | {cw[1]:.1f} | {f_write:.4f} | {kw[1]:.1f} | {write_b:.4g} |",
                   "", f"- HBM bytes per launch (scaled counters): {fetch_b + write_b:.4g} "
-                  f"= {(fetch_b + write_b) / alg:.3f} x algorithmic",
+                  f"= {(fetch_b + write_b) / alg:.3f} x algorithmic "
+                  f"(reads {fetch_b / (alg / 2):.3f} x, writes {write_b / (alg / 2):.3f} x)",
                   f"- counter bandwidth at the average duration: {(fetch_b + write_b) / avg_ns:.1f} GB/s"]
         out.update(fetch_bytes_per_launch=fetch_b, write_bytes_per_launch=write_b,
                    hbm_bytes_per_launch=fetch_b + write_b, fetch_scale=f_fetch, write_scale=f_write,
-                   copy_kernel=pick(fm, args.copy_kernel), copy_bytes=args.copy_bytes)
-    if args.sources:
-        out["kernel_source_sha"] = sources_sha(args.sources)
-        out["sources"] = args.sources
-        lines += ["", f"Kernel sources {args.sources} sha256[:16] = {out['kernel_source_sha']}"]
-    out["command"] = args.command
-    out["counter_command"] = args.counter_command
-    with open(args.out, "w") as f:
+                   copy_kernel=pick(fm, copy_kernel), copy_bytes=copy_bytes)
+    if sources:
+        out["kernel_source_sha"] = sources_sha(sources)
+        out["sources"] = list(sources)
+        lines += ["", f"Kernel sources {list(sources)} sha256[:16] = {out['kernel_source_sha']}"]
+    out["command"] = command
+    out["counter_command"] = counter_command
+    with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
-    if args.json:
-        with open(args.json, "w") as f:
+    if json_out:
+        with open(json_out, "w") as f:
             json.dump(out, f, indent=1)
-    print("\n".join(lines))
+    return out
+
+
+# --- collect -----------------------------------------------------------------------------
+
+BENCH = "/root/repo/bench.py"
+TRACE_ARGS = ["--steps", "100", "--warmup", "10", "--no-cpu", "--copy-probe"]
+FD_COUNTER_ARGS = ["--steps", "20", "--warmup", "2", "--no-cpu", "--no-compare", "--no-batch", "--copy-probe"]
+MRT_COUNTER_ARGS = ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--copy-probe"]
+
+DECAY = "8192 x 8192 periodic decaying flow (modes 0<|k|<=32, max|field| 0.02), nu 0.02"
+KERNELS = [
+    # file stem, kernel name pattern, algorithmic bytes per launch, counter pair, sources, workload
+    ("fd3_f32_8192", "fd_sweep_kernel<float, 4, 3, false>", 24 * N * N, "fd", FD_SOURCES,
+     f"{DECAY}; FD-LBM 3-point, FP32 (3 words read + 3 written per node)"),
+    ("mrt_f32_8192", "mrt_sweep_kernel<float, 4, false>", 72 * N * N, "mrt", MRT_SOURCES,
+     f"{DECAY}; MRT D2Q9, FP32 (9 words read + 9 written per node)"),
+    ("fd3_f64_8192", "fd_sweep_kernel<double, 2, 3, false>", 48 * N * N, None, FD_SOURCES,
+     f"{DECAY}; FD-LBM 3-point, FP64"),
+    ("fd3_f16_8192", "fd_sweep_kernel<__half, 2, 3, false>", 12 * N * N, None, FD_SOURCES,
+     f"{DECAY}; FD-LBM 3-point, FP16 storage, FP32 arithmetic"),
+    ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false>", 24 * N * N, None, FD_SOURCES,
+     f"{DECAY}; FD-LBM 5-point, FP32"),
+    ("mrt_f64_8192", "mrt_sweep_kernel<double, 2, false>", 144 * N * N, None, MRT_SOURCES,
+     f"{DECAY}; MRT D2Q9, FP64"),
+    ("fd3_f32_channel_16384x1024", "fd_sweep_kernel<float, 4, 3, true>", 24 * CHANNEL, None, FD_SOURCES,
+     "Poiseuille channel 16384 x 1024, walls at y=-1/2 and ny-1/2, body force; FD-LBM 3-point, FP32"),
+    ("mrt_f32_channel_16384x1024", "mrt_sweep_kernel<float, 4, true>", 72 * CHANNEL, None, MRT_SOURCES,
+     "Poiseuille channel 16384 x 1024, halfway bounce-back walls, body force; MRT D2Q9, FP32"),
+    ("fd3_f32_batch512", "fd_batch_kernel<float", 24 * BATCH_NODES, None,
+     [f"{CSRC}/fd_batch.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"],
+     "512 periodic shear-wave instances N x N, N ~ U{32..1024}, one launch per step for all; FP32"),
+    ("copy_1gib", "copy_kernel", 2 * COPY_BYTES, None, [f"{CSRC}/diag.hip"],
+     "fdlbm_device_copy of 1 GiB (the achievable-bandwidth probe)"),
+]
+
+
+def _run(cmd, log, limit, kill_signal):
+    print("+", " ".join(cmd), flush=True)
+    with open(log, "w") as f:
+        rc = subprocess.call(["timeout", "-s", kill_signal, "-k", "10", str(limit)] + cmd, stdout=f,
+                             stderr=subprocess.STDOUT, cwd="/tmp", env=dict(os.environ, TMPDIR="/tmp"))
+    if rc != 0:
+        sys.stdout.write(open(log).read()[-3000:])
+        raise SystemExit(f"step failed with exit status {rc}: {' '.join(cmd)}")
+
+
+def collect(raw, out):
+    raw = os.path.abspath(raw)
+    os.makedirs(raw, exist_ok=True)
+    os.makedirs(out, exist_ok=True)
+    py = ["python3", "-u", BENCH]
+    trace_cmd = ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv", "-d", f"{raw}/trace", "--"] + py
+    _run(trace_cmd + TRACE_ARGS, f"{raw}/trace.log", 400, "TERM")
+    pmc = {}
+    for name, args in (("fd", FD_COUNTER_ARGS), ("mrt", MRT_COUNTER_ARGS)):
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            d = f"{raw}/{name}_{counter.lower()}"
+            _run(["rocprofv3", "--pmc", counter, "--output-format", "csv", "-d", d, "--"] + py + args,
+                 f"{d}.log", 120, "KILL")
+        pmc[name] = (f"{raw}/{name}_fetch_size", f"{raw}/{name}_write_size",
+                     f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
+                     f"-d <dir> -- python3 -u {BENCH} " + " ".join(args))
+    trace_str = "cd /tmp && TMPDIR=/tmp " + " ".join(trace_cmd[:-4] + ["-d", "<dir>", "--"] + py + TRACE_ARGS)
+    results = {}
+    for stem, pattern, alg, counters, sources, workload in KERNELS:
+        kw = {}
+        if counters:
+            f, w, cc = pmc[counters]
+            kw = dict(fetch=f, write=w, counter_command=cc, json_out=os.path.join(out, f"{stem}_counters.json"))
+        results[stem] = summarise(f"{raw}/trace", pattern, alg, os.path.join(out, f"{stem}.md"), sources=sources,
+                                  command=trace_str, workload=workload, **kw)
+        r = results[stem]
+        print(f"{stem}: {r['avg_ns']:.0f} ns, {r['alg_gbs']:.0f} GB/s algorithmic"
+              + (f", HBM {r['hbm_bytes_per_launch'] / alg:.3f} x algorithmic" if "hbm_bytes_per_launch" in r else ""))
+    print(f"(regenerate: python -m paper_1803_00437_amd.profiling collect --raw {raw} --out {out})")
+    return results
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect", help="run rocprofv3 on the bench and write every summary")
+    c.add_argument("--raw", required=True, help="directory for rocprofv3 output (large; not for committing)")
+    c.add_argument("--out", required=True, help="directory for the summaries")
+    s = sub.add_parser("summarise", help="summarise existing rocprofv3 output for one kernel")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--fetch")
+    s.add_argument("--write")
+    s.add_argument("--kernel", required=True, help="substring of the kernel name to summarise")
+    s.add_argument("--launch-alg-bytes", type=int, required=True, help="algorithmic bytes moved per launch")
+    s.add_argument("--command", default="")
+    s.add_argument("--counter-command", default="")
+    s.add_argument("--out", required=True)
+    s.add_argument("--json")
+    s.add_argument("--sources", nargs="*", default=[])
+    s.add_argument("--n", type=int, default=N)
+    args = ap.parse_args()
+    if args.cmd == "collect":
+        collect(args.raw, args.out)
+    else:
+        summarise(args.trace, args.kernel, args.launch_alg_bytes, args.out, fetch=args.fetch, write=args.write,
+                  json_out=args.json, sources=args.sources, command=args.command,
+                  counter_command=args.counter_command, n=args.n)
+        print(open(args.out).read())
 
 
 if __name__ == "__main__":

@@ -1,0 +1,158 @@
+"""The configurations of the build at their own sizes, on the GPU.
+
+* 256 x 256 "Stokes modes": band-limited random fields (modes 0 < |k| <= 8).  Against the
+  oracle over 200 steps, and -- at tiny amplitude, where the scheme is linear -- every
+  sampled Fourier mode after 2000 steps against the amplification matrix H(k)^2000
+  (decay of the shear root, speed and damping of the sound roots).
+* Poiseuille channel 16384 x 1024 with walls and a body force (section 3-c), FP32: the
+  x-invariant profile against the FP64 oracle on an 8-column channel, and the analytic
+  parabola.
+* 8192 x 8192 decaying flow over 2000 steps: FP32 and FP16 storage against the FP64 GPU
+  run (itself checked against the oracle at this size in test_gpu_sweep.py).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import symbol as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1803_00437_amd as F
+
+    F.load_library()
+    return F
+
+
+def rel_l2(a, b):
+    return math.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(a, b)) / sum(float(np.sum(y * y)) for y in b))
+
+
+def fourier(f, mx, my):
+    ny, nx = f.shape[-2:]
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    return np.sum(f * np.exp(-2j * np.pi * (mx * x / nx + my * y / ny)), axis=(-2, -1))
+
+
+def run_gpu(F, init, steps, **kw):
+    ny, nx = init[0].shape
+    sim = F.FdLbm(nx, ny, **kw)
+    sim.set_state(*init)
+    sim.step(steps)
+    out = sim.get_populations() if kw.get("scheme") == "mrt" else sim.get_state()
+    sim.close()
+    return out
+
+
+NU = 0.05  # Table 2's long-wavelength viscosity
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_stokes_modes_256_against_oracle(F, scheme, dtype, tol):
+    init = W.stokes_modes_256(seed=2)
+    s_xx = O.rate_from_viscosity(NU)
+    steps = 200
+    if scheme == "mrt":
+        got = run_gpu(F, init, steps, scheme="mrt", dtype=dtype, s_xx=s_xx, quartic=True)
+        want = O.mrt_run(O.mrt_init(*init), steps, s_xx=s_xx, s_q=O.quartic_s_q(s_xx))
+        err = math.sqrt(float(np.sum((got - want) ** 2)) / float(np.sum(want ** 2)))
+    else:
+        st = int(scheme[2])
+        got = run_gpu(F, init, steps, scheme="fd", stencil=st, dtype=dtype, s_xx=s_xx, s_e=1.0)
+        want = O.fd_run(*init, steps, s_xx=s_xx, s_e=1.0, stencil=st)
+        err = rel_l2(got, want)
+    print(f"  256^2 {scheme} {dtype} 200 steps rel L2 {err:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+def test_stokes_modes_256_dispersion(F, scheme):
+    """At RMS amplitude 1e-12 the 2000-step evolution of each Fourier mode is H(k)^2000
+    applied to its initial amplitudes (shear decay, sound speed and sound damping).  The
+    residual is the quadratic coupling between modes: it scales with the amplitude (about
+    240 x rms on the FP64 oracle for this field), so 1e-8 leaves a margin of 40."""
+    init = W.stokes_modes_256(seed=2, rms=1e-12)
+    n, steps = 256, 2000
+    s_xx = O.rate_from_viscosity(NU)
+    modes = [(1, 0), (3, 4), (8, 0), (5, 5), (6, -3), (0, 7)]
+    if scheme == "mrt":
+        s_q = O.quartic_s_q(s_xx)
+        f0 = O.mrt_init(*init)
+        got = run_gpu(F, init, steps, scheme="mrt", dtype="f64", s_xx=s_xx, quartic=True)
+    else:
+        st = int(scheme[2])
+        got = run_gpu(F, init, steps, scheme="fd", stencil=st, dtype="f64", s_xx=s_xx, s_e=1.0)
+    for m in modes:
+        kx, ky = 2 * math.pi * m[0] / n, 2 * math.pi * m[1] / n
+        if scheme == "mrt":
+            H = S.mrt_symbol(kx, ky, s_xx=s_xx, s_q=s_q)
+            phi0, phi = fourier(f0, *m), fourier(got, *m)
+        else:
+            H = S.fd_symbol(kx, ky, s_xx=s_xx, s_e=1.0, stencil=int(scheme[2]))
+            phi0 = np.array([fourier(a, *m) for a in init])
+            phi = np.array([fourier(a, *m) for a in got])
+        pred = np.linalg.matrix_power(H, steps) @ phi0
+        err = np.max(np.abs(phi - pred)) / np.max(np.abs(pred))
+        assert err < 1e-8, (m, err)
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "mrt"])
+def test_poiseuille_channel_16384x1024(F, scheme):
+    """FP32 channel 16384 x 1024 started from the analytic parabola: after 2000 steps the
+    profile is x-invariant, equals the FP64 oracle's on an 8-column channel, and stays
+    within 5e-6 of the parabola (relative L2; the FP64 oracle is within 5e-7)."""
+    nx, ny, steps = 16384, 1024, 2000
+    nu = 1 / math.sqrt(108)
+    s_xx = O.rate_from_viscosity(nu)
+    r, x, y, Fx = W.poiseuille_profile(nx, ny, nu, 0.05)
+    exact = x[:, 0].copy()
+    kw = dict(bc="walls", dtype="f32", s_xx=s_xx, force=(Fx, 0.0))
+    if scheme == "mrt":
+        sim = F.FdLbm(nx, ny, scheme="mrt", quartic=True, **kw)
+    else:
+        sim = F.FdLbm(nx, ny, scheme="fd", stencil=3, s_e=1.0, **kw)
+    sim.set_state(r, x, y)
+    sim.step(steps)
+    gr, gx, gy = sim.get_state()
+    sim.close()
+    spread = float(np.max(np.abs(gx - gx[:, :1])))
+    assert spread < 1e-7 * 0.05, spread
+    u = gx.mean(axis=1) + Fx / 2
+    r8, x8, y8 = (a[:, :8].copy() for a in (r, x, y))
+    if scheme == "mrt":
+        want = O.mrt_moments(O.mrt_run(O.mrt_init(r8, x8, y8), steps, s_xx=s_xx, s_q=O.quartic_s_q(s_xx),
+                                       walls=True, fx=Fx))[1][:, 0] + Fx / 2
+    else:
+        want = O.fd_run(r8, x8, y8, steps, s_xx=s_xx, s_e=1.0, stencil=3, walls=True, fx=Fx)[1][:, 0] + Fx / 2
+    err_oracle = np.linalg.norm(u - want) / np.linalg.norm(want)
+    err_parab = np.linalg.norm(u - exact) / np.linalg.norm(exact)
+    print(f"  {scheme}: rel L2 vs oracle {err_oracle:.2e}, vs parabola {err_parab:.2e}")
+    assert err_oracle < 1e-5
+    assert err_parab < 5e-6
+
+
+def test_decaying_flow_8192_2000_steps(F):
+    """FP32 keeps the FP64 result to 1e-5 over 2000 steps (measured 3e-7: the update adds
+    small differences to the stored state, so no rounding bias accumulates).  FP16 storage
+    is limited by its 11-bit significand: on this slowly varying flow a step changes a value
+    by about one FP16 unit, and after 2000 steps the relative L2 error is 2.9e-2 (5e-4 after
+    12 steps, see test_gpu_sweep.py); the bound 5e-2 states that measurement."""
+    n, steps = 8192, 2000
+    init = W.decaying_flow(n=n, seed=4, kmax=32, amp=0.02)
+    s_xx = O.rate_from_viscosity(0.02)
+    ref = run_gpu(F, init, steps, scheme="fd", stencil=3, dtype="f64", s_xx=s_xx, s_e=1.0)
+    e32 = rel_l2(run_gpu(F, init, steps, scheme="fd", stencil=3, dtype="f32", s_xx=s_xx, s_e=1.0), ref)
+    e16 = rel_l2(run_gpu(F, init, steps, scheme="fd", stencil=3, dtype="f16", s_xx=s_xx, s_e=1.0), ref)
+    print(f"  8192^2 2000 steps: FP32 rel L2 {e32:.2e}, FP16 storage rel L2 {e16:.2e} (vs FP64 GPU)")
+    assert e32 < 1e-5
+    assert e16 < 5e-2
