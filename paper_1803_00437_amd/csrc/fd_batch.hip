@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = b.tile / I.strips_x;
-    sweep_tile<T, 1, 3, false>(t, band, b.tile - band * I.strips_x);
+    sweep_tile<T, 1, 3, false, false>(t, band, b.tile - band * I.strips_x);
 }
 
 // Single instance in the same tiling: the one-launch-per-grid path of the comparison.
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict_
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = blockIdx.x / I.strips_x;
-    sweep_tile<T, 1, 3, false>(t, band, blockIdx.x - band * I.strips_x);
+    sweep_tile<T, 1, 3, false, false>(t, band, blockIdx.x - band * I.strips_x);
 }
 
 __device__ __forceinline__ double wave_sum(double v)

@@ -5,7 +5,7 @@
 // the propagated populations (eq. 2) and adds their difference from the node's own to the
 // stored (drho, jx, jy).  It moves about four times the bytes of the fused kernel and
 // exists as the plain GPU rendering that the fused kernel must match bit for bit; both
-// use fd_node_fstar(), row_sum(), fd_partial() and fd_finish().
+// use fd_node_fstar(), row_sum(), same_row_part(), fd_partial() and fd_finish().
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
 
@@ -38,7 +38,7 @@ template <typename T, bool WALLS> struct View {
     }
 };
 
-template <typename T, int ST, bool WALLS>
+template <typename T, int ST, bool WALLS, bool FORCE>
 __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typename Storage<T>::C> k, int row0,
                                                     int nrows, typename Storage<T>::C *__restrict__ fstar)
 {
@@ -72,7 +72,8 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
     C P[5], Rx[5], Ry[5], Q[5];
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
-        const C ax = xX[o] + k.hfx, ay = yX[o] + k.hfy, bx = xY[o] + k.hfx, by = yY[o] + k.hfy;
+        const C ax = plus_force<FORCE>(xX[o], k.hfx), ay = plus_force<FORCE>(yX[o], k.hfy);
+        const C bx = plus_force<FORCE>(xY[o], k.hfx), by = plus_force<FORCE>(yY[o], k.hfy);
         P[o] = ax * ax;
         Rx[o] = ax * ay;
         Ry[o] = bx * by;
@@ -84,14 +85,14 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
     d[9] = S::diff(Q[0], Q[1], Q[3], Q[4]);
 
     C f[9];
-    fd_node_fstar<C>(rX[2], xX[2] + k.hfx, yX[2] + k.hfy, d, k, f);
+    fd_node_fstar<C, FORCE>(rX[2], plus_force<FORCE>(xX[2], k.hfx), plus_force<FORCE>(yX[2], k.hfy), d, k, f);
     const size_t plane = (size_t)nrows * (size_t)v.nx;
     const size_t p = (size_t)rr * (size_t)v.nx + (size_t)i;
 #pragma unroll
     for (int q = 0; q < 9; ++q) fstar[q * plane + p] = f[q];
 }
 
-template <typename T, bool WALLS>
+template <typename T, bool WALLS, bool FORCE>
 __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::C *__restrict__ fstar,
                                                      const T *__restrict__ in, FdCoef<typename Storage<T>::C> k,
                                                      int nx, int ny, int row0, int nrows, T *__restrict__ odr,
@@ -110,8 +111,8 @@ __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::
         return fstar[q * plane + (size_t)rr * (size_t)nx + (size_t)ii];
     };
     // arriving minus own, per source row: same row, row below, row above
-    const C pc = row_sum(F(0, 0, 0), F(1, -1, 0), F(3, 1, 0)) - row_sum(F(0, 0, 0), F(1, 0, 0), F(3, 0, 0));
-    const C pcx = (F(1, -1, 0) - F(3, 1, 0)) - (F(1, 0, 0) - F(3, 0, 0));
+    C pc, pcx;
+    same_row_part<C>(F(1, -1, 0) - F(1, 0, 0), F(3, 1, 0) - F(3, 0, 0), pc, pcx);
     const C pu = row_sum(F(2, 0, -1), F(5, -1, -1), F(6, 1, -1)) - row_sum(F(2, 0, 0), F(5, 0, 0), F(6, 0, 0));
     const C pux = (F(5, -1, -1) - F(6, 1, -1)) - (F(5, 0, 0) - F(6, 0, 0));
     const C pd = row_sum(F(4, 0, 1), F(8, -1, 1), F(7, 1, 1)) - row_sum(F(4, 0, 0), F(8, 0, 0), F(7, 0, 0));
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::
     const size_t n = (size_t)nx * (size_t)ny;
     const size_t p = (size_t)j * (size_t)nx + (size_t)i;
     C r, x, y;
-    fd_finish<C>(fd_partial<C>(pc, pcx, pu, pux), pd, pdx, Storage<T>::load(in[p]), Storage<T>::load(in[n + p]),
+    fd_finish<C, FORCE>(fd_partial<C>(pc, pcx, pu, pux), pd, pdx, Storage<T>::load(in[p]), Storage<T>::load(in[n + p]),
                  Storage<T>::load(in[2 * n + p]), k.dfx, k.dfy, r, x, y);
     odr[p] = Storage<T>::store(r);
     ojx[p] = Storage<T>::store(x);
@@ -142,7 +143,7 @@ template <typename T> FdCoef<typename Storage<T>::C> make_coef(const FdArgs &a)
     return k;
 }
 
-template <typename T, int ST, bool WALLS>
+template <typename T, int ST, bool WALLS, bool FORCE>
 hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
 {
     using C = typename Storage<T>::C;
@@ -154,20 +155,29 @@ hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStre
     const int row0 = WALLS ? -1 : 0, nrows = WALLS ? a.ny + 2 : a.ny;
     dim3 blk(64, 4);
     dim3 g1((a.nx + 63) / 64, (nrows + 3) / 4);
-    hipLaunchKernelGGL((fd_ref_fstar<T, ST, WALLS>), g1, blk, 0, s, v, k, row0, nrows, static_cast<C *>(fstar));
+    hipLaunchKernelGGL((fd_ref_fstar<T, ST, WALLS, FORCE>), g1, blk, 0, s, v, k, row0, nrows, static_cast<C *>(fstar));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g2((a.nx + 63) / 64, (a.ny + 3) / 4);
-    hipLaunchKernelGGL((fd_ref_gather<T, WALLS>), g2, blk, 0, s, static_cast<const C *>(fstar), in, k, a.nx, a.ny,
+    hipLaunchKernelGGL((fd_ref_gather<T, WALLS, FORCE>), g2, blk, 0, s, static_cast<const C *>(fstar), in, k, a.nx, a.ny,
                        row0, nrows, out, out + n, out + 2 * n);
     return hipGetLastError();
+}
+
+template <typename T, int ST, bool WALLS>
+hipError_t dispatch_force(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
+{
+    if (a.fx != 0.0 || a.fy != 0.0) return run<T, ST, WALLS, true>(a, src, dst, fstar, s);
+    return run<T, ST, WALLS, false>(a, src, dst, fstar, s);
 }
 
 template <typename T>
 hipError_t dispatch_stencil(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
 {
-    if (a.stencil == 3) return a.walls ? run<T, 3, true>(a, src, dst, fstar, s) : run<T, 3, false>(a, src, dst, fstar, s);
-    return a.walls ? run<T, 5, true>(a, src, dst, fstar, s) : run<T, 5, false>(a, src, dst, fstar, s);
+    if (a.stencil == 3)
+        return a.walls ? dispatch_force<T, 3, true>(a, src, dst, fstar, s)
+                       : dispatch_force<T, 3, false>(a, src, dst, fstar, s);
+    return a.walls ? dispatch_force<T, 5, true>(a, src, dst, fstar, s) : dispatch_force<T, 5, false>(a, src, dst, fstar, s);
 }
 
 }  // namespace

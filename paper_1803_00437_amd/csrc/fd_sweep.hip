@@ -26,8 +26,9 @@
 //     block of rows: the halo rows a block shares with the bands above and below are then
 //     re-read from cache, and HBM sees a few long sequential streams;
 //   * all row bookkeeping is wave-uniform (scalar registers).
-// Per node the arithmetic is fd_node_fstar() and the summation order is fd_gather()'s, so
-// the result equals the reference path bit for bit.
+// Per node the arithmetic is fd_node_fstar() and the update is formed with the helpers and
+// in the order of fdlbm_device.hpp, so the result equals the reference path bit for bit.
+// A run without body force uses kernels built without the force additions.
 //
 // Walls (rows -1 .. -(h+1) and ny .. ny+h are ghosts): the mirror of the xi = 1/2
 // extrapolation of section 3-c is applied as a row is loaded (drho even, J odd).
@@ -43,15 +44,15 @@ template <typename T> struct SweepArgs {
     int strips_x;
 };
 
-template <typename T, int CPL, int ST, bool WALLS>
+template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
 __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 {
     // blocks dealt out row band after row band
     const int band = blockIdx.x / a.strips_x;
-    sweep_tile<T, CPL, ST, WALLS>(a.t, band, blockIdx.x - band * a.strips_x);
+    sweep_tile<T, CPL, ST, WALLS, FORCE>(a.t, band, blockIdx.x - band * a.strips_x);
 }
 
-template <typename T, int CPL, int ST, bool WALLS>
+template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
 hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
     using C = typename Storage<T>::C;
@@ -68,24 +69,31 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     a.t.ojy = out + 2 * n;
     a.t.nx = fa.nx;
     a.t.ny = fa.ny;
-    // rows per wavefront (>= 2, see the tile body); 8 measured best at 8192^2
-    a.t.rows = tile_rows >= 2 ? tile_rows : 8;
+    // rows per wavefront (>= 2, see the tile body); 16 measured best at 8192^2
+    a.t.rows = tile_rows >= 2 ? tile_rows : 16;
     a.t.k = make_coef<C>(ST, fa.s_xx, fa.s_e, fa.fx, fa.fy);
     a.strips_x = (fa.nx + G::S - 1) / G::S;
     const int nbands = (fa.ny + WV * a.t.rows - 1) / (WV * a.t.rows);
-    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS>), a.strips_x * nbands, 64 * WV, 0, s, a);
+    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS, FORCE>), a.strips_x * nbands, 64 * WV, 0, s, a);
     return hipGetLastError();
+}
+
+template <typename T, int CPL, int ST, bool WALLS>
+hipError_t dispatch_force(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s)
+{
+    if (a.fx != 0.0 || a.fy != 0.0) return run<T, CPL, ST, WALLS, true>(a, tile_rows, src, dst, s);
+    return run<T, CPL, ST, WALLS, false>(a, tile_rows, src, dst, s);
 }
 
 template <typename T, int CPL>
 hipError_t dispatch_cpl(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
     if (a.stencil == 3)
-        return a.walls ? run<T, CPL, 3, true>(a, tile_rows, src, dst, s)
-                       : run<T, CPL, 3, false>(a, tile_rows, src, dst, s);
+        return a.walls ? dispatch_force<T, CPL, 3, true>(a, tile_rows, src, dst, s)
+                       : dispatch_force<T, CPL, 3, false>(a, tile_rows, src, dst, s);
     if constexpr (CPL >= 2)
-        return a.walls ? run<T, CPL, 5, true>(a, tile_rows, src, dst, s)
-                       : run<T, CPL, 5, false>(a, tile_rows, src, dst, s);
+        return a.walls ? dispatch_force<T, CPL, 5, true>(a, tile_rows, src, dst, s)
+                       : dispatch_force<T, CPL, 5, false>(a, tile_rows, src, dst, s);
     return hipErrorInvalidValue;
 }
 

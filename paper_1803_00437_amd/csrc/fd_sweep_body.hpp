@@ -77,7 +77,7 @@ enum { PUB_DN = 0, PUB_DNX, PUB_UP, PUB_UPX, OWN_PC, OWN_PCX, OWN_LU, OWN_LUX, O
 
 // One tile: the block's WV wavefronts over column strip sx and row band `band` of one
 // grid.  Called by every wavefront of the block (it contains a block barrier).
-template <typename T, int CPL, int ST, bool WALLS>
+template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
 __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int sx)
 {
     using C = typename Storage<T>::C;
@@ -165,7 +165,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     // y-derivative fields (drho, Jy, Jx, JxJy, Jy^2) -> d[1], d[3], d[5], d[7], d[9]
     // (products of J_a).  yfield(q, slot, c): y-derivative field q of a window row.
     auto yfield = [&](int q, int slot, int c) -> C {
-        const C xa = w[1][slot][c] + a.k.hfx, ya = w[2][slot][c] + a.k.hfy;
+        const C xa = plus_force<FORCE>(w[1][slot][c], a.k.hfx), ya = plus_force<FORCE>(w[2][slot][c], a.k.hfy);
         return q == 0 ? w[0][slot][c] : q == 1 ? w[2][slot][c] : q == 2 ? w[1][slot][c] : q == 3 ? xa * ya : ya * ya;
     };
 
@@ -182,8 +182,8 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
             C xf[5][CPL], jxa[CPL], jya[CPL];
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                jxa[c] = w[1][cs][c] + a.k.hfx;
-                jya[c] = w[2][cs][c] + a.k.hfy;
+                jxa[c] = plus_force<FORCE>(w[1][cs][c], a.k.hfx);
+                jya[c] = plus_force<FORCE>(w[2][cs][c], a.k.hfy);
                 xf[0][c] = w[0][cs][c];
                 xf[1][c] = w[1][cs][c];
                 xf[2][c] = w[2][cs][c];
@@ -217,7 +217,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
                     d[2 * q] = S::diff(m2, m1, p1, p2);
                     d[2 * q + 1] = S::diff(ym2, yfield(q, (ph + H - 1) % NW, c), yfield(q, (ph + H + 1) % NW, c), yp2);
                 }
-                fd_node_fstar<C>(w[0][cs][c], jxa[c], jya[c], d, a.k, f[c]);
+                fd_node_fstar<C, FORCE>(w[0][cs][c], jxa[c], jya[c], d, a.k, f[c]);
             }
             // populations moving along +x come from the column on the left, along -x from
             // the column on the right
@@ -240,8 +240,8 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
                 // the same groups of this node's own populations
                 const C lu = row_sum(f[c][2], f[c][5], f[c][6]), lux = f[c][5] - f[c][6];
                 const C ld = row_sum(f[c][4], f[c][8], f[c][7]), ldx = f[c][8] - f[c][7];
-                const C pc = row_sum(f[c][0], c1, c3) - row_sum(f[c][0], f[c][1], f[c][3]);
-                const C pcx = (c1 - c3) - (f[c][1] - f[c][3]);
+                C pc, pcx;
+                same_row_part<C>(c1 - f[c][1], c3 - f[c][3], pc, pcx);
                 const C pd = dn - LD[c], pdx = dnx - LDX[c];  // row-above part of row r - 1
                 if (!bottom && it == 0) {
                     // f* of the first row: its downward sums complete the last output row
@@ -260,7 +260,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
                 }
                 // output row r - 1
                 C nr, nxv, nyv;
-                fd_finish<C>(QP[c], pd, pdx, w[0][os][c], w[1][os][c], w[2][os][c], a.k.dfx, a.k.dfy, nr, nxv, nyv);
+                fd_finish<C, FORCE>(QP[c], pd, pdx, w[0][os][c], w[1][os][c], w[2][os][c], a.k.dfx, a.k.dfy, nr, nxv, nyv);
                 gr.v[c] = Storage<T>::store(nr);
                 gx.v[c] = Storage<T>::store(nxv);
                 gy.v[c] = Storage<T>::store(nyv);
@@ -312,7 +312,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
             const C pu = lds[wv - 1][PUB_UP][c][lane] - lds[wv][OWN_LU][c][lane];
             const C pux = lds[wv - 1][PUB_UPX][c][lane] - lds[wv][OWN_LUX][c][lane];
             C nr, nxv, nyv;
-            fd_finish<C>(fd_partial<C>(lds[wv][OWN_PC][c][lane], lds[wv][OWN_PCX][c][lane], pu, pux),
+            fd_finish<C, FORCE>(fd_partial<C>(lds[wv][OWN_PC][c][lane], lds[wv][OWN_PCX][c][lane], pu, pux),
                          lds[wv][OWN_PD][c][lane], lds[wv][OWN_PDX][c][lane], Storage<T>::load(o0r.v[c]),
                          Storage<T>::load(o0x.v[c]), Storage<T>::load(o0y.v[c]), a.k.dfx, a.k.dfy, nr, nxv, nyv);
             gr.v[c] = Storage<T>::store(nr);
@@ -334,7 +334,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
             const C pd = lds[wv + 1][PUB_DN][c][lane] - LD[c];
             const C pdx = lds[wv + 1][PUB_DNX][c][lane] - LDX[c];
             C nr, nxv, nyv;
-            fd_finish<C>(QP[c], pd, pdx, Storage<T>::load(o1r.v[c]), Storage<T>::load(o1x.v[c]),
+            fd_finish<C, FORCE>(QP[c], pd, pdx, Storage<T>::load(o1r.v[c]), Storage<T>::load(o1x.v[c]),
                          Storage<T>::load(o1y.v[c]), a.k.dfx, a.k.dfy, nr, nxv, nyv);
             gr.v[c] = Storage<T>::store(nr);
             gx.v[c] = Storage<T>::store(nxv);

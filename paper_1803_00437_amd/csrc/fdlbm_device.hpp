@@ -3,7 +3,8 @@
 // Obrecht, Tekitek) and the update order of the propagation (section 1, eq. 2).
 //
 // Every kernel that advances an FD-LBM state calls fd_node_fstar() with the same inputs
-// in the same order, and forms the new state with row_sum(), fd_partial() and fd_finish()
+// in the same order, and forms the new state with row_sum(), same_row_part(), fd_partial()
+// and fd_finish()
 // in the same order, so the reference and the fused kernels produce bit-identical states.
 // The library is compiled with -ffp-contract=off; every fused multiply-add below is
 // written out.
@@ -64,6 +65,10 @@ template <> struct Stencil<5> {
     }
 };
 
+// x + f for the force terms: a run without body force drops the additions (its kernels are
+// instantiated with FORCE = false; adding a zero changes no value).
+template <bool FORCE, typename C> __device__ __forceinline__ C plus_force(C x, C f) { return FORCE ? x + f : x; }
+
 // Per-step constants of the reconstruction.
 template <typename C> struct FdCoef {
     C ke;     // SCALE * (1 - 1/s_e)   multiplies theta_E (unscaled derivatives)
@@ -86,7 +91,7 @@ template <typename C> struct FdCoef {
 //   XY = Jx Jy/rho + (1 - 1/s_xx) theta_XY,  q = -J,  eps = rho - 3|J|^2/rho;
 // then f* = M^{-1} m* written out per velocity (M^{-1} = M^T diag(1/9, 1/6, 1/6, 1/36,
 // 1/4, 1/4, 1/12, 1/12, 1/36), section 1), as deviations from the rest populations.
-template <typename C>
+template <typename C, bool FORCE>
 __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10], const FdCoef<C> &k, C (&f)[9])
 {
     const C rx = d[0], ry = d[1], a = d[2], b = d[3], c = d[4], dd = d[5];
@@ -116,13 +121,13 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
     const C A_dg = fmac(dr, C(1.0 / 36.0), fmac(te, C(1.0 / 18.0), k12));
     f[0] = fmac(dr, C(4.0 / 9.0), fmac(K, C(-2.0 / 3.0), te * C(-1.0 / 9.0)));
     const C axp = fmac(XX, C(0.25), A_ax), axm = fmac(XX, C(-0.25), A_ax);
-    const C ux = (jx + k.qfx) * C(1.0 / 3.0), uy = (jy + k.qfy) * C(1.0 / 3.0);
+    const C ux = plus_force<FORCE>(jx, k.qfx) * C(1.0 / 3.0), uy = plus_force<FORCE>(jy, k.qfy) * C(1.0 / 3.0);
     f[1] = axp + ux;
     f[3] = axp - ux;
     f[2] = axm + uy;
     f[4] = axm - uy;
     const C dgp = fmac(XY, C(0.25), A_dg), dgm = fmac(XY, C(-0.25), A_dg);
-    const C vx = (jx + k.dfx) * C(1.0 / 12.0), vy = (jy + k.dfy) * C(1.0 / 12.0);
+    const C vx = plus_force<FORCE>(jx, k.dfx) * C(1.0 / 12.0), vy = plus_force<FORCE>(jy, k.dfy) * C(1.0 / 12.0);
     const C s = vx + vy, t = vy - vx;
     f[5] = dgp + s;
     f[7] = dgp - s;
@@ -135,15 +140,23 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
 // to sum_k f*_k(x) = drho(x) and sum_k e_k f*_k(x) = J(x) + F, and
 //   drho' = drho + sum_k [f*_k(x - e_k) - f*_k(x)],   J' = J + F + sum_k e_k [f*_k(x - e_k) - f*_k(x)].
 // The populations are grouped by the row they come from:
-//   same row   f0(x), f1(x - ex), f3(x + ex)
+//   same row   f1(x - ex), f3(x + ex)                       (f0 stays: no change)
 //   row below  f2(x - ey), f5(x - ex - ey), f6(x + ex - ey)
 //   row above  f4(x + ey), f8(x - ex + ey), f7(x + ex + ey)
-// Each group is summed (middle, from the left, from the right) and the same sum of the
-// node's own populations is subtracted; the three small differences are added to the
+// In the same row each arriving population is compared with the node's own one; the two
+// other rows are summed (middle, from the left, from the right) and the same sum of the
+// node's own populations is subtracted.  The three small differences are added to the
 // stored value last.  Summing the nine arriving populations directly rounds at the scale
-// of the field every step, and because the rounded weights 1/9, 1/36, 1/3, 1/12 do not add
-// up to exactly one in FP32, a slowly varying field then drifts by about 3e-8 per step.
+// of the field every step, and because the rounded weights 1/9, 1/36, 1/3, 1/12 do not
+// add up to exactly one in FP32, a slowly varying field then drifts by about 3e-8 per step.
 template <typename C> __device__ __forceinline__ C row_sum(C mid, C from_l, C from_r) { return (mid + from_l) + from_r; }
+
+// Same-row part from e1 = f1(x - ex) - f1(x) and e3 = f3(x + ex) - f3(x): drho and Jx parts.
+template <typename C> __device__ __forceinline__ void same_row_part(C e1, C e3, C &pc, C &pcx)
+{
+    pc = e1 + e3;
+    pcx = e1 - e3;
+}
 
 // The update in two halves, so that a kernel which meets the three source rows at
 // different times forms exactly the same sums.  pc, pu, pd: (arriving - own) for drho from
@@ -157,13 +170,13 @@ template <typename C> __device__ __forceinline__ FdPartial<C> fd_partial(C pc, C
 {
     return FdPartial<C>{pc + pu, pcx + pux, pu};
 }
-template <typename C>
+template <typename C, bool FORCE>
 __device__ __forceinline__ void fd_finish(const FdPartial<C> &a, C pd, C pdx, C odr, C ojx, C ojy, C fx, C fy, C &dr,
                                           C &jx, C &jy)
 {
     dr = odr + (a.q + pd);
-    jx = ojx + ((a.qx + pdx) + fx);
-    jy = ojy + ((a.pu - pd) + fy);
+    jx = ojx + plus_force<FORCE>(a.qx + pdx, fx);
+    jy = ojy + plus_force<FORCE>(a.pu - pd, fy);
 }
 
 }  // namespace fdlbm
