@@ -44,7 +44,7 @@ def bytes_per_node(scheme, dtype):
 
 
 def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with_diag, tile_rows=0, lane_cols=0,
-             bc="periodic", nu=NU, force=(0.0, 0.0)):
+             bc="periodic", nu=NU, force=(0.0, 0.0), autotune=True):
     ny, nx = init[0].shape
     s_xx = F.fdlbm_rate_from_viscosity(nu)
     kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel, tile_rows=tile_rows, bc=bc, force=force)
@@ -56,6 +56,10 @@ def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with
         kw["quartic"] = True
     sim = F.FdLbm(nx, ny, **kw)
     sim.set_state(*init)
+    shape = None
+    if autotune and not (tile_rows or lane_cols):
+        # tile shape picked by the library's tuner on this grid (untimed set-up)
+        shape = sim.autotune(reps=10)[:2]
     sim.step(warmup)
     torch.cuda.synchronize()
     # kernel-only region, timed with HIP events on the library's stream
@@ -87,6 +91,7 @@ def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with
         "kernel_mlups": nodes / (kernel_ms * 1e3),
         "alg_gbs": bytes_per_node(scheme, dtype) * nodes / (kernel_ms * 1e6),
         "nonfinite": diag["nonfinite"],
+        "tile": {"lane_cols": shape[0], "tile_rows": shape[1]} if shape else None,
     }
 
 
@@ -109,7 +114,7 @@ def measure_copy(F, torch, probe=False, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e6)
 
 
-def run_batch(F, torch, W, steps, per_instance_steps, every=10):
+def run_batch(F, torch, W, steps, per_instance_steps, every=10, autotune=True):
     """The 512-instance shear-wave sweep: N ~ U{32..1024}, nu ~ U[0.005, 0.1], m ~ U{1..4},
     FP32, 3-point differences; one launch per step for all instances with A(t) sampled every
     `every` steps (graph-replayed), against one launch per instance per step."""
@@ -119,6 +124,7 @@ def run_batch(F, torch, W, steps, per_instance_steps, every=10):
     for i, d in enumerate(insts):
         b.set_state(i, *W.shear_wave_y(d["n"], d["n"], d["amp"], d["m"]))
     nodes = sum(d["n"] * d["n"] for d in insts)
+    rows = b.autotune(reps=3)[0] if autotune else 8
     b.step(20, sample_every=every, use_graph=True)
     b.stream.synchronize()
     t0 = time.perf_counter()
@@ -134,7 +140,7 @@ def run_batch(F, torch, W, steps, per_instance_steps, every=10):
     nsamp = b.amplitudes().shape[1]
     b.close()
     return {
-        "instances": len(insts), "nodes": nodes, "sample_every": every, "samples": nsamp,
+        "instances": len(insts), "nodes": nodes, "sample_every": every, "samples": nsamp, "tile_rows": rows,
         "graph_steps": steps, "graph_ms_per_step": round(graph_s * 1e3 / steps, 4),
         "graph_instance_steps_per_s": round(len(insts) * steps / graph_s, 1),
         "graph_mlups": round(nodes * steps / graph_s / 1e6, 1),
@@ -201,6 +207,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wavefront strip of the sweep kernel (0 = default)")
     ap.add_argument("--lane-cols", type=int, default=0, help="grid columns per lane of the sweep kernel (0 = default)")
     ap.add_argument("--only", default=None, help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default tile shapes instead of tuning them before timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run the 1 GiB streaming copy a few more times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -232,13 +240,13 @@ def main():
         scheme = "mrt" if name == "mrt" else "fd"
         stencil = int(name[2]) if scheme == "fd" else 0
         case = run_case(F, torch, init, scheme, dtype, stencil, args.steps, args.warmup, args.kernel, False,
-                        args.tile_rows, args.lane_cols)
+                        args.tile_rows, args.lane_cols, autotune=not args.no_autotune)
         print(json.dumps({"case": args.only, "tile_rows": args.tile_rows, "lane_cols": args.lane_cols, **case}),
               flush=True)
         return
 
     main_case = run_case(F, torch, init, "fd", "f32", 3, args.steps, args.warmup, args.kernel, True,
-                         args.tile_rows, args.lane_cols)
+                         args.tile_rows, args.lane_cols, autotune=not args.no_autotune)
     print(f"# fd3 f32: {main_case}", file=sys.stderr, flush=True)
 
     compare = {}
@@ -247,7 +255,8 @@ def main():
         for scheme, dtype, stencil in (("mrt", "f32", 0), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5),
                                        ("mrt", "f64", 0)):
             key = f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"
-            compare[key] = run_case(F, torch, init, scheme, dtype, stencil, short, 10, args.kernel, False)
+            compare[key] = run_case(F, torch, init, scheme, dtype, stencil, short, 10, args.kernel, False,
+                                    autotune=not args.no_autotune)
             print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
         # the 16384 x 1024 Poiseuille channel: walls at y = -1/2 and ny - 1/2, body force along x
         nu_ch = 1.0 / math.sqrt(108.0)
@@ -255,13 +264,13 @@ def main():
         for scheme, stencil in (("fd", 3), ("mrt", 0)):
             key = f"poiseuille_16384x1024_{scheme}{stencil if scheme == 'fd' else ''}_f32"
             compare[key] = run_case(F, torch, (r, x, y), scheme, "f32", stencil, short, 10, args.kernel, False,
-                                    bc="walls", nu=nu_ch, force=(fx, 0.0))
+                                    bc="walls", nu=nu_ch, force=(fx, 0.0), autotune=not args.no_autotune)
             print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
         del r, x, y
 
     batch = None
     if not args.no_batch:
-        batch = run_batch(F, torch, W, args.batch_steps, max(10, args.batch_steps // 4))
+        batch = run_batch(F, torch, W, args.batch_steps, max(10, args.batch_steps // 4), autotune=not args.no_autotune)
         print(f"# batch: {batch}", file=sys.stderr, flush=True)
 
     cpu = None
@@ -310,7 +319,7 @@ def main():
             "workload": f"{n}x{n} periodic decaying flow, random Fourier modes 0<|k|<=32, max|field|=0.02, seed 4; "
                         f"FD-LBM D2Q9 3-point finite differences, nu={NU}, s_e=1, FP32; FP64 diagnostics every "
                         f"{DIAG_EVERY} steps",
-            "nx": n, "ny": n, "stencil": 3, "kernel": args.kernel,
+            "nx": n, "ny": n, "stencil": 3, "kernel": args.kernel, "tile": main_case["tile"],
         },
         "roofline": {
             "bound": "hbm",

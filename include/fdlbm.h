@@ -134,6 +134,18 @@ int fdlbm_mode_projection(fdlbm_ctx *c, double *out);
 /* Number of steps taken since the last set_state / set_populations. */
 int64_t fdlbm_step_count(const fdlbm_ctx *c);
 
+/* Tile-shape tuning (not part of the method; the results do not depend on the shape, only
+ * the speed does).  Times `reps` launches (1..10000) of this context's step kernel for
+ * each candidate shape on its own grid and keeps the fastest in the context: FD-LBM sweep
+ * kernel: grid columns per lane (1, 2, 4 where supported) x rows per wavefront (4, 6, 8,
+ * 12, 16, 24); MRT sweep kernel: rows per tile (2, 4, 8, 16).  The reference kernels have
+ * no shape and are only timed.  The state does not advance: each timed launch reads the
+ * current state and writes the spare buffer, which the next step overwrites.  Synchronises
+ * the stream.  The chosen shape goes to *out_lane_cols and *out_tile_rows (0 where the
+ * kernel has no such parameter) and its time per step in ms to *out_ms; each may be NULL.
+ * FDLBM_EINVAL for a NULL context or reps out of range, FDLBM_EDEVICE on a HIP error. */
+int fdlbm_autotune(fdlbm_ctx *c, int32_t reps, int32_t *out_lane_cols, int32_t *out_tile_rows, double *out_ms);
+
 /* Release the context.  Frees nothing the caller owns. */
 void fdlbm_destroy(fdlbm_ctx *c);
 
@@ -186,6 +198,14 @@ int fdlbm_batch_step(fdlbm_batch *b, int64_t nsteps, int32_t sample_every, int32
 
 /* The same steps with one launch per instance per step (the comparison path). */
 int fdlbm_batch_step_per_instance(fdlbm_batch *b, int64_t nsteps);
+
+/* Tile-height tuning of the batched launch: times `reps` (1..10000) one-launch steps of
+ * all instances for 4, 6, 8, 12 and 16 rows per wavefront, keeps the fastest (it is 8
+ * until tuned) and drops the cached graph replays, which are captured again on the next
+ * fdlbm_batch_step.  No step is taken (timed launches write the spare buffer).
+ * Synchronises the stream.  *out_rows, *out_ms (may be NULL): the choice and its time
+ * per step in ms.  FDLBM_EINVAL for a NULL batch or reps out of range. */
+int fdlbm_batch_autotune(fdlbm_batch *b, int32_t reps, int32_t *out_rows, double *out_ms);
 
 /* Number of recorded samples in *nsamples and, if out != NULL, the count x max_samples
  * table (row i: instance i; entries beyond *nsamples are undefined).  Synchronises. */

@@ -32,10 +32,10 @@ EXPORTED = (
     "fdlbm_set_populations", "fdlbm_get_populations", "fdlbm_step", "mrt_step",
     "fdlbm_diagnostics", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
     "fdlbm_destroy", "fdlbm_strerror", "fdlbm_last_error", "fdlbm_rate_from_viscosity",
-    "fdlbm_quartic_s_q", "fdlbm_device_copy",
+    "fdlbm_quartic_s_q", "fdlbm_device_copy", "fdlbm_autotune",
     "fdlbm_batch_workspace_bytes", "fdlbm_batch_create", "fdlbm_batch_set_state", "fdlbm_batch_get_state",
     "fdlbm_batch_step", "fdlbm_batch_step_per_instance", "fdlbm_batch_amplitudes", "fdlbm_batch_step_count",
-    "fdlbm_batch_destroy", "fdlbm_batch_last_error",
+    "fdlbm_batch_destroy", "fdlbm_batch_last_error", "fdlbm_batch_autotune",
 )
 
 
@@ -110,6 +110,7 @@ def load_library(path=LIB_PATH):
         "fdlbm_rate_from_viscosity": (ctypes.c_double, [ctypes.c_double]),
         "fdlbm_quartic_s_q": (ctypes.c_double, [ctypes.c_double]),
         "fdlbm_device_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
+        "fdlbm_autotune": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp]),
         "fdlbm_batch_workspace_bytes": (i32, [ctypes.POINTER(Instance), i32, i32, i32, ctypes.POINTER(ctypes.c_size_t),
                                               ctypes.POINTER(ctypes.c_size_t)]),
         "fdlbm_batch_create": (i32, [ctypes.POINTER(Instance), i32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp,
@@ -122,6 +123,7 @@ def load_library(path=LIB_PATH):
         "fdlbm_batch_step_count": (i64, [vp]),
         "fdlbm_batch_destroy": (None, [vp]),
         "fdlbm_batch_last_error": (ctypes.c_char_p, []),
+        "fdlbm_batch_autotune": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -228,6 +230,15 @@ def fdlbm_quartic_s_q(s_xx):
     return float(load_library().fdlbm_quartic_s_q(float(s_xx)))
 
 
+def fdlbm_autotune(ctx, reps=20):
+    """Time the candidate tile shapes of this context's step kernel and keep the fastest.
+    Returns (lane_cols, tile_rows, ms_per_step); the state does not advance."""
+    cols, rows, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load_library().fdlbm_autotune(ctx, int(reps), ctypes.byref(cols), ctypes.byref(rows), ctypes.byref(ms)),
+           "fdlbm_autotune")
+    return cols.value, rows.value, ms.value
+
+
 def fdlbm_device_copy(dst, src, nbytes, stream=0):
     """Streaming copy of nbytes between device pointers (ints) on a HIP stream handle."""
     _check(load_library().fdlbm_device_copy(dst, src, int(nbytes), stream or None), "fdlbm_device_copy")
@@ -292,6 +303,11 @@ class FdLbm:
     @property
     def steps(self):
         return fdlbm_step_count(self.ctx)
+
+    def autotune(self, reps=20):
+        """Pick the fastest tile shape for this grid (fdlbm_autotune); returns
+        (lane_cols, tile_rows, ms_per_step)."""
+        return fdlbm_autotune(self.ctx, reps)
 
     # diagnostics
     def diagnostics(self):
@@ -380,6 +396,14 @@ class FdLbmBatch:
 
     def step_per_instance(self, nsteps):
         self._chk(load_library().fdlbm_batch_step_per_instance(self.ctx, int(nsteps)), "fdlbm_batch_step_per_instance")
+
+    def autotune(self, reps=5):
+        """Pick the fastest rows per wavefront for the one-launch step (fdlbm_batch_autotune);
+        returns (rows, ms_per_step).  No step is taken."""
+        rows, ms = ctypes.c_int32(), ctypes.c_double()
+        self._chk(load_library().fdlbm_batch_autotune(self.ctx, int(reps), ctypes.byref(rows), ctypes.byref(ms)),
+                  "fdlbm_batch_autotune")
+        return rows.value, ms.value
 
     def amplitudes(self):
         """(count, nsamples) array of A(t) samples."""

@@ -2,6 +2,7 @@
 // Host code only: validation, scratch layout, stream-ordered launches of the kernels in
 // the other translation units, and FP64 host <-> device staging.
 #include <cmath>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -317,6 +318,69 @@ int fdlbm_mode_projection(fdlbm_ctx *c, double *out)
     if (rc) return rc;
     if (!(d[6] > 0)) return FDLBM_EINVAL;
     *out = d[5] / d[6];
+    return FDLBM_OK;
+}
+
+int fdlbm_autotune(fdlbm_ctx *c, int32_t reps, int32_t *out_lane_cols, int32_t *out_tile_rows, double *out_ms)
+{
+    if (!c || reps < 1 || reps > 10000) return FDLBM_EINVAL;
+    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+    const bool fd = c->p.scheme == FDLBM_SCHEME_FD;
+    const FdArgs fa = fd_args(c->p);
+    const bool ref = fd ? uses_reference(c->p) : c->p.kernel == FDLBM_KERNEL_REFERENCE;
+    // candidate shapes: (lane_cols, tile_rows); the reference kernels have none to choose
+    struct Shape {
+        int cols, rows;
+    };
+    std::vector<Shape> cand;
+    if (ref) {
+        cand.push_back({c->p.lane_cols, c->p.tile_rows});
+    } else if (fd) {
+        for (int cols : {1, 2, 4})
+            if (fd_sweep_supported(fa, cols))
+                for (int rows : {4, 6, 8, 12, 16, 24}) cand.push_back({cols, rows});
+    } else {
+        for (int rows : {2, 4, 8, 16}) cand.push_back({0, rows});
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // every timed launch reads the current state and writes the spare buffer, which the
+    // next step overwrites: the state does not advance
+    void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
+    auto launch = [&](const Shape &sh) -> hipError_t {
+        if (fd && ref) return launch_fd_reference(fa, src, dst, c->scratch + c->L.fstar, c->stream);
+        if (fd) return launch_fd_sweep(fa, sh.rows, sh.cols, src, dst, c->stream);
+        const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
+                         c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, sh.rows};
+        return launch_mrt(ma, src, dst, c->stream);
+    };
+    Shape best{0, 0};
+    float best_ms = 0.0f;
+    for (const Shape &sh : cand) {
+        if (e == hipSuccess) e = launch(sh);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(sh);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return device_error(e, "fdlbm_autotune");
+    if (!ref) {
+        c->p.lane_cols = best.cols;
+        c->p.tile_rows = best.rows;
+    }
+    if (out_lane_cols) *out_lane_cols = best.cols;
+    if (out_tile_rows) *out_tile_rows = best.rows;
+    if (out_ms) *out_ms = (double)best_ms / reps;
     return FDLBM_OK;
 }
 

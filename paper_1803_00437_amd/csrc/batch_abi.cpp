@@ -34,7 +34,9 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t al64(size_t x) { return (x + 63) & ~size_t(63); }
 bool rate_in_range(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
 
-constexpr int BATCH_ROWS = 8;  // rows per wavefront
+constexpr int BATCH_ROWS = 8;               // rows per wavefront unless tuned
+constexpr int BATCH_TUNE_ROWS[] = {4, 6, 8, 12, 16};  // candidates of fdlbm_batch_autotune
+constexpr int BATCH_MIN_ROWS = 4;           // the block table is sized for the smallest
 
 struct Plan {
     std::vector<BatchInstance> inst;
@@ -56,11 +58,28 @@ int validate(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max
     return FDLBM_OK;
 }
 
+// Tiles of every instance for `rows` rows per wavefront: the instances' band counts and
+// the block table, largest grids first so that the last blocks to start are small ones.
+void tile_tables(Plan &P, int rows)
+{
+    const int RB = batch_rows_per_block(rows);
+    for (BatchInstance &I : P.inst) I.nbands = (I.ny + RB - 1) / RB;
+    const int count = (int)P.inst.size();
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (size_t)P.inst[a].nx * P.inst[a].ny > (size_t)P.inst[b].nx * P.inst[b].ny;
+    });
+    P.blocks.clear();
+    for (int i : order)
+        for (int t = 0; t < P.inst[i].strips_x * P.inst[i].nbands; ++t) P.blocks.push_back(BatchBlock{i, t});
+}
+
 Plan plan(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max_samples)
 {
     Plan P;
     P.inst.resize(count);
-    const int S = batch_strip_stride(), RB = batch_rows_per_block(BATCH_ROWS);
+    const int S = batch_strip_stride();
     int chunk0 = 0;
     for (int i = 0; i < count; ++i) {
         BatchInstance &I = P.inst[i];
@@ -72,7 +91,6 @@ Plan plan(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max_sa
         I.nx = in[i].nx;
         I.ny = in[i].ny;
         I.strips_x = (I.nx + S - 1) / S;
-        I.nbands = (I.ny + RB - 1) / RB;
         I.first_chunk = chunk0;
         I.nchunks = (int)((n + BATCH_CHUNK - 1) / BATCH_CHUNK);
         chunk0 += I.nchunks;
@@ -81,14 +99,10 @@ Plan plan(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max_sa
         P.max_n = std::max(P.max_n, n);
         for (int c = 0; c < I.nchunks; ++c) P.chunks.push_back(BatchChunk{i, c});
     }
-    // tiles of the largest grids first, so that the last blocks to start are small ones
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (size_t)P.inst[a].nx * P.inst[a].ny > (size_t)P.inst[b].nx * P.inst[b].ny;
-    });
-    for (int i : order)
-        for (int t = 0; t < P.inst[i].strips_x * P.inst[i].nbands; ++t) P.blocks.push_back(BatchBlock{i, t});
+    // the block table is sized for the smallest tile height a tuning run may choose
+    tile_tables(P, BATCH_MIN_ROWS);
+    const size_t max_blocks = P.blocks.size();
+    tile_tables(P, BATCH_ROWS);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -96,7 +110,7 @@ Plan plan(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max_sa
         return o;
     };
     P.o_inst = take(sizeof(BatchInstance) * P.inst.size());
-    P.o_blocks = take(sizeof(BatchBlock) * P.blocks.size());
+    P.o_blocks = take(sizeof(BatchBlock) * max_blocks);
     P.o_chunks = take(sizeof(BatchChunk) * P.chunks.size());
     P.o_partials = take(2 * sizeof(double) * P.chunks.size());
     P.o_counter = take(sizeof(int));
@@ -252,6 +266,57 @@ int fdlbm_batch_get_state(fdlbm_batch *b, int32_t i, double *drho, double *jx, d
     BHIPCHK(hipMemcpyAsync(jx, st + n, nb, hipMemcpyDeviceToHost, b->stream), "batch get_state download");
     BHIPCHK(hipMemcpyAsync(jy, st + 2 * n, nb, hipMemcpyDeviceToHost, b->stream), "batch get_state download");
     BHIPCHK(hipStreamSynchronize(b->stream), "batch get_state");
+    return FDLBM_OK;
+}
+
+int fdlbm_batch_autotune(fdlbm_batch *b, int32_t reps, int32_t *out_rows, double *out_ms)
+{
+    if (!b || reps < 1 || reps > 10000) return FDLBM_EINVAL;
+    BHIPCHK(hipSetDevice(b->device), "hipSetDevice");
+    // upload the tile tables for `rows` rows per wavefront and point the launch at them
+    auto use_rows = [&](int rows) -> hipError_t {
+        tile_tables(b->P, rows);
+        hipError_t e = hipMemcpyAsync(b->scratch + b->P.o_inst, b->P.inst.data(),
+                                      sizeof(BatchInstance) * b->P.inst.size(), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->scratch + b->P.o_blocks, b->P.blocks.data(), sizeof(BatchBlock) * b->P.blocks.size(),
+                               hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        b->L.rows = rows;
+        b->L.nblocks = (int)b->P.blocks.size();
+        return e;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // timed launches read the current state and write the spare buffer: no step is taken
+    void *src = b->buf[b->cur], *dst = b->buf[b->cur ^ 1];
+    int best = b->L.rows;
+    float best_ms = 0.0f;
+    for (int rows : BATCH_TUNE_ROWS) {
+        if (e == hipSuccess) e = use_rows(rows);
+        if (e == hipSuccess) e = launch_batch_step(b->L, src, dst, b->stream);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch_step(b->L, src, dst, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = rows;
+        }
+    }
+    if (e == hipSuccess) e = use_rows(best);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    // replays captured before hold the old grid size
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+    if (e != hipSuccess) return batch_device_error(e, "fdlbm_batch_autotune");
+    if (out_rows) *out_rows = best;
+    if (out_ms) *out_ms = (double)best_ms / reps;
     return FDLBM_OK;
 }
 

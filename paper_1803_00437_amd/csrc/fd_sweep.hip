@@ -52,6 +52,15 @@ __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
     sweep_tile<T, CPL, ST, WALLS, FORCE>(a.t, band, blockIdx.x - band * a.strips_x);
 }
 
+// Rows per wavefront when the caller leaves the choice open (fastest at 8192^2): FP32
+// 3-point 8, FP32 5-point 16, FP16 storage 16, FP64 8.  fdlbm_autotune measures instead.
+int default_rows(const FdArgs &a)
+{
+    if (a.dtype == FDLBM_F64) return 8;
+    if (a.dtype == FDLBM_F16DEV) return 16;
+    return a.stencil == 3 ? 8 : 16;
+}
+
 template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
 hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
@@ -69,8 +78,8 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     a.t.ojy = out + 2 * n;
     a.t.nx = fa.nx;
     a.t.ny = fa.ny;
-    // rows per wavefront (>= 2, see the tile body); 16 measured best at 8192^2
-    a.t.rows = tile_rows >= 2 ? tile_rows : 16;
+    // rows per wavefront (>= 2, see the tile body)
+    a.t.rows = tile_rows >= 2 ? tile_rows : default_rows(fa);
     a.t.k = make_coef<C>(ST, fa.s_xx, fa.s_e, fa.fx, fa.fy);
     a.strips_x = (fa.nx + G::S - 1) / G::S;
     const int nbands = (fa.ny + WV * a.t.rows - 1) / (WV * a.t.rows);

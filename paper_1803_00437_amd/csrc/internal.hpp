@@ -33,8 +33,8 @@ hipError_t launch_fd_reference(const FdArgs &a, const void *src, void *dst, void
 size_t fd_reference_scratch_bytes(const FdArgs &a);
 
 // FD-LBM, fused sweep path: one kernel per step, no scratch.  tile_rows: rows per
-// wavefront strip (0 = fit every tile in one resident wave); lane_cols: columns per lane
-// (0 = default; 1 FP64 3-point only, 2, or 4 FP32/FP16 only).
+// wavefront (0 or 1 = default for the dtype and stencil); lane_cols: columns per lane
+// (0 = default; 1 for 3-point differences only, 2, or 4 for FP32/FP16 only).
 hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, int lane_cols, const void *src, void *dst, hipStream_t s);
 bool fd_sweep_supported(const FdArgs &a, int lane_cols);
 

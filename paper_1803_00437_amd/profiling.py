@@ -8,7 +8,7 @@ counter passes of their own) and write one summary per kernel:
 Summarise an existing set of rocprofv3 directories (``--output-format csv``) for one kernel:
 
     python -m paper_1803_00437_amd.profiling summarise --trace DIR [--fetch DIR --write DIR] \\
-        --kernel "fd_sweep_kernel<float, 4, 3, false>" --launch-alg-bytes 1610612736 \\
+        --kernel "fd_sweep_kernel<float, 4, 3, false, false>" --launch-alg-bytes 1610612736 \\
         --out profiles/NAME.md [--json profiles/NAME.json --sources a.hip b.hpp]
 
 The HBM counters are scaled by what they read for the library's streaming copy kernel
@@ -49,12 +49,13 @@ def kernel_stats(d):
     return rows
 
 
-def counter_means(d):
-    """{kernel name: (dispatches, mean counter value)} of a --pmc run."""
+def counter_means(d, counter):
+    """{kernel name: (dispatches, mean value of `counter`)} of a --pmc run."""
     acc = defaultdict(list)
     for p in _csvs(d, "counter_collection.csv"):
         for r in csv.DictReader(open(p)):
-            acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
 
 
@@ -74,13 +75,15 @@ def sources_sha(paths, root=ROOT):
 
 
 def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=None, sources=(), command="",
-              counter_command="", workload="", n=N, copy_kernel="copy_kernel", copy_bytes=COPY_BYTES):
+              counter_command="", workload="", n=N, copy_kernel="copy_kernel", copy_bytes=COPY_BYTES, generator=""):
     stats = kernel_stats(trace)
     names = {r["Name"]: r for r in stats}
     kname = pick(names, kernel)
     k = names[kname]
     avg_ns = float(k["AverageNs"])
     lines = [f"# rocprofv3 summary: `{kernel}`", ""]
+    if generator:
+        lines += [f"Written by: `{generator}` (runs the commands below on the GPU, then summarises)", ""]
     if workload:
         lines += [f"Workload: {workload}", ""]
     lines += [f"Command (kernel trace): `{command}`", "",
@@ -93,7 +96,7 @@ def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=No
     out = {"kernel": kname, "avg_ns": avg_ns, "calls": int(k["Calls"]), "alg_bytes_per_launch": alg, "n": n,
            "alg_gbs": alg / avg_ns}
     if fetch and write:
-        fm, wm = counter_means(fetch), counter_means(write)
+        fm, wm = counter_means(fetch, "FETCH_SIZE"), counter_means(write, "WRITE_SIZE")
         kf, kw = fm[pick(fm, kernel)], wm[pick(wm, kernel)]
         cf, cw = fm[pick(fm, copy_kernel)], wm[pick(wm, copy_kernel)]
         f_fetch = copy_bytes / 1024.0 / cf[1]
@@ -129,26 +132,28 @@ def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=No
 # --- collect -----------------------------------------------------------------------------
 
 BENCH = "/root/repo/bench.py"
-TRACE_ARGS = ["--steps", "100", "--warmup", "10", "--no-cpu", "--copy-probe"]
-FD_COUNTER_ARGS = ["--steps", "20", "--warmup", "2", "--no-cpu", "--no-compare", "--no-batch", "--copy-probe"]
-MRT_COUNTER_ARGS = ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--copy-probe"]
+# default tile shapes (no tuning launches mixed into the averages)
+TRACE_ARGS = ["--steps", "100", "--warmup", "10", "--no-cpu", "--copy-probe", "--no-autotune"]
+FD_COUNTER_ARGS = ["--steps", "20", "--warmup", "2", "--no-cpu", "--no-compare", "--no-batch", "--copy-probe",
+                   "--no-autotune"]
+MRT_COUNTER_ARGS = ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--copy-probe", "--no-autotune"]
 
 DECAY = "8192 x 8192 periodic decaying flow (modes 0<|k|<=32, max|field| 0.02), nu 0.02"
 KERNELS = [
     # file stem, kernel name pattern, algorithmic bytes per launch, counter pair, sources, workload
-    ("fd3_f32_8192", "fd_sweep_kernel<float, 4, 3, false>", 24 * N * N, "fd", FD_SOURCES,
+    ("fd3_f32_8192", "fd_sweep_kernel<float, 4, 3, false, false>", 24 * N * N, "fd", FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP32 (3 words read + 3 written per node)"),
     ("mrt_f32_8192", "mrt_sweep_kernel<float, 4, false>", 72 * N * N, "mrt", MRT_SOURCES,
      f"{DECAY}; MRT D2Q9, FP32 (9 words read + 9 written per node)"),
-    ("fd3_f64_8192", "fd_sweep_kernel<double, 2, 3, false>", 48 * N * N, None, FD_SOURCES,
+    ("fd3_f64_8192", "fd_sweep_kernel<double, 2, 3, false, false>", 48 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP64"),
-    ("fd3_f16_8192", "fd_sweep_kernel<__half, 2, 3, false>", 12 * N * N, None, FD_SOURCES,
+    ("fd3_f16_8192", "fd_sweep_kernel<__half, 2, 3, false, false>", 12 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP16 storage, FP32 arithmetic"),
-    ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false>", 24 * N * N, None, FD_SOURCES,
+    ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false, false>", 24 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 5-point, FP32"),
     ("mrt_f64_8192", "mrt_sweep_kernel<double, 2, false>", 144 * N * N, None, MRT_SOURCES,
      f"{DECAY}; MRT D2Q9, FP64"),
-    ("fd3_f32_channel_16384x1024", "fd_sweep_kernel<float, 4, 3, true>", 24 * CHANNEL, None, FD_SOURCES,
+    ("fd3_f32_channel_16384x1024", "fd_sweep_kernel<float, 4, 3, true, true>", 24 * CHANNEL, None, FD_SOURCES,
      "Poiseuille channel 16384 x 1024, walls at y=-1/2 and ny-1/2, body force; FD-LBM 3-point, FP32"),
     ("mrt_f32_channel_16384x1024", "mrt_sweep_kernel<float, 4, true>", 72 * CHANNEL, None, MRT_SOURCES,
      "Poiseuille channel 16384 x 1024, halfway bounce-back walls, body force; MRT D2Q9, FP32"),
@@ -170,23 +175,27 @@ def _run(cmd, log, limit, kill_signal):
         raise SystemExit(f"step failed with exit status {rc}: {' '.join(cmd)}")
 
 
-def collect(raw, out):
+def collect(raw, out, run=True):
+    """run=False only rewrites the summaries from rocprofv3 output already in `raw`."""
     raw = os.path.abspath(raw)
     os.makedirs(raw, exist_ok=True)
     os.makedirs(out, exist_ok=True)
     py = ["python3", "-u", BENCH]
-    trace_cmd = ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv", "-d", f"{raw}/trace", "--"] + py
-    _run(trace_cmd + TRACE_ARGS, f"{raw}/trace.log", 400, "TERM")
+    trace_opts = ["--kernel-trace", "--stats", "--output-format", "csv"]
+    if run:
+        _run(["rocprofv3"] + trace_opts + ["-d", f"{raw}/trace", "--"] + py + TRACE_ARGS, f"{raw}/trace.log", 400,
+             "TERM")
     pmc = {}
     for name, args in (("fd", FD_COUNTER_ARGS), ("mrt", MRT_COUNTER_ARGS)):
         for counter in ("FETCH_SIZE", "WRITE_SIZE"):
             d = f"{raw}/{name}_{counter.lower()}"
-            _run(["rocprofv3", "--pmc", counter, "--output-format", "csv", "-d", d, "--"] + py + args,
-                 f"{d}.log", 120, "KILL")
+            if run:
+                _run(["rocprofv3", "--pmc", counter, "--output-format", "csv", "-d", d, "--"] + py + args,
+                     f"{d}.log", 120, "KILL")
         pmc[name] = (f"{raw}/{name}_fetch_size", f"{raw}/{name}_write_size",
                      f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
                      f"-d <dir> -- python3 -u {BENCH} " + " ".join(args))
-    trace_str = "cd /tmp && TMPDIR=/tmp " + " ".join(trace_cmd[:-4] + ["-d", "<dir>", "--"] + py + TRACE_ARGS)
+    trace_str = "cd /tmp && TMPDIR=/tmp " + " ".join(["rocprofv3"] + trace_opts + ["-d", "<dir>", "--"] + py + TRACE_ARGS)
     results = {}
     for stem, pattern, alg, counters, sources, workload in KERNELS:
         kw = {}
@@ -194,7 +203,9 @@ def collect(raw, out):
             f, w, cc = pmc[counters]
             kw = dict(fetch=f, write=w, counter_command=cc, json_out=os.path.join(out, f"{stem}_counters.json"))
         results[stem] = summarise(f"{raw}/trace", pattern, alg, os.path.join(out, f"{stem}.md"), sources=sources,
-                                  command=trace_str, workload=workload, **kw)
+                                  command=trace_str, workload=workload,
+                                  generator="python -m paper_1803_00437_amd.profiling collect --raw <dir> --out profiles",
+                                  **kw)
         r = results[stem]
         print(f"{stem}: {r['avg_ns']:.0f} ns, {r['alg_gbs']:.0f} GB/s algorithmic"
               + (f", HBM {r['hbm_bytes_per_launch'] / alg:.3f} x algorithmic" if "hbm_bytes_per_launch" in r else ""))
@@ -208,6 +219,7 @@ def main():
     c = sub.add_parser("collect", help="run rocprofv3 on the bench and write every summary")
     c.add_argument("--raw", required=True, help="directory for rocprofv3 output (large; not for committing)")
     c.add_argument("--out", required=True, help="directory for the summaries")
+    c.add_argument("--summaries-only", action="store_true", help="rewrite the summaries from existing output")
     s = sub.add_parser("summarise", help="summarise existing rocprofv3 output for one kernel")
     s.add_argument("--trace", required=True)
     s.add_argument("--fetch")
@@ -222,7 +234,7 @@ def main():
     s.add_argument("--n", type=int, default=N)
     args = ap.parse_args()
     if args.cmd == "collect":
-        collect(args.raw, args.out)
+        collect(args.raw, args.out, run=not args.summaries_only)
     else:
         summarise(args.trace, args.kernel, args.launch_alg_bytes, args.out, fetch=args.fetch, write=args.write,
                   json_out=args.json, sources=args.sources, command=args.command,

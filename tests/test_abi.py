@@ -108,3 +108,9 @@ def test_batch_workspace_and_validation():
         assert e.value.code == F.FDLBM_EINVAL
     with pytest.raises(F.FdlbmError):
         F.fdlbm_batch_workspace_bytes(specs, "f32", -1)
+
+
+def test_autotune_rejects_bad_arguments_without_a_device():
+    lib = F.load_library()
+    assert lib.fdlbm_autotune(None, 5, None, None, None) == F.FDLBM_EINVAL
+    assert lib.fdlbm_batch_autotune(None, 5, None, None) == F.FDLBM_EINVAL

@@ -1,0 +1,52 @@
+"""Host checks of the rocprofv3 summariser: the scaling of the HBM byte counters by the
+copy kernel of known traffic, and the constants it uses for the bench workloads."""
+import csv
+import os
+
+import pytest
+
+from paper_1803_00437_amd import profiling as P
+
+
+def _write_csv(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_summary_scales_counters_by_the_copy_kernel(tmp_path):
+    trace, fetch, write = (str(tmp_path / d) for d in ("trace", "fetch", "write"))
+    _write_csv(os.path.join(trace, "vm", "1_kernel_stats.csv"),
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"],
+               [["void k<float>(int)", 10, 4000000, 400000, 90, 390000, 410000, 1],
+                ["copy_kernel(x)", 5, 1500000, 300000, 10, 290000, 310000, 1]])
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    copy_kib = (1 << 30) / 1024
+    # the fetch counter reads half of the copy's bytes, the write counter all of them
+    _write_csv(os.path.join(fetch, "vm", "1_counter_collection.csv"), hdr,
+               [["copy_kernel(x)", "FETCH_SIZE", copy_kib / 2], ["void k<float>(int)", "FETCH_SIZE", 600000.0],
+                ["void k<float>(int)", "FETCH_SIZE", 600000.0]])
+    _write_csv(os.path.join(write, "vm", "1_counter_collection.csv"), hdr,
+               [["copy_kernel(x)", "WRITE_SIZE", copy_kib], ["void k<float>(int)", "WRITE_SIZE", 800000.0]])
+    out = P.summarise(trace, "k<float>", 1_600_000_000, str(tmp_path / "s.md"), fetch=fetch, write=write,
+                      command="cmd", counter_command="ccmd")
+    assert out["avg_ns"] == 400000
+    assert out["fetch_scale"] == pytest.approx(2.0)
+    assert out["write_scale"] == pytest.approx(1.0)
+    assert out["hbm_bytes_per_launch"] == pytest.approx(600000 * 1024 * 2 + 800000 * 1024)
+    text = open(tmp_path / "s.md").read()
+    assert "cmd" in text and "ccmd" in text and "FETCH_SIZE" in text
+
+
+def test_batch_node_count_matches_the_workload():
+    import workloads as W
+
+    assert P.BATCH_NODES == sum(d["n"] ** 2 for d in W.batch_instances(512, seed=5))
+
+
+def test_kernel_sources_exist():
+    for _, _, _, _, sources, _ in P.KERNELS:
+        for s in sources:
+            assert os.path.exists(os.path.join(P.ROOT, s)), s
