@@ -4,6 +4,8 @@
 // same bits as the reference path.  See fd_sweep.hip for the mapping.
 #pragma once
 
+#include <type_traits>
+
 #include "fdlbm_device.hpp"
 
 namespace fdlbm {
@@ -40,16 +42,33 @@ template <> struct Word<4> { using type = unsigned int; };
 template <> struct Word<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
 template <> struct Word<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
 
-template <typename T, int CPL> __device__ __forceinline__ Group<T, CPL> load_group(const T *p)
+template <typename T, int CPL, typename P> __device__ __forceinline__ Group<T, CPL> load_group(P p)
 {
     static_assert(sizeof(Group<T, CPL>) == sizeof(T) * CPL, "packed group");
     using Wd = typename Word<sizeof(T) * CPL>::type;
-    return __builtin_bit_cast(Group<T, CPL>, *reinterpret_cast<const Wd *>(p));
+    using GW = __attribute__((address_space(1))) const Wd;
+    return __builtin_bit_cast(Group<T, CPL>, *(GW *)(p));  // address-space cast
 }
-template <typename T, int CPL> __device__ __forceinline__ void store_group(T *p, const Group<T, CPL> &g)
+template <typename T, int CPL, typename P> __device__ __forceinline__ void store_group(P p, const Group<T, CPL> &g)
 {
     using Wd = typename Word<sizeof(T) * CPL>::type;
-    __builtin_nontemporal_store(__builtin_bit_cast(Wd, g), reinterpret_cast<Wd *>(p));
+    using GW = __attribute__((address_space(1))) Wd;
+    __builtin_nontemporal_store(__builtin_bit_cast(Wd, g), (GW *)(p));
+}
+
+// Address of column `col` of row `row` in a plane, in the global address space: the row
+// start is wave-uniform and pinned to scalar registers (otherwise the compiler turns the
+// row walk into a per-lane 64-bit pointer increment), the column a 32-bit lane byte
+// offset, so loads and stores take the scalar-base addressing form.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> cell(T *plane, int row, int nx, unsigned col)
+{
+    const unsigned long long r = reinterpret_cast<unsigned long long>(plane + (size_t)(unsigned)row * (size_t)(unsigned)nx);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)r);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(r >> 32));
+    using B = __attribute__((address_space(1))) typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    B *rowp = reinterpret_cast<B *>(((unsigned long long)hi << 32) | lo);
+    return reinterpret_cast<gptr<T>>(rowp + col * (unsigned)sizeof(T));
 }
 
 // Strip geometry: a strip loads W columns starting at s*S - P and stores the S = W - 2P
@@ -69,49 +88,46 @@ template <typename T> struct TileArgs {
     FdCoef<typename Storage<T>::C> k;
 };
 
-// LDS slots per wavefront, each CPL x 64 values: the row sums a wavefront publishes for its
-// neighbours (populations its first f* row sends down, its last f* row sends up), and the
-// parts of its own first output row that it keeps until the barrier (same-row and
-// row-above differences, and its own upward row sum to subtract from what arrives).
-enum { PUB_DN = 0, PUB_DNX, PUB_UP, PUB_UPX, OWN_PC, OWN_PCX, OWN_LU, OWN_LUX, OWN_PD, OWN_PDX, NSLOT };
+// Each wavefront of a block sweeps its rows in one direction: even wavefronts downward,
+// odd ones upward.  Two neighbouring wavefronts then both start, or both end, at the
+// boundary between them, so the rows there are loaded by both at about the same time and
+// the second load is served by the caches.
+//
+// LDS slots per wavefront, each CPL x 64 values: the row sums its first f* row sends across
+// its start side (START_*) and its last f* row across its end side (END_*), and what its
+// first output row keeps until the barrier (OWN_*: the same-row part, its own sums toward
+// the start side, to subtract from what arrives there, the part from the row after it,
+// and its stored values, loaded long before and no longer in cache by then).
+enum {
+    START_S = 0, START_SX, END_S, END_SX, OWN_PC, OWN_PCX, OWN_L, OWN_LX, OWN_P2, OWN_P2X, OWN_R, OWN_X, OWN_Y, NSLOT
+};
 
-// One tile: the block's WV wavefronts over column strip sx and row band `band` of one
-// grid.  Called by every wavefront of the block (it contains a block barrier).
-template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
-__device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int sx)
+// The rows of one wavefront in direction DIR (+1: upward, -1: downward).  "Forward" sums
+// go to the next row in sweep order, "backward" sums to the previous one; row r's output
+// needs its same-row part, the forward sums of the row before it and the backward sums of
+// the row after it, combined in the order fd_partial / fd_finish fix (same-row, below,
+// above) whatever the direction.
+template <int DIR, typename T, int CPL, int ST, bool WALLS, bool FORCE>
+__device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storage<T>::C (&lds)[WV][NSLOT][CPL][64],
+                                           int wv, int lane, unsigned col, bool store_ok, int ybeg, int yend,
+                                           bool empty, bool bottom, bool top)
 {
     using C = typename Storage<T>::C;
     using S = Stencil<ST>;
     constexpr int H = S::H;
     constexpr int NW = 2 * H + 1;  // rows in the input window
-    using G = Strip<CPL, H>;
-    static_assert(CPL >= 2 || H == 1, "5-point differences need two columns per lane");
-    __shared__ C lds[WV][NSLOT][CPL][64];
-
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nx = a.nx, ny = a.ny;
-    const int xl = sx * G::S - G::P + CPL * lane;  // first column of this lane (unwrapped)
-    const int col = ((xl % nx) + nx) % nx;          // wrapped (x periodic)
-    const bool store_ok = CPL * lane >= G::P && CPL * lane < G::P + G::S && xl < nx;
 
-    // rows of this wavefront: R each; a single leftover row at the end of the band is
-    // absorbed by the wavefront below it, so every non-empty wavefront has >= 2 rows
-    // unless the whole band has one row
-    const int b0 = band * WV * a.rows, b1 = min(b0 + WV * a.rows, ny);
-    const int ybeg = b0 + wv * a.rows;
-    int yend = min(ybeg + a.rows, b1);
-    if (b1 - yend == 1) yend = b1;
-    const bool empty = ybeg >= b1 || (wv > 0 && b1 - ybeg == 1);
-    const bool bottom = wv == 0;  // computes f* of row ybeg - 1 itself
-    const bool top = yend == b1;  // computes f* of row yend itself
-    const int rb = bottom ? ybeg - 1 : ybeg;
-    const int re = top ? yend : yend - 1;
-    const int nf = empty ? 0 : re - rb + 1;  // rows whose f* this wavefront computes
-    const int row0 = rb - H;                 // first input row
+    const int rb = bottom ? ybeg - 1 : ybeg;  // f* rows rb .. re (the band's outer
+    const int re = top ? yend : yend - 1;     // wavefronts also take the row beyond)
+    const int nf = empty ? 0 : re - rb + 1;
+    const bool start_edge = DIR > 0 ? bottom : top;  // start / end side on the band edge
+    const bool end_edge = DIR > 0 ? top : bottom;
+    const int first = DIR > 0 ? rb : re;  // first f* row in sweep order
+    const int row0 = first - DIR * H;     // first input row
 
-    // rolling window of input rows: drho and J (sign-flipped on ghost rows); the products
-    // of J_a = J + F/2 are formed where the derivatives need them
+    // rolling window of input rows in sweep order: drho and J (sign-flipped on ghost rows);
+    // the products of J_a = J + F/2 are formed where the derivatives need them
     C w[3][NW][CPL];
     Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
     C ps = C(1);               // its sign (-1: ghost row beyond a wall)
@@ -125,10 +141,9 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
         } else {
             src = j < 0 ? j + ny : (j >= ny ? j - ny : j);
         }
-        const size_t off = (size_t)src * (size_t)nx + (size_t)col;
-        pr = load_group<T, CPL>(a.dr + off);
-        px = load_group<T, CPL>(a.jx + off);
-        py = load_group<T, CPL>(a.jy + off);
+        pr = load_group<T, CPL>(cell(a.dr, src, nx, col));
+        px = load_group<T, CPL>(cell(a.jx, src, nx, col));
+        py = load_group<T, CPL>(cell(a.jy, src, nx, col));
         ps = sgn;
     };
     auto insert = [&](int wslot) {
@@ -140,25 +155,28 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
         }
     };
 
-    // carried between rows, when f* of row r is being computed: QP = fd_partial of output
-    // row r-1 (its same-row and row-below parts), LD, LDX = the own downward row sums of
-    // row r-1, UPp, UPXp = the row sums row r-1 sends up
+    // carried from the previous f* row (= the output row b finished at this one):
+    // FW, FWX = the forward sums it sends to the current row; LB, LBX = its own sums in the
+    // backward group; upward sweep: QP = fd_partial of b; downward: PC, PCX (same-row
+    // part of b) and PF, PFX (its part from the row before it, i.e. from above)
+    C FW[CPL], FWX[CPL], LB[CPL], LBX[CPL];
     FdPartial<C> QP[CPL];
-    C LD[CPL], LDX[CPL], UPp[CPL], UPXp[CPL];
+    C PC[CPL], PCX[CPL], PF[CPL], PFX[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
+        FW[c] = FWX[c] = LB[c] = LBX[c] = C(0);
         QP[c].q = QP[c].qx = QP[c].pu = C(0);
-        LD[c] = LDX[c] = UPp[c] = UPXp[c] = C(0);
+        PC[c] = PCX[c] = PF[c] = PFX[c] = C(0);
     }
 
     if (nf > 0) {
         // prologue: the first 2H input rows, then the prefetch of the next one
 #pragma unroll
-        for (int r = 0; r < 2 * H; ++r) {
-            fetch(row0 + r);
-            insert(r);
+        for (int m = 0; m < 2 * H; ++m) {
+            fetch(row0 + DIR * m);
+            insert(m);
         }
-        fetch(row0 + 2 * H);
+        fetch(row0 + DIR * 2 * H);
     }
 
     // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
@@ -175,9 +193,11 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
             const int it = it0 + ph;
             if (it >= nf) break;
             insert((ph + 2 * H) % NW);
-            if (it + 1 < nf) fetch(row0 + 2 * H + it + 1);
+            if (it + 1 < nf) fetch(row0 + DIR * (2 * H + it + 1));
 
-            const int cs = (ph + H) % NW;  // window slot of the row whose f* is computed
+            const int cs = (ph + H) % NW;  // window slot of the row r whose f* is computed
+            // window slot of row r + k (k rows up the grid)
+            auto sl = [&](int k) { return (ph + H + DIR * k + 2 * NW) % NW; };
             // x-derivative fields of this row, and the J_a of its nodes
             C xf[5][CPL], jxa[CPL], jya[CPL];
 #pragma unroll
@@ -211,11 +231,11 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
                     if (H == 2) {
                         m2 = c >= 2 ? xf[q][c >= 2 ? c - 2 : 0] : (c == 1 ? xl1[q] : xl2[q]);
                         p2 = c + 2 < CPL ? xf[q][c + 2 < CPL ? c + 2 : 0] : (c + 2 == CPL ? xr1[q] : xr2[q]);
-                        ym2 = yfield(q, ph % NW, c);
-                        yp2 = yfield(q, (ph + 2 * H) % NW, c);
+                        ym2 = yfield(q, sl(-2), c);
+                        yp2 = yfield(q, sl(2), c);
                     }
                     d[2 * q] = S::diff(m2, m1, p1, p2);
-                    d[2 * q + 1] = S::diff(ym2, yfield(q, (ph + H - 1) % NW, c), yfield(q, (ph + H + 1) % NW, c), yp2);
+                    d[2 * q + 1] = S::diff(ym2, yfield(q, sl(-1), c), yfield(q, sl(1), c), yp2);
                 }
                 fd_node_fstar<C, FORCE>(w[0][cs][c], jxa[c], jya[c], d, a.k, f[c]);
             }
@@ -223,7 +243,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
             // the column on the right
             const C f1l = from_left(f[CPL - 1][1]), f5l = from_left(f[CPL - 1][5]), f8l = from_left(f[CPL - 1][8]);
             const C f3r = from_right(f[0][3]), f6r = from_right(f[0][6]), f7r = from_right(f[0][7]);
-            const int os = (ph + H - 1) % NW;  // window slot of output row r - 1
+            const int os = sl(-DIR);  // window slot of the output row b = r - DIR
             Group<T, CPL> gr, gx, gy;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
@@ -234,119 +254,176 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
                 const C c3 = c < CPL - 1 ? f[cr][3] : f3r;
                 const C u6 = c < CPL - 1 ? f[cr][6] : f6r;
                 const C d7 = c < CPL - 1 ? f[cr][7] : f7r;
-                // row sums arriving at row r from row r, at r + 1 (up) and at r - 1 (dn)
+                // row sums leaving row r upward (to r + 1) and downward (to r - 1), and the
+                // same groups of this node's own populations
                 const C up = row_sum(f[c][2], u5, u6), upx = u5 - u6;
                 const C dn = row_sum(f[c][4], d8, d7), dnx = d8 - d7;
-                // the same groups of this node's own populations
                 const C lu = row_sum(f[c][2], f[c][5], f[c][6]), lux = f[c][5] - f[c][6];
                 const C ld = row_sum(f[c][4], f[c][8], f[c][7]), ldx = f[c][8] - f[c][7];
+                const C fw = DIR > 0 ? up : dn, fwx = DIR > 0 ? upx : dnx;  // forward
+                const C bw = DIR > 0 ? dn : up, bwx = DIR > 0 ? dnx : upx;  // backward
+                const C lf = DIR > 0 ? lu : ld, lfx = DIR > 0 ? lux : ldx;  // own, forward group
+                const C lb = DIR > 0 ? ld : lu, lbx = DIR > 0 ? ldx : lux;  // own, backward group
                 C pc, pcx;
                 same_row_part<C>(c1 - f[c][1], c3 - f[c][3], pc, pcx);
-                const C pd = dn - LD[c], pdx = dnx - LDX[c];  // row-above part of row r - 1
-                if (!bottom && it == 0) {
-                    // f* of the first row: its downward sums complete the last output row
-                    // of the wavefront below; its own row still lacks the upward sums of
-                    // that wavefront
-                    lds[wv][PUB_DN][c][lane] = dn;
-                    lds[wv][PUB_DNX][c][lane] = dnx;
+                const C pF = FW[c] - lf, pFx = FWX[c] - lfx;  // row r, from the row before it
+                const C pB = bw - LB[c], pBx = bwx - LBX[c];  // row b, from row r
+                if (!start_edge && it == 0) {
+                    // f* of the first row: its backward sums complete the first output row
+                    // of the neighbour across the start side, which sends its own back
+                    lds[wv][START_S][c][lane] = bw;
+                    lds[wv][START_SX][c][lane] = bwx;
                     lds[wv][OWN_PC][c][lane] = pc;
                     lds[wv][OWN_PCX][c][lane] = pcx;
-                    lds[wv][OWN_LU][c][lane] = lu;
-                    lds[wv][OWN_LUX][c][lane] = lux;
+                    lds[wv][OWN_L][c][lane] = lf;
+                    lds[wv][OWN_LX][c][lane] = lfx;
+                    lds[wv][OWN_R][c][lane] = w[0][cs][c];
+                    lds[wv][OWN_X][c][lane] = w[1][cs][c];
+                    lds[wv][OWN_Y][c][lane] = w[2][cs][c];
                 }
-                if (!bottom && it == 1) {
-                    lds[wv][OWN_PD][c][lane] = pd;
-                    lds[wv][OWN_PDX][c][lane] = pdx;
+                if (!start_edge && it == 1) {
+                    lds[wv][OWN_P2][c][lane] = pB;
+                    lds[wv][OWN_P2X][c][lane] = pBx;
                 }
-                // output row r - 1
+                // output row b
                 C nr, nxv, nyv;
-                fd_finish<C, FORCE>(QP[c], pd, pdx, w[0][os][c], w[1][os][c], w[2][os][c], a.k.dfx, a.k.dfy, nr, nxv, nyv);
+                if constexpr (DIR > 0)
+                    fd_finish<C, FORCE>(QP[c], pB, pBx, w[0][os][c], w[1][os][c], w[2][os][c], a.k.dfx, a.k.dfy, nr,
+                                        nxv, nyv);
+                else
+                    fd_finish<C, FORCE>(fd_partial<C>(PC[c], PCX[c], pB, pBx), PF[c], PFX[c], w[0][os][c],
+                                        w[1][os][c], w[2][os][c], a.k.dfx, a.k.dfy, nr, nxv, nyv);
                 gr.v[c] = Storage<T>::store(nr);
                 gx.v[c] = Storage<T>::store(nxv);
                 gy.v[c] = Storage<T>::store(nyv);
-                QP[c] = fd_partial<C>(pc, pcx, UPp[c] - lu, UPXp[c] - lux);
-                LD[c] = ld;
-                LDX[c] = ldx;
-                UPp[c] = up;
-                UPXp[c] = upx;
+                if constexpr (DIR > 0) {
+                    QP[c] = fd_partial<C>(pc, pcx, pF, pFx);
+                } else {
+                    PC[c] = pc;
+                    PCX[c] = pcx;
+                    PF[c] = pF;
+                    PFX[c] = pFx;
+                }
+                FW[c] = fw;
+                FWX[c] = fwx;
+                LB[c] = lb;
+                LBX[c] = lbx;
             }
-            // output row rb + it - 1 is complete once f* of rows rb + it - 2 .. rb + it are known
+            // output row b is complete once f* of the rows on both sides of it are known
             if (it >= 2 && store_ok) {
-                const size_t off = (size_t)(rb + it - 1) * (size_t)nx + (size_t)col;
-                store_group<T, CPL>(a.odr + off, gr);
-                store_group<T, CPL>(a.ojx + off, gx);
-                store_group<T, CPL>(a.ojy + off, gy);
+                const int orow = first + DIR * (it - 1);
+                store_group<T, CPL>(cell(a.odr, orow, nx, col), gr);
+                store_group<T, CPL>(cell(a.ojx, orow, nx, col), gx);
+                store_group<T, CPL>(cell(a.ojy, orow, nx, col), gy);
             }
         }
     }
-    // stored values of the two output rows completed after the barrier (interior rows)
-    Group<T, CPL> o0r, o0x, o0y, o1r, o1x, o1y;
-    if (!empty && !bottom) {
-        const size_t off = (size_t)ybeg * (size_t)nx + (size_t)col;
-        o0r = load_group<T, CPL>(a.dr + off);
-        o0x = load_group<T, CPL>(a.jx + off);
-        o0y = load_group<T, CPL>(a.jy + off);
-    }
-    if (!empty && !top) {
-        const size_t off = (size_t)(yend - 1) * (size_t)nx + (size_t)col;
-        o1r = load_group<T, CPL>(a.dr + off);
-        o1x = load_group<T, CPL>(a.jx + off);
-        o1y = load_group<T, CPL>(a.jy + off);
-    }
-    if (!top && !empty) {
-        // the upward sums of the last f* row complete the first output row of the
-        // wavefront above
+    // stored values of the last output row in sweep order (end side), completed after the
+    // barrier: loaded again (it was loaded a row or two ago and is still in cache)
+    const int last = first + DIR * (nf - 1);
+    Group<T, CPL> o1r, o1x, o1y;
+    if (!empty && !end_edge) {
+        o1r = load_group<T, CPL>(cell(a.dr, last, nx, col));
+        o1x = load_group<T, CPL>(cell(a.jx, last, nx, col));
+        o1y = load_group<T, CPL>(cell(a.jy, last, nx, col));
+        // the forward sums of the last f* row complete the last output row of the
+        // neighbour across the end side
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            lds[wv][PUB_UP][c][lane] = UPp[c];
-            lds[wv][PUB_UPX][c][lane] = UPXp[c];
+            lds[wv][END_S][c][lane] = FW[c];
+            lds[wv][END_SX][c][lane] = FWX[c];
         }
     }
     __syncthreads();
     if (empty) return;
-    if (!bottom) {
-        // first output row: own same-row and row-above parts, upward sums from below
+    if (!start_edge) {
+        // first output row: own same-row and next-row parts, and the sums sent across the
+        // start side by the neighbour there
+        const int nb = wv - DIR;
         Group<T, CPL> gr, gx, gy;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const C pu = lds[wv - 1][PUB_UP][c][lane] - lds[wv][OWN_LU][c][lane];
-            const C pux = lds[wv - 1][PUB_UPX][c][lane] - lds[wv][OWN_LUX][c][lane];
+            const C pF = lds[nb][START_S][c][lane] - lds[wv][OWN_L][c][lane];
+            const C pFx = lds[nb][START_SX][c][lane] - lds[wv][OWN_LX][c][lane];
+            const C pc = lds[wv][OWN_PC][c][lane], pcx = lds[wv][OWN_PCX][c][lane];
+            const C p2 = lds[wv][OWN_P2][c][lane], p2x = lds[wv][OWN_P2X][c][lane];
+            const C odr = lds[wv][OWN_R][c][lane], ojx = lds[wv][OWN_X][c][lane], ojy = lds[wv][OWN_Y][c][lane];
             C nr, nxv, nyv;
-            fd_finish<C, FORCE>(fd_partial<C>(lds[wv][OWN_PC][c][lane], lds[wv][OWN_PCX][c][lane], pu, pux),
-                         lds[wv][OWN_PD][c][lane], lds[wv][OWN_PDX][c][lane], Storage<T>::load(o0r.v[c]),
-                         Storage<T>::load(o0x.v[c]), Storage<T>::load(o0y.v[c]), a.k.dfx, a.k.dfy, nr, nxv, nyv);
+            if constexpr (DIR > 0)
+                fd_finish<C, FORCE>(fd_partial<C>(pc, pcx, pF, pFx), p2, p2x, odr, ojx, ojy, a.k.dfx, a.k.dfy, nr,
+                                    nxv, nyv);
+            else
+                fd_finish<C, FORCE>(fd_partial<C>(pc, pcx, p2, p2x), pF, pFx, odr, ojx, ojy, a.k.dfx, a.k.dfy, nr,
+                                    nxv, nyv);
             gr.v[c] = Storage<T>::store(nr);
             gx.v[c] = Storage<T>::store(nxv);
             gy.v[c] = Storage<T>::store(nyv);
         }
         if (store_ok) {
-            const size_t off = (size_t)ybeg * (size_t)nx + (size_t)col;
-            store_group<T, CPL>(a.odr + off, gr);
-            store_group<T, CPL>(a.ojx + off, gx);
-            store_group<T, CPL>(a.ojy + off, gy);
+            store_group<T, CPL>(cell(a.odr, first, nx, col), gr);
+            store_group<T, CPL>(cell(a.ojx, first, nx, col), gx);
+            store_group<T, CPL>(cell(a.ojy, first, nx, col), gy);
         }
     }
-    if (!top) {
-        // last output row: carried parts + downward sums from the wavefront above
+    if (!end_edge) {
+        // last output row: carried parts and the sums sent across the end side
+        const int nb = wv + DIR;
         Group<T, CPL> gr, gx, gy;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const C pd = lds[wv + 1][PUB_DN][c][lane] - LD[c];
-            const C pdx = lds[wv + 1][PUB_DNX][c][lane] - LDX[c];
+            const C pB = lds[nb][END_S][c][lane] - LB[c];
+            const C pBx = lds[nb][END_SX][c][lane] - LBX[c];
             C nr, nxv, nyv;
-            fd_finish<C, FORCE>(QP[c], pd, pdx, Storage<T>::load(o1r.v[c]), Storage<T>::load(o1x.v[c]),
-                         Storage<T>::load(o1y.v[c]), a.k.dfx, a.k.dfy, nr, nxv, nyv);
+            if constexpr (DIR > 0)
+                fd_finish<C, FORCE>(QP[c], pB, pBx, Storage<T>::load(o1r.v[c]), Storage<T>::load(o1x.v[c]),
+                                    Storage<T>::load(o1y.v[c]), a.k.dfx, a.k.dfy, nr, nxv, nyv);
+            else
+                fd_finish<C, FORCE>(fd_partial<C>(PC[c], PCX[c], pB, pBx), PF[c], PFX[c], Storage<T>::load(o1r.v[c]),
+                                    Storage<T>::load(o1x.v[c]), Storage<T>::load(o1y.v[c]), a.k.dfx, a.k.dfy, nr,
+                                    nxv, nyv);
             gr.v[c] = Storage<T>::store(nr);
             gx.v[c] = Storage<T>::store(nxv);
             gy.v[c] = Storage<T>::store(nyv);
         }
         if (store_ok) {
-            const size_t off = (size_t)(yend - 1) * (size_t)nx + (size_t)col;
-            store_group<T, CPL>(a.odr + off, gr);
-            store_group<T, CPL>(a.ojx + off, gx);
-            store_group<T, CPL>(a.ojy + off, gy);
+            store_group<T, CPL>(cell(a.odr, last, nx, col), gr);
+            store_group<T, CPL>(cell(a.ojx, last, nx, col), gx);
+            store_group<T, CPL>(cell(a.ojy, last, nx, col), gy);
         }
     }
+}
+
+// One tile: the block's WV wavefronts over column strip sx and row band `band` of one
+// grid.  Called by every wavefront of the block (it contains a block barrier).
+template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
+__device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int sx)
+{
+    using C = typename Storage<T>::C;
+    using G = Strip<CPL, Stencil<ST>::H>;
+    static_assert(CPL >= 2 || ST == 3, "5-point differences need two columns per lane");
+    __shared__ C lds[WV][NSLOT][CPL][64];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nx = a.nx, ny = a.ny;
+    const int xl = sx * G::S - G::P + CPL * lane;  // first column of this lane (unwrapped)
+    const unsigned col = ((xl % nx) + nx) % nx;     // wrapped (x periodic)
+    const bool store_ok = CPL * lane >= G::P && CPL * lane < G::P + G::S && xl < nx;
+
+    // rows of this wavefront: R each; a single leftover row at the end of the band is
+    // absorbed by the wavefront below it, so every non-empty wavefront has >= 2 rows
+    // unless the whole band has one row
+    const int b0 = band * WV * a.rows, b1 = min(b0 + WV * a.rows, ny);
+    const int ybeg = b0 + wv * a.rows;
+    int yend = min(ybeg + a.rows, b1);
+    if (b1 - yend == 1) yend = b1;
+    const bool empty = ybeg >= b1 || (wv > 0 && b1 - ybeg == 1);
+    const bool bottom = wv == 0;  // computes f* of row ybeg - 1 itself
+    const bool top = yend == b1;  // computes f* of row yend itself
+    if (wv & 1)
+        sweep_wave<1, T, CPL, ST, WALLS, FORCE>(a, lds, wv, lane, col, store_ok, ybeg, yend, empty, bottom, top);
+    else
+        sweep_wave<-1, T, CPL, ST, WALLS, FORCE>(a, lds, wv, lane, col, store_ok, ybeg, yend, empty, bottom, top);
 }
 
 
