@@ -71,6 +71,79 @@ template <typename T> __device__ __forceinline__ gptr<T> cell(T *plane, int row,
     return reinterpret_cast<gptr<T>>(rowp + col * (unsigned)sizeof(T));
 }
 
+// Row accesses through a buffer resource.  The hardware range-checks every buffer access
+// against the resource's size: an access at OFF_NONE (beyond any row) is dropped (a load
+// returns zero).  The sweep loop uses this instead of branching around its row loads and
+// stores, so every iteration issues the same memory operations and the waits for the
+// prefetched row never have to wait for the previous row's stores as well.
+constexpr unsigned OFF_NONE = 0x80000000u;
+constexpr int RSRC_WORD3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+constexpr int NT_HINT = 2;              // non-temporal store (written once, read next step)
+
+template <typename T> __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T *plane, int row, int nx)
+{
+    const unsigned long long r = reinterpret_cast<unsigned long long>(plane + (size_t)(unsigned)row * (size_t)(unsigned)nx);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)r);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(r >> 32));
+    void *base = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, nx * (int)sizeof(T), RSRC_WORD3);
+}
+
+template <int BYTES> struct BufOps;
+template <> struct BufOps<2> {
+    using W = Word<2>::type;
+    static __device__ __forceinline__ W load(__amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void store(W v, __amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, NT_HINT);
+    }
+};
+template <> struct BufOps<4> {
+    using W = Word<4>::type;
+    static __device__ __forceinline__ W load(__amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void store(W v, __amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, NT_HINT);
+    }
+};
+template <> struct BufOps<8> {
+    using W = Word<8>::type;
+    static __device__ __forceinline__ W load(__amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void store(W v, __amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, NT_HINT);
+    }
+};
+template <> struct BufOps<16> {
+    using W = Word<16>::type;
+    static __device__ __forceinline__ W load(__amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void store(W v, __amdgpu_buffer_rsrc_t r, unsigned off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, NT_HINT);
+    }
+};
+template <typename T, int CPL> __device__ __forceinline__ Group<T, CPL> buf_load_group(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(Group<T, CPL>, BufOps<sizeof(T) * CPL>::load(r, off));
+}
+template <typename T, int CPL>
+__device__ __forceinline__ void buf_store_group(__amdgpu_buffer_rsrc_t r, unsigned off, const Group<T, CPL> &g)
+{
+    BufOps<sizeof(T) * CPL>::store(__builtin_bit_cast(typename Word<sizeof(T) * CPL>::type, g), r, off);
+}
+
 // Strip geometry: a strip loads W columns starting at s*S - P and stores the S = W - 2P
 // columns [s*S, s*S + S), where P = h+1 rounded up to whole lanes.
 template <int CPL, int H> struct Strip {
@@ -132,7 +205,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
     C ps = C(1);               // its sign (-1: ghost row beyond a wall)
 
-    auto fetch = [&](int j) {
+    const unsigned voff = col * (unsigned)sizeof(T);  // this lane's byte offset in a row
+    // load input row j (mirrored or wrapped); `use` false issues the same loads, dropped
+    auto fetch = [&](int j, bool use) {
         int src = j;
         C sgn = C(1);
         if (WALLS) {
@@ -141,9 +216,11 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         } else {
             src = j < 0 ? j + ny : (j >= ny ? j - ny : j);
         }
-        pr = load_group<T, CPL>(cell(a.dr, src, nx, col));
-        px = load_group<T, CPL>(cell(a.jx, src, nx, col));
-        py = load_group<T, CPL>(cell(a.jy, src, nx, col));
+        src = min(max(src, 0), ny - 1);
+        const unsigned off = use ? voff : OFF_NONE;
+        pr = buf_load_group<T, CPL>(row_rsrc(a.dr, src, nx), off);
+        px = buf_load_group<T, CPL>(row_rsrc(a.jx, src, nx), off);
+        py = buf_load_group<T, CPL>(row_rsrc(a.jy, src, nx), off);
         ps = sgn;
     };
     auto insert = [&](int wslot) {
@@ -173,10 +250,10 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         // prologue: the first 2H input rows, then the prefetch of the next one
 #pragma unroll
         for (int m = 0; m < 2 * H; ++m) {
-            fetch(row0 + DIR * m);
+            fetch(row0 + DIR * m, true);
             insert(m);
         }
-        fetch(row0 + DIR * 2 * H);
+        fetch(row0 + DIR * 2 * H, true);
     }
 
     // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
@@ -193,7 +270,7 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             const int it = it0 + ph;
             if (it >= nf) break;
             insert((ph + 2 * H) % NW);
-            if (it + 1 < nf) fetch(row0 + DIR * (2 * H + it + 1));
+            fetch(row0 + DIR * (2 * H + it + 1), it + 1 < nf);
 
             const int cs = (ph + H) % NW;  // window slot of the row r whose f* is computed
             // window slot of row r + k (k rows up the grid)
@@ -310,11 +387,12 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
                 LBX[c] = lbx;
             }
             // output row b is complete once f* of the rows on both sides of it are known
-            if (it >= 2 && store_ok) {
-                const int orow = first + DIR * (it - 1);
-                store_group<T, CPL>(cell(a.odr, orow, nx, col), gr);
-                store_group<T, CPL>(cell(a.ojx, orow, nx, col), gx);
-                store_group<T, CPL>(cell(a.ojy, orow, nx, col), gy);
+            {
+                const int orow = min(max(first + DIR * (it - 1), 0), ny - 1);
+                const unsigned off = it >= 2 && store_ok ? voff : OFF_NONE;
+                buf_store_group<T, CPL>(row_rsrc(a.odr, orow, nx), off, gr);
+                buf_store_group<T, CPL>(row_rsrc(a.ojx, orow, nx), off, gx);
+                buf_store_group<T, CPL>(row_rsrc(a.ojy, orow, nx), off, gy);
             }
         }
     }
