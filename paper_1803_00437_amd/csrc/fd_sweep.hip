@@ -106,13 +106,13 @@ hipError_t dispatch_cpl(const FdArgs &a, int tile_rows, const void *src, void *d
     return hipErrorInvalidValue;
 }
 
-// Columns per lane (measured at 8192^2): FP32 4 (16-byte accesses), FP16 2 (4-byte
-// accesses, fewer live registers), FP64 2 (16-byte accesses); narrower when nx is not a
-// multiple (1 is available for 3-point differences only).
+// Columns per lane (measured at 8192^2): FP32 and FP16 4 (16- and 8-byte accesses), FP64
+// 2 (16-byte accesses); narrower when nx is not a multiple (1 is available for 3-point
+// differences only).
 int choose_cpl(const FdArgs &a, int lane_cols)
 {
     if (lane_cols > 0) return lane_cols;
-    int c = a.dtype == FDLBM_F32 ? 4 : 2;
+    int c = a.dtype == FDLBM_F64 ? 2 : 4;
     while (c > 1 && a.nx % c) c /= 2;
     return c;
 }

@@ -147,7 +147,7 @@ KERNELS = [
      f"{DECAY}; MRT D2Q9, FP32 (9 words read + 9 written per node)"),
     ("fd3_f64_8192", "fd_sweep_kernel<double, 2, 3, false, false>", 48 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP64"),
-    ("fd3_f16_8192", "fd_sweep_kernel<__half, 2, 3, false, false>", 12 * N * N, None, FD_SOURCES,
+    ("fd3_f16_8192", "fd_sweep_kernel<__half, 4, 3, false, false>", 12 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP16 storage, FP32 arithmetic"),
     ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false, false>", 24 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 5-point, FP32"),

@@ -223,3 +223,27 @@ def test_mrt_sweep_equals_reference_bitwise(F, dtype, walls, shape, tile_rows):
         out.append(sim.get_populations())
         sim.close()
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_unit_rates_reduce_every_scheme_to_bgk(F, walls):
+    """With every relaxation rate equal to 1 the theta terms drop out (section 2): FD-LBM
+    with 3 and 5 points become the same scheme, and on a periodic grid also equal MRT, i.e.
+    BGK with tau = 1.  GPU, FP64, 30 steps with a force: agreement to rounding.  (With walls
+    only the two FD-LBM stencils coincide: the mirror ghost rows and MRT's bounce-back send
+    different diagonal populations.)"""
+    nx, ny, n = 70, 45, 30
+    r, x, y = W.random_state(nx, ny, seed=91, amp=0.02)
+    bc = "walls" if walls else "periodic"
+    cases = [dict(scheme="fd", stencil=3), dict(scheme="fd", stencil=5)]
+    if not walls:
+        cases.append(dict(scheme="mrt", s_q=1.0, s_eps=1.0))
+    out = []
+    for kw in cases:
+        sim = F.FdLbm(nx, ny, bc=bc, dtype="f64", s_xx=1.0, s_e=1.0, force=(1e-5, 2e-5), **kw)
+        sim.set_state(r, x, y)
+        sim.step(n)
+        out.append(sim.get_state())
+        sim.close()
+    for other in out[1:]:
+        assert rel_l2(other, out[0]) < 1e-13

@@ -45,16 +45,17 @@ def run(F, kernel, nx, ny, steps, init, **kw):
 @pytest.mark.parametrize("shape,tile_rows", [((296, 77), 0), ((8, 13), 5), ((520, 40), 3), ((252, 64), 16),
                                               ((24, 9), 2)])
 @pytest.mark.parametrize("wide", [False, True])
-def test_sweep_equals_reference_bitwise(F, dtype, stencil, walls, shape, tile_rows, wide):
+@pytest.mark.parametrize("forced", [False, True])
+def test_sweep_equals_reference_bitwise(F, dtype, stencil, walls, shape, tile_rows, wide, forced):
     nx, ny = shape
     lane_cols = {"f64": (2, 1), "f32": (2, 4), "f16": (2, 4)}[dtype][int(wide)]
     if lane_cols == 1 and stencil == 5:
         lane_cols = 2
     print(f"case sweep-vs-reference dtype={dtype} stencil={stencil} walls={walls} shape={shape} "
-          f"tile_rows={tile_rows} lane_cols={lane_cols}", flush=True)
+          f"tile_rows={tile_rows} lane_cols={lane_cols} forced={forced}", flush=True)
     init = W.random_state(nx, ny, seed=nx + ny, amp=0.02)
     kw = dict(stencil=stencil, dtype=dtype, bc="walls" if walls else "periodic", s_xx=1.6, s_e=1.1,
-              force=(2e-5, -1e-5) if walls else (0.0, 0.0))
+              force=(2e-5, -1e-5) if forced else (0.0, 0.0))
     a = run(F, "reference", nx, ny, 9, init, **kw)
     b = run(F, "sweep", nx, ny, 9, init, tile_rows=tile_rows, lane_cols=lane_cols, **kw)
     for u, v in zip(a, b):

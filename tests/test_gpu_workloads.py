@@ -106,6 +106,35 @@ def test_stokes_modes_256_dispersion(F, scheme):
         assert err < 1e-8, (m, err)
 
 
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+def test_stokes_modes_256_dispersion_10000_steps(F, scheme):
+    """The same linear check over the configuration's 10000 steps, on the long-lived modes
+    (|k| <= 2*pi*sqrt(5)/256), FP64: each mode equals H(k)^10000 applied to its initial
+    amplitudes to 1e-7."""
+    init = W.stokes_modes_256(seed=2, rms=1e-12)
+    n, steps = 256, 10000
+    s_xx = O.rate_from_viscosity(NU)
+    modes = [(1, 0), (0, 1), (1, 1), (2, 1), (-1, 2)]
+    if scheme == "mrt":
+        s_q = O.quartic_s_q(s_xx)
+        f0 = O.mrt_init(*init)
+        got = run_gpu(F, init, steps, scheme="mrt", dtype="f64", s_xx=s_xx, quartic=True)
+    else:
+        got = run_gpu(F, init, steps, scheme="fd", stencil=int(scheme[2]), dtype="f64", s_xx=s_xx, s_e=1.0)
+    for m in modes:
+        kx, ky = 2 * math.pi * m[0] / n, 2 * math.pi * m[1] / n
+        if scheme == "mrt":
+            H = S.mrt_symbol(kx, ky, s_xx=s_xx, s_q=s_q)
+            phi0, phi = fourier(f0, *m), fourier(got, *m)
+        else:
+            H = S.fd_symbol(kx, ky, s_xx=s_xx, s_e=1.0, stencil=int(scheme[2]))
+            phi0 = np.array([fourier(a, *m) for a in init])
+            phi = np.array([fourier(a, *m) for a in got])
+        pred = np.linalg.matrix_power(H, steps) @ phi0
+        err = np.max(np.abs(phi - pred)) / np.max(np.abs(pred))
+        assert err < 1e-7, (m, err)
+
+
 @pytest.mark.parametrize("scheme", ["fd3", "mrt"])
 def test_poiseuille_channel_16384x1024(F, scheme):
     """FP32 channel 16384 x 1024 started from the analytic parabola: after 2000 steps the
