@@ -24,6 +24,7 @@ import glob
 import hashlib
 import json
 import os
+import shutil
 import subprocess
 import sys
 from collections import defaultdict
@@ -183,6 +184,10 @@ def collect(raw, out, run=True):
     py = ["python3", "-u", BENCH]
     trace_opts = ["--kernel-trace", "--stats", "--output-format", "csv"]
     if run:
+        # rocprofv3 names its files by process id: start from empty directories so that no
+        # earlier run's files are summarised with this one's
+        for sub in ("trace", "fd_fetch_size", "fd_write_size", "mrt_fetch_size", "mrt_write_size"):
+            shutil.rmtree(os.path.join(raw, sub), ignore_errors=True)
         _run(["rocprofv3"] + trace_opts + ["-d", f"{raw}/trace", "--"] + py + TRACE_ARGS, f"{raw}/trace.log", 400,
              "TERM")
     pmc = {}
