@@ -181,6 +181,12 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
 // side has no neighbour to take from and only feeds its neighbour, so strips overlap by
 // one lane on each side.  Populations moving along y go to the row above or below (or
 // bounce back at a wall).  Wavefronts are dealt out row band after row band.
+//
+// The nine planes of the next row are loaded while the current one is collided (two row
+// buffers, the loop unrolled by two so that they alternate without copies).  Loads and
+// stores go through range-checked buffer resources: the halo lanes' stores and the
+// prefetch past the last row use an offset beyond the row and are dropped, so every row
+// issues the same memory operations without branches.
 template <typename T, int CPL, bool WALLS>
 __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
                                                         int rows, int strips_x, int ntiles,
@@ -194,19 +200,28 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
     if (tile >= ntiles) return;  // uniform over the wavefront
     const int band = tile / strips_x, sx = tile - band * strips_x;
     const int xl = sx * S - CPL + CPL * lane;  // first column of this lane (unwrapped)
-    const int col = ((xl % nx) + nx) % nx;
+    const unsigned col = ((xl % nx) + nx) % nx;
     const bool store_ok = lane >= 1 && lane <= 62 && xl < nx;
+    const unsigned voff = col * (unsigned)sizeof(T);
+    const unsigned soff = store_ok ? voff : OFF_NONE;  // halo lanes do not store
     const size_t n = (size_t)nx * (size_t)ny;
     const int y0 = band * rows, y1 = min(y0 + rows, ny);
-    for (int y = y0; y < y1; ++y) {
-        const size_t p = (size_t)y * (size_t)nx + (size_t)col;
+
+    auto load_row = [&](int y, bool use, Group<T, CPL>(&g)[9]) {
+        const int yy = min(y, ny - 1);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) g[q] = buf_load_group<T, CPL>(row_rsrc(in + q * n, yy, nx), use ? voff : OFF_NONE);
+    };
+    auto put = [&](int q, int y, const Group<T, CPL> &g) {
+        buf_store_group<T, CPL>(row_rsrc(out + q * n, y, nx), soff, g);
+    };
+    // collide row y (populations in `cur`) and push its post-collision populations
+    auto process = [&](int y, const Group<T, CPL>(&cur)[9]) {
         C f[CPL][9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const Group<T, CPL> g = load_group<T, CPL>(in + q * n + p);
+        for (int q = 0; q < 9; ++q)
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) f[c][q] = Storage<T>::load(g.v[c]);
-        }
+            for (int c = 0; c < CPL; ++c) f[c][q] = Storage<T>::load(cur[q].v[c]);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) collide<C>(f[c], k);
         // destination rows (wave-uniform); with walls a population leaving the channel
@@ -217,7 +232,6 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
             if (yp == ny) yp = 0;
             if (ym < 0) ym = ny - 1;
         }
-        const size_t prow = (size_t)yp * (size_t)nx + (size_t)col, mrow = (size_t)ym * (size_t)nx + (size_t)col;
         Group<T, CPL> g[9];
         // velocities (0,0), (0,+1), (0,-1) keep their column
 #pragma unroll
@@ -238,43 +252,52 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
                 g[lq[t]].v[c] = Storage<T>::store(c < CPL - 1 ? f[c < CPL - 1 ? c + 1 : 0][lq[t]] : fr);
             }
         }
-        if (!store_ok) continue;
-        store_group<T, CPL>(out + 0 * n + p, g[0]);
-        store_group<T, CPL>(out + 1 * n + p, g[1]);
-        store_group<T, CPL>(out + 3 * n + p, g[3]);
-        if (!top_wall) {
-            store_group<T, CPL>(out + 2 * n + prow, g[2]);
-            store_group<T, CPL>(out + 5 * n + prow, g[5]);
-            store_group<T, CPL>(out + 6 * n + prow, g[6]);
-        }
-        if (!bottom_wall) {
-            store_group<T, CPL>(out + 4 * n + mrow, g[4]);
-            store_group<T, CPL>(out + 7 * n + mrow, g[7]);
-            store_group<T, CPL>(out + 8 * n + mrow, g[8]);
-        }
-        if (top_wall || bottom_wall) {
-            // unshifted post-collision values of this row for the bounce-back
-            Group<T, CPL> b2, b5, b6, b4, b7, b8;
+        put(0, y, g[0]);
+        put(1, y, g[1]);
+        put(3, y, g[3]);
+        if (top_wall) {
+            // the upward movers return into this row's downward planes, unshifted
+            Group<T, CPL> b2, b5, b6;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 b2.v[c] = Storage<T>::store(f[c][2]);
                 b5.v[c] = Storage<T>::store(f[c][5]);
                 b6.v[c] = Storage<T>::store(f[c][6]);
+            }
+            put(4, y, b2);
+            put(7, y, b5);
+            put(8, y, b6);
+        } else {
+            put(2, yp, g[2]);
+            put(5, yp, g[5]);
+            put(6, yp, g[6]);
+        }
+        if (bottom_wall) {
+            Group<T, CPL> b4, b7, b8;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
                 b4.v[c] = Storage<T>::store(f[c][4]);
                 b7.v[c] = Storage<T>::store(f[c][7]);
                 b8.v[c] = Storage<T>::store(f[c][8]);
             }
-            if (top_wall) {
-                store_group<T, CPL>(out + 4 * n + p, b2);
-                store_group<T, CPL>(out + 7 * n + p, b5);
-                store_group<T, CPL>(out + 8 * n + p, b6);
-            }
-            if (bottom_wall) {
-                store_group<T, CPL>(out + 2 * n + p, b4);
-                store_group<T, CPL>(out + 5 * n + p, b7);
-                store_group<T, CPL>(out + 6 * n + p, b8);
-            }
+            put(2, y, b4);
+            put(5, y, b7);
+            put(6, y, b8);
+        } else {
+            put(4, ym, g[4]);
+            put(7, ym, g[7]);
+            put(8, ym, g[8]);
         }
+    };
+
+    Group<T, CPL> A[9], B[9];
+    load_row(y0, true, A);
+    for (int y = y0; y < y1; y += 2) {
+        load_row(y + 1, y + 1 < y1, B);
+        process(y, A);
+        if (y + 1 >= y1) break;
+        load_row(y + 2, y + 2 < y1, A);
+        process(y + 1, B);
     }
 }
 
@@ -315,7 +338,7 @@ template <typename T, int CPL>
 hipError_t run_sweep(const MrtArgs &a, MrtCoef<typename Storage<T>::C> k, const void *src, void *dst, hipStream_t s)
 {
     constexpr int S = 64 * CPL - 2 * CPL;
-    const int rows = a.tile_rows > 0 ? a.tile_rows : 4;  // 4 measured best at 8192^2
+    const int rows = a.tile_rows > 0 ? a.tile_rows : 2;  // 2 measured best at 8192^2
     const int strips_x = (a.nx + S - 1) / S;
     const int ntiles = strips_x * ((a.ny + rows - 1) / rows);
     const int blocks = (ntiles + 3) / 4;
