@@ -42,6 +42,7 @@ struct Plan {
     std::vector<BatchInstance> inst;
     std::vector<BatchBlock> blocks;
     std::vector<BatchChunk> chunks;
+    int class_begin[BATCH_CLASSES] = {}, class_blocks[BATCH_CLASSES] = {};
     size_t state_elems = 0, mode_elems = 0, max_n = 0;
     // scratch offsets (bytes)
     size_t o_inst, o_blocks, o_chunks, o_partials, o_counter, o_amps, o_mode, o_staging, total;
@@ -58,8 +59,19 @@ int validate(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max
     return FDLBM_OK;
 }
 
+// Columns per lane of an instance's tiles: the widest lane group that divides its width
+// (FP64 keeps at most two, as the single-grid kernel does).
+int instance_cpl(int nx, int dtype)
+{
+    if (dtype != FDLBM_F64 && nx % 4 == 0) return 4;
+    return nx % 2 == 0 ? 2 : 1;
+}
+
+int class_of_cpl(int cpl) { return cpl == 4 ? 0 : cpl == 2 ? 1 : 2; }
+
 // Tiles of every instance for `rows` rows per wavefront: the instances' band counts and
-// the block table, largest grids first so that the last blocks to start are small ones.
+// the block table, grouped by lane-group class (one launch each) and, within a class,
+// largest grids first so that the last blocks to start are small ones.
 void tile_tables(Plan &P, int rows)
 {
     const int RB = batch_rows_per_block(rows);
@@ -68,18 +80,38 @@ void tile_tables(Plan &P, int rows)
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (size_t)P.inst[a].nx * P.inst[a].ny > (size_t)P.inst[b].nx * P.inst[b].ny;
+        const BatchInstance &A = P.inst[a], &B = P.inst[b];
+        if (A.cpl != B.cpl) return A.cpl > B.cpl;
+        return (size_t)A.nx * A.ny > (size_t)B.nx * B.ny;
     });
     P.blocks.clear();
-    for (int i : order)
-        for (int t = 0; t < P.inst[i].strips_x * P.inst[i].nbands; ++t) P.blocks.push_back(BatchBlock{i, t});
+    for (int c = 0; c < BATCH_CLASSES; ++c) P.class_blocks[c] = 0;
+    for (int i : order) {
+        const int tiles = P.inst[i].strips_x * P.inst[i].nbands;
+        P.class_blocks[class_of_cpl(P.inst[i].cpl)] += tiles;
+        for (int t = 0; t < tiles; ++t) P.blocks.push_back(BatchBlock{i, t});
+    }
+    for (int c = 0, begin = 0; c < BATCH_CLASSES; ++c) {
+        P.class_begin[c] = begin;
+        begin += P.class_blocks[c];
+    }
+}
+
+// Point a launch description at the block table the plan holds.
+void use_tables(BatchLaunch &L, const Plan &P, int rows)
+{
+    L.rows = rows;
+    L.nblocks = (int)P.blocks.size();
+    for (int c = 0; c < BATCH_CLASSES; ++c) {
+        L.class_begin[c] = P.class_begin[c];
+        L.class_blocks[c] = P.class_blocks[c];
+    }
 }
 
 Plan plan(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max_samples)
 {
     Plan P;
     P.inst.resize(count);
-    const int S = batch_strip_stride();
     int chunk0 = 0;
     for (int i = 0; i < count; ++i) {
         BatchInstance &I = P.inst[i];
@@ -90,6 +122,8 @@ Plan plan(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max_sa
         P.mode_elems = al64(P.mode_elems + 2 * n);
         I.nx = in[i].nx;
         I.ny = in[i].ny;
+        I.cpl = instance_cpl(I.nx, dtype);
+        const int S = batch_strip_stride(I.cpl);
         I.strips_x = (I.nx + S - 1) / S;
         I.first_chunk = chunk0;
         I.nchunks = (int)((n + BATCH_CHUNK - 1) / BATCH_CHUNK);
@@ -195,8 +229,7 @@ int fdlbm_batch_create(const fdlbm_instance *instances, int32_t count, int32_t d
     BatchLaunch &L = b->L;
     L.dtype = dtype;
     L.count = count;
-    L.rows = BATCH_ROWS;
-    L.nblocks = (int)P.blocks.size();
+    use_tables(L, P, BATCH_ROWS);
     L.nchunks = (int)P.chunks.size();
     L.max_samples = max_samples;
     L.inst = reinterpret_cast<const BatchInstance *>(b->scratch + P.o_inst);
@@ -282,8 +315,7 @@ int fdlbm_batch_autotune(fdlbm_batch *b, int32_t reps, int32_t *out_rows, double
             e = hipMemcpyAsync(b->scratch + b->P.o_blocks, b->P.blocks.data(), sizeof(BatchBlock) * b->P.blocks.size(),
                                hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        b->L.rows = rows;
-        b->L.nblocks = (int)b->P.blocks.size();
+        use_tables(b->L, b->P, rows);
         return e;
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -372,7 +404,8 @@ int fdlbm_batch_step_per_instance(fdlbm_batch *b, int64_t nsteps)
     for (int64_t s = 0; s < nsteps; ++s) {
         for (int i = 0; i < b->count; ++i) {
             const BatchInstance &I = b->P.inst[i];
-            BHIPCHK(launch_batch_single(b->L, i, I.strips_x * I.nbands, b->buf[b->cur], b->buf[b->cur ^ 1], b->stream),
+            BHIPCHK(launch_batch_single(b->L, i, I.cpl, I.strips_x * I.nbands, b->buf[b->cur], b->buf[b->cur ^ 1],
+                                        b->stream),
                     "batch single launch");
         }
         b->cur ^= 1;

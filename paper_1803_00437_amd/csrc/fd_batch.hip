@@ -5,8 +5,9 @@
 // is captured once in a HIP graph and replayed.
 //
 // Each block looks up (instance, tile) in a table built on the host and runs the same
-// tile body as the single-grid kernel (one column per lane, so any grid width works), so
-// every instance evolves exactly as it would alone.
+// tile body as the single-grid kernel, so every instance evolves exactly as it would
+// alone.  Instances are grouped by the widest lane group their width allows (4, 2 or 1
+// columns per lane); each group is one launch.
 #include "fd_sweep_body.hpp"
 #include "internal.hpp"
 
@@ -16,7 +17,7 @@ using namespace sweep;
 
 constexpr int PROJ_TPB = 256;
 
-template <typename T>
+template <typename T, int CPL>
 __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__ in, T *__restrict__ out,
                                                            const BatchInstance *__restrict__ inst,
                                                            const BatchBlock *__restrict__ blocks, int rows)
@@ -39,11 +40,11 @@ __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = b.tile / I.strips_x;
-    sweep_tile<T, 1, 3, false, false>(t, band, b.tile - band * I.strips_x);
+    sweep_tile<T, CPL, 3, false, false>(t, band, b.tile - band * I.strips_x);
 }
 
 // Single instance in the same tiling: the one-launch-per-grid path of the comparison.
-template <typename T>
+template <typename T, int CPL>
 __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict__ in, T *__restrict__ out,
                                                             const BatchInstance *__restrict__ inst, int i, int rows)
 {
@@ -64,7 +65,7 @@ __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict_
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = blockIdx.x / I.strips_x;
-    sweep_tile<T, 1, 3, false, false>(t, band, blockIdx.x - band * I.strips_x);
+    sweep_tile<T, CPL, 3, false, false>(t, band, blockIdx.x - band * I.strips_x);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -133,19 +134,39 @@ __global__ void proj_final(const BatchInstance *__restrict__ inst, int count, co
 
 __global__ void advance_counter(int *counter) { *counter += 1; }
 
-template <typename T>
-hipError_t step_all(const BatchLaunch &L, const void *src, void *dst, hipStream_t s)
+template <typename T, int CPL> hipError_t step_class(const BatchLaunch &L, int c, const void *src, void *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(fd_batch_kernel<T>, L.nblocks, 64 * WV, 0, s, static_cast<const T *>(src), static_cast<T *>(dst),
-                       L.inst, L.blocks, L.rows);
+    if (L.class_blocks[c] == 0) return hipSuccess;
+    hipLaunchKernelGGL((fd_batch_kernel<T, CPL>), L.class_blocks[c], 64 * WV, 0, s, static_cast<const T *>(src),
+                       static_cast<T *>(dst), L.inst, L.blocks + L.class_begin[c], L.rows);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t step_one(const BatchLaunch &L, int i, int nblocks, const void *src, void *dst, hipStream_t s)
+hipError_t step_all(const BatchLaunch &L, const void *src, void *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(fd_single_kernel<T>, nblocks, 64 * WV, 0, s, static_cast<const T *>(src), static_cast<T *>(dst),
-                       L.inst, i, L.rows);
+    hipError_t e = hipSuccess;
+    if constexpr (sizeof(T) != 8) e = step_class<T, 4>(L, 0, src, dst, s);
+    if (e == hipSuccess) e = step_class<T, 2>(L, 1, src, dst, s);
+    if (e == hipSuccess) e = step_class<T, 1>(L, 2, src, dst, s);
+    return e;
+}
+
+template <typename T>
+hipError_t step_one(const BatchLaunch &L, int i, int cpl, int nblocks, const void *src, void *dst, hipStream_t s)
+{
+    const T *in = static_cast<const T *>(src);
+    T *out = static_cast<T *>(dst);
+    if constexpr (sizeof(T) != 8) {
+        if (cpl == 4) {
+            hipLaunchKernelGGL((fd_single_kernel<T, 4>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
+            return hipGetLastError();
+        }
+    }
+    if (cpl == 2)
+        hipLaunchKernelGGL((fd_single_kernel<T, 2>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
+    else
+        hipLaunchKernelGGL((fd_single_kernel<T, 1>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
     return hipGetLastError();
 }
 
@@ -165,7 +186,7 @@ template <typename T> hipError_t sample(const BatchLaunch &L, const void *state,
 
 }  // namespace
 
-int batch_strip_stride() { return Strip<1, 1>::S; }
+int batch_strip_stride(int cpl) { return cpl == 4 ? Strip<4, 1>::S : cpl == 2 ? Strip<2, 1>::S : Strip<1, 1>::S; }
 int batch_rows_per_block(int rows) { return WV * rows; }
 
 hipError_t launch_batch_step(const BatchLaunch &L, const void *src, void *dst, hipStream_t s)
@@ -177,12 +198,13 @@ hipError_t launch_batch_step(const BatchLaunch &L, const void *src, void *dst, h
     }
 }
 
-hipError_t launch_batch_single(const BatchLaunch &L, int i, int nblocks, const void *src, void *dst, hipStream_t s)
+hipError_t launch_batch_single(const BatchLaunch &L, int i, int cpl, int nblocks, const void *src, void *dst,
+                               hipStream_t s)
 {
     switch (L.dtype) {
-    case FDLBM_F64: return step_one<double>(L, i, nblocks, src, dst, s);
-    case FDLBM_F32: return step_one<float>(L, i, nblocks, src, dst, s);
-    default: return step_one<__half>(L, i, nblocks, src, dst, s);
+    case FDLBM_F64: return step_one<double>(L, i, cpl, nblocks, src, dst, s);
+    case FDLBM_F32: return step_one<float>(L, i, cpl, nblocks, src, dst, s);
+    default: return step_one<__half>(L, i, cpl, nblocks, src, dst, s);
     }
 }
 

@@ -44,6 +44,7 @@ struct BatchInstance {
     size_t offset;       // element offset of the instance's drho plane in the state buffers
     size_t mode_offset;  // element offset of its J0 planes (jx, jy) in the mode buffer
     int nx, ny, strips_x, nbands;
+    int cpl;             // grid columns per lane of its tiles: 4, 2 or 1 (nx a multiple)
     int first_chunk, nchunks;
     double ke, kxx;      // (1 - 1/s_e) / 2 and (1 - 1/s_xx) / 2 (3-point scale folded in)
 };
@@ -53,8 +54,13 @@ struct BatchBlock {
 struct BatchChunk {
     int instance, chunk;
 };
+// The block table holds the tiles of the instances with 4, 2 and 1 columns per lane in
+// that order; class c (0, 1, 2) starts at class_begin[c] and has class_blocks[c] entries.
+constexpr int BATCH_CLASSES = 3;
+constexpr int batch_class_cpl(int c) { return c == 0 ? 4 : c == 1 ? 2 : 1; }
 struct BatchLaunch {
     int dtype, count, rows, nblocks, nchunks, max_samples;
+    int class_begin[BATCH_CLASSES], class_blocks[BATCH_CLASSES];
     const BatchInstance *inst;
     const BatchBlock *blocks;
     const BatchChunk *chunks;
@@ -63,10 +69,11 @@ struct BatchLaunch {
     int *counter;
     double *amps;
 };
-int batch_strip_stride();
+int batch_strip_stride(int cpl);
 int batch_rows_per_block(int rows);
 hipError_t launch_batch_step(const BatchLaunch &L, const void *src, void *dst, hipStream_t s);
-hipError_t launch_batch_single(const BatchLaunch &L, int i, int nblocks, const void *src, void *dst, hipStream_t s);
+hipError_t launch_batch_single(const BatchLaunch &L, int i, int cpl, int nblocks, const void *src, void *dst,
+                               hipStream_t s);
 hipError_t launch_batch_sample(const BatchLaunch &L, const void *state, hipStream_t s);
 
 // MRT D2Q9 stream-collide (push) step.
