@@ -88,6 +88,12 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1803_00437_amd.build` "
                            "(there is no CPU fallback)")
+    # torch ships its own HIP runtime and asks for it under a name that does not match the
+    # soname of the system one.  Loaded first, torch's copy satisfies this library's
+    # dependency, and both use one runtime; loaded after this library, torch would bring a
+    # second runtime into the process and device buffers would not be shared.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int64
     P = ctypes.POINTER(Params)

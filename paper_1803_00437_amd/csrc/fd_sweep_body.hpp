@@ -20,13 +20,13 @@ constexpr int DPP_WAVE_SHR1 = 0x138;
 
 template <int CTRL> __device__ __forceinline__ float lane_shift(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL> __device__ __forceinline__ double lane_shift(double v)
 {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 template <typename C> __device__ __forceinline__ C from_right(C v) { return lane_shift<DPP_WAVE_SHL1>(v); }
@@ -188,7 +188,8 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     using C = typename Storage<T>::C;
     using S = Stencil<ST>;
     constexpr int H = S::H;
-    constexpr int NW = 2 * H + 1;  // rows in the input window
+    constexpr int NW = 2 * H + 1;  // rows the derivatives and the update read
+    constexpr int U = NW + 1;      // window slots: those rows and the one being loaded
     const int nx = a.nx, ny = a.ny;
 
     const int rb = bottom ? ybeg - 1 : ybeg;  // f* rows rb .. re (the band's outer
@@ -199,15 +200,22 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     const int first = DIR > 0 ? rb : re;  // first f* row in sweep order
     const int row0 = first - DIR * H;     // first input row
 
-    // rolling window of input rows in sweep order: drho and J (sign-flipped on ghost rows);
-    // the products of J_a = J + F/2 are formed where the derivatives need them
-    C w[3][NW][CPL];
-    Group<T, CPL> pr, px, py;  // prefetched row (raw storage)
-    C ps = C(1);               // its sign (-1: ghost row beyond a wall)
+    // rolling window of input rows in sweep order, input row m in slot m % U: drho and J as
+    // used (sign-flipped on ghost rows); the products of J_a = J + F/2 are formed where the
+    // derivatives need them.  The loop below is unrolled U times, so every slot stays in the
+    // same registers; U is even, so values carried from one row to the next alternate
+    // between two sets of registers with no copies.  Rows stored in the arithmetic type are
+    // loaded straight into their slot (RAW = U load targets); FP16 rows are loaded into one
+    // prefetch group and converted into their slot when it comes due (RAW = 1).
+    constexpr int RAW = sizeof(T) < sizeof(C) ? 1 : U;
+    C w[3][U][CPL];
+    Group<T, CPL> pr[RAW], px[RAW], py[RAW];
+    C ps[RAW];  // row sign (-1: ghost row beyond a wall)
 
     const unsigned voff = col * (unsigned)sizeof(T);  // this lane's byte offset in a row
-    // load input row j (mirrored or wrapped); `use` false issues the same loads, dropped
-    auto fetch = [&](int j, bool use) {
+    // load input row j (mirrored or wrapped) into window slot `slot`; `use` false issues the
+    // same loads, dropped
+    auto fetch = [&](int j, bool use, int slot) {
         int src = j;
         C sgn = C(1);
         if (WALLS) {
@@ -218,17 +226,19 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         }
         src = min(max(src, 0), ny - 1);
         const unsigned off = use ? voff : OFF_NONE;
-        pr = buf_load_group<T, CPL>(row_rsrc(a.dr, src, nx), off);
-        px = buf_load_group<T, CPL>(row_rsrc(a.jx, src, nx), off);
-        py = buf_load_group<T, CPL>(row_rsrc(a.jy, src, nx), off);
-        ps = sgn;
+        const int r = slot % RAW;
+        pr[r] = buf_load_group<T, CPL>(row_rsrc(a.dr, src, nx), off);
+        px[r] = buf_load_group<T, CPL>(row_rsrc(a.jx, src, nx), off);
+        py[r] = buf_load_group<T, CPL>(row_rsrc(a.jy, src, nx), off);
+        ps[r] = sgn;
     };
-    auto insert = [&](int wslot) {
+    auto insert = [&](int slot) {
+        const int r = slot % RAW;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            w[0][wslot][c] = Storage<T>::load(pr.v[c]);
-            w[1][wslot][c] = ps * Storage<T>::load(px.v[c]);
-            w[2][wslot][c] = ps * Storage<T>::load(py.v[c]);
+            w[0][slot][c] = Storage<T>::load(pr[r].v[c]);
+            w[1][slot][c] = WALLS ? ps[r] * Storage<T>::load(px[r].v[c]) : Storage<T>::load(px[r].v[c]);
+            w[2][slot][c] = WALLS ? ps[r] * Storage<T>::load(py[r].v[c]) : Storage<T>::load(py[r].v[c]);
         }
     };
 
@@ -250,10 +260,10 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         // prologue: the first 2H input rows, then the prefetch of the next one
 #pragma unroll
         for (int m = 0; m < 2 * H; ++m) {
-            fetch(row0 + DIR * m, true);
+            fetch(row0 + DIR * m, true, m);
             insert(m);
         }
-        fetch(row0 + DIR * 2 * H, true);
+        fetch(row0 + DIR * 2 * H, true, 2 * H);
     }
 
     // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
@@ -264,17 +274,18 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         return q == 0 ? w[0][slot][c] : q == 1 ? w[2][slot][c] : q == 2 ? w[1][slot][c] : q == 3 ? xa * ya : ya * ya;
     };
 
-    for (int it0 = 0; it0 < nf; it0 += NW) {
+    for (int it0 = 0; it0 < nf; it0 += U) {
 #pragma unroll
-        for (int ph = 0; ph < NW; ++ph) {
+        for (int ph = 0; ph < U; ++ph) {
             const int it = it0 + ph;
             if (it >= nf) break;
-            insert((ph + 2 * H) % NW);
-            fetch(row0 + DIR * (2 * H + it + 1), it + 1 < nf);
+            insert((ph + 2 * H) % U);
+            // input row 2H + it + 1 replaces row it - 1, which no later row reads
+            fetch(row0 + DIR * (2 * H + it + 1), it + 1 < nf, (ph + 2 * H + 1) % U);
 
-            const int cs = (ph + H) % NW;  // window slot of the row r whose f* is computed
+            const int cs = (ph + H) % U;  // window slot of the row r whose f* is computed
             // window slot of row r + k (k rows up the grid)
-            auto sl = [&](int k) { return (ph + H + DIR * k + 2 * NW) % NW; };
+            auto sl = [&](int k) { return (ph + H + DIR * k + 2 * U) % U; };
             // x-derivative fields of this row, and the J_a of its nodes
             C xf[5][CPL], jxa[CPL], jya[CPL];
 #pragma unroll
