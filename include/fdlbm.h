@@ -70,7 +70,9 @@ typedef struct fdlbm_params {
                          * every check_every steps and return FDLBM_EUNSTABLE if one is found
                          * (this synchronises the stream at each check)                       */
     int32_t lane_cols;  /* sweep kernel: grid columns per lane, 0 (choose), 1 (3-point only),
-                         * 2, or 4 (FP32 / FP16); nx must be a multiple; tuning knob          */
+                         * 2, or 4 (FP32 / FP16); any nx: where nx is not a multiple, a lane's
+                         * columns are one element-aligned access (FP32, FP64) or one access
+                         * each (FP16), with the same results; tuning knob                    */
 } fdlbm_params;
 
 typedef struct fdlbm_diag {

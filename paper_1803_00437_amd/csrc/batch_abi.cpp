@@ -59,15 +59,17 @@ int validate(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max
     return FDLBM_OK;
 }
 
-// Columns per lane of an instance's tiles: the widest lane group that divides its width
-// (FP64 keeps at most two, as the single-grid kernel does).
-int instance_cpl(int nx, int dtype)
+// Lane class of an instance (BATCH_CLASSES): aligned vector accesses of the widest lane
+// group where its width allows; else FP16 at even widths keeps aligned accesses of two
+// columns, and every other width takes class 2 (measured on the 512-instance workload:
+// FP32 2 mod 4 widths are faster in class 2 than at two columns per lane).
+int instance_class(int nx, int dtype)
 {
-    if (dtype != FDLBM_F64 && nx % 4 == 0) return 4;
-    return nx % 2 == 0 ? 2 : 1;
+    const int w = dtype == FDLBM_F64 ? 2 : 4;
+    if (nx % w == 0) return 0;
+    if (dtype == FDLBM_F16DEV && nx % 2 == 0) return 1;
+    return 2;
 }
-
-int class_of_cpl(int cpl) { return cpl == 4 ? 0 : cpl == 2 ? 1 : 2; }
 
 // Tiles of every instance for `rows` rows per wavefront: the instances' band counts and
 // the block table, grouped by lane-group class (one launch each) and, within a class,
@@ -81,14 +83,14 @@ void tile_tables(Plan &P, int rows)
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const BatchInstance &A = P.inst[a], &B = P.inst[b];
-        if (A.cpl != B.cpl) return A.cpl > B.cpl;
+        if (A.cls != B.cls) return A.cls < B.cls;
         return (size_t)A.nx * A.ny > (size_t)B.nx * B.ny;
     });
     P.blocks.clear();
     for (int c = 0; c < BATCH_CLASSES; ++c) P.class_blocks[c] = 0;
     for (int i : order) {
         const int tiles = P.inst[i].strips_x * P.inst[i].nbands;
-        P.class_blocks[class_of_cpl(P.inst[i].cpl)] += tiles;
+        P.class_blocks[P.inst[i].cls] += tiles;
         for (int t = 0; t < tiles; ++t) P.blocks.push_back(BatchBlock{i, t});
     }
     for (int c = 0, begin = 0; c < BATCH_CLASSES; ++c) {
@@ -122,8 +124,8 @@ Plan plan(const fdlbm_instance *in, int32_t count, int32_t dtype, int32_t max_sa
         P.mode_elems = al64(P.mode_elems + 2 * n);
         I.nx = in[i].nx;
         I.ny = in[i].ny;
-        I.cpl = instance_cpl(I.nx, dtype);
-        const int S = batch_strip_stride(I.cpl);
+        I.cls = instance_class(I.nx, dtype);
+        const int S = batch_strip_stride(batch_class_cpl(I.cls, dtype));
         I.strips_x = (I.nx + S - 1) / S;
         I.first_chunk = chunk0;
         I.nchunks = (int)((n + BATCH_CHUNK - 1) / BATCH_CHUNK);
@@ -404,7 +406,7 @@ int fdlbm_batch_step_per_instance(fdlbm_batch *b, int64_t nsteps)
     for (int64_t s = 0; s < nsteps; ++s) {
         for (int i = 0; i < b->count; ++i) {
             const BatchInstance &I = b->P.inst[i];
-            BHIPCHK(launch_batch_single(b->L, i, I.cpl, I.strips_x * I.nbands, b->buf[b->cur], b->buf[b->cur ^ 1],
+            BHIPCHK(launch_batch_single(b->L, i, I.cls, I.strips_x * I.nbands, b->buf[b->cur], b->buf[b->cur ^ 1],
                                         b->stream),
                     "batch single launch");
         }

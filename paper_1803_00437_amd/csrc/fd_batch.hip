@@ -6,8 +6,8 @@
 //
 // Each block looks up (instance, tile) in a table built on the host and runs the same
 // tile body as the single-grid kernel, so every instance evolves exactly as it would
-// alone.  Instances are grouped by the widest lane group their width allows (4, 2 or 1
-// columns per lane); each group is one launch.
+// alone.  Instances are grouped by lane class (vector or per-column accesses, see
+// BATCH_CLASSES); each class is one launch.
 #include "fd_sweep_body.hpp"
 #include "internal.hpp"
 
@@ -17,7 +17,7 @@ using namespace sweep;
 
 constexpr int PROJ_TPB = 256;
 
-template <typename T, int CPL>
+template <typename T, int CPL, int AM>
 __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__ in, T *__restrict__ out,
                                                            const BatchInstance *__restrict__ inst,
                                                            const BatchBlock *__restrict__ blocks, int rows)
@@ -40,11 +40,11 @@ __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = b.tile / I.strips_x;
-    sweep_tile<T, CPL, 3, false, false>(t, band, b.tile - band * I.strips_x);
+    sweep_tile<T, CPL, 3, false, false, AM>(t, band, b.tile - band * I.strips_x);
 }
 
 // Single instance in the same tiling: the one-launch-per-grid path of the comparison.
-template <typename T, int CPL>
+template <typename T, int CPL, int AM>
 __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict__ in, T *__restrict__ out,
                                                             const BatchInstance *__restrict__ inst, int i, int rows)
 {
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict_
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = blockIdx.x / I.strips_x;
-    sweep_tile<T, CPL, 3, false, false>(t, band, blockIdx.x - band * I.strips_x);
+    sweep_tile<T, CPL, 3, false, false, AM>(t, band, blockIdx.x - band * I.strips_x);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -134,10 +134,11 @@ __global__ void proj_final(const BatchInstance *__restrict__ inst, int count, co
 
 __global__ void advance_counter(int *counter) { *counter += 1; }
 
-template <typename T, int CPL> hipError_t step_class(const BatchLaunch &L, int c, const void *src, void *dst, hipStream_t s)
+template <typename T, int CPL, int AM>
+hipError_t step_class(const BatchLaunch &L, int c, const void *src, void *dst, hipStream_t s)
 {
     if (L.class_blocks[c] == 0) return hipSuccess;
-    hipLaunchKernelGGL((fd_batch_kernel<T, CPL>), L.class_blocks[c], 64 * WV, 0, s, static_cast<const T *>(src),
+    hipLaunchKernelGGL((fd_batch_kernel<T, CPL, AM>), L.class_blocks[c], 64 * WV, 0, s, static_cast<const T *>(src),
                        static_cast<T *>(dst), L.inst, L.blocks + L.class_begin[c], L.rows);
     return hipGetLastError();
 }
@@ -145,28 +146,28 @@ template <typename T, int CPL> hipError_t step_class(const BatchLaunch &L, int c
 template <typename T>
 hipError_t step_all(const BatchLaunch &L, const void *src, void *dst, hipStream_t s)
 {
-    hipError_t e = hipSuccess;
-    if constexpr (sizeof(T) != 8) e = step_class<T, 4>(L, 0, src, dst, s);
-    if (e == hipSuccess) e = step_class<T, 2>(L, 1, src, dst, s);
-    if (e == hipSuccess) e = step_class<T, 1>(L, 2, src, dst, s);
+    constexpr int W = sizeof(T) == 8 ? 2 : 4;
+    constexpr int AM2 = sizeof(T) >= 4 ? AM_UNAL : AM_COL;  // class 2: any width
+    hipError_t e = step_class<T, W, AM_VEC>(L, 0, src, dst, s);
+    if constexpr (W == 4)
+        if (e == hipSuccess) e = step_class<T, 2, AM_VEC>(L, 1, src, dst, s);
+    if (e == hipSuccess) e = step_class<T, W, AM2>(L, 2, src, dst, s);
     return e;
 }
 
 template <typename T>
-hipError_t step_one(const BatchLaunch &L, int i, int cpl, int nblocks, const void *src, void *dst, hipStream_t s)
+hipError_t step_one(const BatchLaunch &L, int i, int cls, int nblocks, const void *src, void *dst, hipStream_t s)
 {
+    constexpr int W = sizeof(T) == 8 ? 2 : 4;
+    constexpr int AM2 = sizeof(T) >= 4 ? AM_UNAL : AM_COL;
     const T *in = static_cast<const T *>(src);
     T *out = static_cast<T *>(dst);
-    if constexpr (sizeof(T) != 8) {
-        if (cpl == 4) {
-            hipLaunchKernelGGL((fd_single_kernel<T, 4>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
-            return hipGetLastError();
-        }
-    }
-    if (cpl == 2)
-        hipLaunchKernelGGL((fd_single_kernel<T, 2>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
+    if (cls == 0)
+        hipLaunchKernelGGL((fd_single_kernel<T, W, AM_VEC>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
+    else if (cls == 1)
+        hipLaunchKernelGGL((fd_single_kernel<T, 2, AM_VEC>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
     else
-        hipLaunchKernelGGL((fd_single_kernel<T, 1>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
+        hipLaunchKernelGGL((fd_single_kernel<T, W, AM2>), nblocks, 64 * WV, 0, s, in, out, L.inst, i, L.rows);
     return hipGetLastError();
 }
 
@@ -198,13 +199,13 @@ hipError_t launch_batch_step(const BatchLaunch &L, const void *src, void *dst, h
     }
 }
 
-hipError_t launch_batch_single(const BatchLaunch &L, int i, int cpl, int nblocks, const void *src, void *dst,
+hipError_t launch_batch_single(const BatchLaunch &L, int i, int cls, int nblocks, const void *src, void *dst,
                                hipStream_t s)
 {
     switch (L.dtype) {
-    case FDLBM_F64: return step_one<double>(L, i, cpl, nblocks, src, dst, s);
-    case FDLBM_F32: return step_one<float>(L, i, cpl, nblocks, src, dst, s);
-    default: return step_one<__half>(L, i, cpl, nblocks, src, dst, s);
+    case FDLBM_F64: return step_one<double>(L, i, cls, nblocks, src, dst, s);
+    case FDLBM_F32: return step_one<float>(L, i, cls, nblocks, src, dst, s);
+    default: return step_one<__half>(L, i, cls, nblocks, src, dst, s);
     }
 }
 

@@ -44,12 +44,12 @@ template <typename T> struct SweepArgs {
     int strips_x;
 };
 
-template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
+template <typename T, int CPL, int ST, bool WALLS, bool FORCE, int AM>
 __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 {
     // blocks dealt out row band after row band
     const int band = blockIdx.x / a.strips_x;
-    sweep_tile<T, CPL, ST, WALLS, FORCE>(a.t, band, blockIdx.x - band * a.strips_x);
+    sweep_tile<T, CPL, ST, WALLS, FORCE, AM>(a.t, band, blockIdx.x - band * a.strips_x);
 }
 
 // Rows per wavefront when the caller leaves the choice open (fastest at 8192^2): FP32
@@ -61,7 +61,7 @@ int default_rows(const FdArgs &a)
     return a.stencil == 3 ? 8 : 16;
 }
 
-template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
+template <typename T, int CPL, int ST, bool WALLS, bool FORCE, int AM>
 hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
     using C = typename Storage<T>::C;
@@ -83,15 +83,26 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     a.t.k = make_coef<C>(ST, fa.s_xx, fa.s_e, fa.fx, fa.fy);
     a.strips_x = (fa.nx + G::S - 1) / G::S;
     const int nbands = (fa.ny + WV * a.t.rows - 1) / (WV * a.t.rows);
-    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS, FORCE>), a.strips_x * nbands, 64 * WV, 0, s, a);
+    hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS, FORCE, AM>), a.strips_x * nbands, 64 * WV, 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T, int CPL, int ST, bool WALLS>
 hipError_t dispatch_force(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
-    if (a.fx != 0.0 || a.fy != 0.0) return run<T, CPL, ST, WALLS, true>(a, tile_rows, src, dst, s);
-    return run<T, CPL, ST, WALLS, false>(a, tile_rows, src, dst, s);
+    // a lane's columns as one aligned vector access where nx is a multiple of CPL; else one
+    // element-aligned vector access (FP32, FP64) or one access per column (FP16)
+    const bool force = a.fx != 0.0 || a.fy != 0.0;
+    if (a.nx % CPL == 0) {
+        if (force) return run<T, CPL, ST, WALLS, true, AM_VEC>(a, tile_rows, src, dst, s);
+        return run<T, CPL, ST, WALLS, false, AM_VEC>(a, tile_rows, src, dst, s);
+    }
+    if constexpr (CPL > 1) {
+        constexpr int AM = sizeof(T) >= 4 ? AM_UNAL : AM_COL;
+        if (force) return run<T, CPL, ST, WALLS, true, AM>(a, tile_rows, src, dst, s);
+        return run<T, CPL, ST, WALLS, false, AM>(a, tile_rows, src, dst, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int CPL>
@@ -107,14 +118,16 @@ hipError_t dispatch_cpl(const FdArgs &a, int tile_rows, const void *src, void *d
 }
 
 // Columns per lane (measured at 8192^2): FP32 and FP16 4 (16- and 8-byte accesses), FP64
-// 2 (16-byte accesses); narrower when nx is not a multiple (1 is available for 3-point
-// differences only).
+// 2 (16-byte accesses), also where nx is not a multiple (element-aligned vector accesses),
+// except FP16 at even widths, which keeps aligned 4-byte accesses of 2 columns (its odd
+// widths access each column on its own).  1 column per lane is available for 3-point
+// differences only.
 int choose_cpl(const FdArgs &a, int lane_cols)
 {
     if (lane_cols > 0) return lane_cols;
-    int c = a.dtype == FDLBM_F64 ? 2 : 4;
-    while (c > 1 && a.nx % c) c /= 2;
-    return c;
+    if (a.dtype == FDLBM_F64) return 2;
+    if (a.dtype == FDLBM_F16DEV && a.nx % 4 == 2) return 2;
+    return 4;
 }
 
 template <typename T>
@@ -139,8 +152,7 @@ bool fd_sweep_supported(const FdArgs &a, int lane_cols)
     if (a.stencil != 3 && a.stencil != 5) return false;
     if (cpl == 1) return a.stencil == 3;
     if (cpl == 4 && f64) return false;
-    if (cpl != 2 && cpl != 4) return false;
-    return a.nx % cpl == 0;
+    return cpl == 2 || cpl == 4;
 }
 
 hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, int lane_cols, const void *src, void *dst, hipStream_t s)

@@ -13,6 +13,11 @@ namespace sweep {
 
 
 constexpr int WV = 4;  // wavefronts stacked per block
+// Input rows loaded ahead of the row that uses them.  Two keep more bytes in flight; FP16
+// storage with four columns per lane keeps one, which leaves it a third wavefront per SIMD
+// (measured at 8192^2: FP32 +1.5 %, FP16 with two columns per lane +7 %, FP16 with four
+// columns -3 % with two rows ahead).
+template <typename T, int CPL> constexpr int prefetch_rows() { return sizeof(T) == 2 && CPL == 4 ? 1 : 2; }
 
 // whole-wave lane shifts: shl gives lane i the value of lane i+1, shr the value of lane i-1
 constexpr int DPP_WAVE_SHL1 = 0x130;
@@ -41,35 +46,6 @@ template <> struct Word<2> { using type = unsigned short; };
 template <> struct Word<4> { using type = unsigned int; };
 template <> struct Word<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
 template <> struct Word<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
-
-template <typename T, int CPL, typename P> __device__ __forceinline__ Group<T, CPL> load_group(P p)
-{
-    static_assert(sizeof(Group<T, CPL>) == sizeof(T) * CPL, "packed group");
-    using Wd = typename Word<sizeof(T) * CPL>::type;
-    using GW = __attribute__((address_space(1))) const Wd;
-    return __builtin_bit_cast(Group<T, CPL>, *(GW *)(p));  // address-space cast
-}
-template <typename T, int CPL, typename P> __device__ __forceinline__ void store_group(P p, const Group<T, CPL> &g)
-{
-    using Wd = typename Word<sizeof(T) * CPL>::type;
-    using GW = __attribute__((address_space(1))) Wd;
-    __builtin_nontemporal_store(__builtin_bit_cast(Wd, g), (GW *)(p));
-}
-
-// Address of column `col` of row `row` in a plane, in the global address space: the row
-// start is wave-uniform and pinned to scalar registers (otherwise the compiler turns the
-// row walk into a per-lane 64-bit pointer increment), the column a 32-bit lane byte
-// offset, so loads and stores take the scalar-base addressing form.
-template <typename T> using gptr = __attribute__((address_space(1))) T *;
-template <typename T> __device__ __forceinline__ gptr<T> cell(T *plane, int row, int nx, unsigned col)
-{
-    const unsigned long long r = reinterpret_cast<unsigned long long>(plane + (size_t)(unsigned)row * (size_t)(unsigned)nx);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)r);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(r >> 32));
-    using B = __attribute__((address_space(1))) typename std::conditional<std::is_const<T>::value, const char, char>::type;
-    B *rowp = reinterpret_cast<B *>(((unsigned long long)hi << 32) | lo);
-    return reinterpret_cast<gptr<T>>(rowp + col * (unsigned)sizeof(T));
-}
 
 // Row accesses through a buffer resource.  The hardware range-checks every buffer access
 // against the resource's size: an access at OFF_NONE (beyond any row) is dropped (a load
@@ -144,6 +120,100 @@ __device__ __forceinline__ void buf_store_group(__amdgpu_buffer_rsrc_t r, unsign
     BufOps<sizeof(T) * CPL>::store(__builtin_bit_cast(typename Word<sizeof(T) * CPL>::type, g), r, off);
 }
 
+// How a lane reaches its CPL columns of a row (x periodic):
+//   AM_VEC   one access at a CPL-aligned offset (nx a multiple of CPL)
+//   AM_COL   one access per column, each at its own wrapped offset (any nx)
+//   AM_UNAL  one access at an element-aligned offset; a lane whose columns cross the
+//            periodic edge accesses them one by one instead, behind a branch that only
+//            the wavefronts holding such a lane take (any nx; 4- and 8-byte elements,
+//            whose vector accesses need no more than element alignment on this GPU)
+constexpr int AM_VEC = 0, AM_COL = 1, AM_UNAL = 2;
+
+// Byte offsets of a lane's loads and stores in a row (OFF_NONE: none): [0] the vector
+// access (AM_VEC, AM_UNAL), [c] or [1 + c] column c (AM_COL, AM_UNAL).  Stores leave out the
+// columns the tile does not store.
+template <int CPL, int AM> struct LaneCols {
+    static constexpr int K = AM == AM_VEC ? 1 : AM == AM_COL ? CPL : 1 + CPL;
+    unsigned ld[K], st[K];
+    bool edge;   // AM_UNAL: a lane of this wavefront crosses the edge (wave-uniform)
+    bool cross;  // AM_UNAL: this lane's columns cross the edge
+};
+
+template <typename T, int CPL, int AM>
+__device__ __forceinline__ LaneCols<CPL, AM> make_lane_cols(int xl, int nx, bool stored)
+{
+    LaneCols<CPL, AM> lc;
+    lc.edge = lc.cross = false;
+    auto wrapped = [&](int x) { return (unsigned)(((x % nx) + nx) % nx); };
+    if constexpr (AM == AM_COL) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            lc.ld[c] = wrapped(xl + c) * (unsigned)sizeof(T);
+            lc.st[c] = stored && xl + c < nx ? lc.ld[c] : OFF_NONE;
+        }
+    } else {
+        const unsigned cx = wrapped(xl);
+        const bool cross = AM == AM_UNAL && cx + CPL > (unsigned)nx;  // group runs past column nx - 1
+        lc.ld[0] = cross ? OFF_NONE : cx * (unsigned)sizeof(T);
+        lc.st[0] = stored && xl < nx && !cross ? cx * (unsigned)sizeof(T) : OFF_NONE;
+        if constexpr (AM == AM_UNAL) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const unsigned o = wrapped(xl + c) * (unsigned)sizeof(T);
+                lc.ld[1 + c] = cross ? o : OFF_NONE;
+                lc.st[1 + c] = cross && stored && xl + c < nx ? o : OFF_NONE;
+            }
+            lc.edge = __builtin_amdgcn_ballot_w64(cross) != 0;
+            lc.cross = cross;
+        }
+    }
+    return lc;
+}
+
+template <typename T, int CPL, int AM>
+__device__ __forceinline__ Group<T, CPL> row_load(__amdgpu_buffer_rsrc_t r, const LaneCols<CPL, AM> &lc, bool use)
+{
+    using W1 = typename Word<sizeof(T)>::type;
+    if constexpr (AM == AM_COL) {
+        Group<T, CPL> g;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) g.v[c] = __builtin_bit_cast(T, BufOps<sizeof(T)>::load(r, use ? lc.ld[c] : OFF_NONE));
+        return g;
+    } else {
+        Group<T, CPL> g = buf_load_group<T, CPL>(r, use ? lc.ld[0] : OFF_NONE);
+        if constexpr (AM == AM_UNAL) {
+            if (lc.edge && lc.cross) {
+                // only the crossing lane is active here; its vector load read zeros
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    g.v[c] = __builtin_bit_cast(T, BufOps<sizeof(T)>::load(r, use ? lc.ld[1 + c] : OFF_NONE));
+            }
+        }
+        return g;
+    }
+}
+
+template <typename T, int CPL, int AM>
+__device__ __forceinline__ void row_store(__amdgpu_buffer_rsrc_t r, const LaneCols<CPL, AM> &lc, bool use,
+                                          const Group<T, CPL> &g)
+{
+    using W1 = typename Word<sizeof(T)>::type;
+    if constexpr (AM == AM_COL) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+            BufOps<sizeof(T)>::store(__builtin_bit_cast(W1, g.v[c]), r, use ? lc.st[c] : OFF_NONE);
+    } else {
+        buf_store_group<T, CPL>(r, use ? lc.st[0] : OFF_NONE, g);
+        if constexpr (AM == AM_UNAL) {
+            if (lc.edge && lc.cross) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    BufOps<sizeof(T)>::store(__builtin_bit_cast(W1, g.v[c]), r, use ? lc.st[1 + c] : OFF_NONE);
+            }
+        }
+    }
+}
+
 // Strip geometry: a strip loads W columns starting at s*S - P and stores the S = W - 2P
 // columns [s*S, s*S + S), where P = h+1 rounded up to whole lanes.
 template <int CPL, int H> struct Strip {
@@ -180,16 +250,17 @@ enum {
 // needs its same-row part, the forward sums of the row before it and the backward sums of
 // the row after it, combined in the order fd_partial / fd_finish fix (same-row, below,
 // above) whatever the direction.
-template <int DIR, typename T, int CPL, int ST, bool WALLS, bool FORCE>
+template <int DIR, typename T, int CPL, int ST, bool WALLS, bool FORCE, int AM>
 __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storage<T>::C (&lds)[WV][NSLOT][CPL][64],
-                                           int wv, int lane, unsigned col, bool store_ok, int ybeg, int yend,
+                                           int wv, int lane, const LaneCols<CPL, AM> &lc, int ybeg, int yend,
                                            bool empty, bool bottom, bool top)
 {
     using C = typename Storage<T>::C;
     using S = Stencil<ST>;
     constexpr int H = S::H;
     constexpr int NW = 2 * H + 1;  // rows the derivatives and the update read
-    constexpr int U = NW + 1;      // window slots: those rows and the one being loaded
+    constexpr int PD = prefetch_rows<T, CPL>();
+    constexpr int U = (NW + PD + 1) & ~1;  // window slots: those rows and the ones in flight, even
     const int nx = a.nx, ny = a.ny;
 
     const int rb = bottom ? ybeg - 1 : ybeg;  // f* rows rb .. re (the band's outer
@@ -206,13 +277,13 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     // same registers; U is even, so values carried from one row to the next alternate
     // between two sets of registers with no copies.  Rows stored in the arithmetic type are
     // loaded straight into their slot (RAW = U load targets); FP16 rows are loaded into one
-    // prefetch group and converted into their slot when it comes due (RAW = 1).
-    constexpr int RAW = sizeof(T) < sizeof(C) ? 1 : U;
+    // prefetch group per row in flight and converted into their slot when it comes due.
+    constexpr int RAW = sizeof(T) < sizeof(C) ? PD : U;
+    static_assert(U % RAW == 0, "a slot's load group must not depend on the loop iteration");
     C w[3][U][CPL];
     Group<T, CPL> pr[RAW], px[RAW], py[RAW];
     C ps[RAW];  // row sign (-1: ghost row beyond a wall)
 
-    const unsigned voff = col * (unsigned)sizeof(T);  // this lane's byte offset in a row
     // load input row j (mirrored or wrapped) into window slot `slot`; `use` false issues the
     // same loads, dropped
     auto fetch = [&](int j, bool use, int slot) {
@@ -225,11 +296,10 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             src = j < 0 ? j + ny : (j >= ny ? j - ny : j);
         }
         src = min(max(src, 0), ny - 1);
-        const unsigned off = use ? voff : OFF_NONE;
         const int r = slot % RAW;
-        pr[r] = buf_load_group<T, CPL>(row_rsrc(a.dr, src, nx), off);
-        px[r] = buf_load_group<T, CPL>(row_rsrc(a.jx, src, nx), off);
-        py[r] = buf_load_group<T, CPL>(row_rsrc(a.jy, src, nx), off);
+        pr[r] = row_load<T, CPL, AM>(row_rsrc(a.dr, src, nx), lc, use);
+        px[r] = row_load<T, CPL, AM>(row_rsrc(a.jx, src, nx), lc, use);
+        py[r] = row_load<T, CPL, AM>(row_rsrc(a.jy, src, nx), lc, use);
         ps[r] = sgn;
     };
     auto insert = [&](int slot) {
@@ -263,7 +333,8 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             fetch(row0 + DIR * m, true, m);
             insert(m);
         }
-        fetch(row0 + DIR * 2 * H, true, 2 * H);
+#pragma unroll
+        for (int d = 0; d < PD; ++d) fetch(row0 + DIR * (2 * H + d), d < nf, 2 * H + d);
     }
 
     // x-derivative fields (drho, Jx, Jy, Jx^2, JxJy) -> d[0], d[2], d[4], d[6], d[8];
@@ -280,8 +351,8 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             const int it = it0 + ph;
             if (it >= nf) break;
             insert((ph + 2 * H) % U);
-            // input row 2H + it + 1 replaces row it - 1, which no later row reads
-            fetch(row0 + DIR * (2 * H + it + 1), it + 1 < nf, (ph + 2 * H + 1) % U);
+            // input row 2H + it + PD replaces a row that no later f* row reads
+            fetch(row0 + DIR * (2 * H + it + PD), it + PD < nf, (ph + 2 * H + PD) % U);
 
             const int cs = (ph + H) % U;  // window slot of the row r whose f* is computed
             // window slot of row r + k (k rows up the grid)
@@ -400,10 +471,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             // output row b is complete once f* of the rows on both sides of it are known
             {
                 const int orow = min(max(first + DIR * (it - 1), 0), ny - 1);
-                const unsigned off = it >= 2 && store_ok ? voff : OFF_NONE;
-                buf_store_group<T, CPL>(row_rsrc(a.odr, orow, nx), off, gr);
-                buf_store_group<T, CPL>(row_rsrc(a.ojx, orow, nx), off, gx);
-                buf_store_group<T, CPL>(row_rsrc(a.ojy, orow, nx), off, gy);
+                row_store<T, CPL, AM>(row_rsrc(a.odr, orow, nx), lc, it >= 2, gr);
+                row_store<T, CPL, AM>(row_rsrc(a.ojx, orow, nx), lc, it >= 2, gx);
+                row_store<T, CPL, AM>(row_rsrc(a.ojy, orow, nx), lc, it >= 2, gy);
             }
         }
     }
@@ -412,9 +482,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     const int last = first + DIR * (nf - 1);
     Group<T, CPL> o1r, o1x, o1y;
     if (!empty && !end_edge) {
-        o1r = load_group<T, CPL>(cell(a.dr, last, nx, col));
-        o1x = load_group<T, CPL>(cell(a.jx, last, nx, col));
-        o1y = load_group<T, CPL>(cell(a.jy, last, nx, col));
+        o1r = row_load<T, CPL, AM>(row_rsrc(a.dr, last, nx), lc, true);
+        o1x = row_load<T, CPL, AM>(row_rsrc(a.jx, last, nx), lc, true);
+        o1y = row_load<T, CPL, AM>(row_rsrc(a.jy, last, nx), lc, true);
         // the forward sums of the last f* row complete the last output row of the
         // neighbour across the end side
 #pragma unroll
@@ -448,11 +518,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             gx.v[c] = Storage<T>::store(nxv);
             gy.v[c] = Storage<T>::store(nyv);
         }
-        if (store_ok) {
-            store_group<T, CPL>(cell(a.odr, first, nx, col), gr);
-            store_group<T, CPL>(cell(a.ojx, first, nx, col), gx);
-            store_group<T, CPL>(cell(a.ojy, first, nx, col), gy);
-        }
+        row_store<T, CPL, AM>(row_rsrc(a.odr, first, nx), lc, true, gr);
+        row_store<T, CPL, AM>(row_rsrc(a.ojx, first, nx), lc, true, gx);
+        row_store<T, CPL, AM>(row_rsrc(a.ojy, first, nx), lc, true, gy);
     }
     if (!end_edge) {
         // last output row: carried parts and the sums sent across the end side
@@ -474,17 +542,15 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             gx.v[c] = Storage<T>::store(nxv);
             gy.v[c] = Storage<T>::store(nyv);
         }
-        if (store_ok) {
-            store_group<T, CPL>(cell(a.odr, last, nx, col), gr);
-            store_group<T, CPL>(cell(a.ojx, last, nx, col), gx);
-            store_group<T, CPL>(cell(a.ojy, last, nx, col), gy);
-        }
+        row_store<T, CPL, AM>(row_rsrc(a.odr, last, nx), lc, true, gr);
+        row_store<T, CPL, AM>(row_rsrc(a.ojx, last, nx), lc, true, gx);
+        row_store<T, CPL, AM>(row_rsrc(a.ojy, last, nx), lc, true, gy);
     }
 }
 
 // One tile: the block's WV wavefronts over column strip sx and row band `band` of one
 // grid.  Called by every wavefront of the block (it contains a block barrier).
-template <typename T, int CPL, int ST, bool WALLS, bool FORCE>
+template <typename T, int CPL, int ST, bool WALLS, bool FORCE, int AM>
 __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int sx)
 {
     using C = typename Storage<T>::C;
@@ -496,8 +562,9 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nx = a.nx, ny = a.ny;
     const int xl = sx * G::S - G::P + CPL * lane;  // first column of this lane (unwrapped)
-    const unsigned col = ((xl % nx) + nx) % nx;     // wrapped (x periodic)
-    const bool store_ok = CPL * lane >= G::P && CPL * lane < G::P + G::S && xl < nx;
+    const bool stored = CPL * lane >= G::P && CPL * lane < G::P + G::S;  // the strip's own columns
+    static_assert(AM != AM_UNAL || sizeof(T) >= 4, "element-aligned vector accesses need 4- or 8-byte elements");
+    const LaneCols<CPL, AM> lc = make_lane_cols<T, CPL, AM>(xl, nx, stored);
 
     // rows of this wavefront: R each; a single leftover row at the end of the band is
     // absorbed by the wavefront below it, so every non-empty wavefront has >= 2 rows
@@ -510,9 +577,9 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     const bool bottom = wv == 0;  // computes f* of row ybeg - 1 itself
     const bool top = yend == b1;  // computes f* of row yend itself
     if (wv & 1)
-        sweep_wave<1, T, CPL, ST, WALLS, FORCE>(a, lds, wv, lane, col, store_ok, ybeg, yend, empty, bottom, top);
+        sweep_wave<1, T, CPL, ST, WALLS, FORCE, AM>(a, lds, wv, lane, lc, ybeg, yend, empty, bottom, top);
     else
-        sweep_wave<-1, T, CPL, ST, WALLS, FORCE>(a, lds, wv, lane, col, store_ok, ybeg, yend, empty, bottom, top);
+        sweep_wave<-1, T, CPL, ST, WALLS, FORCE, AM>(a, lds, wv, lane, lc, ybeg, yend, empty, bottom, top);
 }
 
 

@@ -44,7 +44,7 @@ struct BatchInstance {
     size_t offset;       // element offset of the instance's drho plane in the state buffers
     size_t mode_offset;  // element offset of its J0 planes (jx, jy) in the mode buffer
     int nx, ny, strips_x, nbands;
-    int cpl;             // grid columns per lane of its tiles: 4, 2 or 1 (nx a multiple)
+    int cls;             // lane class of its tiles (BATCH_CLASSES)
     int first_chunk, nchunks;
     double ke, kxx;      // (1 - 1/s_e) / 2 and (1 - 1/s_xx) / 2 (3-point scale folded in)
 };
@@ -54,10 +54,16 @@ struct BatchBlock {
 struct BatchChunk {
     int instance, chunk;
 };
-// The block table holds the tiles of the instances with 4, 2 and 1 columns per lane in
-// that order; class c (0, 1, 2) starts at class_begin[c] and has class_blocks[c] entries.
+// Lane classes of the batched step, one launch each; W = 4 columns per lane (FP32, FP16)
+// or 2 (FP64):
+//   0: W columns as one vector access (nx a multiple of W)
+//   1: 2 columns as one vector access (FP16, nx even)
+//   2: W columns, any nx: element-aligned vector accesses (FP32, FP64) or one access per
+//      column (FP16)
+// The block table holds the tiles of class 0, 1, 2 in that order; class c starts at
+// class_begin[c] and has class_blocks[c] entries.
 constexpr int BATCH_CLASSES = 3;
-constexpr int batch_class_cpl(int c) { return c == 0 ? 4 : c == 1 ? 2 : 1; }
+inline int batch_class_cpl(int cls, int dtype) { return cls == 1 ? 2 : dtype == FDLBM_F64 ? 2 : 4; }
 struct BatchLaunch {
     int dtype, count, rows, nblocks, nchunks, max_samples;
     int class_begin[BATCH_CLASSES], class_blocks[BATCH_CLASSES];
@@ -69,10 +75,10 @@ struct BatchLaunch {
     int *counter;
     double *amps;
 };
-int batch_strip_stride(int cpl);
+int batch_strip_stride(int cpl);  // columns stored per strip at `cpl` columns per lane
 int batch_rows_per_block(int rows);
 hipError_t launch_batch_step(const BatchLaunch &L, const void *src, void *dst, hipStream_t s);
-hipError_t launch_batch_single(const BatchLaunch &L, int i, int cpl, int nblocks, const void *src, void *dst,
+hipError_t launch_batch_single(const BatchLaunch &L, int i, int cls, int nblocks, const void *src, void *dst,
                                hipStream_t s);
 hipError_t launch_batch_sample(const BatchLaunch &L, const void *state, hipStream_t s);
 

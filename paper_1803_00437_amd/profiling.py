@@ -76,12 +76,24 @@ def sources_sha(paths, root=ROOT):
 
 
 def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=None, sources=(), command="",
-              counter_command="", workload="", n=N, copy_kernel="copy_kernel", copy_bytes=COPY_BYTES, generator=""):
+              counter_command="", workload="", n=N, copy_kernel="copy_kernel", copy_bytes=COPY_BYTES, generator="",
+              group=False):
+    """group=True: every kernel matching `kernel` is launched once per unit of work (the
+    batched step launches one kernel per lane-width class); their average durations add up
+    to the unit's time and `alg` is the bytes of the whole unit."""
     stats = kernel_stats(trace)
     names = {r["Name"]: r for r in stats}
-    kname = pick(names, kernel)
-    k = names[kname]
-    avg_ns = float(k["AverageNs"])
+    if group:
+        hits = sorted(k for k in names if kernel in k)
+        if not hits:
+            raise SystemExit(f"no kernel matches {kernel!r}")
+        kname = " + ".join(hits)
+        k = {"Calls": str(min(int(names[h]["Calls"]) for h in hits))}
+        avg_ns = sum(float(names[h]["AverageNs"]) for h in hits)
+    else:
+        kname = pick(names, kernel)
+        k = names[kname]
+        avg_ns = float(k["AverageNs"])
     lines = [f"# rocprofv3 summary: `{kernel}`", ""]
     if generator:
         lines += [f"Written by: `{generator}` (runs the commands below on the GPU, then summarises)", ""]
@@ -91,7 +103,9 @@ def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=No
               "| kernel | calls | average ns | min ns | max ns |", "|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
         lines.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['MinNs']} | {r['MaxNs']} |")
-    lines += ["", f"Summarised kernel: `{kname}`", f"- calls: {k['Calls']}", f"- average duration: {avg_ns:.0f} ns",
+    lines += ["", f"Summarised kernel: `{kname}`", f"- calls: {k['Calls']}",
+              f"- average duration: {avg_ns:.0f} ns" + (" (sum of the kernels' averages: one launch of each per step)"
+                                                        if group else ""),
               f"- algorithmic bytes per launch: {alg} ({alg / avg_ns:.1f} GB/s at the average duration, "
               f"{alg / avg_ns / 8000:.3f} of 8 TB/s)"]
     out = {"kernel": kname, "avg_ns": avg_ns, "calls": int(k["Calls"]), "alg_bytes_per_launch": alg, "n": n,
@@ -142,6 +156,7 @@ MRT_COUNTER_ARGS = ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--co
 DECAY = "8192 x 8192 periodic decaying flow (modes 0<|k|<=32, max|field| 0.02), nu 0.02"
 KERNELS = [
     # file stem, kernel name pattern, algorithmic bytes per launch, counter pair, sources, workload
+    # (the batch stem sums its per-class kernels, see summarise(group=True))
     ("fd3_f32_8192", "fd_sweep_kernel<float, 4, 3, false, false>", 24 * N * N, "fd", FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP32 (3 words read + 3 written per node)"),
     ("mrt_f32_8192", "mrt_sweep_kernel<float, 4, false>", 72 * N * N, "mrt", MRT_SOURCES,
@@ -158,7 +173,7 @@ KERNELS = [
      "Poiseuille channel 16384 x 1024, walls at y=-1/2 and ny-1/2, body force; FD-LBM 3-point, FP32"),
     ("mrt_f32_channel_16384x1024", "mrt_sweep_kernel<float, 4, true>", 72 * CHANNEL, None, MRT_SOURCES,
      "Poiseuille channel 16384 x 1024, halfway bounce-back walls, body force; MRT D2Q9, FP32"),
-    ("fd3_f32_batch512", "fd_batch_kernel<float", 24 * BATCH_NODES, None,
+    ("fd3_f32_batch512", "fd_batch_kernel<float, ", 24 * BATCH_NODES, None,
      [f"{CSRC}/fd_batch.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"],
      "512 periodic shear-wave instances N x N, N ~ U{32..1024}, one launch per step for all; FP32"),
     ("copy_1gib", "copy_kernel", 2 * COPY_BYTES, None, [f"{CSRC}/diag.hip"],
@@ -208,7 +223,7 @@ def collect(raw, out, run=True):
             f, w, cc = pmc[counters]
             kw = dict(fetch=f, write=w, counter_command=cc, json_out=os.path.join(out, f"{stem}_counters.json"))
         results[stem] = summarise(f"{raw}/trace", pattern, alg, os.path.join(out, f"{stem}.md"), sources=sources,
-                                  command=trace_str, workload=workload,
+                                  command=trace_str, workload=workload, group=stem.endswith("batch512"),
                                   generator="python -m paper_1803_00437_amd.profiling collect --raw <dir> --out profiles",
                                   **kw)
         r = results[stem]

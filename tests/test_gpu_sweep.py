@@ -3,8 +3,8 @@
 Both kernels evaluate the same per-node arithmetic in the same order, so any difference
 is a data-movement error: a wrong lane shift, window slot, strip overlap, wrap, ghost row
 or a partial sum exchanged between the stacked wavefronts of a block.  Shapes are chosen
-so that strips are partial in x (widths that are not multiples of the strip width), the
-grid can be narrower than one strip, row bands end early (with a single leftover row
+so that strips are partial in x (widths that are not multiples of the strip width, nor of
+the lane group), the grid can be narrower than one strip, row bands end early (with a single leftover row
 absorbed by the wavefront below, or a band of one row), and the rows per wavefront vary
 (including fewer than the row window).
 """
@@ -54,6 +54,33 @@ def test_sweep_equals_reference_bitwise(F, dtype, stencil, walls, shape, tile_ro
     print(f"case sweep-vs-reference dtype={dtype} stencil={stencil} walls={walls} shape={shape} "
           f"tile_rows={tile_rows} lane_cols={lane_cols} forced={forced}", flush=True)
     init = W.random_state(nx, ny, seed=nx + ny, amp=0.02)
+    kw = dict(stencil=stencil, dtype=dtype, bc="walls" if walls else "periodic", s_xx=1.6, s_e=1.1,
+              force=(2e-5, -1e-5) if forced else (0.0, 0.0))
+    a = run(F, "reference", nx, ny, 9, init, **kw)
+    b = run(F, "sweep", nx, ny, 9, init, tile_rows=tile_rows, lane_cols=lane_cols, **kw)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v), float(np.max(np.abs(u - v)))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("shape,tile_rows", [((297, 77), 0), ((9, 13), 5), ((523, 40), 3), ((250, 64), 16),
+                                              ((27, 9), 2)])
+@pytest.mark.parametrize("narrow", [False, True])
+@pytest.mark.parametrize("forced", [False, True])
+def test_sweep_per_column_access_equals_reference_bitwise(F, dtype, stencil, walls, shape, tile_rows, narrow,
+                                                          forced):
+    """Widths that are not a multiple of the lane group (odd, or 2 mod 4): each column is
+    loaded and stored on its own and wraps across the periodic edge on its own, at 4 (FP32,
+    FP16) or 2 columns per lane; the 9-wide grid wraps many times inside one strip."""
+    nx, ny = shape
+    lane_cols = 2 if narrow or dtype == "f64" else 4
+    if narrow and dtype == "f64":
+        pytest.skip("FP64 has one lane width with 16-byte accesses")
+    print(f"case per-column dtype={dtype} stencil={stencil} walls={walls} shape={shape} "
+          f"tile_rows={tile_rows} lane_cols={lane_cols} forced={forced}", flush=True)
+    init = W.random_state(nx, ny, seed=nx * ny, amp=0.02)
     kw = dict(stencil=stencil, dtype=dtype, bc="walls" if walls else "periodic", s_xx=1.6, s_e=1.1,
               force=(2e-5, -1e-5) if forced else (0.0, 0.0))
     a = run(F, "reference", nx, ny, 9, init, **kw)
