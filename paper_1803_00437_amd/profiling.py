@@ -8,7 +8,7 @@ counter passes of their own) and write one summary per kernel:
 Summarise an existing set of rocprofv3 directories (``--output-format csv``) for one kernel:
 
     python -m paper_1803_00437_amd.profiling summarise --trace DIR [--fetch DIR --write DIR] \\
-        --kernel "fd_sweep_kernel<float, 4, 3, false, false>" --launch-alg-bytes 1610612736 \\
+        --kernel "fd_sweep_kernel<float, 4, 3, false, false, 0>" --launch-alg-bytes 1610612736 \\
         --out profiles/NAME.md [--json profiles/NAME.json --sources a.hip b.hpp]
 
 The HBM counters are scaled by what they read for the library's streaming copy kernel
@@ -157,19 +157,19 @@ DECAY = "8192 x 8192 periodic decaying flow (modes 0<|k|<=32, max|field| 0.02), 
 KERNELS = [
     # file stem, kernel name pattern, algorithmic bytes per launch, counter pair, sources, workload
     # (the batch stem sums its per-class kernels, see summarise(group=True))
-    ("fd3_f32_8192", "fd_sweep_kernel<float, 4, 3, false, false>", 24 * N * N, "fd", FD_SOURCES,
+    ("fd3_f32_8192", "fd_sweep_kernel<float, 4, 3, false, false, 0>", 24 * N * N, "fd", FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP32 (3 words read + 3 written per node)"),
     ("mrt_f32_8192", "mrt_sweep_kernel<float, 4, false>", 72 * N * N, "mrt", MRT_SOURCES,
      f"{DECAY}; MRT D2Q9, FP32 (9 words read + 9 written per node)"),
-    ("fd3_f64_8192", "fd_sweep_kernel<double, 2, 3, false, false>", 48 * N * N, None, FD_SOURCES,
+    ("fd3_f64_8192", "fd_sweep_kernel<double, 2, 3, false, false, 0>", 48 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP64"),
-    ("fd3_f16_8192", "fd_sweep_kernel<__half, 4, 3, false, false>", 12 * N * N, None, FD_SOURCES,
+    ("fd3_f16_8192", "fd_sweep_kernel<__half, 4, 3, false, false, 0>", 12 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP16 storage, FP32 arithmetic"),
-    ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false, false>", 24 * N * N, None, FD_SOURCES,
+    ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false, false, 0>", 24 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 5-point, FP32"),
     ("mrt_f64_8192", "mrt_sweep_kernel<double, 2, false>", 144 * N * N, None, MRT_SOURCES,
      f"{DECAY}; MRT D2Q9, FP64"),
-    ("fd3_f32_channel_16384x1024", "fd_sweep_kernel<float, 4, 3, true, true>", 24 * CHANNEL, None, FD_SOURCES,
+    ("fd3_f32_channel_16384x1024", "fd_sweep_kernel<float, 4, 3, true, true, 0>", 24 * CHANNEL, None, FD_SOURCES,
      "Poiseuille channel 16384 x 1024, walls at y=-1/2 and ny-1/2, body force; FD-LBM 3-point, FP32"),
     ("mrt_f32_channel_16384x1024", "mrt_sweep_kernel<float, 4, true>", 72 * CHANNEL, None, MRT_SOURCES,
      "Poiseuille channel 16384 x 1024, halfway bounce-back walls, body force; MRT D2Q9, FP32"),
