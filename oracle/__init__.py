@@ -6,7 +6,8 @@ never imports it.
 
 Contents
   * ``fdlbm_oracle.c`` (loaded here through ctypes): the node-by-node FP64 step of the
-    FD-LBM scheme (section 2) and of the MRT D2Q9 scheme (section 1, eqs. 1-2), with the
+    FD-LBM scheme (section 2), of the LW-ACM scheme it starts from (section 1-b) and of
+    the MRT D2Q9 scheme (section 1, eqs. 1-2), with the
     3-, 5- and 9-point finite differences of section 2, periodic or xi=1/2 walls
     (section 3-c) and a Strang-split body force (section 1).
   * ``matrix_form``: a second, independent NumPy rendering of the same steps written as
@@ -50,6 +51,8 @@ def _load():
     lib.oracle_fd_step.restype = i32
     lib.oracle_mrt_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, dbl, dbl, dbl, _dp, i64]
     lib.oracle_mrt_step.restype = i32
+    lib.oracle_lwacm_step.argtypes = [i32, i32, dbl, _dp, _dp, _dp, i64]
+    lib.oracle_lwacm_step.restype = i32
     lib.oracle_mrt_init.argtypes = [i32, i32, _dp, _dp, _dp, _dp]
     lib.oracle_mrt_init.restype = i32
     lib.oracle_mrt_moments.argtypes = [i32, i32, _dp, _dp, _dp, _dp]
@@ -128,6 +131,16 @@ def fd_run(drho, jx, jy, nsteps, *, s_xx, s_e=1.0, stencil=3, walls=False, fx=0.
     ny, nx = r.shape
     _check(_load().oracle_fd_step(nx, ny, int(stencil), int(bool(walls)), float(s_e), float(s_xx),
                                   float(fx), float(fy), rp, xp, yp, int(nsteps)), "fd_step")
+    return r, x, y
+
+
+def lwacm_run(drho, jx, jy, nsteps, *, nu):
+    """Advance the LW-ACM state (section 1-b, Theta = 1 - 6 nu; periodic) by nsteps."""
+    r, rp = _c(np.array(drho, dtype=np.float64, copy=True))
+    x, xp = _c(np.array(jx, dtype=np.float64, copy=True))
+    y, yp = _c(np.array(jy, dtype=np.float64, copy=True))
+    ny, nx = r.shape
+    _check(_load().oracle_lwacm_step(nx, ny, float(nu), rp, xp, yp, int(nsteps)), "lwacm_step")
     return r, x, y
 
 

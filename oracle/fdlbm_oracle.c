@@ -1,5 +1,6 @@
 /*
- * FP64 CPU oracle for the FD-LBM D2Q9 time step and the MRT D2Q9 stream-collide step
+ * FP64 CPU oracle for the FD-LBM D2Q9 time step, the LW-ACM step of section 1-b and the
+ * MRT D2Q9 stream-collide step
  * of Dubois, Lallemand, Obrecht and Tekitek, "Lattice Boltzmann model approximated with
  * finite difference expressions" (Computers & Fluids 155, 2017; arXiv 1803.00437).
  *
@@ -27,7 +28,9 @@
  *   R6  the cubic term of theta_E is taken exactly as printed;
  *   R8  body force (Strang): J_a = J + F/2 enters equilibria and theta, J* = J + F;
  *   R9  walls at xi = 1/2: ghost nodes hold the linear extrapolation with zero velocity on
- *       the wall (J odd, rho even about the wall); MRT uses halfway bounce-back.
+ *       the wall (J odd, rho even about the wall); MRT uses halfway bounce-back;
+ *   R16 LW-ACM: the node (i0, j0) in the reconstruction of section 1-b is the one that link
+ *       k reaches from (i, j), as in eq. 2; u = J / rho inside f^eq and f^eo.
  *
  * What pins this file (tests/test_oracle_pins.py): the moment matrix against the physical
  * moments it names, the equilibria against the textbook D2Q9 polynomial, the stencils
@@ -35,7 +38,11 @@
  * reduction to textbook BGK at unit rates, its linear response against the amplification
  * matrix (whose hyperviscosities reproduce Table 1), the shear viscosity nu(1 - 3V^2) in
  * mean flow along both axes and both diagonals (every velocity-cubic term of theta_XX and
- * theta_XY), and the Poiseuille parabola.
+ * theta_XY), and the Poiseuille parabola.  LW-ACM: the reduction to textbook BGK at
+ * Theta = 0, conservation, its linear response (at rest and in a mean flow) against its
+ * amplification matrix, which matches the one printed in section 1-b to third order in k,
+ * and the transport coefficients printed there (c_s = sqrt(2 nu), Gamma_s = nu/2 + 1/12,
+ * nu(v) = nu - v^2/2, instability above c_s).
  * PARITY UNPINNED: the density-gradient terms of theta_E, theta_XX, theta_XY and the
  * coefficient of the cubic term of theta_E.  No value printed in the paper exercises them
  * (they act on sound waves in mean flow, for which the paper states no number); they are
@@ -451,5 +458,76 @@ int oracle_mrt_step(int nx, int ny, int walls, double s_e, double s_xx, double s
         memcpy(df, fnew, 9 * n * sizeof(double));
     }
     free(fnew);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* LW-ACM (section 1-b), the link-wise artificial-compressibility step the paper takes    */
+/* as its starting point.  Periodic grid.                                                 */
+/* ------------------------------------------------------------------------------------ */
+
+/*
+ * One step, written as section 1-b defines it:
+ *   f^eq(rho, u)  the D2Q9 equilibrium of the table in section 1-a (M^{-1} m^eq),
+ *   f^eo(rho, u) = (f^eq(rho, u) - f^eq(rho, -u)) / 2,
+ *   f*_k(x)      = f^eq_k(x) + Theta (f^eo_k(x + e_k) - f^eo_k(x)),  Theta = 1 - 6 nu,
+ * where x + e_k is the node that link k reaches from x (the "(i0, j0)" of eq. 2), and
+ *   f^{n+1}_k(x + e_k) = f*_k(x)   (eq. 2);   rho^{n+1}, J^{n+1} = moments of f^{n+1}.
+ * The velocity enters through J = rho u (u -> -u is J -> -J at fixed rho > 0).
+ * Populations are deviations from w (see the conventions at the top of this file).
+ */
+int oracle_lwacm_step(int nx, int ny, double nu, double *drho, double *jx, double *jy, int64_t nsteps)
+{
+    if (nx < 1 || ny < 1 || nsteps < 0) return -1;
+    double minv[9][9];
+    inverse_moment_matrix(minv);
+    const double theta = 1.0 - 6.0 * nu;
+    const size_t n = (size_t)nx * (size_t)ny;
+    double *feq = (double *)malloc(9 * n * sizeof(double));
+    double *feo = (double *)malloc(9 * n * sizeof(double));
+    if (!feq || !feo) {
+        free(feq);
+        free(feo);
+        return -2;
+    }
+    for (int64_t step = 0; step < nsteps; ++step) {
+        /* f^eq and f^eo of every node */
+#pragma omp parallel for schedule(static)
+        for (size_t p = 0; p < n; ++p) {
+            double mp[9], mm[9];
+            equilibrium_moments(drho[p], jx[p], jy[p], mp);
+            equilibrium_moments(drho[p], -jx[p], -jy[p], mm);
+            for (int k = 0; k < 9; ++k) {
+                double fp = 0.0, fm = 0.0;
+                for (int l = 0; l < 9; ++l) {
+                    fp += minv[k][l] * mp[l];
+                    fm += minv[k][l] * mm[l];
+                }
+                feq[(size_t)k * n + p] = fp;
+                feo[(size_t)k * n + p] = 0.5 * (fp - fm);
+            }
+        }
+        /* the new state at x gathers f*_k from x - e_k, whose link k ends at x */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < ny; ++j) {
+            for (int i = 0; i < nx; ++i) {
+                const size_t p = (size_t)j * nx + (size_t)i;
+                double r = 0.0, x = 0.0, y = 0.0;
+                for (int k = 0; k < 9; ++k) {
+                    const size_t s = (size_t)wrap(j - EY[k], ny) * nx + (size_t)wrap(i - EX[k], nx);
+                    const double fs = feq[(size_t)k * n + s] + theta * (feo[(size_t)k * n + p] - feo[(size_t)k * n + s]);
+                    r += fs;
+                    x += EX[k] * fs;
+                    y += EY[k] * fs;
+                }
+                /* only feq and feo are read in this pass, so the state is overwritten in place */
+                drho[p] = r;
+                jx[p] = x;
+                jy[p] = y;
+            }
+        }
+    }
+    free(feq);
+    free(feo);
     return 0;
 }

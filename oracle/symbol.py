@@ -8,7 +8,8 @@ step (Phi^{n+1} = H Phi^n); the roots z of det(H - z Id) = 0 give Gamma = -log z
 Section 2 interprets the shear root as Gamma = nu_0 k^2 + nu_2 k^4 ("hyperviscosity" nu_2),
 and solves the full cubic numerically up to k = pi for linear stability.
 
-Here H is assembled numerically about the rest state rho = 1, J = 0:
+Here H is assembled numerically about the rest state rho = 1, J = 0 (LW-ACM also about a
+uniform flow, see lwacm_symbol):
   FD-LBM:  H = P(k) diag(exp(-i k.e_k)) M^{-1} L(k), where L(k) maps Phi to the
            linearised post-collision moments (the theta terms keep only their linear
            parts, the finite differences become their Fourier symbols) and P(k) takes
@@ -72,6 +73,39 @@ def mrt_symbol(kx, ky, *, s_xx, s_e=1.0, s_q, s_eps=1.0):
     Q[8, 0] = 1
     C = MINV @ (np.eye(9) - S + S @ Q) @ M
     return _propagation(kx, ky) @ C
+
+
+def _equilibrium_jacobian(vx, vy):
+    """d m^eq / d(rho, Jx, Jy) of the section 1-a table at rho = 1, J = (vx, vy)."""
+    v2 = vx * vx + vy * vy
+    return np.array([
+        [1, 0, 0],
+        [0, 1, 0],
+        [0, 0, 1],
+        [-2 - 3 * v2, 6 * vx, 6 * vy],          # E = -2 rho + 3 |J|^2 / rho
+        [-(vx * vx - vy * vy), 2 * vx, -2 * vy],  # XX = (Jx^2 - Jy^2) / rho
+        [-vx * vy, vy, vx],                      # XY = Jx Jy / rho
+        [0, -1, 0],                              # qx = -Jx
+        [0, 0, -1],                              # qy = -Jy
+        [1 + 3 * v2, -6 * vx, -6 * vy],          # eps = rho - 3 |J|^2 / rho
+    ], dtype=float)
+
+
+def lwacm_symbol(kx, ky, *, nu, vx=0.0, vy=0.0):
+    """3x3 amplification matrix of the LW-ACM step (section 1-b) on (drho, Jx, Jy) about the
+    uniform state rho = 1, J = (vx, vy).
+
+    f^{n+1}_k(x) = f^eq_k(x - e_k) + Theta (f^eo_k(x) - f^eo_k(x - e_k)), Theta = 1 - 6 nu, so
+    a plane wave gives  f^{n+1} = [P (A_eq - Theta A_eo) + Theta A_eo] Phi  with A_eq, A_eo the
+    Jacobians of f^eq and f^eo and P = diag(exp(-i k.e_k)).  f^eo keeps the part of m^eq odd
+    in J: its rows J and q, which are linear and do not depend on rho."""
+    theta = 1.0 - 6.0 * nu
+    A_eq = MINV @ _equilibrium_jacobian(vx, vy)
+    m_eo = np.zeros((9, 3))
+    m_eo[1, 1] = m_eo[2, 2] = 1
+    m_eo[6, 1] = m_eo[7, 2] = -1
+    A_eo = MINV @ m_eo
+    return M[:3] @ (_propagation(kx, ky) @ (A_eq - theta * A_eo) + theta * A_eo)
 
 
 def _moments3(scheme, v):

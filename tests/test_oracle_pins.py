@@ -443,3 +443,137 @@ def test_unstable_stencil_grows_and_stable_ones_decay():
     j0 = np.max(np.abs(x))
     assert not np.all(np.isfinite(bad[1])) or np.max(np.abs(bad[1])) > 10 * j0
     assert np.max(np.abs(good[1])) < j0
+
+
+# ------------------------------------------------------------- LW-ACM (section 1-b) ----
+
+def printed_lwacm_matrix(k, v, nu):
+    """The amplification matrix printed in section 1-b for the LW-ACM step: wave vector along
+    x, mean flow v along it, entries to second order in k, acting on (drho, Jx, Jy)."""
+    return np.array([
+        [1 - 6j * v * k * nu - k * k * (1 + 3 * v * v) / 6, -6j * nu * k - v * k * k, 0],
+        [-1j * k * (1 + 3 * v * v) / 3 + v * (1 - 3 * v * k * k), 1 - 2j * k * v - 3 * nu * k * k, 0],
+        [0, 0, 1 - 1j * k * v - nu * k * k],
+    ])
+
+
+def _textbook_bgk(r, x, y, steps):
+    """f(x, t+1) = f^eq(x - e_k, t) with the D2Q9 polynomial equilibrium (BGK, tau = 1)."""
+    ex, ey = O.velocities()
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    br, bx, by = r.copy(), x.copy(), y.copy()
+    for _ in range(steps):
+        rho = 1.0 + br
+        nr, nx_, ny_ = np.zeros_like(br), np.zeros_like(br), np.zeros_like(br)
+        for k in range(9):
+            ej = ex[k] * bx + ey[k] * by
+            fk = w[k] * (rho + 3 * ej + 4.5 * ej * ej / rho - 1.5 * (bx * bx + by * by) / rho) - w[k]
+            fk = np.roll(fk, shift=(ey[k], ex[k]), axis=(0, 1))
+            nr += fk
+            nx_ += ex[k] * fk
+            ny_ += ey[k] * fk
+        br, bx, by = nr, nx_, ny_
+    return br, bx, by
+
+
+def test_lwacm_reduces_to_textbook_bgk_when_theta_is_zero():
+    """nu = 1/6 makes Theta = 1 - 6 nu = 0: the reconstruction is f* = f^eq, textbook BGK with
+    tau = 1, on a nonlinear state."""
+    r, x, y = W.random_state(10, 9, seed=18, amp=0.03)
+    out = O.lwacm_run(r, x, y, 20, nu=1 / 6)
+    for u, v in zip(out, _textbook_bgk(r, x, y, 20)):
+        assert np.max(np.abs(u - v)) < 1e-15
+
+
+def test_lwacm_conserves_mass_and_momentum():
+    r, x, y = W.random_state(17, 12, seed=19, amp=0.03)
+    out = O.lwacm_run(r, x, y, 25, nu=0.03)
+    for u, v in zip(out, (r, x, y)):
+        assert abs(np.sum(u) - np.sum(v)) < 1e-13
+
+
+@pytest.mark.parametrize("nu", [0.005, 0.02, 0.1])
+def test_lwacm_symbol_matches_printed_matrix_at_rest(nu):
+    """Every entry of the symbol equals the printed matrix up to third order in k: the error
+    falls by 8 when k halves, and is far below a wrong second-order coefficient."""
+    e1 = np.max(np.abs(S.lwacm_symbol(0.02, 0.0, nu=nu) - printed_lwacm_matrix(0.02, 0.0, nu)))
+    e2 = np.max(np.abs(S.lwacm_symbol(0.01, 0.0, nu=nu) - printed_lwacm_matrix(0.01, 0.0, nu)))
+    # a wrong second-order coefficient c would leave an error of about c k^2
+    assert e1 < 0.02 * 0.02 ** 2 and e1 / e2 > 6, (e1, e2)
+
+
+@pytest.mark.parametrize("v", [0.02, 0.05, 0.1])
+def test_lwacm_symbol_matches_printed_flow_entries(v):
+    """In a mean flow the printed J columns and shear entry hold to third order.  The printed
+    density column does not: at k = 0 it would make H differ from the identity, which mass
+    and momentum conservation forbid (a garbled passage); the symbol keeps H(0) = Id."""
+    nu = 0.02
+    for k in (0.02, 0.01):
+        d = S.lwacm_symbol(k, 0.0, nu=nu, vx=v) - printed_lwacm_matrix(k, v, nu)
+        assert np.max(np.abs(d[:, 1:])) < 3 * k ** 3, (k, d)
+    assert np.max(np.abs(S.lwacm_symbol(0.0, 0.0, nu=nu, vx=v) - np.eye(3))) < 1e-15
+
+
+@pytest.mark.parametrize("nu", [0.005, 0.02, 0.05])
+def test_lwacm_transport_coefficients(nu):
+    """Section 1-b: at rest the sound speed is sqrt(2 nu) and its damping nu/2 + 1/12; the shear
+    viscosity is nu, and nu - v^2/2 in a mean flow v along k, which also advects it at v."""
+    k = 1e-3
+    H = S.lwacm_symbol(k, 0.0, nu=nu)
+    g = -np.log(np.linalg.eigvals(H[:2, :2]))
+    assert np.allclose(sorted(np.abs(g.imag) / k), [math.sqrt(2 * nu)] * 2, rtol=1e-4)
+    assert np.allclose(g.real / k ** 2, nu / 2 + 1 / 12, rtol=1e-4)
+    assert abs((-np.log(H[2, 2])).real / k ** 2 - nu) < 1e-4 * nu
+    for v in (0.3 * math.sqrt(2 * nu), 0.7 * math.sqrt(2 * nu)):
+        g = -np.log(S.lwacm_symbol(k, 0.0, nu=nu, vx=v)[2, 2])
+        assert abs(g.real / k ** 2 - (nu - v * v / 2)) < 1e-4 * nu, (v, g)
+        assert abs(g.imag / k - v) < 1e-6
+
+
+@pytest.mark.parametrize("nu", [0.01, 0.05])
+def test_lwacm_unstable_above_the_sound_speed(nu):
+    """nu(v) = nu - v^2/2 turns negative for v > sqrt(2 nu) = c_s: shear waves then grow, in
+    the symbol and in the nonlinear oracle."""
+    cs = math.sqrt(2 * nu)
+    k = 2 * math.pi / 64
+    assert abs(S.lwacm_symbol(k, 0.0, nu=nu, vx=0.8 * cs)[2, 2]) < 1
+    assert abs(S.lwacm_symbol(k, 0.0, nu=nu, vx=1.25 * cs)[2, 2]) > 1
+    amps = {}
+    for f in (0.8, 1.25):
+        r, x, y = W.shear_wave(64, 4, 1e-6, 1, 0, V=f * cs)
+        _, _, jy = O.lwacm_run(r, x, y, 400, nu=nu)
+        amps[f] = abs(fourier_coeff(jy, 1, 0)) / abs(fourier_coeff(y, 1, 0))
+    assert amps[0.8] < 1 < amps[1.25], amps
+
+
+@pytest.mark.parametrize("mode", [(1, 0), (2, 1), (1, 1)])
+@pytest.mark.parametrize("V", [(0.0, 0.0), (0.05, 0.02)])
+def test_lwacm_linear_response_equals_symbol_power(mode, V):
+    """A small plane wave on a uniform flow: after 40 steps of the C oracle its Fourier
+    amplitudes are the symbol's 40th power applied to the initial ones."""
+    n, steps, nu = 32, 40, 0.03
+    rng = np.random.default_rng(31)
+    phi0 = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) * 1e-9
+    kx, ky = 2 * math.pi * mode[0] / n, 2 * math.pi * mode[1] / n
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    wave = np.exp(1j * (kx * x + ky * y))
+    f = [np.real(p * wave) for p in phi0]
+    out = O.lwacm_run(f[0], f[1] + V[0], f[2] + V[1], steps, nu=nu)
+    got = np.array([fourier_coeff(u, *mode) for u in out]) * 2 / n ** 2
+    expect = np.linalg.matrix_power(S.lwacm_symbol(kx, ky, nu=nu, vx=V[0], vy=V[1]), steps) @ phi0
+    assert np.max(np.abs(got - expect)) < 1e-6 * np.max(np.abs(expect))
+
+
+@pytest.mark.parametrize("V", [0.1, 0.2])
+def test_lwacm_galilean_shear_viscosity(V):
+    """The nonlinear oracle damps a shear wave in a mean flow V along k with nu - V^2/2 (the
+    velocity-square dependence that section 3-a shows for this model in Fig. 1)."""
+    nu, nx, ny, T1, T2 = 0.05, 128, 4, 200, 1200
+    k = 2 * math.pi / nx
+    rates = {}
+    for v in (0.0, V):
+        r, x, y = W.shear_wave(nx, ny, 1e-6, 1, 0, V=v)
+        m1 = O.lwacm_run(r, x, y, T1, nu=nu)
+        m2 = O.lwacm_run(*m1, T2 - T1, nu=nu)
+        rates[v] = math.log(abs(fourier_coeff(m1[2], 1, 0)) / abs(fourier_coeff(m2[2], 1, 0))) / (T2 - T1) / k ** 2
+    assert abs(rates[V] / rates[0.0] - (1 - V * V / (2 * nu))) < 2e-3, rates
