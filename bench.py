@@ -39,7 +39,7 @@ def kernel_source_sha():
 
 
 def bytes_per_node(scheme, dtype):
-    words = 3 if scheme == "fd" else 9
+    words = 9 if scheme == "mrt" else 3
     return 2 * words * {"f64": 8, "f32": 4, "f16": 2}[dtype]
 
 
@@ -48,11 +48,11 @@ def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with
     ny, nx = init[0].shape
     s_xx = F.fdlbm_rate_from_viscosity(nu)
     kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel, tile_rows=tile_rows, bc=bc, force=force)
-    if scheme == "fd":
+    if scheme != "mrt":
         kw["lane_cols"] = lane_cols
     if scheme == "fd":
         kw["stencil"] = stencil
-    else:
+    elif scheme == "mrt":
         kw["quartic"] = True
     sim = F.FdLbm(nx, ny, **kw)
     sim.set_state(*init)
@@ -170,6 +170,8 @@ def band_errors(F, O, init, n, s_steps, rows, cases, threads):
         t0 = time.perf_counter()
         if scheme == "fd":
             res = O.fd_run(*band, s_steps, s_xx=s_xx, s_e=1.0, stencil=stencil)
+        elif scheme == "lwacm":
+            res = O.lwacm_run(*band, s_steps, nu=NU)
         else:
             res = O.mrt_moments(O.mrt_run(O.mrt_init(*band), s_steps, s_xx=s_xx, s_q=O.quartic_s_q(s_xx)))
         dt = time.perf_counter() - t0
@@ -178,7 +180,7 @@ def band_errors(F, O, init, n, s_steps, rows, cases, threads):
         refs[(scheme, stencil)] = tuple(a[m:m + rows] for a in res)
     for scheme, dtype, stencil in cases:
         kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0)
-        kw.update({"stencil": stencil} if scheme == "fd" else {"quartic": True})
+        kw.update({"stencil": stencil} if scheme == "fd" else {"quartic": True} if scheme == "mrt" else {})
         sim = F.FdLbm(n, n, **kw)
         sim.set_state(*init)
         sim.step(s_steps)
@@ -206,7 +208,8 @@ def main():
     ap.add_argument("--err-rows", type=int, default=512)
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wavefront strip of the sweep kernel (0 = default)")
     ap.add_argument("--lane-cols", type=int, default=0, help="grid columns per lane of the sweep kernel (0 = default)")
-    ap.add_argument("--only", default=None, help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16")
+    ap.add_argument("--only", default=None,
+                    help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16, lwacm_f32")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default tile shapes instead of tuning them before timing")
     ap.add_argument("--copy-probe", action="store_true",
@@ -237,7 +240,7 @@ def main():
 
     if args.only:
         name, dtype = args.only.split("_")
-        scheme = "mrt" if name == "mrt" else "fd"
+        scheme = name if name in ("mrt", "lwacm") else "fd"
         stencil = int(name[2]) if scheme == "fd" else 0
         case = run_case(F, torch, init, scheme, dtype, stencil, args.steps, args.warmup, args.kernel, False,
                         args.tile_rows, args.lane_cols, autotune=not args.no_autotune)
@@ -253,7 +256,7 @@ def main():
     if not args.no_compare:
         short = max(100, args.steps // 4)
         for scheme, dtype, stencil in (("mrt", "f32", 0), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5),
-                                       ("mrt", "f64", 0)):
+                                       ("mrt", "f64", 0), ("lwacm", "f32", 0)):
             key = f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"
             compare[key] = run_case(F, torch, init, scheme, dtype, stencil, short, 10, args.kernel, False,
                                     autotune=not args.no_autotune)
@@ -280,7 +283,7 @@ def main():
 
         threads = min(os.cpu_count() or 1, 16)
         cases = [("fd", "f32", 3), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5), ("mrt", "f32", 0),
-                 ("mrt", "f64", 0)]
+                 ("mrt", "f64", 0), ("lwacm", "f32", 0)]
         errors, (updates, secs) = band_errors(F, O, init, n, args.err_steps, args.err_rows, cases, threads)
         print(f"# errors vs oracle: {errors}", file=sys.stderr, flush=True)
         cpu = {

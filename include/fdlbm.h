@@ -39,7 +39,10 @@ extern "C" {
 #define FDLBM_EDEVICE (-3)   /* a HIP runtime call failed */
 #define FDLBM_EUNSTABLE (-4) /* the periodic check found a non-finite value in the state */
 
-enum { FDLBM_SCHEME_FD = 0, FDLBM_SCHEME_MRT = 1 };
+/* FD: the FD-LBM step of section 2.  MRT: the D2Q9 MRT step of section 1.  LWACM: the
+ * link-wise artificial-compressibility step of section 1-b that FD-LBM starts from
+ * (periodic grids, no body force; same stored state as FD-LBM). */
+enum { FDLBM_SCHEME_FD = 0, FDLBM_SCHEME_MRT = 1, FDLBM_SCHEME_LWACM = 2 };
 enum { FDLBM_BC_PERIODIC = 0, FDLBM_BC_WALLS_Y = 1 };
 /* Storage dtype of the state.  F64: FP64 storage and arithmetic.  F32: FP32 storage and
  * arithmetic.  F16DEV: FP16 storage of the deviations (drho, jx, jy), FP32 arithmetic
@@ -53,7 +56,7 @@ enum { FDLBM_KERNEL_AUTO = 0, FDLBM_KERNEL_REFERENCE = 1, FDLBM_KERNEL_SWEEP = 2
 
 typedef struct fdlbm_params {
     int32_t nx, ny;     /* grid; FD-LBM: nx >= 8; walls: ny >= 4; periodic y: ny >= 8      */
-    int32_t scheme;     /* FDLBM_SCHEME_FD or FDLBM_SCHEME_MRT                               */
+    int32_t scheme;     /* FDLBM_SCHEME_FD, FDLBM_SCHEME_MRT or FDLBM_SCHEME_LWACM          */
     int32_t stencil;    /* FD-LBM finite differences of section 2: 3 or 5 points           */
     int32_t bc;         /* FDLBM_BC_PERIODIC or FDLBM_BC_WALLS_Y                            */
     int32_t dtype;      /* FDLBM_F64, FDLBM_F32, FDLBM_F16DEV                               */
@@ -121,6 +124,13 @@ int fdlbm_step(fdlbm_ctx *c, int64_t nsteps);
 /* Advance the MRT populations by nsteps stream-collide steps (section 1, eqs. 1-2) with
  * halfway bounce-back on walls.  Asynchronous.  FDLBM_EINVAL if the context is FD-LBM. */
 int mrt_step(fdlbm_ctx *c, int64_t nsteps);
+
+/* Advance the LW-ACM state (drho, Jx, Jy) by nsteps steps of section 1-b:
+ * f*_k(x) = f^eq_k(x) + Theta (f^eo_k(x + e_k) - f^eo_k(x)), Theta = 1 - 6 nu with
+ * nu = (1/s_xx - 1/2)/3, f^eo the part of f^eq odd in the velocity, then propagation
+ * (eq. 2).  Same kernels, layout, dtypes and tuning knobs as fdlbm_step (stencil, s_e and
+ * the MRT rates are ignored).  Asynchronous.  FDLBM_EINVAL if the context is not LW-ACM. */
+int lwacm_step(fdlbm_ctx *c, int64_t nsteps);
 
 /* FP64 reduction over the current state (section 3-a diagnostics): totals, kinetic
  * energy, max |J|, non-finite count and, if a mode was set, sum J.J0.  Synchronises. */

@@ -1,10 +1,10 @@
-"""MI355X (gfx950) FD-LBM and MRT D2Q9 steps -- thin Python binding of libfdlbm.so.
+"""MI355X (gfx950) FD-LBM, LW-ACM and MRT D2Q9 steps -- thin Python binding of libfdlbm.so.
 
 The binding only marshals arguments: every step of the computation runs in the HIP
 kernels of ``csrc/``, behind the C ABI declared in ``include/fdlbm.h``.  PyTorch is used
 to allocate the caller-owned device buffers and to supply the HIP stream.
 
-Module-level functions carry the C names (``fdlbm_create``, ``fdlbm_step``, ``mrt_step``,
+Module-level functions carry the C names (``fdlbm_create``, ``fdlbm_step``, ``mrt_step``, ``lwacm_step``,
 ``fdlbm_diagnostics`` ...); :class:`FdLbm` owns the buffers of one simulation.
 
 There is no fallback: if ``_build/libfdlbm.so`` is missing, importing the binding's entry
@@ -22,14 +22,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libfdlbm.so")
 
 FDLBM_OK, FDLBM_EINVAL, FDLBM_ENOMEM, FDLBM_EDEVICE, FDLBM_EUNSTABLE = 0, -1, -2, -3, -4
-SCHEME = {"fd": 0, "mrt": 1}
+SCHEME = {"fd": 0, "mrt": 1, "lwacm": 2}
 BC = {"periodic": 0, "walls": 1}
 DTYPE = {"f64": 0, "f32": 1, "f16": 2}
 KERNEL = {"auto": 0, "reference": 1, "sweep": 2}
 
 EXPORTED = (
     "fdlbm_workspace_bytes", "fdlbm_create", "fdlbm_set_state", "fdlbm_get_state",
-    "fdlbm_set_populations", "fdlbm_get_populations", "fdlbm_step", "mrt_step",
+    "fdlbm_set_populations", "fdlbm_get_populations", "fdlbm_step", "mrt_step", "lwacm_step",
     "fdlbm_diagnostics", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
     "fdlbm_destroy", "fdlbm_strerror", "fdlbm_last_error", "fdlbm_rate_from_viscosity",
     "fdlbm_quartic_s_q", "fdlbm_device_copy", "fdlbm_autotune",
@@ -106,6 +106,7 @@ def load_library(path=LIB_PATH):
         "fdlbm_get_populations": (i32, [vp, dp]),
         "fdlbm_step": (i32, [vp, i64]),
         "mrt_step": (i32, [vp, i64]),
+        "lwacm_step": (i32, [vp, i64]),
         "fdlbm_diagnostics": (i32, [vp, ctypes.POINTER(Diag)]),
         "fdlbm_set_mode": (i32, [vp, dp, dp]),
         "fdlbm_mode_projection": (i32, [vp, dp]),
@@ -203,6 +204,10 @@ def mrt_step(ctx, nsteps):
     _check(load_library().mrt_step(ctx, int(nsteps)), "mrt_step")
 
 
+def lwacm_step(ctx, nsteps):
+    _check(load_library().lwacm_step(ctx, int(nsteps)), "lwacm_step")
+
+
 def fdlbm_diagnostics(ctx):
     d = Diag()
     _check(load_library().fdlbm_diagnostics(ctx, ctypes.byref(d)), "fdlbm_diagnostics")
@@ -264,7 +269,7 @@ class FdLbm:
 
     Keyword arguments follow ``fdlbm_params`` (see include/fdlbm.h); ``dtype`` is one of
     "f64", "f32", "f16" (FP16-stored deviations, FP32 arithmetic), ``bc`` "periodic" or
-    "walls", ``scheme`` "fd" or "mrt", ``kernel`` "auto", "reference" or "sweep".
+    "walls", ``scheme`` "fd", "mrt" or "lwacm", ``kernel`` "auto", "reference" or "sweep".
     """
 
     def __init__(self, nx, ny, device="cuda", stream=None, **kw):
@@ -303,6 +308,8 @@ class FdLbm:
     def step(self, nsteps=1):
         if self.scheme == "mrt":
             mrt_step(self.ctx, nsteps)
+        elif self.scheme == "lwacm":
+            lwacm_step(self.ctx, nsteps)
         else:
             fdlbm_step(self.ctx, nsteps)
 

@@ -37,14 +37,18 @@ struct Layout {
     size_t partials, out, mode, staging, fstar, total;
 };
 
+// FD-LBM and LW-ACM store (drho, Jx, Jy) and run on the FD-LBM kernels; MRT stores populations
+bool three_words(int scheme) { return scheme != FDLBM_SCHEME_MRT; }
+
 FdArgs fd_args(const fdlbm_params &p)
 {
-    return FdArgs{p.nx, p.ny, p.stencil, p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, p.dtype, p.s_xx, p.s_e, p.force_x, p.force_y};
+    const int stencil = p.scheme == FDLBM_SCHEME_LWACM ? LWACM_STENCIL : p.stencil;
+    return FdArgs{p.nx, p.ny, stencil, p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, p.dtype, p.s_xx, p.s_e, p.force_x, p.force_y};
 }
 
 bool uses_reference(const fdlbm_params &p)
 {
-    if (p.scheme != FDLBM_SCHEME_FD) return false;
+    if (!three_words(p.scheme)) return false;
     if (p.kernel == FDLBM_KERNEL_REFERENCE) return true;
     return !fd_sweep_supported(fd_args(p), p.lane_cols);
 }
@@ -52,7 +56,8 @@ bool uses_reference(const fdlbm_params &p)
 int validate(const fdlbm_params *p)
 {
     if (!p) return FDLBM_EINVAL;
-    if (p->scheme != FDLBM_SCHEME_FD && p->scheme != FDLBM_SCHEME_MRT) return FDLBM_EINVAL;
+    if (p->scheme != FDLBM_SCHEME_FD && p->scheme != FDLBM_SCHEME_MRT && p->scheme != FDLBM_SCHEME_LWACM)
+        return FDLBM_EINVAL;
     if (p->bc != FDLBM_BC_PERIODIC && p->bc != FDLBM_BC_WALLS_Y) return FDLBM_EINVAL;
     if (p->nx < 8 || p->nx > (1 << 20)) return FDLBM_EINVAL;
     if (p->ny < (p->bc == FDLBM_BC_WALLS_Y ? 4 : 8) || p->ny > (1 << 20)) return FDLBM_EINVAL;
@@ -61,8 +66,12 @@ int validate(const fdlbm_params *p)
     if (!std::isfinite(p->force_x) || !std::isfinite(p->force_y)) return FDLBM_EINVAL;
     if (p->kernel < FDLBM_KERNEL_AUTO || p->kernel > FDLBM_KERNEL_SWEEP) return FDLBM_EINVAL;
     if (p->tile_rows < 0 || p->check_every < 0) return FDLBM_EINVAL;
-    if (p->scheme == FDLBM_SCHEME_FD) {
-        if (p->stencil != 3 && p->stencil != 5) return FDLBM_EINVAL;  // the 9-point form is unstable on {1,1}
+    if (three_words(p->scheme)) {
+        if (p->scheme == FDLBM_SCHEME_FD && p->stencil != 3 && p->stencil != 5)
+            return FDLBM_EINVAL;  // the 9-point form is unstable on {1,1}
+        if (p->scheme == FDLBM_SCHEME_LWACM &&
+            (p->bc != FDLBM_BC_PERIODIC || p->force_x != 0.0 || p->force_y != 0.0))
+            return FDLBM_EINVAL;  // section 1-b defines the step on a periodic grid without force
         if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32 && p->dtype != FDLBM_F16DEV) return FDLBM_EINVAL;
         if (p->lane_cols != 0 && p->lane_cols != 1 && p->lane_cols != 2 && p->lane_cols != 4) return FDLBM_EINVAL;
         if (p->kernel == FDLBM_KERNEL_SWEEP && !fd_sweep_supported(fd_args(*p), p->lane_cols)) return FDLBM_EINVAL;
@@ -173,7 +182,7 @@ int fdlbm_set_state(fdlbm_ctx *c, const double *drho, const double *jx, const do
     HIPCHK(hipMemcpyAsync(st, drho, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
     HIPCHK(hipMemcpyAsync(st + n, jx, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
     HIPCHK(hipMemcpyAsync(st + 2 * n, jy, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
-    if (c->p.scheme == FDLBM_SCHEME_FD)
+    if (three_words(c->p.scheme))
         HIPCHK(launch_pack(c->p.dtype, st, c->buf[c->cur], 3 * n, c->stream), "pack");
     else
         HIPCHK(launch_mrt_init(c->p.dtype, st, st + n, st + 2 * n, c->buf[c->cur], n, c->stream), "mrt_init");
@@ -188,7 +197,7 @@ int fdlbm_get_state(fdlbm_ctx *c, double *drho, double *jx, double *jy)
     HIPCHK(hipSetDevice(c->device), "hipSetDevice");
     const size_t n = c->n(), nb = n * sizeof(double);
     double *st = c->sd(c->L.staging);
-    if (c->p.scheme == FDLBM_SCHEME_FD)
+    if (three_words(c->p.scheme))
         HIPCHK(launch_unpack(c->p.dtype, c->buf[c->cur], st, 3 * n, c->stream), "unpack");
     else
         HIPCHK(launch_mrt_moments(c->p.dtype, c->buf[c->cur], st, st + n, st + 2 * n, n, c->stream), "mrt_moments");
@@ -241,7 +250,7 @@ static int run_diag(fdlbm_ctx *c, double out[DIAG_SLOTS])
 static int advance(fdlbm_ctx *c, int64_t nsteps)
 {
     HIPCHK(hipSetDevice(c->device), "hipSetDevice");
-    const bool fd = c->p.scheme == FDLBM_SCHEME_FD;
+    const bool fd = three_words(c->p.scheme);
     const bool ref = uses_reference(c->p);
     const FdArgs fa = fd_args(c->p);
     const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
@@ -255,7 +264,10 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
             e = launch_fd_reference(fa, src, dst, c->scratch + c->L.fstar, c->stream);
         else
             e = launch_fd_sweep(fa, c->p.tile_rows, c->p.lane_cols, src, dst, c->stream);
-        if (e != hipSuccess) return device_error(e, fd ? "fdlbm_step launch" : "mrt_step launch");
+        if (e != hipSuccess)
+            return device_error(e, c->p.scheme == FDLBM_SCHEME_FD    ? "fdlbm_step launch"
+                                   : c->p.scheme == FDLBM_SCHEME_MRT ? "mrt_step launch"
+                                                                      : "lwacm_step launch");
         c->cur ^= 1;
         ++c->steps;
         if (c->p.check_every > 0 && c->steps % c->p.check_every == 0) {
@@ -277,6 +289,12 @@ int fdlbm_step(fdlbm_ctx *c, int64_t nsteps)
 int mrt_step(fdlbm_ctx *c, int64_t nsteps)
 {
     if (!c || nsteps < 0 || c->p.scheme != FDLBM_SCHEME_MRT) return FDLBM_EINVAL;
+    return advance(c, nsteps);
+}
+
+int lwacm_step(fdlbm_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0 || c->p.scheme != FDLBM_SCHEME_LWACM) return FDLBM_EINVAL;
     return advance(c, nsteps);
 }
 
@@ -325,7 +343,7 @@ int fdlbm_autotune(fdlbm_ctx *c, int32_t reps, int32_t *out_lane_cols, int32_t *
 {
     if (!c || reps < 1 || reps > 10000) return FDLBM_EINVAL;
     HIPCHK(hipSetDevice(c->device), "hipSetDevice");
-    const bool fd = c->p.scheme == FDLBM_SCHEME_FD;
+    const bool fd = three_words(c->p.scheme);
     const FdArgs fa = fd_args(c->p);
     const bool ref = fd ? uses_reference(c->p) : c->p.kernel == FDLBM_KERNEL_REFERENCE;
     // candidate shapes: (lane_cols, tile_rows); the reference kernels have none to choose

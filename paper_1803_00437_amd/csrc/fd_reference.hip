@@ -5,7 +5,8 @@
 // the propagated populations (eq. 2) and adds their difference from the node's own to the
 // stored (drho, jx, jy).  It moves about four times the bytes of the fused kernel and
 // exists as the plain GPU rendering that the fused kernel must match bit for bit; both
-// use fd_node_fstar(), row_sum(), same_row_part(), fd_partial() and fd_finish().
+// use fd_node_fstar() (lw_node_g() for the LW-ACM step), row_sum(), same_row_part(),
+// fd_partial() and fd_finish().
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
 
@@ -48,6 +49,16 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
     const int rr = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= v.nx || rr >= nrows) return;
     const int j = row0 + rr;
+    const size_t plane = (size_t)nrows * (size_t)v.nx;
+    const size_t p = (size_t)rr * (size_t)v.nx + (size_t)i;
+    if constexpr (ST == 1) {  // LW-ACM: the populations g of the node alone
+        C r, x, y, f[9];
+        v.at(i, j, r, x, y);
+        lw_node_g<C>(r, x, y, k.lin, f);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fstar[q * plane + p] = f[q];
+        return;
+    }
 
     // values along the x and y axes through the node, offsets -2..2 (index o + 2)
     C rX[5], xX[5], yX[5], rY[5], xY[5], yY[5];
@@ -86,8 +97,6 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
 
     C f[9];
     fd_node_fstar<C, FORCE>(rX[2], plus_force<FORCE>(xX[2], k.hfx), plus_force<FORCE>(yX[2], k.hfy), d, k, f);
-    const size_t plane = (size_t)nrows * (size_t)v.nx;
-    const size_t p = (size_t)rr * (size_t)v.nx + (size_t)i;
 #pragma unroll
     for (int q = 0; q < 9; ++q) fstar[q * plane + p] = f[q];
 }
@@ -140,6 +149,7 @@ template <typename T> FdCoef<typename Storage<T>::C> make_coef(const FdArgs &a)
     k.qfy = C(0.25 * a.fy);
     k.dfx = C(a.fx);
     k.dfy = C(a.fy);
+    k.lin = C(2.0 / a.s_xx - 1.0);
     return k;
 }
 
@@ -174,6 +184,7 @@ hipError_t dispatch_force(const FdArgs &a, const void *src, void *dst, void *fst
 template <typename T>
 hipError_t dispatch_stencil(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
 {
+    if (a.stencil == 1) return run<T, 1, false, false>(a, src, dst, fstar, s);  // LW-ACM, periodic
     if (a.stencil == 3)
         return a.walls ? dispatch_force<T, 3, true>(a, src, dst, fstar, s)
                        : dispatch_force<T, 3, false>(a, src, dst, fstar, s);

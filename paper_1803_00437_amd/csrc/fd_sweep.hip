@@ -53,12 +53,12 @@ __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 }
 
 // Rows per wavefront when the caller leaves the choice open (fastest at 8192^2): FP32
-// 3-point 8, FP32 5-point 16, FP16 storage 16, FP64 8.  fdlbm_autotune measures instead.
+// 3-point 8, FP32 5-point 16, FP16 storage 16, FP64 8 (LW-ACM as 3-point).  fdlbm_autotune measures instead.
 int default_rows(const FdArgs &a)
 {
     if (a.dtype == FDLBM_F64) return 8;
     if (a.dtype == FDLBM_F16DEV) return 16;
-    return a.stencil == 3 ? 8 : 16;
+    return a.stencil == 5 ? 16 : 8;
 }
 
 template <typename T, int CPL, int ST, bool WALLS, bool FORCE, int AM>
@@ -92,14 +92,17 @@ hipError_t dispatch_force(const FdArgs &a, int tile_rows, const void *src, void 
 {
     // a lane's columns as one aligned vector access where nx is a multiple of CPL; else one
     // element-aligned vector access (FP32, FP64) or one access per column (FP16)
-    const bool force = a.fx != 0.0 || a.fy != 0.0;
+    // (LW-ACM, stencil 1, has no body force)
+    const bool force = ST != 1 && (a.fx != 0.0 || a.fy != 0.0);
     if (a.nx % CPL == 0) {
-        if (force) return run<T, CPL, ST, WALLS, true, AM_VEC>(a, tile_rows, src, dst, s);
+        if constexpr (ST != 1)
+            if (force) return run<T, CPL, ST, WALLS, true, AM_VEC>(a, tile_rows, src, dst, s);
         return run<T, CPL, ST, WALLS, false, AM_VEC>(a, tile_rows, src, dst, s);
     }
     if constexpr (CPL > 1) {
         constexpr int AM = sizeof(T) >= 4 ? AM_UNAL : AM_COL;
-        if (force) return run<T, CPL, ST, WALLS, true, AM>(a, tile_rows, src, dst, s);
+        if constexpr (ST != 1)
+            if (force) return run<T, CPL, ST, WALLS, true, AM>(a, tile_rows, src, dst, s);
         return run<T, CPL, ST, WALLS, false, AM>(a, tile_rows, src, dst, s);
     }
     return hipErrorInvalidValue;
@@ -108,6 +111,7 @@ hipError_t dispatch_force(const FdArgs &a, int tile_rows, const void *src, void 
 template <typename T, int CPL>
 hipError_t dispatch_cpl(const FdArgs &a, int tile_rows, const void *src, void *dst, hipStream_t s)
 {
+    if (a.stencil == 1) return dispatch_force<T, CPL, 1, false>(a, tile_rows, src, dst, s);  // LW-ACM, periodic
     if (a.stencil == 3)
         return a.walls ? dispatch_force<T, CPL, 3, true>(a, tile_rows, src, dst, s)
                        : dispatch_force<T, CPL, 3, false>(a, tile_rows, src, dst, s);
@@ -121,7 +125,7 @@ hipError_t dispatch_cpl(const FdArgs &a, int tile_rows, const void *src, void *d
 // 2 (16-byte accesses), also where nx is not a multiple (element-aligned vector accesses),
 // except FP16 at even widths, which keeps aligned 4-byte accesses of 2 columns (its odd
 // widths access each column on its own).  1 column per lane is available for 3-point
-// differences only.
+// differences and LW-ACM only.
 int choose_cpl(const FdArgs &a, int lane_cols)
 {
     if (lane_cols > 0) return lane_cols;
@@ -149,8 +153,9 @@ bool fd_sweep_supported(const FdArgs &a, int lane_cols)
 {
     const int cpl = choose_cpl(a, lane_cols);
     const bool f64 = a.dtype == FDLBM_F64;
-    if (a.stencil != 3 && a.stencil != 5) return false;
-    if (cpl == 1) return a.stencil == 3;
+    if (a.stencil != 1 && a.stencil != 3 && a.stencil != 5) return false;
+    if (a.stencil == 1 && (a.walls || a.fx != 0.0 || a.fy != 0.0)) return false;  // LW-ACM: periodic, no force
+    if (cpl == 1) return a.stencil != 5;
     if (cpl == 4 && f64) return false;
     return cpl == 2 || cpl == 4;
 }

@@ -258,7 +258,10 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     using C = typename Storage<T>::C;
     using S = Stencil<ST>;
     constexpr int H = S::H;
-    constexpr int NW = 2 * H + 1;  // rows the derivatives and the update read
+    constexpr bool LW = ST == 1;   // LW-ACM: populations from the node alone
+    // rows in use: the 2H + 1 the derivatives read, which include the output row when
+    // H > 0; without derivatives, the f* row and the output row before it
+    constexpr int NW = H > 0 ? 2 * H + 1 : 2;
     constexpr int PD = prefetch_rows<T, CPL>();
     constexpr int U = (NW + PD + 1) & ~1;  // window slots: those rows and the ones in flight, even
     const int nx = a.nx, ny = a.ny;
@@ -357,6 +360,11 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             const int cs = (ph + H) % U;  // window slot of the row r whose f* is computed
             // window slot of row r + k (k rows up the grid)
             auto sl = [&](int k) { return (ph + H + DIR * k + 2 * U) % U; };
+            C f[CPL][9];
+            if constexpr (LW) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) lw_node_g<C>(w[0][cs][c], w[1][cs][c], w[2][cs][c], a.k.lin, f[c]);
+            } else {
             // x-derivative fields of this row, and the J_a of its nodes
             C xf[5][CPL], jxa[CPL], jya[CPL];
 #pragma unroll
@@ -378,7 +386,6 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
                 xl2[q] = H == 2 ? from_left(xf[q][CPL >= 2 ? CPL - 2 : 0]) : C(0);
                 xr2[q] = H == 2 ? from_right(xf[q][CPL > 1 ? 1 : 0]) : C(0);
             }
-            C f[CPL][9];
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 C d[10];
@@ -397,6 +404,7 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
                     d[2 * q + 1] = S::diff(ym2, yfield(q, sl(-1), c), yfield(q, sl(1), c), yp2);
                 }
                 fd_node_fstar<C, FORCE>(w[0][cs][c], jxa[c], jya[c], d, a.k, f[c]);
+            }
             }
             // populations moving along +x come from the column on the left, along -x from
             // the column on the right
@@ -555,7 +563,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
 {
     using C = typename Storage<T>::C;
     using G = Strip<CPL, Stencil<ST>::H>;
-    static_assert(CPL >= 2 || ST == 3, "5-point differences need two columns per lane");
+    static_assert(CPL >= 2 || ST != 5, "5-point differences need two columns per lane");
     __shared__ C lds[WV][NSLOT][CPL][64];
 
     const int lane = threadIdx.x & 63;
@@ -598,6 +606,7 @@ template <typename C> inline FdCoef<C> make_coef(int stencil, double s_xx, doubl
     k.qfy = C(0.25 * fy);
     k.dfx = C(fx);
     k.dfy = C(fy);
+    k.lin = C(2.0 / s_xx - 1.0);
     return k;
 }
 

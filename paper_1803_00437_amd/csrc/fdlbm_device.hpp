@@ -49,6 +49,13 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // The theta terms are linear in the derivatives, so the power-of-two scale is folded into
 // the relaxation factors, which is exact.
 template <int STENCIL> struct Stencil;
+// The LW-ACM step (section 1-b) runs on the same kernels as "stencil 1": it takes no
+// differences, so a node's populations depend on the node alone (half width 0).
+template <> struct Stencil<1> {
+    static constexpr int H = 0;
+    static constexpr double SCALE = 0.5;
+    template <typename C> static __device__ __forceinline__ C diff(C, C, C, C) { return C(0); }
+};
 template <> struct Stencil<3> {
     static constexpr int H = 1;  // half width
     static constexpr double SCALE = 0.5;
@@ -76,6 +83,7 @@ template <typename C> struct FdCoef {
     C hfx, hfy;  // F/2: J_a = J + F/2 (Strang splitting, section 1)
     C qfx, qfy;  // F/4: axis populations carry (J_a + F/4)/3
     C dfx, dfy;  // F  : diagonal populations carry (J_a + F)/12
+    C lin;       // LW-ACM: 1 - Theta = 6 nu = 2/s_xx - 1 (see lw_node_g)
 };
 
 // Inputs of one node: J_a = J + F/2 and the ten unscaled derivatives (of drho, of the
@@ -128,6 +136,40 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
     f[4] = axm - uy;
     const C dgp = fmac(XY, C(0.25), A_dg), dgm = fmac(XY, C(-0.25), A_dg);
     const C vx = plus_force<FORCE>(jx, k.dfx) * C(1.0 / 12.0), vy = plus_force<FORCE>(jy, k.dfy) * C(1.0 / 12.0);
+    const C s = vx + vy, t = vy - vx;
+    f[5] = dgp + s;
+    f[7] = dgp - s;
+    f[6] = dgm + t;
+    f[8] = dgm - t;
+}
+
+// LW-ACM (section 1-b): f*_k(x) = f^eq_k(x) + Theta (f^eo_k(x + e_k) - f^eo_k(x)) with
+// Theta = 1 - 6 nu, and f* propagates to x + e_k.  Regrouped by the node it depends on, the
+// population that arrives at x along k is g_k(x - e_k) + Theta f^eo_k(x) with
+// g_k = f^eq_k - Theta f^eo_k.  f^eo (the part of f^eq odd in J) carries no mass and
+// momentum J, so the node's own term adds Theta J(x) to J; g carries drho and lin J with
+// lin = 1 - Theta.  The update is therefore the FD-LBM one of fd_partial() / fd_finish()
+// with g in place of f*: new = old + sum_k [g_k(x - e_k) - g_k(x)] for drho and for J.
+// f^eo is linear in J, so g is the equilibrium of the section 1-a table with its linear
+// part scaled by lin.  Output: the nine g_k as deviations from the rest populations.
+template <typename C> __device__ __forceinline__ void lw_node_g(C dr, C jx, C jy, C lin, C (&f)[9])
+{
+    const C p0 = jx * jx, q0 = jy * jy, r0 = jx * jy;
+    const C rinv = recip(C(1) + dr);
+    const C K = (p0 + q0) * rinv;  // |J|^2 / rho
+    const C XX = (p0 - q0) * rinv, XY = r0 * rinv;
+    const C k12 = K * C(1.0 / 12.0);
+    const C A_ax = fmac(dr, C(1.0 / 9.0), k12);
+    const C A_dg = fmac(dr, C(1.0 / 36.0), k12);
+    f[0] = fmac(dr, C(4.0 / 9.0), K * C(-2.0 / 3.0));
+    const C axp = fmac(XX, C(0.25), A_ax), axm = fmac(XX, C(-0.25), A_ax);
+    const C ux = lin * jx * C(1.0 / 3.0), uy = lin * jy * C(1.0 / 3.0);
+    f[1] = axp + ux;
+    f[3] = axp - ux;
+    f[2] = axm + uy;
+    f[4] = axm - uy;
+    const C dgp = fmac(XY, C(0.25), A_dg), dgm = fmac(XY, C(-0.25), A_dg);
+    const C vx = lin * jx * C(1.0 / 12.0), vy = lin * jy * C(1.0 / 12.0);
     const C s = vx + vy, t = vy - vx;
     f[5] = dgp + s;
     f[7] = dgp - s;

@@ -16,6 +16,9 @@ inline size_t dtype_bytes(int dtype) { return dtype == FDLBM_F64 ? 8 : dtype == 
 inline size_t compute_bytes(int dtype) { return dtype == FDLBM_F64 ? 8 : 4; }
 
 // Geometry and coefficients of one FD-LBM step, as the kernels need them.
+// FD-LBM step arguments; the LW-ACM step (section 1-b) runs on the same kernels with
+// stencil = LWACM_STENCIL (no differences, periodic, no force).
+constexpr int LWACM_STENCIL = 1;
 struct FdArgs {
     int nx, ny, stencil, walls, dtype;
     double s_xx, s_e, fx, fy;

@@ -167,6 +167,8 @@ KERNELS = [
      f"{DECAY}; FD-LBM 3-point, FP16 storage, FP32 arithmetic"),
     ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false, false, 0>", 24 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 5-point, FP32"),
+    ("lwacm_f32_8192", "fd_sweep_kernel<float, 4, 1, false, false, 0>", 24 * N * N, None, FD_SOURCES,
+     f"{DECAY}; LW-ACM (section 1-b), FP32, the same 3 words per node as FD-LBM"),
     ("mrt_f64_8192", "mrt_sweep_kernel<double, 2, false>", 144 * N * N, None, MRT_SOURCES,
      f"{DECAY}; MRT D2Q9, FP64"),
     ("fd3_f32_channel_16384x1024", "fd_sweep_kernel<float, 4, 3, true, true, 0>", 24 * CHANNEL, None, FD_SOURCES,

@@ -61,6 +61,17 @@ def test_invalid_parameters_are_rejected(bad):
     assert e.value.code == F.FDLBM_EINVAL
 
 
+def test_lwacm_is_periodic_without_force():
+    """Section 1-b defines the LW-ACM step on a periodic grid without body force; its stencil
+    and s_e are not used."""
+    F.fdlbm_workspace_bytes(good(scheme="lwacm", stencil=9, s_e=1.7))
+    F.fdlbm_workspace_bytes(good(scheme="lwacm", dtype="f16", lane_cols=1, kernel="sweep"))
+    for bad in (dict(bc="walls"), dict(force=(1e-5, 0.0)), dict(lane_cols=3)):
+        with pytest.raises(F.FdlbmError) as e:
+            F.fdlbm_workspace_bytes(good(scheme="lwacm", **bad))
+        assert e.value.code == F.FDLBM_EINVAL
+
+
 def test_walls_allow_small_ny_and_quartic_needs_no_s_q():
     F.fdlbm_workspace_bytes(good(bc="walls", ny=4))
     F.fdlbm_workspace_bytes(good(scheme="mrt", quartic=True, s_q=0.0))
@@ -81,6 +92,7 @@ def test_null_context_is_rejected():
     lib = F.load_library()
     assert lib.fdlbm_step(None, 1) == F.FDLBM_EINVAL
     assert lib.mrt_step(None, 1) == F.FDLBM_EINVAL
+    assert lib.lwacm_step(None, 1) == F.FDLBM_EINVAL
     assert lib.fdlbm_step_count(None) == -1
 
 
