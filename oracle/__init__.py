@@ -47,9 +47,9 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
     i32, i64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_double
-    lib.oracle_fd_step.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, dbl, _dp, _dp, _dp, i64]
+    lib.oracle_fd_step.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl, dbl, dbl, _dp, _dp, _dp, i64]
     lib.oracle_fd_step.restype = i32
-    lib.oracle_mrt_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, dbl, dbl, dbl, _dp, i64]
+    lib.oracle_mrt_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, dbl, dbl, dbl, dbl, _dp, i64]
     lib.oracle_mrt_step.restype = i32
     lib.oracle_lwacm_step.argtypes = [i32, i32, dbl, _dp, _dp, _dp, i64]
     lib.oracle_lwacm_step.restype = i32
@@ -123,13 +123,14 @@ def derivative(field, stencil, axis):
     return out
 
 
-def fd_run(drho, jx, jy, nsteps, *, s_xx, s_e=1.0, stencil=3, walls=False, fx=0.0, fy=0.0):
-    """Advance the FD-LBM state (section 2) by nsteps; returns new (drho, jx, jy)."""
+def fd_run(drho, jx, jy, nsteps, *, s_xx, s_e=1.0, stencil=3, walls=False, xi=0.5, fx=0.0, fy=0.0):
+    """Advance the FD-LBM state (section 2) by nsteps; returns new (drho, jx, jy).  With
+    walls, they lie at distance xi beyond the first and last rows (0 < xi <= 1)."""
     r, rp = _c(np.array(drho, dtype=np.float64, copy=True))
     x, xp = _c(np.array(jx, dtype=np.float64, copy=True))
     y, yp = _c(np.array(jy, dtype=np.float64, copy=True))
     ny, nx = r.shape
-    _check(_load().oracle_fd_step(nx, ny, int(stencil), int(bool(walls)), float(s_e), float(s_xx),
+    _check(_load().oracle_fd_step(nx, ny, int(stencil), int(bool(walls)), float(xi), float(s_e), float(s_xx),
                                   float(fx), float(fy), rp, xp, yp, int(nsteps)), "fd_step")
     return r, x, y
 
@@ -164,12 +165,13 @@ def mrt_moments(df):
     return r, x, y
 
 
-def mrt_run(df, nsteps, *, s_xx, s_e=1.0, s_q=None, s_eps=1.0, walls=False, fx=0.0, fy=0.0):
-    """Advance MRT populations (eqs. 1-2) by nsteps; s_q defaults to the quartic value."""
+def mrt_run(df, nsteps, *, s_xx, s_e=1.0, s_q=None, s_eps=1.0, walls=False, xi=0.5, fx=0.0, fy=0.0):
+    """Advance MRT populations (eqs. 1-2) by nsteps; s_q defaults to the quartic value.  With
+    walls, they lie at distance xi beyond the first and last rows (interpolated bounce-back)."""
     if s_q is None:
         s_q = quartic_s_q(s_xx)
     d, dp = _c(np.array(df, dtype=np.float64, copy=True))
     _, ny, nx = d.shape
-    _check(_load().oracle_mrt_step(nx, ny, int(bool(walls)), float(s_e), float(s_xx), float(s_q),
+    _check(_load().oracle_mrt_step(nx, ny, int(bool(walls)), float(xi), float(s_e), float(s_xx), float(s_q),
                                    float(s_eps), float(fx), float(fy), dp, int(nsteps)), "mrt_step")
     return d

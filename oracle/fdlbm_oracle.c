@@ -29,6 +29,9 @@
  *   R8  body force (Strang): J_a = J + F/2 enters equilibria and theta, J* = J + F;
  *   R9  walls at xi = 1/2: ghost nodes hold the linear extrapolation with zero velocity on
  *       the wall (J odd, rho even about the wall); MRT uses halfway bounce-back;
+ *   R18 walls at a general distance xi (Fig. 6): ghost nodes hold the mirror-point value
+ *       described at fill_ghosts(); MRT uses the linear interpolated bounce-back of Bouzidi
+ *       et al. (both reduce to R9 at xi = 1/2);
  *   R16 LW-ACM: the node (i0, j0) in the reconstruction of section 1-b is the one that link
  *       k reaches from (i, j), as in eq. 2; u = J / rho inside f^eq and f^eo.
  *
@@ -144,8 +147,45 @@ static inline double at(const xfield *f, int i, int j)
 static inline double *row(xfield *f, int j) { return f->a + (size_t)(j + G) * (size_t)f->nx; }
 
 /* Fill ghost rows.  parity = +1 for even fields (density), -1 for odd ones (velocity),
- * 0 for fields that must not be mirrored (periodic case only). */
-static void fill_ghosts(xfield *f, int walls, double parity)
+ * 0 for fields that must not be mirrored (periodic case only).
+ *
+ * Walls (section 3-b, 3-c): the wall lies at distance xi (0 < xi <= 1) beyond the last
+ * fluid row, at y = -xi and y = ny - 1 + xi.  Reading R18: the ghost node at distance
+ * d = g - xi beyond the wall (ghost row -g, g = 1, 2, ...) holds the value at its mirror
+ * point, d inside the fluid (y_m = g - 2 xi), with the velocity negated, so that the
+ * velocity varies linearly through zero on the wall.  The value at y_m is interpolated
+ * linearly between the fluid rows around it; when y_m lies between the wall and the last
+ * fluid row, the velocity is interpolated between zero on the wall and that row, and the
+ * density taken from that row (zero normal gradient).  Which expression applies depends on
+ * where the wall cuts the link from the last fluid node to the ghost node (xi < or >= 1/2
+ * for the first ghost row), as in the scheme of Bouzidi et al.  At xi = 1/2 every ghost
+ * row mirrors a fluid row exactly: ghost row -1-m holds parity times fluid row m. */
+static void ghost_row(xfield *f, int walls_top, int g, double parity, double xi)
+{
+    const int nx = f->nx, ny = f->ny;
+    /* fluid row k counted from the wall side, and the ghost row written */
+    double *dst = walls_top ? row(f, ny - 1 + g) : row(f, -g);
+    const double ym = (double)g - 2.0 * xi;
+#define FROM(k) (walls_top ? row(f, ny - 1 - (k)) : row(f, (k)))
+    if (ym >= 0.0) {
+        const int s0 = (int)floor(ym);
+        const double t = ym - (double)s0;
+        const double *a = FROM(s0);
+        if (t == 0.0) {
+            for (int i = 0; i < nx; ++i) dst[i] = parity * a[i];
+        } else {
+            const double *b = FROM(s0 + 1);
+            for (int i = 0; i < nx; ++i) dst[i] = parity * ((1.0 - t) * a[i] + t * b[i]);
+        }
+    } else {
+        const double *a = FROM(0);
+        const double w = parity < 0.0 ? (ym + xi) / xi : 1.0;
+        for (int i = 0; i < nx; ++i) dst[i] = parity * w * a[i];
+    }
+#undef FROM
+}
+
+static void fill_ghosts(xfield *f, int walls, double parity, double xi)
 {
     int nx = f->nx, ny = f->ny;
     for (int m = 0; m < G; ++m) {
@@ -155,14 +195,8 @@ static void fill_ghosts(xfield *f, int walls, double parity)
             memcpy(lo, slo, (size_t)nx * sizeof(double));
             memcpy(hi, shi, (size_t)nx * sizeof(double));
         } else {
-            /* linear extrapolation with zero velocity on a wall half-way between the last
-             * fluid row and the first ghost row: the ghost at distance m+1/2 beyond the wall
-             * mirrors the fluid row at distance m+1/2 inside it. */
-            const double *slo = row(f, m), *shi = row(f, ny - 1 - m);
-            for (int i = 0; i < nx; ++i) {
-                lo[i] = parity * slo[i];
-                hi[i] = parity * shi[i];
-            }
+            ghost_row(f, 0, m + 1, parity, xi);
+            ghost_row(f, 1, m + 1, parity, xi);
         }
     }
 }
@@ -198,7 +232,7 @@ int oracle_fd_derivative(int nx, int ny, int stencil, int axis, const double *in
     xfield g;
     if (!xf_alloc(&g, nx, ny)) return -2;
     for (int j = 0; j < ny; ++j) memcpy(row(&g, j), in + (size_t)j * nx, (size_t)nx * sizeof(double));
-    fill_ghosts(&g, 0, 0.0);
+    fill_ghosts(&g, 0, 0.0, 0.5);
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i)
             out[(size_t)j * nx + i] = axis == 0 ? ddx(&g, stencil, i, j) : ddy(&g, stencil, i, j);
@@ -206,10 +240,10 @@ int oracle_fd_derivative(int nx, int ny, int stencil, int axis, const double *in
     return 0;
 }
 
-static int check_grid(int nx, int ny, int walls)
+static int check_grid(int nx, int ny, int walls, double xi)
 {
     if (nx < 1 || ny < 1) return -1;
-    if (walls && ny < G) return -1;
+    if (walls && (ny < (xi == 0.5 ? G : G + 1) || !(xi > 0.0 && xi <= 1.0))) return -1;
     return 0;
 }
 
@@ -230,10 +264,10 @@ static int check_grid(int nx, int ny, int walls)
  *   5. f* = M^{-1} m*  (section 1);
  *   6. propagation f^{n+1}(x + e_k) = f*_k(x) (eq. 2), then the new rho, J = rows 0..2 of M f.
  */
-int oracle_fd_step(int nx, int ny, int stencil, int walls, double s_e, double s_xx, double fx,
+int oracle_fd_step(int nx, int ny, int stencil, int walls, double xi, double s_e, double s_xx, double fx,
                    double fy, double *drho, double *jx, double *jy, int64_t nsteps)
 {
-    if (check_grid(nx, ny, walls) || (stencil != 3 && stencil != 5 && stencil != 9)) return -1;
+    if (check_grid(nx, ny, walls, xi) || (stencil != 3 && stencil != 5 && stencil != 9)) return -1;
     double minv[9][9];
     inverse_moment_matrix(minv);
     const double ce = 1.0 - 1.0 / s_e, cxx = 1.0 - 1.0 / s_xx;
@@ -256,9 +290,9 @@ int oracle_fd_step(int nx, int ny, int stencil, int walls, double s_e, double s_
             memcpy(row(&vx, j), jx + (size_t)j * nx, (size_t)nx * sizeof(double));
             memcpy(row(&vy, j), jy + (size_t)j * nx, (size_t)nx * sizeof(double));
         }
-        fill_ghosts(&r, walls, +1.0);
-        fill_ghosts(&vx, walls, -1.0);
-        fill_ghosts(&vy, walls, -1.0);
+        fill_ghosts(&r, walls, +1.0, xi);
+        fill_ghosts(&vx, walls, -1.0, xi);
+        fill_ghosts(&vy, walls, -1.0, xi);
         for (int j = -G; j < ny + G; ++j) {
             double *ax = row(&vx, j), *ay = row(&vy, j);
             for (int i = 0; i < nx; ++i) { ax[i] += 0.5 * fx; ay[i] += 0.5 * fy; }
@@ -408,55 +442,82 @@ int oracle_mrt_moments(int nx, int ny, const double *df, double *drho, double *j
  * MRT step: m = M f; J_a = J + F/2; m*_k = m_k + s_k (m_k^eq(rho, J_a) - m_k) for the
  * non-conserved moments (eq. 1), J* = J + F; f* = M^{-1} m*; f^{n+1}(x + e_k) = f*_k(x)
  * (eq. 2).  With walls, a population whose destination lies beyond a wall returns to its
- * source node with the opposite velocity (halfway bounce-back).
+ * source node x with the opposite velocity.  The wall cuts that link at the fraction q = xi
+ * of its length (walls at y = -xi and ny - 1 + xi); the returning population is the
+ * linear interpolation of Bouzidi, Firdaouss and Lallemand (reading R18):
+ *   q <  1/2:  f_kbar(x) = 2q f*_k(x) + (1 - 2q) f*_k(x - e_k),
+ *   q >= 1/2:  f_kbar(x) = f*_k(x) / (2q) + (2q - 1)/(2q) f*_kbar(x),
+ * which is halfway bounce-back, f_kbar(x) = f*_k(x), at q = 1/2.
  * Rates: s = (-, -, -, s_e, s_xx, s_xx, s_q, s_q, s_eps).
  */
-int oracle_mrt_step(int nx, int ny, int walls, double s_e, double s_xx, double s_q, double s_eps,
+int oracle_mrt_step(int nx, int ny, int walls, double xi, double s_e, double s_xx, double s_q, double s_eps,
                     double fx, double fy, double *df, int64_t nsteps)
 {
-    if (check_grid(nx, ny, walls)) return -1;
+    if (check_grid(nx, ny, walls, xi)) return -1;
     double minv[9][9];
     inverse_moment_matrix(minv);
     const double s[9] = {0.0, 0.0, 0.0, s_e, s_xx, s_xx, s_q, s_q, s_eps};
     const size_t n = (size_t)nx * (size_t)ny;
+    double *fstar = (double *)malloc(9 * n * sizeof(double));
     double *fnew = (double *)malloc(9 * n * sizeof(double));
-    if (!fnew) return -2;
+    if (!fstar || !fnew) {
+        free(fstar);
+        free(fnew);
+        return -2;
+    }
     for (int64_t step = 0; step < nsteps; ++step) {
+        /* collision at every node */
+#pragma omp parallel for schedule(static)
+        for (size_t p = 0; p < n; ++p) {
+            double m[9], meq[9], ms[9];
+            for (int l = 0; l < 9; ++l) {
+                double acc = 0.0;
+                for (int k = 0; k < 9; ++k) acc += MOM[l][k] * df[(size_t)k * n + p];
+                m[l] = acc;
+            }
+            const double ux = m[1] + 0.5 * fx, uy = m[2] + 0.5 * fy;
+            equilibrium_moments(m[0], ux, uy, meq);
+            ms[0] = m[0];
+            ms[1] = m[1] + fx;
+            ms[2] = m[2] + fy;
+            for (int l = 3; l < 9; ++l) ms[l] = m[l] + s[l] * (meq[l] - m[l]);
+            for (int k = 0; k < 9; ++k) {
+                double f = 0.0;
+                for (int l = 0; l < 9; ++l) f += minv[k][l] * ms[l];
+                fstar[(size_t)k * n + p] = f;
+            }
+        }
+        /* propagation (eq. 2), interpolated bounce-back at the walls */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < ny; ++j) {
             for (int i = 0; i < nx; ++i) {
                 const size_t p = (size_t)j * nx + (size_t)i;
-                double m[9], meq[9], ms[9], fs[9];
-                for (int l = 0; l < 9; ++l) {
-                    double acc = 0.0;
-                    for (int k = 0; k < 9; ++k) acc += MOM[l][k] * df[(size_t)k * n + p];
-                    m[l] = acc;
-                }
-                const double ux = m[1] + 0.5 * fx, uy = m[2] + 0.5 * fy;
-                equilibrium_moments(m[0], ux, uy, meq);
-                ms[0] = m[0];
-                ms[1] = m[1] + fx;
-                ms[2] = m[2] + fy;
-                for (int l = 3; l < 9; ++l) ms[l] = m[l] + s[l] * (meq[l] - m[l]);
                 for (int k = 0; k < 9; ++k) {
-                    double f = 0.0;
-                    for (int l = 0; l < 9; ++l) f += minv[k][l] * ms[l];
-                    fs[k] = f;
-                }
-                for (int k = 0; k < 9; ++k) {
+                    const double fk = fstar[(size_t)k * n + p];
                     int jd = j + EY[k];
                     const int id = wrap(i + EX[k], nx);
                     if (walls && (jd < 0 || jd >= ny)) {
-                        fnew[(size_t)OPP[k] * n + p] = fs[k];
+                        const int kb = OPP[k];
+                        double v;
+                        if (xi == 0.5) {
+                            v = fk;
+                        } else if (xi < 0.5) {
+                            const size_t pb = (size_t)(j - EY[k]) * nx + (size_t)wrap(i - EX[k], nx);
+                            v = 2.0 * xi * fk + (1.0 - 2.0 * xi) * fstar[(size_t)k * n + pb];
+                        } else {
+                            v = fk / (2.0 * xi) + (2.0 * xi - 1.0) / (2.0 * xi) * fstar[(size_t)kb * n + p];
+                        }
+                        fnew[(size_t)kb * n + p] = v;
                         continue;
                     }
                     jd = wrap(jd, ny);
-                    fnew[(size_t)k * n + (size_t)jd * nx + (size_t)id] = fs[k];
+                    fnew[(size_t)k * n + (size_t)jd * nx + (size_t)id] = fk;
                 }
             }
         }
         memcpy(df, fnew, 9 * n * sizeof(double));
     }
+    free(fstar);
     free(fnew);
     return 0;
 }

@@ -577,3 +577,55 @@ def test_lwacm_galilean_shear_viscosity(V):
         m2 = O.lwacm_run(*m1, T2 - T1, nu=nu)
         rates[v] = math.log(abs(fourier_coeff(m1[2], 1, 0)) / abs(fourier_coeff(m2[2], 1, 0))) / (T2 - T1) / k ** 2
     assert abs(rates[V] / rates[0.0] - (1 - V * V / (2 * nu))) < 2e-3, rates
+
+
+# ------------------------------------------- walls at a general distance xi (Fig. 6) ----
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("xi", [0.2, 0.5, 0.7, 1.0])
+def test_ghost_rows_continue_a_linear_shear_through_the_wall(stencil, xi):
+    """The ghost rows extrapolate linearly with zero velocity on the wall (section 3-b): for a
+    shear jx = a (y + xi), zero on the wall at y = -xi, and uniform density, one step with the
+    wall equals one step on a taller domain whose extra rows hold that same linear field."""
+    nx, ny, extra, a = 6, 12, 6, 1e-3
+    fx = 2e-5
+    y = np.arange(ny, dtype=float)
+    walled = [np.zeros((ny, nx)), np.repeat((a * (y + xi))[:, None], nx, 1), np.zeros((ny, nx))]
+    ye = np.arange(-extra, ny, dtype=float)
+    tall = [np.zeros((ny + extra, nx)), np.repeat((a * (ye + xi))[:, None], nx, 1), np.zeros((ny + extra, nx))]
+    got = O.fd_run(*walled, 1, s_xx=1.4, s_e=1.1, stencil=stencil, walls=True, xi=xi, fx=fx)
+    want = O.fd_run(*tall, 1, s_xx=1.4, s_e=1.1, stencil=stencil, walls=True, xi=0.5, fx=fx)
+    for g, w in zip(got, want):
+        assert np.max(np.abs(g[:4] - w[extra:extra + 4])) < 1e-17
+
+
+def _channel_wall_location(scheme, xi, ny=15, steps=4000):
+    """Fitted zero of the steady Poiseuille profile beyond the first and last rows."""
+    nx, nu, uc = 4, 1 / math.sqrt(108), 0.01
+    s_xx = O.rate_from_viscosity(nu)
+    L = ny - 1 + 2 * xi
+    fx = 8 * nu * uc / L ** 2
+    y = np.arange(ny, dtype=float)
+    u = fx / (2 * nu) * (y + xi) * (ny - 1 + xi - y)
+    r, x, z = np.zeros((ny, nx)), np.repeat(u[:, None], nx, 1) - fx / 2, np.zeros((ny, nx))
+    if scheme == "mrt":
+        d = O.mrt_run(O.mrt_init(r, x, z), steps, s_xx=s_xx, s_q=O.quartic_s_q(s_xx), walls=True, xi=xi, fx=fx)
+        prof = O.mrt_moments(d)[1][:, 0] + fx / 2
+    else:
+        prof = O.fd_run(r, x, z, steps, s_xx=s_xx, s_e=1.0, stencil=int(scheme[2]), walls=True, xi=xi, fx=fx)[1][:, 0]
+        prof = prof + fx / 2
+    lo, hi = np.sort(np.roots(np.polyfit(y, prof, 2)).real)
+    return -lo, hi - (ny - 1)
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+def test_channel_wall_location_tracks_xi(scheme):
+    """Fig. 6: in the channel [1 - xi, 15 + xi] the fitted zero of the velocity follows the
+    imposed xi (bounce-back alone would stay at 1/2), for FD-LBM with extrapolated ghost rows
+    and for MRT with interpolated bounce-back; both walls give the same location."""
+    xis = (0.25, 0.5, 0.75, 1.0)
+    got = [_channel_wall_location(scheme, xi) for xi in xis]
+    for xi, (lo, hi) in zip(xis, got):
+        assert abs(lo - hi) < 1e-9
+        assert abs(lo - xi) < 0.06, (xi, lo)
+    assert all(b[0] > a[0] + 0.15 for a, b in zip(got, got[1:]))
