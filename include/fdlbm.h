@@ -76,6 +76,13 @@ typedef struct fdlbm_params {
                          * 2, or 4 (FP32 / FP16); any nx: where nx is not a multiple, a lane's
                          * columns are one element-aligned access (FP32, FP64) or one access
                          * each (FP16), with the same results; tuning knob                    */
+    double wall_xi;     /* walls: their distance beyond the first and last fluid rows, in
+                         * (0, 1]; 0 selects 1/2 (sections 3-b, 3-c: the channel
+                         * [1 - xi, N + xi] of Fig. 6).  FD-LBM: ghost rows by linear
+                         * extrapolation with zero velocity on the wall, the expression chosen
+                         * by where the wall cuts the link.  MRT: interpolated bounce-back of
+                         * Bouzidi et al. (halfway bounce-back at 1/2; other values run the
+                         * one-thread-per-node MRT kernel).  Ignored without walls.          */
 } fdlbm_params;
 
 typedef struct fdlbm_diag {

@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
         ("s_eps", ctypes.c_double), ("quartic", ctypes.c_int32),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
         ("kernel", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("lane_cols", ctypes.c_int32),
+        ("lane_cols", ctypes.c_int32), ("wall_xi", ctypes.c_double),
     ]
 
 
@@ -153,10 +153,11 @@ def _dptr(a):
 
 def make_params(nx, ny, scheme="fd", stencil=3, bc="periodic", dtype="f32", s_xx=1.0, s_e=1.0,
                 s_q=1.0, s_eps=1.0, quartic=False, force=(0.0, 0.0), kernel="auto", tile_rows=0,
-                check_every=0, lane_cols=0):
+                check_every=0, lane_cols=0, wall_xi=0.5):
     return Params(int(nx), int(ny), SCHEME[scheme], int(stencil), BC[bc], DTYPE[dtype], float(s_xx),
                   float(s_e), float(s_q), float(s_eps), int(bool(quartic)), float(force[0]),
-                  float(force[1]), KERNEL[kernel], int(tile_rows), int(check_every), int(lane_cols))
+                  float(force[1]), KERNEL[kernel], int(tile_rows), int(check_every), int(lane_cols),
+                  float(wall_xi))
 
 
 def fdlbm_workspace_bytes(params):

@@ -40,10 +40,14 @@ struct Layout {
 // FD-LBM and LW-ACM store (drho, Jx, Jy) and run on the FD-LBM kernels; MRT stores populations
 bool three_words(int scheme) { return scheme != FDLBM_SCHEME_MRT; }
 
+// distance of the walls beyond the first and last rows (0 selects 1/2)
+double wall_xi(const fdlbm_params &p) { return p.wall_xi == 0.0 ? 0.5 : p.wall_xi; }
+
 FdArgs fd_args(const fdlbm_params &p)
 {
     const int stencil = p.scheme == FDLBM_SCHEME_LWACM ? LWACM_STENCIL : p.stencil;
-    return FdArgs{p.nx, p.ny, stencil, p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, p.dtype, p.s_xx, p.s_e, p.force_x, p.force_y};
+    return FdArgs{p.nx, p.ny, stencil, p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, p.dtype, p.s_xx, p.s_e, p.force_x, p.force_y,
+                  wall_xi(p)};
 }
 
 bool uses_reference(const fdlbm_params &p)
@@ -64,6 +68,7 @@ int validate(const fdlbm_params *p)
     if ((size_t)p->nx * (size_t)p->ny > (size_t(1) << 32)) return FDLBM_EINVAL;
     if (!rate_ok(p->s_xx) || !rate_ok(p->s_e)) return FDLBM_EINVAL;
     if (!std::isfinite(p->force_x) || !std::isfinite(p->force_y)) return FDLBM_EINVAL;
+    if (p->bc == FDLBM_BC_WALLS_Y && !(wall_xi(*p) > 0.0 && wall_xi(*p) <= 1.0)) return FDLBM_EINVAL;
     if (p->kernel < FDLBM_KERNEL_AUTO || p->kernel > FDLBM_KERNEL_SWEEP) return FDLBM_EINVAL;
     if (p->tile_rows < 0 || p->check_every < 0) return FDLBM_EINVAL;
     if (three_words(p->scheme)) {
@@ -78,6 +83,9 @@ int validate(const fdlbm_params *p)
     } else {
         if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32) return FDLBM_EINVAL;
         if (!rate_ok(p->s_eps)) return FDLBM_EINVAL;
+        // interpolated bounce-back (walls away from the half-way point) runs on the
+        // one-thread-per-node kernel only
+        if (p->kernel == FDLBM_KERNEL_SWEEP && p->bc == FDLBM_BC_WALLS_Y && wall_xi(*p) != 0.5) return FDLBM_EINVAL;
         if (!p->quartic && !rate_ok(p->s_q)) return FDLBM_EINVAL;
     }
     return FDLBM_OK;
@@ -254,7 +262,7 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
     const bool ref = uses_reference(c->p);
     const FdArgs fa = fd_args(c->p);
     const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
-                     c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, c->p.tile_rows};
+                     c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, c->p.tile_rows, wall_xi(c->p)};
     for (int64_t s = 0; s < nsteps; ++s) {
         void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
         hipError_t e;
@@ -370,7 +378,7 @@ int fdlbm_autotune(fdlbm_ctx *c, int32_t reps, int32_t *out_lane_cols, int32_t *
         if (fd && ref) return launch_fd_reference(fa, src, dst, c->scratch + c->L.fstar, c->stream);
         if (fd) return launch_fd_sweep(fa, sh.rows, sh.cols, src, dst, c->stream);
         const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
-                         c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, sh.rows};
+                         c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, sh.rows, wall_xi(c->p)};
         return launch_mrt(ma, src, dst, c->stream);
     };
     Shape best{0, 0};

@@ -16,26 +16,38 @@ namespace {
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Value of (drho, J) at node (i, j) with the boundary rules: x periodic; y periodic, or,
-// with walls, a ghost node mirrors the fluid node at the same distance from the wall
-// (linear extrapolation with zero velocity on the wall: drho even, J odd).
+// with walls, a ghost node takes the rule of ghost_rules() (linear extrapolation with zero
+// velocity on the wall; at xi = 1/2 it mirrors the fluid node at the same distance from the
+// wall, drho even and J odd).
 template <typename T, bool WALLS> struct View {
     using C = typename Storage<T>::C;
     const T *dr, *jx, *jy;
     int nx, ny;
+    GhostRules<C> gr;
     __device__ __forceinline__ void at(int i, int j, C &r, C &x, C &y) const
     {
         i = wrap(wrap(i, nx), nx);
-        C sgn = C(1);
-        if (WALLS) {
-            if (j < 0) { j = -1 - j; sgn = C(-1); }
-            else if (j >= ny) { j = 2 * ny - 1 - j; sgn = C(-1); }
-        } else {
-            j = wrap(wrap(j, ny), ny);
+        if (WALLS && (j < 0 || j >= ny)) {
+            const GhostRule<C> q = ghost_rule(gr, j < 0 ? -j : j - ny + 1);
+            const int ja = j < 0 ? q.sa : ny - 1 - q.sa;
+            const size_t pa = (size_t)ja * (size_t)nx + (size_t)i;
+            r = q.car * Storage<T>::load(dr[pa]);
+            x = q.caj * Storage<T>::load(jx[pa]);
+            y = q.caj * Storage<T>::load(jy[pa]);
+            if (q.sb >= 0) {
+                const int jb = j < 0 ? q.sb : ny - 1 - q.sb;
+                const size_t pb = (size_t)jb * (size_t)nx + (size_t)i;
+                r = r + q.cbr * Storage<T>::load(dr[pb]);
+                x = x + q.cbj * Storage<T>::load(jx[pb]);
+                y = y + q.cbj * Storage<T>::load(jy[pb]);
+            }
+            return;
         }
+        if (!WALLS) j = wrap(wrap(j, ny), ny);
         const size_t p = (size_t)j * (size_t)nx + (size_t)i;
         r = Storage<T>::load(dr[p]);
-        x = sgn * Storage<T>::load(jx[p]);
-        y = sgn * Storage<T>::load(jy[p]);
+        x = Storage<T>::load(jx[p]);
+        y = Storage<T>::load(jy[p]);
     }
 };
 
@@ -161,7 +173,7 @@ hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStre
     const T *in = static_cast<const T *>(src);
     T *out = static_cast<T *>(dst);
     auto k = make_coef<T>(a);
-    View<T, WALLS> v{in, in + n, in + 2 * n, a.nx, a.ny};
+    View<T, WALLS> v{in, in + n, in + 2 * n, a.nx, a.ny, ghost_rules<C>(a.xi)};
     const int row0 = WALLS ? -1 : 0, nrows = WALLS ? a.ny + 2 : a.ny;
     dim3 blk(64, 4);
     dim3 g1((a.nx + 63) / 64, (nrows + 3) / 4);

@@ -81,6 +81,7 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     // rows per wavefront (>= 2, see the tile body)
     a.t.rows = tile_rows >= 2 ? tile_rows : default_rows(fa);
     a.t.k = make_coef<C>(ST, fa.s_xx, fa.s_e, fa.fx, fa.fy);
+    a.t.gr = ghost_rules<C>(fa.xi);
     a.strips_x = (fa.nx + G::S - 1) / G::S;
     const int nbands = (fa.ny + WV * a.t.rows - 1) / (WV * a.t.rows);
     hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS, FORCE, AM>), a.strips_x * nbands, 64 * WV, 0, s, a);

@@ -229,6 +229,7 @@ template <typename T> struct TileArgs {
     T *odr, *ojx, *ojy;
     int nx, ny, rows;
     FdCoef<typename Storage<T>::C> k;
+    GhostRules<typename Storage<T>::C> gr;  // walls only
 };
 
 // Each wavefront of a block sweeps its rows in one direction: even wavefronts downward,
@@ -285,16 +286,26 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     static_assert(U % RAW == 0, "a slot's load group must not depend on the loop iteration");
     C w[3][U][CPL];
     Group<T, CPL> pr[RAW], px[RAW], py[RAW];
-    C ps[RAW];  // row sign (-1: ghost row beyond a wall)
+    // with walls, a loaded row's factors for drho and J (1, 1 in the fluid) and, for a ghost
+    // row interpolated between two fluid rows, the second row and its factors
+    C pca[RAW], pcj[RAW], pbr[RAW], pbj[RAW];
+    int psb[RAW];
 
     // load input row j (mirrored or wrapped) into window slot `slot`; `use` false issues the
     // same loads, dropped
     auto fetch = [&](int j, bool use, int slot) {
-        int src = j;
-        C sgn = C(1);
+        int src = j, srcb = -1;
+        C ca = C(1), cj = C(1), br = C(0), bj = C(0);
         if (WALLS) {
-            if (j < 0) { src = -1 - j; sgn = C(-1); }
-            else if (j >= ny) { src = 2 * ny - 1 - j; sgn = C(-1); }
+            if (j < 0 || j >= ny) {  // ghost row beyond a wall
+                const GhostRule<C> q = ghost_rule(a.gr, j < 0 ? -j : j - ny + 1);
+                src = j < 0 ? q.sa : ny - 1 - q.sa;
+                if (q.sb >= 0) srcb = min(max(j < 0 ? q.sb : ny - 1 - q.sb, 0), ny - 1);
+                ca = q.car;
+                cj = q.caj;
+                br = q.cbr;
+                bj = q.cbj;
+            }
         } else {
             src = j < 0 ? j + ny : (j >= ny ? j - ny : j);
         }
@@ -303,15 +314,32 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         pr[r] = row_load<T, CPL, AM>(row_rsrc(a.dr, src, nx), lc, use);
         px[r] = row_load<T, CPL, AM>(row_rsrc(a.jx, src, nx), lc, use);
         py[r] = row_load<T, CPL, AM>(row_rsrc(a.jy, src, nx), lc, use);
-        ps[r] = sgn;
+        pca[r] = ca;
+        pcj[r] = cj;
+        pbr[r] = br;
+        pbj[r] = bj;
+        psb[r] = srcb;
     };
     auto insert = [&](int slot) {
         const int r = slot % RAW;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            w[0][slot][c] = Storage<T>::load(pr[r].v[c]);
-            w[1][slot][c] = WALLS ? ps[r] * Storage<T>::load(px[r].v[c]) : Storage<T>::load(px[r].v[c]);
-            w[2][slot][c] = WALLS ? ps[r] * Storage<T>::load(py[r].v[c]) : Storage<T>::load(py[r].v[c]);
+            w[0][slot][c] = WALLS ? pca[r] * Storage<T>::load(pr[r].v[c]) : Storage<T>::load(pr[r].v[c]);
+            w[1][slot][c] = WALLS ? pcj[r] * Storage<T>::load(px[r].v[c]) : Storage<T>::load(px[r].v[c]);
+            w[2][slot][c] = WALLS ? pcj[r] * Storage<T>::load(py[r].v[c]) : Storage<T>::load(py[r].v[c]);
+        }
+        if (WALLS && psb[r] >= 0) {
+            // ghost row between two fluid rows (walls at a general distance): the second
+            // row is read here, a few times per sweep at most
+            const Group<T, CPL> br_ = row_load<T, CPL, AM>(row_rsrc(a.dr, psb[r], nx), lc, true);
+            const Group<T, CPL> bx_ = row_load<T, CPL, AM>(row_rsrc(a.jx, psb[r], nx), lc, true);
+            const Group<T, CPL> by_ = row_load<T, CPL, AM>(row_rsrc(a.jy, psb[r], nx), lc, true);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                w[0][slot][c] = w[0][slot][c] + pbr[r] * Storage<T>::load(br_.v[c]);
+                w[1][slot][c] = w[1][slot][c] + pbj[r] * Storage<T>::load(bx_.v[c]);
+                w[2][slot][c] = w[2][slot][c] + pbj[r] * Storage<T>::load(by_.v[c]);
+            }
         }
     };
 

@@ -72,6 +72,61 @@ template <> struct Stencil<5> {
     }
 };
 
+// Ghost rows beyond a wall at distance xi past the last fluid row (0 < xi <= 1; sections
+// 3-b and 3-c).  The ghost node at distance d beyond the wall takes the value at its mirror
+// point, d inside the fluid, with the velocity negated: linear extrapolation with zero
+// velocity on the wall.  The mirror value is interpolated between the fluid rows around it,
+// or, between the wall and the last fluid row, between zero velocity on the wall and that
+// row (the density taken from that row); the case depends on where the wall cuts the link,
+// as in Bouzidi et al.  Ghost row g (g = 1, 2, 3 rows beyond the last fluid row) holds
+//   drho = car v(sa) + cbr v(sb),   J = caj v(sa) + cbj v(sb)
+// with fluid rows sa, sb counted from the wall (0 = the last fluid row); sb < 0: one row.
+// At xi = 1/2 ghost row g is fluid row g - 1 with J negated (car = 1, caj = -1).
+constexpr int NGHOST = 3;
+template <typename C> struct GhostRule {
+    int sa, sb;
+    C car, caj, cbr, cbj;
+};
+template <typename C> struct GhostRules {
+    GhostRule<C> g[NGHOST];
+};
+template <typename C> inline GhostRules<C> ghost_rules(double xi)
+{
+    GhostRules<C> r;
+    for (int g = 1; g <= NGHOST; ++g) {
+        GhostRule<C> &q = r.g[g - 1];
+        const double ym = g - 2.0 * xi;  // mirror point, rows inside the last fluid row
+        if (ym >= 0.0) {
+            const int s0 = (int)ym;
+            const double t = ym - s0;
+            q.sa = s0;
+            q.car = C(1.0 - t);
+            q.caj = C(-(1.0 - t));
+            if (t == 0.0) {
+                q.sb = -1;
+                q.cbr = q.cbj = C(0);
+            } else {
+                q.sb = s0 + 1;
+                q.cbr = C(t);
+                q.cbj = C(-t);
+            }
+        } else {
+            q.sa = 0;
+            q.sb = -1;
+            q.car = C(1);
+            q.caj = C(-(ym + xi) / xi);
+            q.cbr = q.cbj = C(0);
+        }
+    }
+    return r;
+}
+// The rule of the ghost row at distance g (clamped to the table; rows past the third
+// ghost row are never used), selected without indexing the table dynamically.
+template <typename C> __device__ __forceinline__ GhostRule<C> ghost_rule(const GhostRules<C> &r, int g)
+{
+    return g <= 1 ? r.g[0] : g == 2 ? r.g[1] : r.g[2];
+}
+
 // x + f for the force terms: a run without body force drops the additions (its kernels are
 // instantiated with FORCE = false; adding a zero changes no value).
 template <bool FORCE, typename C> __device__ __forceinline__ C plus_force(C x, C f) { return FORCE ? x + f : x; }

@@ -22,12 +22,14 @@ constexpr int LWACM_STENCIL = 1;
 struct FdArgs {
     int nx, ny, stencil, walls, dtype;
     double s_xx, s_e, fx, fy;
+    double xi;  // walls: their distance beyond the first and last rows (0 < xi <= 1)
 };
 
 struct MrtArgs {
     int nx, ny, walls, dtype;
     double s_e, s_xx, s_q, s_eps, fx, fy;
     int kernel, tile_rows;  // FDLBM_KERNEL_REFERENCE: one thread per node; else the vector sweep
+    double xi;              // walls: distance beyond the first and last rows (interpolated bounce-back)
 };
 
 // FD-LBM, reference path: pass 1 writes the nine f* planes (compute dtype) for every

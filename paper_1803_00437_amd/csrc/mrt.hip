@@ -128,10 +128,17 @@ template <typename C> __device__ __forceinline__ void collide(C (&f)[9], const M
     add_increment<C>(d, f);
 }
 
-// Reference MRT step: one thread per node.
+// Reference MRT step: one thread per node.  With walls, a population whose destination
+// lies beyond a wall returns to its node with the opposite velocity.  The wall cuts that
+// link at the fraction xi of its length (walls at y = -xi and ny - 1 + xi), and the
+// returning population is the linear interpolation of Bouzidi, Firdaouss and Lallemand:
+//   xi <  1/2:  f_kbar(x) = 2 xi f*_k(x) + (1 - 2 xi) f*_k(x - e_k)
+//   xi >= 1/2:  f_kbar(x) = f*_k(x) / (2 xi) + (2 xi - 1) / (2 xi) f*_kbar(x)
+// which is halfway bounce-back at xi = 1/2 (the only case of the vector sweep kernel).
+// For xi < 1/2 the thread collides the node behind it, x - e_k, once more.
 template <typename T, bool WALLS>
 __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
-                                                  MrtCoef<typename Storage<T>::C> k)
+                                                  MrtCoef<typename Storage<T>::C> k, typename Storage<T>::C xi)
 {
     using C = typename Storage<T>::C;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -151,6 +158,26 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
         if (jm < 0) jm = ny - 1;
     }
     const size_t row = (size_t)j * nx, rowp = (size_t)jp * nx, rowm = (size_t)jm * nx;
+    // post-collision population q at node (ii, jj), collided again (interpolated bounce-back)
+    auto post_at = [&](int ii, int jj, int q) -> C {
+        ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+        const size_t pp = (size_t)jj * (size_t)nx + (size_t)ii;
+        C g[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) g[r] = Storage<T>::load(in[r * n + pp]);
+        collide<C>(g, k);
+        C v = g[0];
+#pragma unroll
+        for (int r = 1; r < 9; ++r)
+            if (r == q) v = g[r];
+        return v;
+    };
+    // population kq leaving toward the wall along (ex, ey), returning as kb
+    auto back = [&](int kq, int kb, int ex, int ey) -> C {
+        if (xi == C(0.5)) return f[kq];
+        if (xi > C(0.5)) return f[kq] / (C(2) * xi) + (C(2) * xi - C(1)) / (C(2) * xi) * f[kb];
+        return C(2) * xi * f[kq] + (C(1) - C(2) * xi) * post_at(i - ex, j - ey, kq);
+    };
     out[0 * n + p] = Storage<T>::store(f[0]);
     out[1 * n + row + ip] = Storage<T>::store(f[1]);
     out[3 * n + row + im] = Storage<T>::store(f[3]);
@@ -159,18 +186,18 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
         out[5 * n + rowp + ip] = Storage<T>::store(f[5]);
         out[6 * n + rowp + im] = Storage<T>::store(f[6]);
     } else {  // bounce-back at the upper wall
-        out[4 * n + p] = Storage<T>::store(f[2]);
-        out[7 * n + p] = Storage<T>::store(f[5]);
-        out[8 * n + p] = Storage<T>::store(f[6]);
+        out[4 * n + p] = Storage<T>::store(back(2, 4, 0, 1));
+        out[7 * n + p] = Storage<T>::store(back(5, 7, 1, 1));
+        out[8 * n + p] = Storage<T>::store(back(6, 8, -1, 1));
     }
     if (!WALLS || jm >= 0) {
         out[4 * n + rowm + i] = Storage<T>::store(f[4]);
         out[7 * n + rowm + im] = Storage<T>::store(f[7]);
         out[8 * n + rowm + ip] = Storage<T>::store(f[8]);
     } else {  // bounce-back at the lower wall
-        out[2 * n + p] = Storage<T>::store(f[4]);
-        out[5 * n + p] = Storage<T>::store(f[7]);
-        out[6 * n + p] = Storage<T>::store(f[8]);
+        out[2 * n + p] = Storage<T>::store(back(4, 2, 0, -1));
+        out[5 * n + p] = Storage<T>::store(back(7, 5, -1, -1));
+        out[6 * n + p] = Storage<T>::store(back(8, 6, 1, -1));
     }
 }
 
@@ -355,7 +382,7 @@ template <typename T> hipError_t run(const MrtArgs &a, const void *src, void *ds
 {
     using C = typename Storage<T>::C;
     MrtCoef<C> k{C(a.s_e), C(a.s_xx), C(a.s_q), C(a.s_eps), C(0.5 * a.fx), C(0.5 * a.fy), C(a.fx), C(a.fy)};
-    if (a.kernel != FDLBM_KERNEL_REFERENCE) {
+    if (a.kernel != FDLBM_KERNEL_REFERENCE && !(a.walls && a.xi != 0.5)) {
         constexpr int CPL = sizeof(T) == 8 ? 2 : 4;
         if (a.nx % CPL == 0) return run_sweep<T, CPL>(a, k, src, dst, s);
         if (a.nx % 2 == 0) return run_sweep<T, 2>(a, k, src, dst, s);
@@ -364,10 +391,10 @@ template <typename T> hipError_t run(const MrtArgs &a, const void *src, void *ds
     dim3 blk(64, 4), grd((a.nx + 63) / 64, (a.ny + 3) / 4);
     if (a.walls)
         hipLaunchKernelGGL((mrt_kernel<T, true>), grd, blk, 0, s, static_cast<const T *>(src), static_cast<T *>(dst),
-                           a.nx, a.ny, k);
+                           a.nx, a.ny, k, C(a.xi));
     else
         hipLaunchKernelGGL((mrt_kernel<T, false>), grd, blk, 0, s, static_cast<const T *>(src), static_cast<T *>(dst),
-                           a.nx, a.ny, k);
+                           a.nx, a.ny, k, C(0.5));
     return hipGetLastError();
 }
 

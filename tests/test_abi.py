@@ -29,8 +29,9 @@ def test_library_loads_and_exports_every_declared_function():
 
 
 def test_params_struct_layout_matches_header():
-    # 6 int32, 4 doubles, int32 (+pad), 2 doubles, 4 int32
-    assert ctypes.sizeof(F.Params) == 6 * 4 + 4 * 8 + 8 + 2 * 8 + 4 * 4
+    # 6 int32, 4 doubles, int32 (+pad), 2 doubles, 4 int32, 1 double
+    assert ctypes.sizeof(F.Params) == 6 * 4 + 4 * 8 + 8 + 2 * 8 + 4 * 4 + 8
+    assert F.Params.wall_xi.offset == 96
     assert ctypes.sizeof(F.Diag) == 8 * 8
 
 
@@ -59,6 +60,21 @@ def test_invalid_parameters_are_rejected(bad):
     with pytest.raises(F.FdlbmError) as e:
         F.fdlbm_workspace_bytes(good(**bad))
     assert e.value.code == F.FDLBM_EINVAL
+
+
+def test_wall_distance_is_checked_with_walls_only():
+    """wall_xi: 0 selects 1/2, (0, 1] is accepted, other values are rejected with walls and
+    ignored without them; MRT's vector sweep kernel has halfway bounce-back only."""
+    for xi in (0.0, 0.1, 0.5, 1.0):
+        F.fdlbm_workspace_bytes(good(bc="walls", wall_xi=xi))
+        F.fdlbm_workspace_bytes(good(bc="walls", wall_xi=xi, scheme="mrt", quartic=True))
+    F.fdlbm_workspace_bytes(good(wall_xi=-3.0))
+    for bad in (dict(wall_xi=-0.1), dict(wall_xi=1.5), dict(wall_xi=float("nan")),
+                dict(wall_xi=0.3, scheme="mrt", quartic=True, kernel="sweep")):
+        with pytest.raises(F.FdlbmError) as e:
+            F.fdlbm_workspace_bytes(good(bc="walls", **bad))
+        assert e.value.code == F.FDLBM_EINVAL
+    F.fdlbm_workspace_bytes(good(bc="walls", wall_xi=0.5, scheme="mrt", quartic=True, kernel="sweep"))
 
 
 def test_lwacm_is_periodic_without_force():
