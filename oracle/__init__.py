@@ -16,9 +16,9 @@ Contents
     analysis of section 1-b, dispersion equation of section 2) and the transport
     coefficients extracted from its eigenvalues.
 
-Parity unpinned: the density-gradient terms of the three theta terms and the coefficient
-of the cubic term of theta_E are checked only by the second rendering (``matrix_form``),
-not by any value the paper prints; everything else is pinned by tests/test_oracle_pins.py.
+Parity unpinned: the velocity-cubic term of theta_E, taken as printed (it differs from the
+exact expansion of the defect it approximates), is checked only by the second rendering
+(``matrix_form``); everything else is pinned by tests/test_oracle_pins.py.
 
 Array convention: float64 arrays of shape (ny, nx), x fastest; the state is the deviation
 from rest (drho = rho - 1, jx, jy); populations are (9, ny, nx) deviations f_k - w_k.
@@ -51,6 +51,8 @@ def _load():
     lib.oracle_fd_step.restype = i32
     lib.oracle_mrt_step.argtypes = [i32, i32, i32, dbl, dbl, dbl, dbl, dbl, dbl, dbl, _dp, i64]
     lib.oracle_mrt_step.restype = i32
+    lib.oracle_fd_theta.argtypes = [i32, i32, i32, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.oracle_fd_theta.restype = i32
     lib.oracle_lwacm_step.argtypes = [i32, i32, dbl, _dp, _dp, _dp, i64]
     lib.oracle_lwacm_step.restype = i32
     lib.oracle_mrt_init.argtypes = [i32, i32, _dp, _dp, _dp, _dp]
@@ -133,6 +135,19 @@ def fd_run(drho, jx, jy, nsteps, *, s_xx, s_e=1.0, stencil=3, walls=False, xi=0.
     _check(_load().oracle_fd_step(nx, ny, int(stencil), int(bool(walls)), float(xi), float(s_e), float(s_xx),
                                   float(fx), float(fy), rp, xp, yp, int(nsteps)), "fd_step")
     return r, x, y
+
+
+def fd_theta(drho, jx, jy, stencil=3):
+    """The defects theta_E, theta_XX, theta_XY of section 2 at every node (periodic, the
+    momentum J in place of v), as the FD-LBM step evaluates them."""
+    r, rp = _c(drho)
+    x, xp = _c(jx)
+    y, yp = _c(jy)
+    ny, nx = r.shape
+    out = [np.empty((ny, nx)) for _ in range(3)]
+    _check(_load().oracle_fd_theta(nx, ny, int(stencil), rp, xp, yp, *(o.ctypes.data_as(_dp) for o in out)),
+           "fd_theta")
+    return tuple(out)
 
 
 def lwacm_run(drho, jx, jy, nsteps, *, nu):

@@ -46,11 +46,14 @@
  * amplification matrix, which matches the one printed in section 1-b to third order in k,
  * and the transport coefficients printed there (c_s = sqrt(2 nu), Gamma_s = nu/2 + 1/12,
  * nu(v) = nu - v^2/2, instability above c_s).
- * PARITY UNPINNED: the density-gradient terms of theta_E, theta_XX, theta_XY and the
- * coefficient of the cubic term of theta_E.  No value printed in the paper exercises them
- * (they act on sound waves in mean flow, for which the paper states no number); they are
- * guarded only by the independent whole-array rendering in matrix_form.py, which catches
- * slips of transcription but not a shared misreading.
+ * The density-gradient terms of theta_E, theta_XX, theta_XY are pinned against the defect of
+ * conservation itself: one textbook-BGK step leaves non-equilibrium moments equal to minus
+ * the exact defect, whose first-order expansion for a density wave on a uniform flow is the
+ * printed terms plus |J|^2 terms that the paper omits (rho close to 1).
+ * PARITY UNPINNED: the velocity-cubic term of theta_E, 6 |v|^2 div v, taken as printed (R6).
+ * The exact expansion of the defect has -3 |J|^2 div J - 3 J.grad |J|^2 there instead, so no
+ * check of this oracle against the definition can confirm the printed term; it is guarded
+ * only by the independent whole-array rendering in matrix_form.py.
  */
 #include <math.h>
 #include <stdint.h>
@@ -240,6 +243,67 @@ int oracle_fd_derivative(int nx, int ny, int stencil, int axis, const double *in
     return 0;
 }
 
+/*
+ * Section 2: the defects of conservation at node (i, j), with v read as the stored momentum
+ * J (here J_a, see R3, R8) and the derivatives estimated by finite differences (R4):
+ *   theta_E  = (2 + 6|v|^2) div v - 2 v . grad rho
+ *   theta_XX = 2/3 (d_x v_x - d_y v_y) - 2/3 (v_x d_x rho - v_y d_y rho)
+ *              - 2 [v_x (d_x v_x^2 + d_y v_x v_y) - v_y (d_x v_x v_y + d_y v_y^2)]
+ *   theta_XY = 1/3 (d_x v_y + d_y v_x) - 1/3 (v_x d_y rho + v_y d_x rho)
+ *              - v_x (d_x v_x v_y + d_y v_y^2) - v_y (d_x v_x^2 + d_y v_x v_y)
+ * (R2: + in the linear part of theta_XY; R6: the cubic term of theta_E as printed.)
+ */
+static void thetas(const xfield *r, const xfield *vx, const xfield *vy, const xfield *pxx, const xfield *pxy,
+                   const xfield *pyy, int stencil, int i, int j, double *te, double *txx, double *txy)
+{
+    const double ux = at(vx, i, j), uy = at(vy, i, j);
+    const double rx = ddx(r, stencil, i, j), ry = ddy(r, stencil, i, j);
+    const double uxx = ddx(vx, stencil, i, j), uyy = ddy(vy, stencil, i, j);
+    const double uyx = ddx(vy, stencil, i, j), uxy = ddy(vx, stencil, i, j);
+    const double dx_xx = ddx(pxx, stencil, i, j), dy_xy = ddy(pxy, stencil, i, j);
+    const double dx_xy = ddx(pxy, stencil, i, j), dy_yy = ddy(pyy, stencil, i, j);
+    *te = (2.0 + 6.0 * (ux * ux + uy * uy)) * (uxx + uyy) - 2.0 * (ux * rx + uy * ry);
+    *txx = (2.0 / 3.0) * (uxx - uyy) - (2.0 / 3.0) * (ux * rx - uy * ry) -
+           2.0 * (ux * (dx_xx + dy_xy) - uy * (dx_xy + dy_yy));
+    *txy = (1.0 / 3.0) * (uyx + uxy) - (1.0 / 3.0) * (ux * ry + uy * rx) - ux * (dx_xy + dy_yy) -
+           uy * (dx_xx + dy_xy);
+}
+
+/* The three defects of every node of a periodic state (no force), for the pins. */
+int oracle_fd_theta(int nx, int ny, int stencil, const double *drho, const double *jx, const double *jy,
+                    double *te, double *txx, double *txy)
+{
+    if (nx < 1 || ny < 1 || (stencil != 3 && stencil != 5 && stencil != 9)) return -1;
+    xfield r, vx, vy, pxx, pxy, pyy;
+    int ok = xf_alloc(&r, nx, ny) && xf_alloc(&vx, nx, ny) && xf_alloc(&vy, nx, ny) &&
+             xf_alloc(&pxx, nx, ny) && xf_alloc(&pxy, nx, ny) && xf_alloc(&pyy, nx, ny);
+    if (!ok) return -2;
+    for (int j = 0; j < ny; ++j) {
+        memcpy(row(&r, j), drho + (size_t)j * nx, (size_t)nx * sizeof(double));
+        memcpy(row(&vx, j), jx + (size_t)j * nx, (size_t)nx * sizeof(double));
+        memcpy(row(&vy, j), jy + (size_t)j * nx, (size_t)nx * sizeof(double));
+    }
+    fill_ghosts(&r, 0, 0.0, 0.5);
+    fill_ghosts(&vx, 0, 0.0, 0.5);
+    fill_ghosts(&vy, 0, 0.0, 0.5);
+    for (int j = -G; j < ny + G; ++j) {
+        const double *ax = row(&vx, j), *ay = row(&vy, j);
+        double *bxx = row(&pxx, j), *bxy = row(&pxy, j), *byy = row(&pyy, j);
+        for (int i = 0; i < nx; ++i) {
+            bxx[i] = ax[i] * ax[i];
+            bxy[i] = ax[i] * ay[i];
+            byy[i] = ay[i] * ay[i];
+        }
+    }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t p = (size_t)j * nx + (size_t)i;
+            thetas(&r, &vx, &vy, &pxx, &pxy, &pyy, stencil, i, j, te + p, txx + p, txy + p);
+        }
+    free(r.a); free(vx.a); free(vy.a); free(pxx.a); free(pxy.a); free(pyy.a);
+    return 0;
+}
+
 static int check_grid(int nx, int ny, int walls, double xi)
 {
     if (nx < 1 || ny < 1) return -1;
@@ -313,18 +377,8 @@ int oracle_fd_step(int nx, int ny, int stencil, int walls, double xi, double s_e
             for (int i = 0; i < nx; ++i) {
                 const double dr = at(&r, i, j), rho = 1.0 + dr;
                 const double ux = at(&vx, i, j), uy = at(&vy, i, j);
-                const double rx = ddx(&r, stencil, i, j), ry = ddy(&r, stencil, i, j);
-                const double uxx = ddx(&vx, stencil, i, j), uyy = ddy(&vy, stencil, i, j);
-                const double uyx = ddx(&vy, stencil, i, j), uxy = ddy(&vx, stencil, i, j);
-                const double dx_xx = ddx(&pxx, stencil, i, j), dy_xy = ddy(&pxy, stencil, i, j);
-                const double dx_xy = ddx(&pxy, stencil, i, j), dy_yy = ddy(&pyy, stencil, i, j);
-
-                const double theta_e = (2.0 + 6.0 * (ux * ux + uy * uy)) * (uxx + uyy) -
-                                       2.0 * (ux * rx + uy * ry);
-                const double theta_xx = (2.0 / 3.0) * (uxx - uyy) - (2.0 / 3.0) * (ux * rx - uy * ry) -
-                                        2.0 * (ux * (dx_xx + dy_xy) - uy * (dx_xy + dy_yy));
-                const double theta_xy = (1.0 / 3.0) * (uyx + uxy) - (1.0 / 3.0) * (ux * ry + uy * rx) -
-                                        ux * (dx_xy + dy_yy) - uy * (dx_xx + dy_xy);
+                double theta_e, theta_xx, theta_xy;
+                thetas(&r, &vx, &vy, &pxx, &pxy, &pyy, stencil, i, j, &theta_e, &theta_xx, &theta_xy);
 
                 const double j2 = ux * ux + uy * uy;
                 double dm[9];

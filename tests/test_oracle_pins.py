@@ -629,3 +629,47 @@ def test_channel_wall_location_tracks_xi(scheme):
         assert abs(lo - hi) < 1e-9
         assert abs(lo - xi) < 0.06, (xi, lo)
     assert all(b[0] > a[0] + 0.15 for a, b in zip(got, got[1:]))
+
+
+# ------------------------------------- theta terms against the defect of a BGK step ----
+
+def _theta_error(nx, ny, mx, my, V, a=1e-6):
+    """theta is the defect of conservation (section 2): one textbook-BGK step (all rates 1)
+    from an equilibrium state leaves non-equilibrium moments m - m^eq(rho', J') = -theta_exact
+    to first order in the gradients, theta_exact = d_t m^eq + div(flux) with d_t from the
+    Euler equations.  For a density wave of amplitude a on a uniform momentum J = V (every
+    derivative of J vanishes) the expansion gives, to first order in a,
+        theta_E  = -2 J.grad rho                         + 6 |J|^2 (J.grad rho)
+        theta_XX = -2/3 (J_x d_x rho - J_y d_y rho)      + 2 (J_x^2 - J_y^2)(J.grad rho)
+        theta_XY = -1/3 (J_x d_y rho + J_y d_x rho)      + 2 J_x J_y (J.grad rho)
+    where the first column is what section 2 prints (and the oracle evaluates) and the second
+    the |J|^2 terms it omits (rho close to 1).  Returns the defect minus (the oracle's theta
+    plus those terms) at the wave's mode, in units of |V| a k, for E, XX, XY."""
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    phase = 2 * np.pi * (mx * xx / nx + my * yy / ny)
+    r, x, y = a * np.cos(phase), np.full((ny, nx), V[0]), np.full((ny, nx), V[1])
+    f1 = O.mrt_run(O.mrt_init(r, x, y), 1, s_xx=1.0, s_e=1.0, s_q=1.0, s_eps=1.0)
+    d = np.tensordot(MF.M, f1 - O.mrt_init(*O.mrt_moments(f1)), axes=(1, 0))
+    t = O.fd_theta(r, x, y, 3)
+    kx, ky = 2 * math.pi * mx / nx, 2 * math.pi * my / ny
+    # amplitude of grad rho under the 3-point differences: i a (sin kx, sin ky)
+    jg = V[0] * 1j * a * math.sin(kx) + V[1] * 1j * a * math.sin(ky)
+    v2 = V[0] ** 2 + V[1] ** 2
+    omitted = (6 * v2 * jg, 2 * (V[0] ** 2 - V[1] ** 2) * jg, 2 * V[0] * V[1] * jg)
+    w = np.exp(-1j * phase) * 2 / (nx * ny)
+    scale = math.hypot(*V) * a * math.hypot(kx, ky)
+    return np.array([(-np.sum(d[3 + q] * w) - np.sum(t[q] * w) - omitted[q]) / scale for q in range(3)])
+
+
+@pytest.mark.parametrize("V", [(0.03, 0.02), (0.05, -0.03), (0.1, 0.07), (0.0, 0.04)])
+@pytest.mark.parametrize("wave", [(256, 4, 1, 0), (4, 256, 0, 1), (128, 128, 1, 1), (128, 128, 1, -1)])
+def test_theta_density_gradient_terms_are_the_bgk_defect(V, wave):
+    """Pins the density-gradient terms -2 v.grad rho, -2/3 (v_x d_x rho - v_y d_y rho) and
+    -1/3 (v_x d_y rho + v_y d_x rho) of theta_E, theta_XX and theta_XY against the defect of
+    a textbook-BGK step.  The error at wave vectors k and k/2 is extrapolated to k = 0 (the
+    step's second-order terms are O(k)); what is left is O(k^2), below 1e-3 of |V| a k,
+    while a wrong coefficient or sign leaves an error of order one."""
+    nx, ny, mx, my = wave
+    e1 = _theta_error(nx, ny, mx, my, V)
+    e2 = _theta_error(2 * nx if nx > 4 else nx, 2 * ny if ny > 4 else ny, mx, my, V)
+    assert np.all(np.abs(2 * e2 - e1) < 1e-3), 2 * e2 - e1
