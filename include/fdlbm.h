@@ -157,7 +157,7 @@ int64_t fdlbm_step_count(const fdlbm_ctx *c);
  * the speed does).  Times `reps` launches (1..10000) of this context's step kernel for
  * each candidate shape on its own grid and keeps the fastest in the context: FD-LBM sweep
  * kernel: grid columns per lane (1, 2, 4 where supported) x rows per wavefront (4, 6, 8,
- * 12, 16, 24); MRT sweep kernel: rows per tile (2, 4, 8, 16).  The reference kernels have
+ * 12, 16, 24); MRT sweep kernel: rows per tile (1, 2, 4, 8, 16).  The reference kernels have
  * no shape and are only timed.  The state does not advance: each timed launch reads the
  * current state and writes the spare buffer, which the next step overwrites.  Synchronises
  * the stream.  The chosen shape goes to *out_lane_cols and *out_tile_rows (0 where the

@@ -366,7 +366,7 @@ int fdlbm_autotune(fdlbm_ctx *c, int32_t reps, int32_t *out_lane_cols, int32_t *
             if (fd_sweep_supported(fa, cols))
                 for (int rows : {4, 6, 8, 12, 16, 24}) cand.push_back({cols, rows});
     } else {
-        for (int rows : {2, 4, 8, 16}) cand.push_back({0, rows});
+        for (int rows : {1, 2, 4, 8, 16}) cand.push_back({0, rows});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);

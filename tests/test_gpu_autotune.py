@@ -45,7 +45,7 @@ def test_autotune_keeps_state_and_results(F, kw):
             elif kw["scheme"] == "fd":
                 assert cols in (1, 2, 4) and rows in (4, 6, 8, 12, 16, 24)
             else:
-                assert rows in (2, 4, 8, 16)
+                assert rows in (1, 2, 4, 8, 16)
             after = sim.get_state()
             assert sim.steps == 0
             for u, v in zip(before, after):
