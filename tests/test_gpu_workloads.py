@@ -185,3 +185,32 @@ def test_decaying_flow_8192_2000_steps(F):
     print(f"  8192^2 2000 steps: FP32 rel L2 {e32:.2e}, FP16 storage rel L2 {e16:.2e} (vs FP64 GPU)")
     assert e32 < 1e-5
     assert e16 < 5e-2
+
+
+@pytest.mark.parametrize("scheme,dtype,tol", [("fd3", "f64", 1e-12), ("fd5", "f32", 1e-5), ("mrt", "f32", 1e-5),
+                                              ("mrt", "f64", 1e-12)])
+def test_full_size_band_other_schemes(F, scheme, dtype, tol):
+    """8192 x 8192 decaying flow in the default launch configuration of each scheme: after 10
+    steps, 128 rows against the oracle run on those rows plus their domain of dependence
+    (3 rows per step for 5-point differences, 2 for 3-point, 1 for MRT)."""
+    n, steps, rows, y0 = 8192, 10, 128, 5000
+    init = W.decaying_flow(n=n, seed=4, kmax=32, amp=0.02)
+    s_xx = O.rate_from_viscosity(0.02)
+    if scheme == "mrt":
+        m = steps + 1
+        band = tuple(np.ascontiguousarray(a[y0 - m:y0 + rows + m]) for a in init)
+        sim = F.FdLbm(n, n, scheme="mrt", dtype=dtype, s_xx=s_xx, quartic=True)
+        sim.set_state(*init)
+        sim.step(steps)
+        got = sim.get_state()  # moments of the populations, reduced on the device
+        sim.close()
+        want = O.mrt_moments(O.mrt_run(O.mrt_init(*band), steps, s_xx=s_xx, s_q=O.quartic_s_q(s_xx)))
+    else:
+        st = int(scheme[2])
+        m = steps * (3 if st == 5 else 2)
+        band = tuple(np.ascontiguousarray(a[y0 - m:y0 + rows + m]) for a in init)
+        got = run_gpu(F, init, steps, scheme="fd", stencil=st, dtype=dtype, s_xx=s_xx, s_e=1.0)
+        want = O.fd_run(*band, steps, s_xx=s_xx, s_e=1.0, stencil=st)
+    err = rel_l2([g[y0:y0 + rows] for g in got], [w[m:m + rows] for w in want])
+    print(f"  8192^2 {scheme} {dtype} band rel L2 {err:.2e}")
+    assert err <= tol
