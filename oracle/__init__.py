@@ -15,6 +15,9 @@ Contents
   * ``symbol``: the linear amplification matrix H(k) of both schemes (von Neumann
     analysis of section 1-b, dispersion equation of section 2) and the transport
     coefficients extracted from its eigenvalues.
+  * ``disk``: the curved no-slip wall of section 3-b around a disk (ghost nodes filled
+    from the fluid before each periodic step) and the decay-rate measurement of the Stokes
+    modes of Tables 2 and 3.
 
 Parity unpinned: the velocity-cubic term of theta_E, taken as printed (it differs from the
 exact expansion of the defect it approximates), is checked only by the second rendering

@@ -1,0 +1,199 @@
+"""Pins of the oracle's curved no-slip wall (a disk, section 3-b) and of the Stokes-mode
+inputs, against what the mathematics and the paper fix:
+
+  * the Bessel column of Tables 2 and 3 (the no-slip eigenvalues of the disk);
+  * the continuum mode: divergence free, zero on the wall, its pressure balancing the decay;
+  * the ghost rules: geometry, and a field that vanishes linearly on the wall continued
+    through it to within the bilinear interpolation error;
+  * the decay rates of all 17 modes of Tables 2 and 3 with both stencils and both
+    viscosities: five-point rates against the closed form nu a^2 / R^2, every rate against
+    the k-dependent viscosity of the bulk scheme (amplification matrix), and every rate
+    against the rates the paper measured.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import disk as D
+from oracle import symbol as S
+
+R, N = 29.9, 72
+C = (N - 1) / 2  # the centre sits between nodes
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "stokes_disk_tables.json")
+NUS = {"0.05": 0.05, "1/sqrt108": 1.0 / math.sqrt(108.0)}
+
+
+def table_modes():
+    """(family, l, m, mode index l) of the rows of Tables 2 and 3: the l-th singlet is the
+    l-th zero of J_1 (m = 0), the l-th doublet the first zero of J_{l+1} (m = l)."""
+    rows = json.load(open(GOLDEN))["rows"]
+    return [(r, 0, r["l"]) if r["family"] == "singlet" else (r, r["l"], 1) for r in rows]
+
+
+@pytest.fixture(scope="module")
+def rules():
+    return D.disk_ghost_rules(N, N, C, C, R)
+
+
+def test_bessel_column_is_the_no_slip_eigenvalue():
+    for row, m, l in table_modes():
+        a2 = (W.disk_mode_wavenumber(m, l, R) * R) ** 2
+        assert abs(a2 - row["bessel_a2"]) < 1e-4, (row, a2)
+
+
+@pytest.mark.parametrize("m,l", [(0, 1), (0, 3), (1, 1), (3, 1), (6, 1)])
+def test_continuum_mode_is_a_decaying_stokes_flow(m, l):
+    """Central differences on a fine grid (h = 1/4 of the lattice, radius 4R): div J ~ 0,
+    J ~ 0 at the wall, and grad p = Gamma J + nu Lap J with p = drho/3, Gamma = nu k^2
+    (the linear momentum equation of a mode decaying as exp(-Gamma t))."""
+    nu, h = 0.05, 0.25
+    Rf = R / h
+    n = 2 * (int(Rf) + 4)
+    c = (n - 1) / 2
+    k = W.disk_mode_wavenumber(m, l, Rf)
+    r, jx, jy = W.disk_stokes_mode(n, n, c, c, Rf, m, k, amp=1.0, nu=nu)
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    rr = np.hypot(x - c, y - c)
+    inner = rr < Rf - 2
+
+    def dx(a):
+        return (np.roll(a, -1, 1) - np.roll(a, 1, 1)) / 2
+
+    def dy(a):
+        return (np.roll(a, -1, 0) - np.roll(a, 1, 0)) / 2
+
+    def lap(a):
+        return np.roll(a, 1, 0) + np.roll(a, -1, 0) + np.roll(a, 1, 1) + np.roll(a, -1, 1) - 4 * a
+
+    div = dx(jx) + dy(jy)
+    assert np.max(np.abs(div[inner])) < 2e-3 * k
+    gam = nu * k * k
+    for g, j in ((dx(r) / 3, jx), (dy(r) / 3, jy)):
+        res = g - (gam * j + nu * lap(j))
+        assert np.max(np.abs(res[inner])) < 0.02 * gam, (m, l)
+    wall = (rr < Rf) & (rr > Rf - 1)
+    assert np.max(np.hypot(jx, jy)[wall]) < 1.5 * k  # |J| <= |dJ/dr| * (R - r), |dJ/dr| <~ k
+
+
+def test_ghost_rule_geometry(rules):
+    fluid, rest = rules["fluid"], rules["rest"]
+    j, i = rules["j"], rules["i"]
+    assert not fluid[j, i].any() and not rest[j, i].any()
+    assert fluid.sum() + rest.sum() + j.size == N * N
+    y, x = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    r = np.hypot(x - C, y - C)
+    assert np.all(fluid == (r < R))
+    fj, fi = np.nonzero(fluid)
+    for a, b in zip(j, i):  # each ghost is within Chebyshev distance 3 of the fluid
+        assert np.min(np.maximum(np.abs(fj - a), np.abs(fi - b))) <= 3
+    for a, b in zip(*np.nonzero(rest)):
+        assert np.min(np.maximum(np.abs(fj - a), np.abs(fi - b))) > 3
+    # the interpolation point lies on the ghost's ray, at the mirror depth or at 3/2
+    px, py = rules["i0"] + rules["wx"], rules["j0"] + rules["wy"]
+    rg = r[j, i]
+    rp = np.hypot(px - C, py - C)
+    cross = (px - C) * (y[j, i] - C) - (py - C) * (x[j, i] - C)
+    assert np.max(np.abs(cross)) < 1e-9 * R
+    delta = rg - R
+    mirror = rules["sj"] == -1.0
+    assert np.allclose(rp[mirror], R - delta[mirror])
+    assert np.allclose(rp[~mirror], R - 1.5)
+    assert np.allclose(rules["sj"][~mirror], -delta[~mirror] / 1.5)
+    assert np.all((rules["wx"] >= 0) & (rules["wx"] < 1) & (rules["wy"] >= 0) & (rules["wy"] < 1))
+    for dj in (0, 1):
+        for di in (0, 1):
+            assert fluid[rules["j0"] + dj, rules["i0"] + di].all()
+    assert mirror.sum() > 0 and (~mirror).sum() > 0
+
+
+def test_ghost_fill_continues_a_field_that_vanishes_on_the_wall(rules):
+    """J = (R - r) c (zero on the wall, linear across it) and a uniform density: the ghost
+    nodes get (R - r) c back to within the bilinear interpolation error of r (its Hessian
+    is at most 1/r, so the error is below |c| / (4 r) at the interpolation point), the
+    density exactly, and the rest nodes zero."""
+    y, x = np.meshgrid(np.arange(N, dtype=float), np.arange(N, dtype=float), indexing="ij")
+    r = np.hypot(x - C, y - C)
+    cvec = (0.3, -0.7)
+    drho = np.full((N, N), 0.125)
+    jx, jy = (R - r) * cvec[0], (R - r) * cvec[1]
+    fr, fx, fy = D.disk_fill(drho, jx, jy, rules)
+    j, i = rules["j"], rules["i"]
+    assert np.all(fr[j, i] == 0.125)
+    bound = math.hypot(*cvec) / (4 * (R - 4.5))
+    for got, comp in ((fx, cvec[0]), (fy, cvec[1])):
+        assert np.max(np.abs(got[j, i] - (R - r[j, i]) * comp)) <= bound
+    rest = rules["rest"]
+    assert np.all(fr[rest] == 0) and np.all(fx[rest] == 0) and np.all(fy[rest] == 0)
+    f = rules["fluid"]
+    assert np.array_equal(fx[f], jx[f]) and np.array_equal(fr[f], drho[f])
+
+
+def test_disk_run_keeps_rest_and_is_stable(rules):
+    """The rest state stays at rest; a random state inside the disk stays bounded."""
+    z = np.zeros((N, N))
+    out = D.disk_run(z, z, z, 20, rules=rules, s_xx=O.rate_from_viscosity(0.05), stencil=5)
+    assert all(np.all(a == 0) for a in out)
+    rng = np.random.default_rng(3)
+    init = tuple(np.where(rules["fluid"], 1e-3 * rng.standard_normal((N, N)), 0.0) for _ in range(3))
+    for st in (3, 5):
+        out = D.disk_run(*init, 400, rules=rules, s_xx=O.rate_from_viscosity(0.05), stencil=st)
+        assert max(np.max(np.abs(a[rules["fluid"]])) for a in out) < 1e-3
+
+
+@pytest.fixture(scope="module")
+def measured(rules):
+    """Relative rate errors Gamma / (nu k^2) - 1 of the 17 modes, per (stencil, nu)."""
+    out = {}
+    for st in (3, 5):
+        for key, nu in NUS.items():
+            errs = []
+            for _, m, l in table_modes():
+                k = W.disk_mode_wavenumber(m, l, R)
+                init = W.disk_stokes_mode(N, N, C, C, R, m, k, nu=nu)
+                g0 = nu * k * k
+                errs.append(D.disk_decay_rate(init, rules=rules, nu=nu, gamma0=g0, stencil=st) / g0 - 1)
+            out[st, key] = np.array(errs)
+    return out
+
+
+@pytest.mark.slow
+def test_five_point_rates_match_the_bessel_rates(measured):
+    for key in NUS:
+        e = measured[5, key]
+        assert np.max(np.abs(e)) < 6e-3, (key, e)
+
+
+@pytest.mark.slow
+def test_rates_follow_the_bulk_dispersion(measured):
+    """Gamma / (nu k^2) - 1 against the shear-root viscosity nu(k) / nu - 1 of the
+    amplification matrix at |k| = a/R, averaged over the wave-vector angle: what remains is
+    the wall's share, below 0.8 % for every mode (the three-point errors reach 16 %)."""
+    for st in (3, 5):
+        for key, nu in NUS.items():
+            pred = []
+            for _, m, l in table_modes():
+                k = W.disk_mode_wavenumber(m, l, R)
+                pred.append(np.mean([S.nu_of_k(k, a, "fd", s_xx=O.rate_from_viscosity(nu), stencil=st)
+                                     for a in np.linspace(0, math.pi / 4, 9)]) / nu - 1)
+            resid = measured[st, key] - np.array(pred)
+            assert np.max(np.abs(resid)) < 8e-3, (st, key, resid)
+            if st == 3:
+                assert np.max(measured[st, key]) > 0.03  # the hyperviscosity is visible
+
+
+@pytest.mark.slow
+def test_rates_agree_with_tables_2_and_3(measured):
+    """The measured rates, (1 + error), against the paper's: within 2 % for the three-point
+    stencil and 0.3 % for the five-point one (the paper's wall expressions are not printed,
+    so only the bulk scheme is shared)."""
+    rows = [r for r, _, _ in table_modes()]
+    for st, tol in ((3, 0.02), (5, 0.003)):
+        for key in NUS:
+            paper = np.array([r[f"fd{st}_nu_{key}"] for r in rows])
+            ratio = (1 + measured[st, key]) / (1 + paper) - 1
+            assert np.max(np.abs(ratio)) < tol, (st, key, ratio)

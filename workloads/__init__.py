@@ -12,6 +12,7 @@ Workloads (the paper measures only synthetic flows, section 3):
   * plane shear waves (section 3-a), optionally carried by a uniform velocity V;
   * band-limited random Fourier fields ("Stokes modes" / decaying flow);
   * the steady Poiseuille channel profile (section 3-c);
+  * the Stokes eigenmodes of a disk with a no-slip wall (section 3-b);
   * a seeded family of independent shear-wave instances of uneven sizes.
 """
 from __future__ import annotations
@@ -29,6 +30,8 @@ __all__ = [
     "poiseuille_profile",
     "batch_instances",
     "random_state",
+    "disk_mode_wavenumber",
+    "disk_stokes_mode",
 ]
 
 
@@ -136,3 +139,45 @@ def random_state(nx, ny, seed, amp=1e-2):
     """Uniform white noise of amplitude amp in each field (small parity cases)."""
     rng = np.random.default_rng(seed)
     return tuple(amp * (2.0 * rng.random((ny, nx)) - 1.0) for _ in range(3))
+
+
+def disk_mode_wavenumber(m, l, R):
+    """k = j_{m+1,l} / R: the l-th Stokes eigenmode of azimuthal order m in a disk of radius
+    R with a no-slip wall decays as exp(-nu k^2 t) (section 3-b).  The stream function
+    psi = [J_m(k r) - J_m(k R) (r/R)^m] cos(m theta) needs psi(R) = psi'(R) = 0, which
+    reduces to J_{m+1}(k R) = 0 (Bessel recurrence); m = 0 gives the singlets (zeros of
+    J_1), m >= 1 the doublets (first zero of J_{m+1} for the l-th doublet, l = m)."""
+    from scipy.special import jn_zeros
+
+    return float(jn_zeros(m + 1, l)[-1]) / R
+
+
+def disk_stokes_mode(nx, ny, cx, cy, R, m, k, amp=1e-3, nu=None):
+    """Velocity of the Stokes mode psi = [J_m(k r) - J_m(k R) (r/R)^m] cos(m theta) of a
+    disk of radius R centred at (cx, cy), scaled to max |J| = amp over the nodes with r < R
+    and zero elsewhere: J = (d psi/dy, -d psi/dx).  With nu given, drho carries the pressure
+    that keeps the mode incompressible as it decays: the harmonic part B r^m cos(m theta)
+    (B = -J_m(kR)/R^m) is the gradient of phi = -B r^m sin(m theta), so drho = 3 nu k^2 phi
+    (c_s^2 = 1/3); the Bessel part needs none.  (cx, cy) must not be a node."""
+    from scipy.special import jv, jvp
+
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    X, Y = x - cx, y - cy
+    r = np.hypot(X, Y)
+    if np.min(r) == 0.0:
+        raise ValueError("the disk centre must not be a node")
+    th = np.arctan2(Y, X)
+    b = jv(m, k * R) / R ** m
+    F = jv(m, k * r) - b * r ** m
+    dF = k * jvp(m, k * r) - (m * b * r ** (m - 1) if m > 0 else 0.0)
+    c, s = np.cos(m * th), np.sin(m * th)
+    dpsi_dx = dF * c * np.cos(th) + m * F / r * s * np.sin(th)
+    dpsi_dy = dF * c * np.sin(th) - m * F / r * s * np.cos(th)
+    inside = r < R
+    scale = amp / np.max(np.hypot(dpsi_dx, dpsi_dy)[inside])
+    jx = np.where(inside, scale * dpsi_dy, 0.0)
+    jy = np.where(inside, -scale * dpsi_dx, 0.0)
+    drho = np.zeros((ny, nx))
+    if nu is not None and m > 0:
+        drho = np.where(inside, 3.0 * nu * k * k * scale * b * r ** m * s, 0.0)
+    return drho, jx, jy
