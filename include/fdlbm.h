@@ -8,7 +8,9 @@
  *   - Grid nx * ny, node (x=i, y=j) at linear index j*nx + i (x fastest).  x is always
  *     periodic.  y is periodic (FDLBM_BC_PERIODIC) or closed by two walls parallel to Ox
  *     at y = -1/2 and y = ny - 1/2 (FDLBM_BC_WALLS_Y; the channel of section 3-c with the
- *     wall half-way between the last fluid node and the first node outside).
+ *     wall half-way between the last fluid node and the first node outside), or the grid
+ *     holds a disk closed by a curved no-slip wall (FDLBM_BC_DISK, the Stokes-mode test of
+ *     section 3-b; see fdlbm_params.disk_r).
  *   - The state is stored as deviations from the rest state rho = 1, J = 0: three planes
  *     drho = rho - 1, jx, jy (FD-LBM) or nine population planes f_k - w_k (MRT), in the
  *     storage dtype, plane after plane, each plane nx*ny elements with no padding.
@@ -43,7 +45,7 @@ extern "C" {
  * link-wise artificial-compressibility step of section 1-b that FD-LBM starts from
  * (periodic grids, no body force; same stored state as FD-LBM). */
 enum { FDLBM_SCHEME_FD = 0, FDLBM_SCHEME_MRT = 1, FDLBM_SCHEME_LWACM = 2 };
-enum { FDLBM_BC_PERIODIC = 0, FDLBM_BC_WALLS_Y = 1 };
+enum { FDLBM_BC_PERIODIC = 0, FDLBM_BC_WALLS_Y = 1, FDLBM_BC_DISK = 2 };
 /* Storage dtype of the state.  F64: FP64 storage and arithmetic.  F32: FP32 storage and
  * arithmetic.  F16DEV: FP16 storage of the deviations (drho, jx, jy), FP32 arithmetic
  * (FD-LBM only).  Diagnostics are always reduced in FP64. */
@@ -83,6 +85,23 @@ typedef struct fdlbm_params {
                          * by where the wall cuts the link.  MRT: interpolated bounce-back of
                          * Bouzidi et al. (halfway bounce-back at 1/2; other values run the
                          * one-thread-per-node MRT kernel).  Ignored without walls.          */
+    /* FDLBM_BC_DISK (FD-LBM and LW-ACM only): a disk of radius disk_r centred at
+     * (disk_cx, disk_cy), in node units, inside the grid; section 3-b.  Fluid nodes lie at
+     * distance r < disk_r from the centre.  Ghost nodes are the other nodes within Chebyshev
+     * distance 3 of a fluid node; at r = disk_r + d on the ray of unit vector n, a ghost
+     * takes the state at its mirror point centre + (disk_r - d) n, momentum negated and
+     * density kept, by bilinear interpolation when the four nodes around that point are
+     * fluid; otherwise the momentum of the sample at depth 3/2, scaled by -d / (3/2) (zero
+     * velocity on the wall, linear across it), and that sample's density.  Every other node
+     * is set to rest.  Each step first fills the ghost and rest nodes from the fluid, then
+     * takes one periodic step of the whole grid (any kernel, dtype and stencil; force
+     * allowed for FD-LBM).  The disk must lie in [2, nx - 3] x [2, ny - 3] (every fluid
+     * node is then 3 nodes from the edges, so no periodic image enters a fluid update),
+     * disk_r must exceed 3/2 (the sample at depth 3/2 then always has four fluid nodes) and
+     * nx * ny must stay below 2^31.
+     * Diagnostics sum over every node, ghost nodes included; give fdlbm_set_mode a J0 that
+     * is zero outside the fluid to project on the fluid only.  Ignored for other bc.      */
+    double disk_cx, disk_cy, disk_r;
 } fdlbm_params;
 
 typedef struct fdlbm_diag {

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libfdlbm.so")
 
 FDLBM_OK, FDLBM_EINVAL, FDLBM_ENOMEM, FDLBM_EDEVICE, FDLBM_EUNSTABLE = 0, -1, -2, -3, -4
 SCHEME = {"fd": 0, "mrt": 1, "lwacm": 2}
-BC = {"periodic": 0, "walls": 1}
+BC = {"periodic": 0, "walls": 1, "disk": 2}
 DTYPE = {"f64": 0, "f32": 1, "f16": 2}
 KERNEL = {"auto": 0, "reference": 1, "sweep": 2}
 
@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
         ("kernel", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("lane_cols", ctypes.c_int32), ("wall_xi", ctypes.c_double),
+        ("disk_cx", ctypes.c_double), ("disk_cy", ctypes.c_double), ("disk_r", ctypes.c_double),
     ]
 
 
@@ -153,11 +154,12 @@ def _dptr(a):
 
 def make_params(nx, ny, scheme="fd", stencil=3, bc="periodic", dtype="f32", s_xx=1.0, s_e=1.0,
                 s_q=1.0, s_eps=1.0, quartic=False, force=(0.0, 0.0), kernel="auto", tile_rows=0,
-                check_every=0, lane_cols=0, wall_xi=0.5):
+                check_every=0, lane_cols=0, wall_xi=0.5, disk=(0.0, 0.0, 0.0)):
+    """disk = (cx, cy, R) with bc="disk": the curved no-slip wall of section 3-b."""
     return Params(int(nx), int(ny), SCHEME[scheme], int(stencil), BC[bc], DTYPE[dtype], float(s_xx),
                   float(s_e), float(s_q), float(s_eps), int(bool(quartic)), float(force[0]),
                   float(force[1]), KERNEL[kernel], int(tile_rows), int(check_every), int(lane_cols),
-                  float(wall_xi))
+                  float(wall_xi), float(disk[0]), float(disk[1]), float(disk[2]))
 
 
 def fdlbm_workspace_bytes(params):
@@ -269,8 +271,9 @@ class FdLbm:
     """One simulation: owns its torch device buffers and its library context.
 
     Keyword arguments follow ``fdlbm_params`` (see include/fdlbm.h); ``dtype`` is one of
-    "f64", "f32", "f16" (FP16-stored deviations, FP32 arithmetic), ``bc`` "periodic" or
-    "walls", ``scheme`` "fd", "mrt" or "lwacm", ``kernel`` "auto", "reference" or "sweep".
+    "f64", "f32", "f16" (FP16-stored deviations, FP32 arithmetic), ``bc`` "periodic",
+    "walls" or "disk" (with ``disk=(cx, cy, R)``), ``scheme`` "fd", "mrt" or "lwacm",
+    ``kernel`` "auto", "reference" or "sweep".
     """
 
     def __init__(self, nx, ny, device="cuda", stream=None, **kw):

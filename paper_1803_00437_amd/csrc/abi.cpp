@@ -34,7 +34,9 @@ bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
 double quartic(double s_xx) { return 1.0 / (0.5 + 1.0 / (6.0 * (1.0 / s_xx - 0.5))); }
 
 struct Layout {
-    size_t partials, out, mode, staging, fstar, total;
+    size_t partials, out, mode, staging, fstar;
+    size_t disk_dst, disk_src, disk_w, disk_span;  // ghost-node table (FDLBM_BC_DISK)
+    size_t total;
 };
 
 // FD-LBM and LW-ACM store (drho, Jx, Jy) and run on the FD-LBM kernels; MRT stores populations
@@ -50,6 +52,12 @@ FdArgs fd_args(const fdlbm_params &p)
                   wall_xi(p)};
 }
 
+// the disk's ghost-node table; false if the disk does not fit (checked by validate)
+bool disk_table(const fdlbm_params &p, DiskTable *t)
+{
+    return build_disk_table(p.nx, p.ny, p.disk_cx, p.disk_cy, p.disk_r, t);
+}
+
 bool uses_reference(const fdlbm_params &p)
 {
     if (!three_words(p.scheme)) return false;
@@ -62,7 +70,7 @@ int validate(const fdlbm_params *p)
     if (!p) return FDLBM_EINVAL;
     if (p->scheme != FDLBM_SCHEME_FD && p->scheme != FDLBM_SCHEME_MRT && p->scheme != FDLBM_SCHEME_LWACM)
         return FDLBM_EINVAL;
-    if (p->bc != FDLBM_BC_PERIODIC && p->bc != FDLBM_BC_WALLS_Y) return FDLBM_EINVAL;
+    if (p->bc != FDLBM_BC_PERIODIC && p->bc != FDLBM_BC_WALLS_Y && p->bc != FDLBM_BC_DISK) return FDLBM_EINVAL;
     if (p->nx < 8 || p->nx > (1 << 20)) return FDLBM_EINVAL;
     if (p->ny < (p->bc == FDLBM_BC_WALLS_Y ? 4 : 8) || p->ny > (1 << 20)) return FDLBM_EINVAL;
     if ((size_t)p->nx * (size_t)p->ny > (size_t(1) << 32)) return FDLBM_EINVAL;
@@ -75,12 +83,17 @@ int validate(const fdlbm_params *p)
         if (p->scheme == FDLBM_SCHEME_FD && p->stencil != 3 && p->stencil != 5)
             return FDLBM_EINVAL;  // the 9-point form is unstable on {1,1}
         if (p->scheme == FDLBM_SCHEME_LWACM &&
-            (p->bc != FDLBM_BC_PERIODIC || p->force_x != 0.0 || p->force_y != 0.0))
+            (p->bc == FDLBM_BC_WALLS_Y || p->force_x != 0.0 || p->force_y != 0.0))
             return FDLBM_EINVAL;  // section 1-b defines the step on a periodic grid without force
+        if (p->bc == FDLBM_BC_DISK) {
+            DiskTable t;
+            if (!disk_table(*p, &t)) return FDLBM_EINVAL;
+        }
         if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32 && p->dtype != FDLBM_F16DEV) return FDLBM_EINVAL;
         if (p->lane_cols != 0 && p->lane_cols != 1 && p->lane_cols != 2 && p->lane_cols != 4) return FDLBM_EINVAL;
         if (p->kernel == FDLBM_KERNEL_SWEEP && !fd_sweep_supported(fd_args(*p), p->lane_cols)) return FDLBM_EINVAL;
     } else {
+        if (p->bc == FDLBM_BC_DISK) return FDLBM_EINVAL;  // the curved wall acts on (drho, J)
         if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32) return FDLBM_EINVAL;
         if (!rate_ok(p->s_eps)) return FDLBM_EINVAL;
         // interpolated bounce-back (walls away from the half-way point) runs on the
@@ -108,6 +121,19 @@ Layout layout(const fdlbm_params &p)
     L.staging = off;
     L.fstar = off;
     off += staging > fstar ? staging : fstar;
+    size_t ng = 0;
+    if (p.bc == FDLBM_BC_DISK) {
+        DiskTable t;
+        if (disk_table(p, &t)) ng = t.dst.size();
+    }
+    L.disk_dst = off;
+    off += align256(sizeof(int32_t) * ng);
+    L.disk_src = off;
+    off += align256(sizeof(int32_t) * ng);
+    L.disk_w = off;
+    off += align256(sizeof(double) * 3 * ng);
+    L.disk_span = off;
+    off += p.bc == FDLBM_BC_DISK ? align256(sizeof(int32_t) * 2 * size_t(p.ny)) : 0;
     L.total = off;
     return L;
 }
@@ -125,6 +151,7 @@ struct fdlbm_ctx {
     hipStream_t stream;
     int64_t steps;
     bool mode_set;
+    DiskFill disk;  // FDLBM_BC_DISK: the ghost-node table in the scratch buffer
 
     size_t n() const { return (size_t)p.nx * (size_t)p.ny; }
     double *sd(size_t off) const { return reinterpret_cast<double *>(scratch + off); }
@@ -163,11 +190,34 @@ int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scra
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->steps = 0;
     c->mode_set = false;
+    c->disk = DiskFill{p->nx, p->ny, 0, nullptr, nullptr, nullptr, nullptr};
     hipError_t e = hipGetDevice(&c->device);
     size_t sb = 0;
     fdlbm_workspace_bytes(p, &sb, nullptr);
     if (e == hipSuccess) e = hipMemsetAsync(state_a, 0, sb, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(state_b, 0, sb, c->stream);
+    DiskTable t;  // outlives the uploads: the stream is synchronised below
+    if (e == hipSuccess && p->bc == FDLBM_BC_DISK) {
+        if (!disk_table(*p, &t)) {
+            delete c;
+            return FDLBM_EINVAL;
+        }
+        char *sc = c->scratch;
+        c->disk.nghost = int(t.dst.size());
+        c->disk.dst = reinterpret_cast<const int32_t *>(sc + L.disk_dst);
+        c->disk.src = reinterpret_cast<const int32_t *>(sc + L.disk_src);
+        c->disk.w = reinterpret_cast<const double *>(sc + L.disk_w);
+        c->disk.span = reinterpret_cast<const int32_t *>(sc + L.disk_span);
+        const size_t ng = t.dst.size();
+        if (ng) e = hipMemcpyAsync(sc + L.disk_dst, t.dst.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && ng)
+            e = hipMemcpyAsync(sc + L.disk_src, t.src.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && ng)
+            e = hipMemcpyAsync(sc + L.disk_w, t.w.data(), 3 * ng * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sc + L.disk_span, t.span.data(), t.span.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -265,6 +315,8 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
                      c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, c->p.tile_rows, wall_xi(c->p)};
     for (int64_t s = 0; s < nsteps; ++s) {
         void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
+        // the curved wall: ghost and rest nodes from the fluid, in place, before the step
+        if (c->p.bc == FDLBM_BC_DISK) HIPCHK(launch_disk_fill(c->disk, c->p.dtype, src, c->stream), "disk fill launch");
         hipError_t e;
         if (!fd)
             e = launch_mrt(ma, src, dst, c->stream);

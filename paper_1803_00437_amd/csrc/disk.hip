@@ -1,0 +1,166 @@
+// Curved no-slip wall around a disk (section 3-b): the ghost-node table, built on the host
+// once per context, and the kernel that fills ghost and rest nodes before each periodic
+// step.
+//
+// Section 3-b states the principle: the nodes just outside the fluid carry a virtual-fluid
+// state, extrapolated linearly with zero velocity on the wall, by an expression chosen from
+// where the wall cuts the link.  The rule implemented here, the curved counterpart of the
+// straight-wall ghost rows: a ghost node at r = R + d on the ray of unit vector n takes the
+// state at its mirror point c + (R - d) n, momentum negated and density kept, bilinearly
+// interpolated when the four nodes around the mirror point are fluid; otherwise (mirror
+// point in the last cell before the wall) the momentum runs linearly from zero on the wall
+// to the sample at depth 3/2, J = -(d / 1.5) J(c + (R - 1.5) n), with that sample's density.
+// Ghost nodes are the non-fluid nodes within Chebyshev distance 3 of the fluid: one
+// propagation link plus the two-node reach of the 5-point differences, so no fluid update
+// reads anything else.
+#include <algorithm>
+#include <cmath>
+
+#include "fdlbm_device.hpp"
+#include "internal.hpp"
+
+namespace fdlbm {
+
+namespace {
+
+constexpr double SAMPLE_DEPTH = 1.5;
+constexpr int GHOST_REACH = 3;
+
+struct Disk {
+    double cx, cy, r;
+    bool fluid(long i, long j) const { return std::hypot(double(i) - cx, double(j) - cy) < r; }
+};
+
+// fluid columns [lo, hi] of row j (lo > hi: none); the disk is convex, so they are contiguous
+void fluid_span(const Disk &d, int j, long *lo, long *hi)
+{
+    const double dy = double(j) - d.cy;
+    *lo = 1;
+    *hi = 0;
+    if (!(std::fabs(dy) < d.r)) return;
+    const double half = std::sqrt(d.r * d.r - dy * dy);
+    long a = (long)std::floor(d.cx - half), b = (long)std::ceil(d.cx + half);
+    // settle the ends with the exact membership test
+    while (d.fluid(a - 1, j)) --a;
+    while (a <= b && !d.fluid(a, j)) ++a;
+    while (d.fluid(b + 1, j)) ++b;
+    while (b >= a && !d.fluid(b, j)) --b;
+    *lo = a;
+    *hi = b;
+}
+
+}  // namespace
+
+bool build_disk_table(int nx, int ny, double cx, double cy, double r, DiskTable *out)
+{
+    if (!(std::isfinite(cx) && std::isfinite(cy) && std::isfinite(r)) || !(r > SAMPLE_DEPTH)) return false;
+    if (size_t(nx) * size_t(ny) >= (size_t(1) << 31)) return false;  // 32-bit node indices
+    // every fluid node (r < R) then lies in [GHOST_REACH, n - 1 - GHOST_REACH] on both axes
+    if (!(cx - r >= GHOST_REACH - 1 && cx + r <= nx - GHOST_REACH && cy - r >= GHOST_REACH - 1 &&
+          cy + r <= ny - GHOST_REACH))
+        return false;
+    const Disk d{cx, cy, r};
+    std::vector<long> flo(ny), fhi(ny);
+    size_t nfluid = 0;
+    for (int j = 0; j < ny; ++j) {
+        fluid_span(d, j, &flo[j], &fhi[j]);
+        if (flo[j] <= fhi[j]) {
+            if (flo[j] < GHOST_REACH || fhi[j] > nx - 1 - GHOST_REACH) return false;
+            if (j < GHOST_REACH || j > ny - 1 - GHOST_REACH) return false;
+            nfluid += size_t(fhi[j] - flo[j] + 1);
+        }
+    }
+    if (nfluid == 0) return false;
+    DiskTable t;
+    t.nfluid = nfluid;
+    t.span.assign(2 * size_t(ny), 0);
+    auto cell = [&](double px, double py, int32_t *src, double *wx, double *wy) {
+        const long i0 = (long)std::floor(px), j0 = (long)std::floor(py);
+        if (!(d.fluid(i0, j0) && d.fluid(i0 + 1, j0) && d.fluid(i0, j0 + 1) && d.fluid(i0 + 1, j0 + 1))) return false;
+        *src = int32_t(j0 * nx + i0);
+        *wx = px - double(i0);
+        *wy = py - double(j0);
+        return true;
+    };
+    for (int j = 0; j < ny; ++j) {
+        // Chebyshev dilation of the fluid by GHOST_REACH, row by row
+        long a = nx, b = -1;
+        for (int k = j - GHOST_REACH; k <= j + GHOST_REACH; ++k) {
+            if (k < 0 || k >= ny || flo[k] > fhi[k]) continue;
+            a = std::min(a, flo[k] - GHOST_REACH);
+            b = std::max(b, fhi[k] + GHOST_REACH);
+        }
+        t.span[2 * size_t(j)] = int32_t(a);
+        t.span[2 * size_t(j) + 1] = int32_t(b);
+        for (long i = a; i <= b; ++i) {
+            if (i >= flo[j] && i <= fhi[j]) continue;
+            const double rr = std::hypot(double(i) - cx, double(j) - cy);
+            const double ux = (double(i) - cx) / rr, uy = (double(j) - cy) / rr;
+            const double delta = rr - r;
+            int32_t src;
+            double wx, wy, sj = -1.0;
+            if (!cell(cx + (r - delta) * ux, cy + (r - delta) * uy, &src, &wx, &wy)) {
+                if (!cell(cx + (r - SAMPLE_DEPTH) * ux, cy + (r - SAMPLE_DEPTH) * uy, &src, &wx, &wy)) return false;
+                sj = -delta / SAMPLE_DEPTH;
+            }
+            t.dst.push_back(int32_t(long(j) * nx + i));
+            t.src.push_back(src);
+            t.w.push_back(wx);
+            t.w.push_back(wy);
+            t.w.push_back(sj);
+        }
+    }
+    *out = std::move(t);
+    return true;
+}
+
+namespace {
+
+constexpr int TPB = 256;
+
+// threads [0, nghost): one ghost node each; threads [nghost, nghost + nx*ny): one node each,
+// set to rest when it lies outside its row's fluid-or-ghost span.  Ghost threads read fluid
+// nodes only and write ghost nodes only, so the fill works in place.
+template <typename T>
+__global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state)
+{
+    using S = Storage<T>;
+    using C = typename S::C;
+    const size_t t = size_t(blockIdx.x) * TPB + threadIdx.x;
+    const size_t plane = size_t(f.nx) * size_t(f.ny);
+    if (t < size_t(f.nghost)) {
+        const size_t s = size_t(f.src[t]), dst = size_t(f.dst[t]);
+        const C wx = C(f.w[3 * t]), wy = C(f.w[3 * t + 1]), sj = C(f.w[3 * t + 2]);
+        const C ux = C(1) - wx, uy = C(1) - wy;
+        for (int p = 0; p < 3; ++p) {
+            const T *a = state + p * plane + s;
+            const C lower = ux * S::load(a[0]) + wx * S::load(a[1]);
+            const C upper = ux * S::load(a[f.nx]) + wx * S::load(a[f.nx + 1]);
+            const C v = uy * lower + wy * upper;
+            state[p * plane + dst] = S::store(p == 0 ? v : sj * v);
+        }
+        return;
+    }
+    const size_t node = t - size_t(f.nghost);
+    if (node >= plane) return;
+    const int j = int(node / size_t(f.nx));
+    const int i = int(node - size_t(j) * size_t(f.nx));
+    if (i >= f.span[2 * j] && i <= f.span[2 * j + 1]) return;
+    for (int p = 0; p < 3; ++p) state[p * plane + node] = S::store(C(0));
+}
+
+}  // namespace
+
+hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, hipStream_t s)
+{
+    const size_t threads = size_t(f.nghost) + size_t(f.nx) * size_t(f.ny);
+    const dim3 grid(unsigned((threads + TPB - 1) / TPB));
+    switch (dtype) {
+    case FDLBM_F64: hipLaunchKernelGGL(disk_fill_kernel<double>, grid, TPB, 0, s, f, (double *)state); break;
+    case FDLBM_F32: hipLaunchKernelGGL(disk_fill_kernel<float>, grid, TPB, 0, s, f, (float *)state); break;
+    default: hipLaunchKernelGGL(disk_fill_kernel<__half>, grid, TPB, 0, s, f, (__half *)state); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fdlbm

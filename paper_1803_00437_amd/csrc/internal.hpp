@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/fdlbm.h"
 
 namespace fdlbm {
@@ -86,6 +88,26 @@ hipError_t launch_batch_step(const BatchLaunch &L, const void *src, void *dst, h
 hipError_t launch_batch_single(const BatchLaunch &L, int i, int cls, int nblocks, const void *src, void *dst,
                                hipStream_t s);
 hipError_t launch_batch_sample(const BatchLaunch &L, const void *state, hipStream_t s);
+
+// Curved no-slip wall around a disk (section 3-b) ----------------------------------------
+// Ghost nodes, filled from the fluid before each periodic step: per ghost its linear index,
+// the linear index of the lower-left node of its interpolation cell, and (wx, wy, sj): the
+// bilinear weights of the right and upper neighbours and the factor on the momentum.  Per
+// row j, the nodes [span[2j], span[2j+1]] are fluid or ghost; the others are set to rest.
+struct DiskTable {
+    std::vector<int32_t> dst, src, span;
+    std::vector<double> w;  // 3 per ghost
+    size_t nfluid = 0;
+};
+// Builds the table; false if the disk does not fit the grid (the fluid must stay 3 nodes
+// from every edge), holds no fluid node, or a ghost finds no fluid interpolation cell.
+bool build_disk_table(int nx, int ny, double cx, double cy, double r, DiskTable *out);
+struct DiskFill {
+    int nx, ny, nghost;
+    const int32_t *dst, *src, *span;
+    const double *w;
+};
+hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, hipStream_t s);
 
 // MRT D2Q9 stream-collide (push) step.
 hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);

@@ -29,9 +29,10 @@ def test_library_loads_and_exports_every_declared_function():
 
 
 def test_params_struct_layout_matches_header():
-    # 6 int32, 4 doubles, int32 (+pad), 2 doubles, 4 int32, 1 double
-    assert ctypes.sizeof(F.Params) == 6 * 4 + 4 * 8 + 8 + 2 * 8 + 4 * 4 + 8
+    # 6 int32, 4 doubles, int32 (+pad), 2 doubles, 4 int32, 4 doubles
+    assert ctypes.sizeof(F.Params) == 6 * 4 + 4 * 8 + 8 + 2 * 8 + 4 * 4 + 4 * 8
     assert F.Params.wall_xi.offset == 96
+    assert F.Params.disk_r.offset == 120
     assert ctypes.sizeof(F.Diag) == 8 * 8
 
 
@@ -142,3 +143,50 @@ def test_autotune_rejects_bad_arguments_without_a_device():
     lib = F.load_library()
     assert lib.fdlbm_autotune(None, 5, None, None, None) == F.FDLBM_EINVAL
     assert lib.fdlbm_batch_autotune(None, 5, None, None) == F.FDLBM_EINVAL
+
+
+def disk(**kw):
+    base = dict(nx=72, ny=72, bc="disk", disk=(35.5, 35.5, 29.9), s_xx=1.5)
+    base.update(kw)
+    return good(**base)
+
+
+def test_disk_table_size_matches_the_oracle_ghost_count():
+    """The scratch buffer grows by the ghost-node table: two int32 and three doubles per
+    ghost node plus two int32 per row, each array 256-byte aligned.  The ghost count is the
+    one the oracle derives from the same geometry (section 3-b), so the host-side table
+    builder and the oracle agree on which nodes are ghosts."""
+    from oracle import disk as D
+
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    for (nx, ny, cx, cy, r) in ((72, 72, 35.5, 35.5, 29.9), (50, 41, 24.3, 19.8, 11.7), (20, 20, 9.0, 9.5, 2.2)):
+        ng = D.disk_ghost_rules(nx, ny, cx, cy, r)["j"].size
+        _, base = F.fdlbm_workspace_bytes(good(nx=nx, ny=ny))
+        _, cb = F.fdlbm_workspace_bytes(good(nx=nx, ny=ny, bc="disk", disk=(cx, cy, r)))
+        assert cb - base == 2 * a256(4 * ng) + a256(24 * ng) + a256(8 * ny), (nx, ny, cx, cy, r, ng)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(disk=(35.5, 35.5, 34.0)),          # reaches past the edge (needs cx - r >= 2)
+    dict(disk=(35.5, 35.5, 33.6)),          # cx + r > nx - 3
+    dict(disk=(10.0, 35.5, 9.0)),
+    dict(disk=(35.5, 35.5, 1.5)),           # the depth-3/2 sample needs r > 3/2
+    dict(disk=(35.5, 35.5, 0.0)),
+    dict(disk=(float("nan"), 35.5, 10.0)),
+    dict(disk=(35.5, 35.5, float("inf"))),
+    dict(scheme="mrt", quartic=True),       # the curved wall acts on (drho, J) only
+    dict(scheme="lwacm", force=(1e-6, 0.0)),
+])
+def test_disk_parameters_are_checked(bad):
+    with pytest.raises(F.FdlbmError) as e:
+        F.fdlbm_workspace_bytes(disk(**bad))
+    assert e.value.code == F.FDLBM_EINVAL
+
+
+def test_disk_accepts_every_fd_variant():
+    for kw in (dict(), dict(stencil=5), dict(dtype="f64"), dict(dtype="f16"), dict(scheme="lwacm"),
+               dict(force=(1e-6, 0.0)), dict(kernel="reference"), dict(kernel="sweep", lane_cols=2),
+               dict(disk=(35.5, 35.5, 1.6)), dict(disk=(31.9, 31.9, 29.9))):
+        F.fdlbm_workspace_bytes(disk(**kw))

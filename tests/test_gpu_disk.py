@@ -1,0 +1,160 @@
+"""The curved no-slip wall around a disk (section 3-b) on the GPU: the sweep kernels bit for
+bit against the reference kernels (the ghost fill is shared), both against the FP64 oracle,
+and the decay rates of the 17 Stokes modes of Tables 2 and 3, measured with the library's
+FP64 device projection, against the oracle's rates, the Bessel rates and the paper's.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import disk as D
+
+pytestmark = pytest.mark.gpu
+
+R, N = 29.9, 72
+C = (N - 1) / 2
+GEOMS = {"centred": (72, 72, C, C, R), "offset": (50, 41, 24.3, 19.8, 11.7)}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "stokes_disk_tables.json")
+NUS = {"0.05": 0.05, "1/sqrt108": 1.0 / math.sqrt(108.0)}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1803_00437_amd as F
+
+    F.load_library()
+    return F
+
+
+@pytest.fixture(scope="module")
+def rules():
+    return {k: D.disk_ghost_rules(*g) for k, g in GEOMS.items()}
+
+
+def rel_l2(a, b):
+    return math.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(a, b)) / sum(float(np.sum(y * y)) for y in b))
+
+
+def inside_noise(geom, seed, amp=1e-3):
+    nx, ny, cx, cy, r = GEOMS[geom]
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    fluid = np.hypot(x - cx, y - cy) < r
+    rng = np.random.default_rng(seed)
+    return tuple(np.where(fluid, amp * rng.standard_normal((ny, nx)), 0.0) for _ in range(3))
+
+
+def run(F, geom, init, steps, **kw):
+    nx, ny, cx, cy, r = GEOMS[geom]
+    sim = F.FdLbm(nx, ny, bc="disk", disk=(cx, cy, r), **kw)
+    sim.set_state(*init)
+    sim.step(steps)
+    out = sim.get_state()
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("scheme,stencil,forced", [("fd", 3, False), ("fd", 5, False), ("fd", 3, True),
+                                                   ("fd", 5, True), ("lwacm", 3, False)])
+def test_disk_sweep_equals_reference_bitwise(F, geom, dtype, scheme, stencil, forced):
+    print(f"case disk sweep-vs-reference geom={geom} dtype={dtype} scheme={scheme} stencil={stencil} forced={forced}",
+          flush=True)
+    init = inside_noise(geom, seed=7)
+    kw = dict(scheme=scheme, stencil=stencil, dtype=dtype, s_xx=O.rate_from_viscosity(0.05),
+              force=(2e-6, -1e-6) if forced else (0.0, 0.0))
+    a = run(F, geom, init, 40, kernel="reference", **kw)
+    b = run(F, geom, init, 40, kernel="sweep", **kw)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v), float(np.max(np.abs(u - v)))
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "lwacm"])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_disk_matches_oracle(F, rules, geom, scheme, dtype, tol):
+    """A Stokes mode plus noise, 200 steps, every node (fluid, ghost and rest) compared."""
+    nx, ny, cx, cy, r = GEOMS[geom]
+    nu, steps = 0.05, 200
+    k = W.disk_mode_wavenumber(2, 1, r)
+    mode = W.disk_stokes_mode(nx, ny, cx, cy, r, 2, k, nu=nu)
+    init = tuple(a + b for a, b in zip(mode, inside_noise(geom, seed=3, amp=2e-4)))
+    s_xx = O.rate_from_viscosity(nu)
+    if scheme == "lwacm":
+        got = run(F, geom, init, steps, scheme="lwacm", dtype=dtype, s_xx=s_xx)
+        want = D.disk_run(*init, steps, rules=rules[geom], scheme="lwacm", s_xx=s_xx)
+    else:
+        st = int(scheme[2])
+        got = run(F, geom, init, steps, scheme="fd", stencil=st, dtype=dtype, s_xx=s_xx, force=(1e-6, 0.0))
+        want = D.disk_run(*init, steps, rules=rules[geom], stencil=st, s_xx=s_xx, fx=1e-6)
+    err = rel_l2(got, want)
+    print(f"  disk {geom} {scheme} {dtype}: rel L2 {err:.2e}")
+    assert err <= tol
+
+
+def test_disk_f16_storage_error(F, rules):
+    k = W.disk_mode_wavenumber(0, 2, R)
+    init = W.disk_stokes_mode(N, N, C, C, R, 0, k, amp=0.01, nu=0.05)
+    s_xx = O.rate_from_viscosity(0.05)
+    got = run(F, "centred", init, 300, stencil=5, dtype="f16", s_xx=s_xx)
+    want = D.disk_run(*init, 300, rules=rules["centred"], stencil=5, s_xx=s_xx)
+    fl = rules["centred"]["fluid"]
+    err = rel_l2([g[fl] for g in got], [w[fl] for w in want])
+    print(f"  disk f16 rel L2 (fluid) {err:.2e}")
+    assert err <= 5e-3
+
+
+def table_modes():
+    rows = json.load(open(GOLDEN))["rows"]
+    return [(r, 0, r["l"]) if r["family"] == "singlet" else (r, r["l"], 1) for r in rows]
+
+
+def device_rate(F, init, nu, gamma0, **kw):
+    t1, t2 = D.decay_times(gamma0)
+    sim = F.FdLbm(N, N, bc="disk", disk=(C, C, R), s_xx=O.rate_from_viscosity(nu), **kw)
+    sim.set_state(*init)
+    sim.set_mode(init[1], init[2])
+    sim.step(t1)
+    a1 = sim.mode_projection()
+    sim.step(t2 - t1)
+    a2 = sim.mode_projection()
+    sim.close()
+    return -math.log(a2 / a1) / (t2 - t1)
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("nukey", list(NUS))
+def test_stokes_mode_rates_tables_2_3(F, rules, stencil, nukey):
+    """FP64 device rates of the 17 modes: equal to the oracle's to 1e-8 (relative), within
+    2 % (3-point) or 0.3 % (5-point) of the paper's measured rates, and, 5-point, within
+    0.6 % of nu a^2 / R^2; FP32 storage moves no rate by more than 1e-4."""
+    nu = NUS[nukey]
+    tol_paper = 0.02 if stencil == 3 else 0.003
+    worst = 0.0
+    for row, m, l in table_modes():
+        k = W.disk_mode_wavenumber(m, l, R)
+        init = W.disk_stokes_mode(N, N, C, C, R, m, k, nu=nu)
+        g0 = nu * k * k
+        got = device_rate(F, init, nu, g0, stencil=stencil, dtype="f64")
+        want = D.disk_decay_rate(init, rules=rules["centred"], nu=nu, gamma0=g0, stencil=stencil)
+        assert abs(got / want - 1) < 1e-8, (row, got, want)
+        paper = row[f"fd{stencil}_nu_{nukey}"]
+        ratio = (got / g0) / (1 + paper) - 1
+        worst = max(worst, abs(ratio))
+        assert abs(ratio) < tol_paper, (row, got / g0 - 1, paper)
+        if stencil == 5:
+            assert abs(got / g0 - 1) < 6e-3, (row, got / g0 - 1)
+        if row["l"] in (1, 6):
+            g32 = device_rate(F, init, nu, g0, stencil=stencil, dtype="f32")
+            assert abs(g32 / got - 1) < 1e-4, (row, g32, got)
+        print(f"  FD{stencil} nu={nukey} {row['family']} l={row['l']}: error {got / g0 - 1:+.5f} "
+              f"(paper {paper:+.5f})")
+    print(f"  FD{stencil} nu={nukey}: worst rate ratio to the paper {worst:.4f}")
