@@ -44,10 +44,11 @@ def bytes_per_node(scheme, dtype):
 
 
 def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with_diag, tile_rows=0, lane_cols=0,
-             bc="periodic", nu=NU, force=(0.0, 0.0), autotune=True):
+             bc="periodic", nu=NU, force=(0.0, 0.0), autotune=True, disk=(0.0, 0.0, 0.0)):
     ny, nx = init[0].shape
     s_xx = F.fdlbm_rate_from_viscosity(nu)
-    kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel, tile_rows=tile_rows, bc=bc, force=force)
+    kw = dict(scheme=scheme, dtype=dtype, s_xx=s_xx, s_e=1.0, kernel=kernel, tile_rows=tile_rows, bc=bc, force=force,
+              disk=disk)
     if scheme != "mrt":
         kw["lane_cols"] = lane_cols
     if scheme == "fd":
@@ -275,6 +276,22 @@ def main():
                                     bc="walls", nu=nu_ch, force=(fx, 0.0), autotune=not args.no_autotune)
             print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
         del r, x, y
+        # a disk of radius n/2 - 6 closed by the curved wall (section 3-b): the ghost fill
+        # (one launch, in place) before each periodic step; the flow is the decaying one,
+        # zero outside the disk
+        import numpy as np
+
+        c, rad = (n - 1) / 2, n / 2 - 6
+        yy, xx = np.ogrid[:n, :n]
+        inside = (xx - c) ** 2 + (yy - c) ** 2 < rad * rad
+        dinit = tuple(np.where(inside, a, 0.0) for a in init)
+        del inside
+        key = f"disk_r{rad:g}_fd3_f32"
+        compare[key] = run_case(F, torch, dinit, "fd", "f32", 3, short, 10, args.kernel, False, bc="disk",
+                                disk=(c, c, rad), autotune=not args.no_autotune)
+        compare[key]["vs_periodic"] = round(compare[key]["kernel_ms"] / main_case["kernel_ms"], 4)
+        print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
+        del dinit
 
     batch = None
     if not args.no_batch:

@@ -35,7 +35,7 @@ double quartic(double s_xx) { return 1.0 / (0.5 + 1.0 / (6.0 * (1.0 / s_xx - 0.5
 
 struct Layout {
     size_t partials, out, mode, staging, fstar;
-    size_t disk_dst, disk_src, disk_w, disk_span;  // ghost-node table (FDLBM_BC_DISK)
+    size_t disk_dst, disk_src, disk_w, disk_span, disk_ring;  // ghost-node table (FDLBM_BC_DISK)
     size_t total;
 };
 
@@ -121,10 +121,13 @@ Layout layout(const fdlbm_params &p)
     L.staging = off;
     L.fstar = off;
     off += staging > fstar ? staging : fstar;
-    size_t ng = 0;
+    size_t ng = 0, nr = 0;
     if (p.bc == FDLBM_BC_DISK) {
         DiskTable t;
-        if (disk_table(p, &t)) ng = t.dst.size();
+        if (disk_table(p, &t)) {
+            ng = t.dst.size();
+            nr = t.ring.size();
+        }
     }
     L.disk_dst = off;
     off += align256(sizeof(int32_t) * ng);
@@ -134,6 +137,8 @@ Layout layout(const fdlbm_params &p)
     off += align256(sizeof(double) * 3 * ng);
     L.disk_span = off;
     off += p.bc == FDLBM_BC_DISK ? align256(sizeof(int32_t) * 2 * size_t(p.ny)) : 0;
+    L.disk_ring = off;
+    off += align256(sizeof(int32_t) * nr);
     L.total = off;
     return L;
 }
@@ -151,7 +156,8 @@ struct fdlbm_ctx {
     hipStream_t stream;
     int64_t steps;
     bool mode_set;
-    DiskFill disk;  // FDLBM_BC_DISK: the ghost-node table in the scratch buffer
+    DiskFill disk;   // FDLBM_BC_DISK: the ghost-node table in the scratch buffer
+    bool disk_full;  // the next fill sets every rest node to rest (the state was just set)
 
     size_t n() const { return (size_t)p.nx * (size_t)p.ny; }
     double *sd(size_t off) const { return reinterpret_cast<double *>(scratch + off); }
@@ -190,7 +196,8 @@ int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scra
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->steps = 0;
     c->mode_set = false;
-    c->disk = DiskFill{p->nx, p->ny, 0, nullptr, nullptr, nullptr, nullptr};
+    c->disk = DiskFill{p->nx, p->ny, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+    c->disk_full = true;
     hipError_t e = hipGetDevice(&c->device);
     size_t sb = 0;
     fdlbm_workspace_bytes(p, &sb, nullptr);
@@ -208,7 +215,9 @@ int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scra
         c->disk.src = reinterpret_cast<const int32_t *>(sc + L.disk_src);
         c->disk.w = reinterpret_cast<const double *>(sc + L.disk_w);
         c->disk.span = reinterpret_cast<const int32_t *>(sc + L.disk_span);
-        const size_t ng = t.dst.size();
+        c->disk.nring = int(t.ring.size());
+        c->disk.ring = reinterpret_cast<const int32_t *>(sc + L.disk_ring);
+        const size_t ng = t.dst.size(), nr = t.ring.size();
         if (ng) e = hipMemcpyAsync(sc + L.disk_dst, t.dst.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess && ng)
             e = hipMemcpyAsync(sc + L.disk_src, t.src.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
@@ -217,6 +226,9 @@ int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scra
         if (e == hipSuccess)
             e = hipMemcpyAsync(sc + L.disk_span, t.span.data(), t.span.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && nr)
+            e = hipMemcpyAsync(sc + L.disk_ring, t.ring.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice,
+                               c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -246,6 +258,7 @@ int fdlbm_set_state(fdlbm_ctx *c, const double *drho, const double *jx, const do
         HIPCHK(launch_mrt_init(c->p.dtype, st, st + n, st + 2 * n, c->buf[c->cur], n, c->stream), "mrt_init");
     HIPCHK(hipStreamSynchronize(c->stream), "set_state");
     c->steps = 0;
+    c->disk_full = true;
     return FDLBM_OK;
 }
 
@@ -315,8 +328,14 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
                      c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, c->p.tile_rows, wall_xi(c->p)};
     for (int64_t s = 0; s < nsteps; ++s) {
         void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
-        // the curved wall: ghost and rest nodes from the fluid, in place, before the step
-        if (c->p.bc == FDLBM_BC_DISK) HIPCHK(launch_disk_fill(c->disk, c->p.dtype, src, c->stream), "disk fill launch");
+        // the curved wall: ghost and rest nodes from the fluid, in place, before the step;
+        // every rest node after the state was set or under a body force (which moves the
+        // rest nodes too), else only the ring the previous step could reach
+        if (c->p.bc == FDLBM_BC_DISK) {
+            const bool full = c->disk_full || c->p.force_x != 0.0 || c->p.force_y != 0.0;
+            HIPCHK(launch_disk_fill(c->disk, c->p.dtype, src, full, c->stream), "disk fill launch");
+            c->disk_full = false;
+        }
         hipError_t e;
         if (!fd)
             e = launch_mrt(ma, src, dst, c->stream);

@@ -12,7 +12,10 @@
 // to the sample at depth 3/2, J = -(d / 1.5) J(c + (R - 1.5) n), with that sample's density.
 // Ghost nodes are the non-fluid nodes within Chebyshev distance 3 of the fluid: one
 // propagation link plus the two-node reach of the 5-point differences, so no fluid update
-// reads anything else.
+// reads anything else.  Every other node is held at rest.  A step maps a rest
+// neighbourhood (all deviations zero) to exactly zero unless a body force acts, so after
+// one full clearing only the ring of rest nodes within that same reach of the fluid and
+// ghost nodes (periodic images included) can leave rest, and only the ring is cleared.
 #include <algorithm>
 #include <cmath>
 
@@ -110,6 +113,35 @@ bool build_disk_table(int nx, int ny, double cx, double cy, double r, DiskTable 
             t.w.push_back(sj);
         }
     }
+    // ring: rest nodes within GHOST_REACH (the step's reach) of a fluid or ghost node,
+    // across the periodic edges as well
+    std::vector<long> rlo(ny, 0), rhi(ny, -1);
+    std::vector<char> dirty(ny, 0);
+    for (int k = 0; k < ny; ++k) {
+        const long a = t.span[2 * size_t(k)], b = t.span[2 * size_t(k) + 1];
+        if (a > b) continue;
+        for (int dj = -GHOST_REACH; dj <= GHOST_REACH; ++dj) {
+            const int j = ((k + dj) % ny + ny) % ny;
+            if (!dirty[j]) {
+                rlo[j] = a - GHOST_REACH;
+                rhi[j] = b + GHOST_REACH;
+                dirty[j] = 1;
+            } else {
+                rlo[j] = std::min(rlo[j], a - GHOST_REACH);
+                rhi[j] = std::max(rhi[j], b + GHOST_REACH);
+            }
+        }
+    }
+    for (int j = 0; j < ny; ++j) {
+        if (!dirty[j]) continue;
+        const long a = t.span[2 * size_t(j)], b = t.span[2 * size_t(j) + 1];
+        const long hi = std::min(rhi[j], rlo[j] + nx - 1);  // at most one whole row
+        for (long c = rlo[j]; c <= hi; ++c) {
+            const long i = (c % nx + nx) % nx;
+            if (i >= a && i <= b) continue;
+            t.ring.push_back(int32_t(long(j) * nx + i));
+        }
+    }
     *out = std::move(t);
     return true;
 }
@@ -118,11 +150,14 @@ namespace {
 
 constexpr int TPB = 256;
 
-// threads [0, nghost): one ghost node each; threads [nghost, nghost + nx*ny): one node each,
-// set to rest when it lies outside its row's fluid-or-ghost span.  Ghost threads read fluid
-// nodes only and write ghost nodes only, so the fill works in place.
+// threads [0, nghost): one ghost node each; then either one thread per ring node (set to
+// rest), or, for a full clearing, one thread per CLEAR_COLS columns of a row, which sets the
+// nodes outside the row's fluid-or-ghost span to rest.  Ghost threads read fluid nodes only
+// and write ghost nodes only, so the fill works in place.
+constexpr int CLEAR_COLS = 8;
+
 template <typename T>
-__global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state)
+__global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state, int full)
 {
     using S = Storage<T>;
     using C = typename S::C;
@@ -141,24 +176,37 @@ __global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state)
         }
         return;
     }
-    const size_t node = t - size_t(f.nghost);
-    if (node >= plane) return;
-    const int j = int(node / size_t(f.nx));
-    const int i = int(node - size_t(j) * size_t(f.nx));
-    if (i >= f.span[2 * j] && i <= f.span[2 * j + 1]) return;
-    for (int p = 0; p < 3; ++p) state[p * plane + node] = S::store(C(0));
+    const size_t u = t - size_t(f.nghost);
+    if (!full) {
+        if (u >= size_t(f.nring)) return;
+        const size_t node = size_t(f.ring[u]);
+        for (int p = 0; p < 3; ++p) state[p * plane + node] = S::store(C(0));
+        return;
+    }
+    const size_t per_row = (size_t(f.nx) + CLEAR_COLS - 1) / CLEAR_COLS;
+    if (u >= per_row * size_t(f.ny)) return;
+    const int j = int(u / per_row);
+    const int i0 = int(u - size_t(j) * per_row) * CLEAR_COLS;
+    const int a = f.span[2 * j], b = f.span[2 * j + 1];
+    for (int i = i0; i < min(i0 + CLEAR_COLS, f.nx); ++i) {
+        if (i >= a && i <= b) continue;
+        const size_t node = size_t(j) * size_t(f.nx) + size_t(i);
+        for (int p = 0; p < 3; ++p) state[p * plane + node] = S::store(C(0));
+    }
 }
 
 }  // namespace
 
-hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, hipStream_t s)
+hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, bool full, hipStream_t s)
 {
-    const size_t threads = size_t(f.nghost) + size_t(f.nx) * size_t(f.ny);
+    const size_t per_row = (size_t(f.nx) + CLEAR_COLS - 1) / CLEAR_COLS;
+    const size_t threads = size_t(f.nghost) + (full ? per_row * size_t(f.ny) : size_t(f.nring));
     const dim3 grid(unsigned((threads + TPB - 1) / TPB));
+    const int fl = full ? 1 : 0;
     switch (dtype) {
-    case FDLBM_F64: hipLaunchKernelGGL(disk_fill_kernel<double>, grid, TPB, 0, s, f, (double *)state); break;
-    case FDLBM_F32: hipLaunchKernelGGL(disk_fill_kernel<float>, grid, TPB, 0, s, f, (float *)state); break;
-    default: hipLaunchKernelGGL(disk_fill_kernel<__half>, grid, TPB, 0, s, f, (__half *)state); break;
+    case FDLBM_F64: hipLaunchKernelGGL(disk_fill_kernel<double>, grid, TPB, 0, s, f, (double *)state, fl); break;
+    case FDLBM_F32: hipLaunchKernelGGL(disk_fill_kernel<float>, grid, TPB, 0, s, f, (float *)state, fl); break;
+    default: hipLaunchKernelGGL(disk_fill_kernel<__half>, grid, TPB, 0, s, f, (__half *)state, fl); break;
     }
     return hipGetLastError();
 }

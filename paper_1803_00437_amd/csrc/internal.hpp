@@ -94,8 +94,10 @@ hipError_t launch_batch_sample(const BatchLaunch &L, const void *state, hipStrea
 // the linear index of the lower-left node of its interpolation cell, and (wx, wy, sj): the
 // bilinear weights of the right and upper neighbours and the factor on the momentum.  Per
 // row j, the nodes [span[2j], span[2j+1]] are fluid or ghost; the others are set to rest.
+// ring: the rest nodes within the step's reach (3) of a fluid or ghost node, periodic images
+// included: without a body force the only rest nodes a step can move.
 struct DiskTable {
-    std::vector<int32_t> dst, src, span;
+    std::vector<int32_t> dst, src, span, ring;
     std::vector<double> w;  // 3 per ghost
     size_t nfluid = 0;
 };
@@ -103,11 +105,13 @@ struct DiskTable {
 // from every edge), holds no fluid node, or a ghost finds no fluid interpolation cell.
 bool build_disk_table(int nx, int ny, double cx, double cy, double r, DiskTable *out);
 struct DiskFill {
-    int nx, ny, nghost;
-    const int32_t *dst, *src, *span;
+    int nx, ny, nghost, nring;
+    const int32_t *dst, *src, *span, *ring;
     const double *w;
 };
-hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, hipStream_t s);
+// full: set every rest node to rest (first step after the state was set, or a body force
+// acts); otherwise the ring only
+hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, bool full, hipStream_t s);
 
 // MRT D2Q9 stream-collide (push) step.
 hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);

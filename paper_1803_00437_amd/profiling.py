@@ -37,6 +37,12 @@ COPY_BYTES = 1 << 30
 N = 8192
 CHANNEL = 16384 * 1024
 BATCH_NODES = 177708266  # sum of N^2 over the 512 shear-wave instances (sizes U{32..1024}, seed 5)
+# the disk of radius N/2 - 6 centred at ((N-1)/2, (N-1)/2): its ghost nodes (within
+# Chebyshev distance 3 of the fluid) and the ring of rest nodes within 3 of those.  A fill
+# reads 4 fluid nodes and a 32-byte table entry and writes 1 node per ghost (92 bytes in
+# FP32), and reads a 4-byte index and writes 1 node per ring node (16 bytes).
+DISK_GHOSTS, DISK_RING = 98196, 98268
+DISK_FILL_BYTES = 92 * DISK_GHOSTS + 16 * DISK_RING
 
 
 def _csvs(d, suffix):
@@ -178,6 +184,10 @@ KERNELS = [
     ("fd3_f32_batch512", "fd_batch_kernel<float, ", 24 * BATCH_NODES, None,
      [f"{CSRC}/fd_batch.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"],
      "512 periodic shear-wave instances N x N, N ~ U{32..1024}, one launch per step for all; FP32"),
+    ("disk_fill_f32_8192", "disk_fill_kernel<float>", DISK_FILL_BYTES, None, [f"{CSRC}/disk.hip"],
+     "disk of radius 4090 in the 8192 x 8192 grid (section 3-b curved wall): ghost nodes and the ring of rest "
+     "nodes set before each FD-LBM 3-point FP32 step (the first fill after the state is set clears every rest "
+     "node and is in the average); algorithmic bytes = 92 per ghost + 16 per ring node"),
     ("copy_1gib", "copy_kernel", 2 * COPY_BYTES, None, [f"{CSRC}/diag.hip"],
      "fdlbm_device_copy of 1 GiB (the achievable-bandwidth probe)"),
 ]

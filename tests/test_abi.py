@@ -153,19 +153,29 @@ def disk(**kw):
 
 def test_disk_table_size_matches_the_oracle_ghost_count():
     """The scratch buffer grows by the ghost-node table: two int32 and three doubles per
-    ghost node plus two int32 per row, each array 256-byte aligned.  The ghost count is the
-    one the oracle derives from the same geometry (section 3-b), so the host-side table
-    builder and the oracle agree on which nodes are ghosts."""
+    ghost node, two int32 per row, and one int32 per ring node (the rest nodes within the
+    step's reach of a fluid or ghost node, across the periodic edges), each array 256-byte
+    aligned.  The counts are the ones the oracle's geometry gives (section 3-b), so the
+    host-side table builder and the oracle agree on which nodes are ghosts."""
+    import numpy as np
     from oracle import disk as D
 
     def a256(x):
         return (x + 255) // 256 * 256
 
-    for (nx, ny, cx, cy, r) in ((72, 72, 35.5, 35.5, 29.9), (50, 41, 24.3, 19.8, 11.7), (20, 20, 9.0, 9.5, 2.2)):
-        ng = D.disk_ghost_rules(nx, ny, cx, cy, r)["j"].size
+    for (nx, ny, cx, cy, r) in ((72, 72, 35.5, 35.5, 29.9), (50, 41, 24.3, 19.8, 11.7), (20, 20, 9.0, 9.5, 2.2),
+                                (12, 12, 5.5, 5.5, 1.6)):
+        rules = D.disk_ghost_rules(nx, ny, cx, cy, r)
+        ng = rules["j"].size
+        active = ~rules["rest"]
+        near = np.zeros_like(active)
+        for dy in range(-3, 4):
+            for dx in range(-3, 4):
+                near |= np.roll(np.roll(active, dy, 0), dx, 1)
+        nr = int(np.count_nonzero(near & rules["rest"]))
         _, base = F.fdlbm_workspace_bytes(good(nx=nx, ny=ny))
         _, cb = F.fdlbm_workspace_bytes(good(nx=nx, ny=ny, bc="disk", disk=(cx, cy, r)))
-        assert cb - base == 2 * a256(4 * ng) + a256(24 * ng) + a256(8 * ny), (nx, ny, cx, cy, r, ng)
+        assert cb - base == 2 * a256(4 * ng) + a256(24 * ng) + a256(8 * ny) + a256(4 * nr), (nx, ny, cx, cy, r)
 
 
 @pytest.mark.parametrize("bad", [

@@ -106,6 +106,31 @@ def test_disk_matches_oracle(F, rules, geom, scheme, dtype, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("geom", ["centred", "tiny"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_disk_rest_nodes_set_by_the_caller_are_cleared(F, rules, geom, forced):
+    """Noise on every node, the disk's outside included: the first step clears every rest
+    node, later steps only the ring the step can reach (or every rest node again under a
+    body force); FP64 against the oracle, which clears every rest node at every step,
+    node by node, over 60 steps and again after a second set_state."""
+    nx, ny, cx, cy, r = GEOMS[geom]
+    rng = np.random.default_rng(11)
+    init = tuple(1e-3 * rng.standard_normal((ny, nx)) for _ in range(3))
+    force = (1e-6, -2e-6) if forced else (0.0, 0.0)
+    s_xx = O.rate_from_viscosity(0.05)
+    sim = F.FdLbm(nx, ny, bc="disk", disk=(cx, cy, r), stencil=5, dtype="f64", s_xx=s_xx, force=force)
+    for rep in range(2):
+        sim.set_state(*init)
+        sim.step(60)
+        got = sim.get_state()
+        want = D.disk_run(*init, 60, rules=rules[geom], stencil=5, s_xx=s_xx, fx=force[0], fy=force[1])
+        err = rel_l2(got, want)
+        print(f"  disk {geom} forced={forced} set {rep}: rel L2 {err:.2e}")
+        assert err <= 1e-12
+        init = tuple(a[::-1, ::-1].copy() for a in init)
+    sim.close()
+
+
 def test_disk_f16_storage_error(F, rules):
     k = W.disk_mode_wavenumber(0, 2, R)
     init = W.disk_stokes_mode(N, N, C, C, R, 0, k, amp=0.01, nu=0.05)
