@@ -364,6 +364,51 @@ def test_shear_wave_64_decays_at_nu_k2(scheme):
     assert abs(mass) < 1e-13
 
 
+def test_fd_lbm_and_mrt_agree_to_order_k2():
+    """Section 2: FD-LBM and MRT share nu, c_s and the bulk viscosity at order k^2; they
+    differ at the next order through the hyperviscosity.  Shear waves of wavelength N = 16,
+    32, 64 (nu = 0.02, rate from two times past the initial layer): Gamma_FD / Gamma_MRT - 1
+    falls by 4 per doubling of N, and equals (nu2_FD - nu2_MRT) k^2 / nu with the printed
+    closed forms nu2 = (2 sigma - 3)(2 sigma - 1)/72 (three points) and sigma (2 sigma - 1)/36
+    (five points) (sigma = 1/s_xx - 1/2, wave vector along an axis) and the quartic MRT's own
+    shear root."""
+    nu = 0.02
+    s_xx = O.rate_from_viscosity(nu)
+    s_q = O.quartic_s_q(s_xx)
+    sig = 1.0 / s_xx - 0.5
+    nu2_fd3 = (2 * sig - 3) * (2 * sig - 1) / 72
+    _, nu2_mrt = S.hyperviscosity(0.0, "mrt", s_xx=s_xx, s_q=s_q)
+    ratio = {}
+    for n in (16, 32, 64):
+        k = 2 * math.pi / n
+        t_end = int(round(0.5 / (nu * k * k)))
+        t1 = t_end // 5
+        r, jx, jy = W.shear_wave_y(n, n, amp=1e-6, m=1)
+        rate = {}
+        for scheme in ("fd3", "fd5", "mrt"):
+            if scheme == "mrt":
+                f = O.mrt_run(O.mrt_init(r, jx, jy), t1, s_xx=s_xx, s_q=s_q)
+                a1 = O.mrt_moments(f)
+                a2 = O.mrt_moments(O.mrt_run(f, t_end - t1, s_xx=s_xx, s_q=s_q))
+            else:
+                a1 = O.fd_run(r, jx, jy, t1, s_xx=s_xx, stencil=int(scheme[2]))
+                a2 = O.fd_run(*a1, t_end - t1, s_xx=s_xx, stencil=int(scheme[2]))
+            rate[scheme] = -math.log(float(np.sum(a2[1] * jx)) / float(np.sum(a1[1] * jx))) / (t_end - t1)
+        ratio[n] = {s: rate[s] / rate["mrt"] - 1 for s in ("fd3", "fd5")}
+        pred = (nu2_fd3 - nu2_mrt) / nu * k * k
+        tol = 0.01 if n == 64 else 0.03 if n == 32 else 0.1
+        assert abs(ratio[n]["fd3"] / pred - 1) < tol, (n, ratio[n]["fd3"], pred)
+    for a, b in ((16, 32), (32, 64)):
+        assert 3.8 < ratio[a]["fd3"] / ratio[b]["fd3"] < 4.2
+    # five points: nu2 = sigma (2 sigma - 1)/36 is close to MRT's, so the k^4 terms still weigh
+    # at N = 32; at N = 64 the difference is within 15 % of the k^2 prediction and ten times
+    # smaller than the three-point one
+    nu2_fd5 = sig * (2 * sig - 1) / 36
+    pred5 = (nu2_fd5 - nu2_mrt) / nu * (2 * math.pi / 64) ** 2
+    assert abs(ratio[64]["fd5"] / pred5 - 1) < 0.15, (ratio[64]["fd5"], pred5)
+    assert abs(ratio[64]["fd5"]) < abs(ratio[64]["fd3"]) / 10
+
+
 # ----------------------------------------- Galilean factor (sections 1-a and 2) ----
 
 @pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
