@@ -50,3 +50,16 @@ def test_kernel_sources_exist():
     for _, _, _, _, sources, _ in P.KERNELS:
         for s in sources:
             assert os.path.exists(os.path.join(P.ROOT, s)), s
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The step runs on one GPU: bench.py --gpus N with N > 1 exits with a message before it
+    touches a device."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
