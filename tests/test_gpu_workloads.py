@@ -214,3 +214,32 @@ def test_full_size_band_other_schemes(F, scheme, dtype, tol):
     err = rel_l2([g[y0:y0 + rows] for g in got], [w[m:m + rows] for w in want])
     print(f"  8192^2 {scheme} {dtype} band rel L2 {err:.2e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_largest_grids_beyond_2_31_nodes(F, dtype):
+    """65536 x 36864 = 2.4e9 nodes, so each plane holds more than 2^31 values (the ABI allows
+    nx * ny up to 2^32).  A uniform state under a body force stays uniform, and the step
+    adds exactly F to J at every node (section 1, Strang splitting; F a power of two, exact
+    in FP16 too), so after k steps the FP64 diagnostics equal n k F exactly, which a node
+    left out or visited twice anywhere in the grid would change.  The state starts at rest
+    (fdlbm_create clears it), so no host array of that size is needed."""
+    import torch
+
+    nx, ny, steps = 65536, 36864, 6
+    fx, fy = 2.0 ** -10, -(2.0 ** -11)
+    n = nx * ny
+    print(f"case largest grid {nx}x{ny} dtype={dtype}", flush=True)
+    sim = F.FdLbm(nx, ny, dtype=dtype, stencil=3, s_xx=1.5, force=(fx, fy))
+    sim.step(steps)
+    d = sim.diagnostics()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    jx, jy = steps * fx, steps * fy
+    print(f"  mass {d['mass']}, momentum ({d['mom_x']}, {d['mom_y']}), max |J| {d['max_abs_j']}")
+    assert d["nonfinite"] == 0
+    assert d["mass"] == 0.0
+    assert d["mom_x"] == n * jx and d["mom_y"] == n * jy
+    assert abs(d["max_abs_j"] - math.hypot(jx, jy)) <= 1e-15
+    assert abs(d["kin_energy"] / (0.5 * n * (jx * jx + jy * jy)) - 1) < 1e-12
