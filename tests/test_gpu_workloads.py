@@ -308,3 +308,38 @@ def test_conservation_8192_2000_steps(F, dtype, bound):
           + ", ".join(f"{x:.2e}" for x in drift))
     assert d1["nonfinite"] == 0
     assert max(drift) < bound
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+@pytest.mark.parametrize("dtype,amp,tol", [("f64", 1e-6, 1.5e-3), ("f32", 1e-4, 3e-3)])
+@pytest.mark.parametrize("direction", [(1, 0), (1, 1)])
+def test_galilean_damping_in_a_mean_flow(F, scheme, dtype, amp, tol, direction):
+    """Sections 1-a and 2: a transverse wave carried by a uniform flow V parallel to its wave
+    vector is damped with nu (1 - 3 V^2) by D2Q9 MRT and by FD-LBM alike (the theta terms
+    give FD-LBM the lattice Boltzmann behaviour, where LW-ACM has nu - V^2/2).  Along an axis
+    the factor comes from the velocity-cubic terms of theta_XY, along a diagonal from those of
+    theta_XX.  The rate is read from the wave's Fourier amplitude in the device state at two
+    times."""
+    nu = 0.05
+    s_xx = O.rate_from_viscosity(nu)
+    nx, ny, t1, t2 = (128, 8, 200, 1200) if direction == (1, 0) else (48, 48, 100, 500)
+    k = 2 * math.pi * math.hypot(direction[0] / nx, direction[1] / ny)
+    t = np.array([-direction[1], direction[0]]) / math.hypot(*direction)
+    kw = dict(scheme="mrt", quartic=True) if scheme == "mrt" else dict(scheme="fd", stencil=int(scheme[2]))
+    rates = {}
+    for V in (0.0, 0.1, 0.2):
+        init = W.shear_wave(nx, ny, amp, direction[0], direction[1], V=V)
+        sim = F.FdLbm(nx, ny, dtype=dtype, s_xx=s_xx, s_e=1.0, **kw)
+        sim.set_state(*init)
+        sim.step(t1)
+        m1 = sim.get_state()
+        sim.step(t2 - t1)
+        m2 = sim.get_state()
+        sim.close()
+        a1 = abs(fourier(t[0] * m1[1] + t[1] * m1[2], *direction))
+        a2 = abs(fourier(t[0] * m2[1] + t[1] * m2[2], *direction))
+        rates[V] = math.log(a1 / a2) / (t2 - t1) / k ** 2
+    for V in (0.1, 0.2):
+        print(f"  {scheme} {dtype} {direction} V={V}: nu_eff/nu {rates[V] / rates[0.0]:.5f} "
+              f"(1 - 3 V^2 = {1 - 3 * V * V:.5f})")
+        assert abs(rates[V] / rates[0.0] - (1 - 3 * V * V)) < tol
