@@ -40,7 +40,7 @@ def kernel_source_sha():
 
 def bytes_per_node(scheme, dtype):
     words = 9 if scheme == "mrt" else 3
-    return 2 * words * {"f64": 8, "f32": 4, "f16": 2}[dtype]
+    return 2 * words * {"f64": 8, "f32": 4, "f16": 2, "f16sr": 2}[dtype]
 
 
 def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with_diag, tile_rows=0, lane_cols=0,
@@ -261,8 +261,8 @@ def main():
     compare = {}
     if not args.no_compare:
         short = max(100, args.steps // 4)
-        for scheme, dtype, stencil in (("mrt", "f32", 0), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5),
-                                       ("mrt", "f64", 0), ("lwacm", "f32", 0)):
+        for scheme, dtype, stencil in (("mrt", "f32", 0), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f16sr", 3),
+                                       ("fd", "f32", 5), ("mrt", "f64", 0), ("lwacm", "f32", 0)):
             key = f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"
             compare[key] = run_case(F, torch, init, scheme, dtype, stencil, short, 10, args.kernel, False,
                                     autotune=not args.no_autotune)
@@ -304,7 +304,8 @@ def main():
         import oracle as O
 
         threads = min(os.cpu_count() or 1, 16)
-        cases = [("fd", "f32", 3), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f32", 5), ("mrt", "f32", 0),
+        cases = [("fd", "f32", 3), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f16sr", 3), ("fd", "f32", 5),
+                 ("mrt", "f32", 0),
                  ("mrt", "f64", 0), ("lwacm", "f32", 0)]
         errors, (updates, secs, band_rows) = band_errors(F, O, init, n, args.err_steps, args.err_rows, cases, threads,
                                               args.cpu_rows)

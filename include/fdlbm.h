@@ -48,8 +48,13 @@ enum { FDLBM_SCHEME_FD = 0, FDLBM_SCHEME_MRT = 1, FDLBM_SCHEME_LWACM = 2 };
 enum { FDLBM_BC_PERIODIC = 0, FDLBM_BC_WALLS_Y = 1, FDLBM_BC_DISK = 2 };
 /* Storage dtype of the state.  F64: FP64 storage and arithmetic.  F32: FP32 storage and
  * arithmetic.  F16DEV: FP16 storage of the deviations (drho, jx, jy), FP32 arithmetic
- * (FD-LBM only).  Diagnostics are always reduced in FP64. */
-enum { FDLBM_F64 = 0, FDLBM_F32 = 1, FDLBM_F16DEV = 2 };
+ * (FD-LBM and LW-ACM only), new values rounded to nearest.  F16DEV_SR: the same storage,
+ * with each step's new values rounded stochastically (up or down to the neighbouring FP16
+ * values with probabilities given by the distances, so increments smaller than half an FP16
+ * unit are kept on average); the random bits come from a counter-based hash of the node and
+ * the step count, so a run is reproducible and the sweep and reference kernels agree bit for
+ * bit; single grids only.  Diagnostics are always reduced in FP64. */
+enum { FDLBM_F64 = 0, FDLBM_F32 = 1, FDLBM_F16DEV = 2, FDLBM_F16DEV_SR = 3 };
 /* Kernel selection.  AUTO picks the vectorised sweep kernels (FD-LBM: one fused pass per
  * step; MRT: lane groups with DPP column shifts).  REFERENCE: the plain kernels (FD-LBM:
  * post-collision planes then gather; MRT: one thread per node).  SWEEP: FD-LBM sweep

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libfdlbm.so")
 FDLBM_OK, FDLBM_EINVAL, FDLBM_ENOMEM, FDLBM_EDEVICE, FDLBM_EUNSTABLE = 0, -1, -2, -3, -4
 SCHEME = {"fd": 0, "mrt": 1, "lwacm": 2}
 BC = {"periodic": 0, "walls": 1, "disk": 2}
-DTYPE = {"f64": 0, "f32": 1, "f16": 2}
+DTYPE = {"f64": 0, "f32": 1, "f16": 2, "f16sr": 3}
 KERNEL = {"auto": 0, "reference": 1, "sweep": 2}
 
 EXPORTED = (
@@ -271,7 +271,8 @@ class FdLbm:
     """One simulation: owns its torch device buffers and its library context.
 
     Keyword arguments follow ``fdlbm_params`` (see include/fdlbm.h); ``dtype`` is one of
-    "f64", "f32", "f16" (FP16-stored deviations, FP32 arithmetic), ``bc`` "periodic",
+    "f64", "f32", "f16" (FP16-stored deviations, FP32 arithmetic), "f16sr" (the same, new
+    values rounded stochastically), ``bc`` "periodic",
     "walls" or "disk" (with ``disk=(cx, cy, R)``), ``scheme`` "fd", "mrt" or "lwacm",
     ``kernel`` "auto", "reference" or "sweep".
     """

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 
+#include "fdlbm_device.hpp"
 #include "internal.hpp"
 
 using namespace fdlbm;
@@ -89,7 +90,7 @@ int validate(const fdlbm_params *p)
             DiskTable t;
             if (!disk_table(*p, &t)) return FDLBM_EINVAL;
         }
-        if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32 && p->dtype != FDLBM_F16DEV) return FDLBM_EINVAL;
+        if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32 && !is_f16(p->dtype)) return FDLBM_EINVAL;
         if (p->lane_cols != 0 && p->lane_cols != 1 && p->lane_cols != 2 && p->lane_cols != 4) return FDLBM_EINVAL;
         if (p->kernel == FDLBM_KERNEL_SWEEP && !fd_sweep_supported(fd_args(*p), p->lane_cols)) return FDLBM_EINVAL;
     } else {
@@ -323,10 +324,12 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
     HIPCHK(hipSetDevice(c->device), "hipSetDevice");
     const bool fd = three_words(c->p.scheme);
     const bool ref = uses_reference(c->p);
-    const FdArgs fa = fd_args(c->p);
+    FdArgs fa = fd_args(c->p);
     const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
                      c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, c->p.tile_rows, wall_xi(c->p)};
     for (int64_t s = 0; s < nsteps; ++s) {
+        // stochastic rounding draws fresh bits every step, reproducibly from the step count
+        fa.seed = pcg_hash(uint32_t(c->steps));
         void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
         // the curved wall: ghost and rest nodes from the fluid, in place, before the step;
         // every rest node after the state was set or under a body force (which moves the

@@ -117,7 +117,7 @@ template <typename T, bool WALLS, bool FORCE>
 __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::C *__restrict__ fstar,
                                                      const T *__restrict__ in, FdCoef<typename Storage<T>::C> k,
                                                      int nx, int ny, int row0, int nrows, T *__restrict__ odr,
-                                                     T *__restrict__ ojx, T *__restrict__ ojy)
+                                                     T *__restrict__ ojx, T *__restrict__ ojy, uint32_t seed)
 {
     using C = typename Storage<T>::C;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,9 +143,12 @@ __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::
     C r, x, y;
     fd_finish<C, FORCE>(fd_partial<C>(pc, pcx, pu, pux), pd, pdx, Storage<T>::load(in[p]), Storage<T>::load(in[n + p]),
                  Storage<T>::load(in[2 * n + p]), k.dfx, k.dfy, r, x, y);
-    odr[p] = Storage<T>::store(r);
-    ojx[p] = Storage<T>::store(x);
-    ojy[p] = Storage<T>::store(y);
+    // rounded for storage (stochastically for HalfSR: the same bits as the sweep kernel)
+    uint32_t rb[3] = {0u, 0u, 0u};
+    if constexpr (Storage<T>::STOCHASTIC) sr_draw(uint32_t(p), seed, rb);
+    odr[p] = Storage<T>::store_r(r, rb[0]);
+    ojx[p] = Storage<T>::store_r(x, rb[1]);
+    ojy[p] = Storage<T>::store_r(y, rb[2]);
 }
 
 template <typename T> FdCoef<typename Storage<T>::C> make_coef(const FdArgs &a)
@@ -182,7 +185,7 @@ hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStre
     if (e != hipSuccess) return e;
     dim3 g2((a.nx + 63) / 64, (a.ny + 3) / 4);
     hipLaunchKernelGGL((fd_ref_gather<T, WALLS, FORCE>), g2, blk, 0, s, static_cast<const C *>(fstar), in, k, a.nx, a.ny,
-                       row0, nrows, out, out + n, out + 2 * n);
+                       row0, nrows, out, out + n, out + 2 * n, a.seed);
     return hipGetLastError();
 }
 
@@ -216,6 +219,7 @@ hipError_t launch_fd_reference(const FdArgs &a, const void *src, void *dst, void
     switch (a.dtype) {
     case FDLBM_F64: return dispatch_stencil<double>(a, src, dst, fstar, s);
     case FDLBM_F32: return dispatch_stencil<float>(a, src, dst, fstar, s);
+    case FDLBM_F16DEV_SR: return dispatch_stencil<HalfSR>(a, src, dst, fstar, s);
     default: return dispatch_stencil<__half>(a, src, dst, fstar, s);
     }
 }

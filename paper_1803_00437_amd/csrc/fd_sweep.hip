@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 int default_rows(const FdArgs &a)
 {
     if (a.dtype == FDLBM_F64) return 8;
-    if (a.dtype == FDLBM_F16DEV) return 16;
+    if (is_f16(a.dtype)) return 16;
     return a.stencil == 5 ? 16 : 8;
 }
 
@@ -82,6 +82,7 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
     a.t.rows = tile_rows >= 2 ? tile_rows : default_rows(fa);
     a.t.k = make_coef<C>(ST, fa.s_xx, fa.s_e, fa.fx, fa.fy);
     a.t.gr = ghost_rules<C>(fa.xi);
+    a.t.seed = fa.seed;
     a.strips_x = (fa.nx + G::S - 1) / G::S;
     const int nbands = (fa.ny + WV * a.t.rows - 1) / (WV * a.t.rows);
     hipLaunchKernelGGL((fd_sweep_kernel<T, CPL, ST, WALLS, FORCE, AM>), a.strips_x * nbands, 64 * WV, 0, s, a);
@@ -131,7 +132,7 @@ int choose_cpl(const FdArgs &a, int lane_cols)
 {
     if (lane_cols > 0) return lane_cols;
     if (a.dtype == FDLBM_F64) return 2;
-    if (a.dtype == FDLBM_F16DEV && a.nx % 4 == 2) return 2;
+    if (is_f16(a.dtype) && a.nx % 4 == 2) return 2;
     return 4;
 }
 
@@ -166,6 +167,7 @@ hipError_t launch_fd_sweep(const FdArgs &a, int tile_rows, int lane_cols, const 
     switch (a.dtype) {
     case FDLBM_F64: return dispatch<double>(a, tile_rows, lane_cols, src, dst, s);
     case FDLBM_F32: return dispatch<float>(a, tile_rows, lane_cols, src, dst, s);
+    case FDLBM_F16DEV_SR: return dispatch<HalfSR>(a, tile_rows, lane_cols, src, dst, s);
     default: return dispatch<__half>(a, tile_rows, lane_cols, src, dst, s);
     }
 }

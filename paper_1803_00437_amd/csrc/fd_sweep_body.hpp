@@ -230,6 +230,7 @@ template <typename T> struct TileArgs {
     int nx, ny, rows;
     FdCoef<typename Storage<T>::C> k;
     GhostRules<typename Storage<T>::C> gr;  // walls only
+    uint32_t seed = 0;                      // stochastic rounding: pcg_hash of the step count
 };
 
 // Each wavefront of a block sweeps its rows in one direction: even wavefronts downward,
@@ -253,8 +254,8 @@ enum {
 // above) whatever the direction.
 template <int DIR, typename T, int CPL, int ST, bool WALLS, bool FORCE, int AM>
 __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storage<T>::C (&lds)[WV][NSLOT][CPL][64],
-                                           int wv, int lane, const LaneCols<CPL, AM> &lc, int ybeg, int yend,
-                                           bool empty, bool bottom, bool top)
+                                           int wv, int lane, const LaneCols<CPL, AM> &lc, int xl, int ybeg,
+                                           int yend, bool empty, bool bottom, bool top)
 {
     using C = typename Storage<T>::C;
     using S = Stencil<ST>;
@@ -266,6 +267,16 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     constexpr int PD = prefetch_rows<T, CPL>();
     constexpr int U = (NW + PD + 1) & ~1;  // window slots: those rows and the ones in flight, even
     const int nx = a.nx, ny = a.ny;
+    // the three new values of column c of row `row`, rounded for storage (stochastically
+    // for HalfSR, with the random bits of that node and step)
+    auto round_out = [&](int row, int c, C nr, C nxv, C nyv, T &gr_, T &gx_, T &gy_) {
+        uint32_t rb_[3] = {0u, 0u, 0u};
+        if constexpr (Storage<T>::STOCHASTIC)
+            sr_draw(uint32_t(row) * uint32_t(nx) + uint32_t(xl + c), a.seed, rb_);
+        gr_ = Storage<T>::store_r(nr, rb_[0]);
+        gx_ = Storage<T>::store_r(nxv, rb_[1]);
+        gy_ = Storage<T>::store_r(nyv, rb_[2]);
+    };
 
     const int rb = bottom ? ybeg - 1 : ybeg;  // f* rows rb .. re (the band's outer
     const int re = top ? yend : yend - 1;     // wavefronts also take the row beyond)
@@ -488,9 +499,7 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
                 else
                     fd_finish<C, FORCE>(fd_partial<C>(PC[c], PCX[c], pB, pBx), PF[c], PFX[c], w[0][os][c],
                                         w[1][os][c], w[2][os][c], a.k.dfx, a.k.dfy, nr, nxv, nyv);
-                gr.v[c] = Storage<T>::store(nr);
-                gx.v[c] = Storage<T>::store(nxv);
-                gy.v[c] = Storage<T>::store(nyv);
+                round_out(min(max(first + DIR * (it - 1), 0), ny - 1), c, nr, nxv, nyv, gr.v[c], gx.v[c], gy.v[c]);
                 if constexpr (DIR > 0) {
                     QP[c] = fd_partial<C>(pc, pcx, pF, pFx);
                 } else {
@@ -550,9 +559,7 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             else
                 fd_finish<C, FORCE>(fd_partial<C>(pc, pcx, p2, p2x), pF, pFx, odr, ojx, ojy, a.k.dfx, a.k.dfy, nr,
                                     nxv, nyv);
-            gr.v[c] = Storage<T>::store(nr);
-            gx.v[c] = Storage<T>::store(nxv);
-            gy.v[c] = Storage<T>::store(nyv);
+            round_out(first, c, nr, nxv, nyv, gr.v[c], gx.v[c], gy.v[c]);
         }
         row_store<T, CPL, AM>(row_rsrc(a.odr, first, nx), lc, true, gr);
         row_store<T, CPL, AM>(row_rsrc(a.ojx, first, nx), lc, true, gx);
@@ -574,9 +581,7 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
                 fd_finish<C, FORCE>(fd_partial<C>(PC[c], PCX[c], pB, pBx), PF[c], PFX[c], Storage<T>::load(o1r.v[c]),
                                     Storage<T>::load(o1x.v[c]), Storage<T>::load(o1y.v[c]), a.k.dfx, a.k.dfy, nr,
                                     nxv, nyv);
-            gr.v[c] = Storage<T>::store(nr);
-            gx.v[c] = Storage<T>::store(nxv);
-            gy.v[c] = Storage<T>::store(nyv);
+            round_out(last, c, nr, nxv, nyv, gr.v[c], gx.v[c], gy.v[c]);
         }
         row_store<T, CPL, AM>(row_rsrc(a.odr, last, nx), lc, true, gr);
         row_store<T, CPL, AM>(row_rsrc(a.ojx, last, nx), lc, true, gx);
@@ -613,9 +618,9 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     const bool bottom = wv == 0;  // computes f* of row ybeg - 1 itself
     const bool top = yend == b1;  // computes f* of row yend itself
     if (wv & 1)
-        sweep_wave<1, T, CPL, ST, WALLS, FORCE, AM>(a, lds, wv, lane, lc, ybeg, yend, empty, bottom, top);
+        sweep_wave<1, T, CPL, ST, WALLS, FORCE, AM>(a, lds, wv, lane, lc, xl, ybeg, yend, empty, bottom, top);
     else
-        sweep_wave<-1, T, CPL, ST, WALLS, FORCE, AM>(a, lds, wv, lane, lc, ybeg, yend, empty, bottom, top);
+        sweep_wave<-1, T, CPL, ST, WALLS, FORCE, AM>(a, lds, wv, lane, lc, xl, ybeg, yend, empty, bottom, top);
 }
 
 

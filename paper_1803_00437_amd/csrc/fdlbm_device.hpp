@@ -18,21 +18,75 @@ namespace fdlbm {
 
 // ------------------------------------------------------------------ storage types ----
 template <typename T> struct Storage;
+// store() rounds to nearest; store_r(v, r) is the rounding a step uses for its new state,
+// given 13 random bits r (used only where STOCHASTIC).
 template <> struct Storage<double> {
     using C = double;  // arithmetic type
+    static constexpr bool STOCHASTIC = false;
     static __device__ __forceinline__ double load(double v) { return v; }
     static __device__ __forceinline__ double store(double v) { return v; }
+    static __device__ __forceinline__ double store_r(double v, uint32_t) { return v; }
 };
 template <> struct Storage<float> {
     using C = float;
+    static constexpr bool STOCHASTIC = false;
     static __device__ __forceinline__ float load(float v) { return v; }
     static __device__ __forceinline__ float store(float v) { return v; }
+    static __device__ __forceinline__ float store_r(float v, uint32_t) { return v; }
 };
 template <> struct Storage<__half> {
     using C = float;
+    static constexpr bool STOCHASTIC = false;
     static __device__ __forceinline__ float load(__half v) { return __half2float(v); }
     static __device__ __forceinline__ __half store(float v) { return __float2half_rn(v); }
+    static __device__ __forceinline__ __half store_r(float v, uint32_t) { return __float2half_rn(v); }
 };
+
+// FP16 deviations whose new values are rounded stochastically: up or down to the two
+// neighbouring FP16 values with probabilities proportional to the distance to the other one,
+// so the rounding is unbiased and an increment smaller than half a unit of the stored value
+// is kept on average instead of being lost every step.  For a value in the FP16 normal range
+// one FP16 unit spans 2^13 units of its FP32 pattern; adding r - 2^12 (r uniform in
+// [0, 2^13)) to that pattern and rounding to nearest gives floor((m + r) / 2^13) for the
+// magnitude bits m, which rounds up with probability (m mod 2^13) / 2^13.  Below the FP16
+// normal range only the lowest 13 of the dropped bits are randomised.  Loads, set_state and
+// the boundary fills round to nearest.
+struct HalfSR {
+    __half h;
+};
+template <> struct Storage<HalfSR> {
+    using C = float;
+    static constexpr bool STOCHASTIC = true;
+    static __device__ __forceinline__ float load(HalfSR v) { return __half2float(v.h); }
+    static __device__ __forceinline__ HalfSR store(float v) { return HalfSR{__float2half_rn(v)}; }
+    static __device__ __forceinline__ HalfSR store_r(float v, uint32_t r)
+    {
+        uint32_t b = __builtin_bit_cast(uint32_t, v);
+        // sign and magnitude: the addition moves |v| (patterns this small are zero in FP16)
+        if ((b & 0x7fffffffu) >= 0x1000u) b = b + r - 0x1000u;
+        return HalfSR{__float2half_rn(__builtin_bit_cast(float, b))};
+    }
+};
+
+// The PCG hash of Jarzynski and Olano ("Hash functions for GPU rendering", JCGT 9(3),
+// 2020): one round of a PCG generator with an output permutation, as a 32-bit to 32-bit
+// map.  The random bits of stochastic rounding are counter-based: node index and step.
+__host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t x)
+{
+    const uint32_t state = x * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+// 13 random bits for each of drho, jx, jy of node `node` (linear index j*nx + i, modulo
+// 2^32) at the step whose seed is `seed` (pcg_hash of the step count).
+__device__ __forceinline__ void sr_draw(uint32_t node, uint32_t seed, uint32_t (&r)[3])
+{
+    const uint32_t h0 = pcg_hash(node ^ seed);
+    const uint32_t h1 = pcg_hash(h0);
+    r[0] = h0 & 0x1fffu;
+    r[1] = (h0 >> 16) & 0x1fffu;
+    r[2] = h1 & 0x1fffu;
+}
 
 __device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }

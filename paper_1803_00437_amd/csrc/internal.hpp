@@ -16,6 +16,8 @@ namespace fdlbm {
 inline size_t dtype_bytes(int dtype) { return dtype == FDLBM_F64 ? 8 : dtype == FDLBM_F32 ? 4 : 2; }
 // Bytes of one arithmetic value (FP16 storage computes in FP32).
 inline size_t compute_bytes(int dtype) { return dtype == FDLBM_F64 ? 8 : 4; }
+// FP16 deviations, rounded to nearest or stochastically (the same layout)
+inline bool is_f16(int dtype) { return dtype == FDLBM_F16DEV || dtype == FDLBM_F16DEV_SR; }
 
 // Geometry and coefficients of one FD-LBM step, as the kernels need them.
 // FD-LBM step arguments; the LW-ACM step (section 1-b) runs on the same kernels with
@@ -25,6 +27,7 @@ struct FdArgs {
     int nx, ny, stencil, walls, dtype;
     double s_xx, s_e, fx, fy;
     double xi;  // walls: their distance beyond the first and last rows (0 < xi <= 1)
+    uint32_t seed = 0;  // FDLBM_F16DEV_SR: pcg_hash of the step count (random bits of the rounding)
 };
 
 struct MrtArgs {

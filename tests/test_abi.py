@@ -55,6 +55,7 @@ def test_workspace_bytes():
 @pytest.mark.parametrize("bad", [
     dict(nx=4), dict(ny=2), dict(ny=6), dict(stencil=9), dict(stencil=4), dict(s_xx=2.0), dict(s_xx=0.0),
     dict(s_e=-1.0), dict(s_xx=float("nan")), dict(scheme="mrt", dtype="f16", s_q=1.0),
+    dict(scheme="mrt", dtype="f16sr", s_q=1.0),
     dict(scheme="mrt", s_q=2.5), dict(scheme="mrt", s_eps=0.0), dict(force=(float("inf"), 0.0)),
 ])
 def test_invalid_parameters_are_rejected(bad):
@@ -200,3 +201,19 @@ def test_disk_accepts_every_fd_variant():
                dict(force=(1e-6, 0.0)), dict(kernel="reference"), dict(kernel="sweep", lane_cols=2),
                dict(disk=(35.5, 35.5, 1.6)), dict(disk=(31.9, 31.9, 29.9))):
         F.fdlbm_workspace_bytes(disk(**kw))
+
+
+def test_stochastic_rounding_storage_is_for_single_fd_grids():
+    """FDLBM_F16DEV_SR: FD-LBM and LW-ACM single grids (any stencil, walls, disk); the batch
+    and MRT reject it."""
+    for kw in (dict(), dict(stencil=5), dict(scheme="lwacm"), dict(bc="walls"),
+               dict(nx=72, ny=72, bc="disk", disk=(35.5, 35.5, 29.9))):
+        sb, _ = F.fdlbm_workspace_bytes(good(dtype="f16sr", **kw))
+        assert sb == F.fdlbm_workspace_bytes(good(dtype="f16", **kw))[0]
+    lib = F.load_library()
+    inst = (F.Instance * 1)(F.Instance(64, 64, 1.5, 1.0))
+    sb, cb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fdlbm_batch_workspace_bytes(inst, 1, F.DTYPE["f16sr"], 4, ctypes.byref(sb),
+                                           ctypes.byref(cb)) == F.FDLBM_EINVAL
+    assert lib.fdlbm_batch_workspace_bytes(inst, 1, F.DTYPE["f16"], 4, ctypes.byref(sb),
+                                           ctypes.byref(cb)) == F.FDLBM_OK
