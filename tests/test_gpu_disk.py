@@ -65,7 +65,7 @@ def run(F, geom, init, steps, **kw):
 
 
 @pytest.mark.parametrize("geom", list(GEOMS))
-@pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "f16sr"])
 @pytest.mark.parametrize("scheme,stencil,forced", [("fd", 3, False), ("fd", 5, False), ("fd", 3, True),
                                                    ("fd", 5, True), ("lwacm", 3, False)])
 def test_disk_sweep_equals_reference_bitwise(F, geom, dtype, scheme, stencil, forced):
