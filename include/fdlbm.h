@@ -66,7 +66,7 @@ typedef struct fdlbm_params {
     int32_t scheme;     /* FDLBM_SCHEME_FD, FDLBM_SCHEME_MRT or FDLBM_SCHEME_LWACM          */
     int32_t stencil;    /* FD-LBM finite differences of section 2: 3 or 5 points           */
     int32_t bc;         /* FDLBM_BC_PERIODIC or FDLBM_BC_WALLS_Y                            */
-    int32_t dtype;      /* FDLBM_F64, FDLBM_F32, FDLBM_F16DEV                               */
+    int32_t dtype;      /* FDLBM_F64, FDLBM_F32, FDLBM_F16DEV, FDLBM_F16DEV_SR               */
     /* Relaxation rates, each in (0, 2).  Section 1-a: nu = (1/s_xx - 1/2)/3,
      * zeta = (1/s_e - 1/2)/3.  FD-LBM uses s_xx and s_e (its q and eps moments sit at
      * equilibrium, section 2); MRT uses all four.                                            */
@@ -221,7 +221,7 @@ typedef struct fdlbm_batch fdlbm_batch;
 int fdlbm_batch_workspace_bytes(const fdlbm_instance *instances, int32_t count, int32_t dtype, int32_t max_samples,
                                 size_t *state_bytes, size_t *scratch_bytes);
 
-/* Lay out `count` instances (dtype FDLBM_F64 / F32 / F16DEV) in the caller's buffers
+/* Lay out `count` instances (dtype FDLBM_F64 / F32 / F16DEV; not F16DEV_SR) in the caller's buffers
  * (256-byte aligned), upload the tile tables and bind the HIP stream.  All states are
  * zero until set.  A stream other than the default one is needed for graph replay. */
 int fdlbm_batch_create(const fdlbm_instance *instances, int32_t count, int32_t dtype, int32_t max_samples,
