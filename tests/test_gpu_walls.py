@@ -110,3 +110,32 @@ def test_channel_wall_location_fig6(F, scheme):
         print(f"  {scheme} xi={xi}: measured {zeros[0]:.4f} (oracle {zeros[1]:.4f})")
         assert abs(zeros[0] - zeros[1]) < 1e-9
         assert abs(zeros[0] - xi) < 0.06
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+@pytest.mark.parametrize("xi", [0.5, 0.2, 1.0])
+def test_narrowest_channel(F, scheme, xi):
+    """The smallest channel the ABI accepts, 4 rows between the walls (every fluid row is then
+    within reach of a wall and the ghost rows of both walls meet): FD-LBM sweep equals the
+    reference kernel bit for bit, and FP64 and FP32 match the oracle after 50 steps."""
+    nx, ny, steps, fx = 40, 4, 50, 1e-5
+    print(f"case narrowest channel {scheme} xi={xi}", flush=True)
+    init = W.random_state(nx, ny, seed=9, amp=0.02)
+    if scheme == "mrt":
+        want = O.mrt_moments(O.mrt_run(O.mrt_init(*init), steps, s_xx=1.6, s_q=O.quartic_s_q(1.6), walls=True, xi=xi,
+                                       fx=fx))
+        for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+            got = run(F, init, steps, scheme="mrt", dtype=dtype, s_xx=1.6, quartic=True, wall_xi=xi, force=(fx, 0.0))
+            assert rel_l2(got, want) <= tol, (dtype, rel_l2(got, want))
+        return
+    st = int(scheme[2])
+    kw = dict(scheme="fd", stencil=st, s_xx=1.6, s_e=1.0, wall_xi=xi, force=(fx, 0.0))
+    want = O.fd_run(*init, steps, s_xx=1.6, s_e=1.0, stencil=st, walls=True, xi=xi, fx=fx)
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        a = run(F, init, steps, kernel="reference", dtype=dtype, **kw)
+        b = run(F, init, steps, kernel="sweep", dtype=dtype, **kw)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+        err = rel_l2(b, want)
+        print(f"  {scheme} {dtype} xi={xi}: rel L2 {err:.2e}")
+        assert err <= tol
