@@ -171,6 +171,8 @@ KERNELS = [
      f"{DECAY}; FD-LBM 3-point, FP64"),
     ("fd3_f16_8192", "fd_sweep_kernel<__half, 4, 3, false, false, 0>", 12 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP16 storage, FP32 arithmetic"),
+    ("fd3_f16sr_8192", "fd_sweep_kernel<fdlbm::HalfSR, 4, 3, false, false, 0>", 12 * N * N, None, FD_SOURCES,
+     f"{DECAY}; FD-LBM 3-point, FP16 storage rounded stochastically, FP32 arithmetic"),
     ("fd5_f32_8192", "fd_sweep_kernel<float, 4, 5, false, false, 0>", 24 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 5-point, FP32"),
     ("lwacm_f32_8192", "fd_sweep_kernel<float, 4, 1, false, false, 0>", 24 * N * N, None, FD_SOURCES,
