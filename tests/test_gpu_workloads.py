@@ -343,3 +343,44 @@ def test_galilean_damping_in_a_mean_flow(F, scheme, dtype, amp, tol, direction):
         print(f"  {scheme} {dtype} {direction} V={V}: nu_eff/nu {rates[V] / rates[0.0]:.5f} "
               f"(1 - 3 V^2 = {1 - 3 * V * V:.5f})")
         assert abs(rates[V] / rates[0.0] - (1 - 3 * V * V)) < tol
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+def test_table1_hyperviscosity_from_simulation(F, stencil):
+    """Section 3-a, Table 1: the hyperviscosity nu_2 at s_xx = 1.85, measured as the paper did,
+    from simulations: transverse waves along {1,0}, {2,1} and {1,1} at five small wave numbers
+    each (FP64, device projection between two times), nu(k) - nu_0 fitted by
+    nu_2 k^2 + nu_4 k^4.  The fits match the printed entries to 1 % (three points) and 5 %
+    (five points, whose nu_2 is 36 times smaller); measured, they agree to the printed
+    digits except at {2,1}, which lies at 26.565 degrees, the printed row at 26.6."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_hyperviscosity.json")))
+    s_xx = g["s_xx"]
+    nu0 = (1.0 / s_xx - 0.5) / 3.0
+    cases = (((1, 0), 128), ((2, 1), 256), ((1, 1), 181))
+    for (d, n), printed in zip(cases, g["nu2"][str(stencil)]):
+        ks, ys = [], []
+        for m in (2, 3, 4, 5, 6):
+            mx, my = m * d[0], m * d[1]
+            kx, ky = 2 * math.pi * mx / n, 2 * math.pi * my / n
+            k2 = kx * kx + ky * ky
+            t1 = int(round(0.2 / (nu0 * k2)))
+            t2 = t1 + int(round(1.0 / (nu0 * k2)))
+            r, jx, jy = W.shear_wave(n, n, 1e-6, mx, my)
+            sim = F.FdLbm(n, n, dtype="f64", stencil=stencil, s_xx=s_xx)
+            sim.set_state(r, jx, jy)
+            sim.set_mode(jx, jy)
+            sim.step(t1)
+            a1 = sim.mode_projection()
+            sim.step(t2 - t1)
+            a2 = sim.mode_projection()
+            sim.close()
+            ks.append(math.sqrt(k2))
+            ys.append(-math.log(a2 / a1) / (t2 - t1) / k2 - nu0)
+        ks = np.array(ks)
+        nu2 = np.linalg.lstsq(np.stack([ks ** 2, ks ** 4], 1), np.array(ys), rcond=None)[0][0]
+        print(f"  FD{stencil} {d}: nu_2 from simulation {nu2:.5f}, Table 1 {printed:.5f}")
+        tol = 0.01 * abs(printed) + 3e-5 if stencil == 3 else 0.05 * abs(printed)
+        assert abs(nu2 - printed) < tol
