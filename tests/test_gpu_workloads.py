@@ -384,3 +384,48 @@ def test_table1_hyperviscosity_from_simulation(F, stencil):
         print(f"  FD{stencil} {d}: nu_2 from simulation {nu2:.5f}, Table 1 {printed:.5f}")
         tol = 0.01 * abs(printed) + 3e-5 if stencil == 3 else 0.05 * abs(printed)
         assert abs(nu2 - printed) < tol
+
+
+@pytest.mark.parametrize("scheme", ["fd3", "fd5", "mrt"])
+@pytest.mark.parametrize("s_e", [1.0, 1.5])
+def test_sound_speed_and_damping(F, scheme, s_e):
+    """Sections 1-a and 2: a sound wave travels at c_s = 1/sqrt(3) and is damped at
+    Gamma_s = (nu + zeta) k^2 / 2, zeta = (1/s_e - 1/2)/3 the bulk viscosity, in MRT and in
+    FD-LBM alike.  A right-moving wave (drho = a cos kx, Jx = c_s drho) on a 128^2 grid, FP64,
+    is followed through the phase and modulus of the Fourier coefficient of the device state;
+    both equal the acoustic root of the amplification matrix (to 1e-5 and 1e-3) and the closed
+    forms (to 5e-4 and 1.5 %), so the step uses s_e where the theory puts it."""
+    from oracle import symbol as S
+
+    n, m, amp, s_xx = 128, 2, 1e-6, 1.8
+    k = 2 * math.pi * m / n
+    nu, zeta, cs = (1 / s_xx - 0.5) / 3, (1 / s_e - 0.5) / 3, 1 / math.sqrt(3)
+    x = np.arange(n)
+    r = np.tile(amp * np.cos(k * x), (n, 1))
+    init = (r, cs * r, np.zeros((n, n)))
+    kw = dict(scheme="mrt", quartic=True) if scheme == "mrt" else dict(scheme="fd", stencil=int(scheme[2]))
+    sim = F.FdLbm(n, n, dtype="f64", s_xx=s_xx, s_e=s_e, **kw)
+    sim.set_state(*init)
+    e = np.exp(-1j * k * x)
+    ts, cs_t = [], []
+    for t in range(0, 1001, 10):
+        if t >= 100:
+            ts.append(t)
+            cs_t.append(np.sum(sim.get_state()[0] * e[None, :]))
+        sim.step(10)
+    sim.close()
+    ts, c = np.array(ts), np.array(cs_t)
+    omega = -np.polyfit(ts, np.unwrap(np.angle(c)), 1)[0]
+    gamma = -np.polyfit(ts, np.log(np.abs(c)), 1)[0]
+    sym_kw = dict(s_xx=s_xx, s_e=s_e)
+    if scheme == "mrt":
+        sym_kw["s_q"] = O.quartic_s_q(s_xx)
+    else:
+        sym_kw["stencil"] = int(scheme[2])
+    root = [z for z in S.sound_gammas(k, 0.0, "mrt" if scheme == "mrt" else "fd", **sym_kw) if z.imag > 0][0]
+    print(f"  {scheme} s_e={s_e}: c {omega / k:.6f} (root {root.imag / k:.6f}, 1/sqrt3 {cs:.6f}); "
+          f"Gamma/k^2 {gamma / k / k:.5f} (root {root.real / k / k:.5f}, (nu+zeta)/2 {(nu + zeta) / 2:.5f})")
+    assert abs(omega / k - root.imag / k) < 1e-5
+    assert abs(gamma / root.real - 1) < 1e-3
+    assert abs(omega / k / cs - 1) < 5e-4
+    assert abs(gamma / k / k / ((nu + zeta) / 2) - 1) < 0.015
