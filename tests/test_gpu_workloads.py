@@ -429,3 +429,45 @@ def test_sound_speed_and_damping(F, scheme, s_e):
     assert abs(gamma / root.real - 1) < 1e-3
     assert abs(omega / k / cs - 1) < 5e-4
     assert abs(gamma / k / k / ((nu + zeta) / 2) - 1) < 0.015
+
+
+def test_d2q9_relative_viscosity_fig5(F):
+    """Section 3-a, Fig. 5: nu(k)/nu_0 of the D2Q9 lattice Boltzmann model along {1,0}, {2,1},
+    {1,1}, whose largest error the caption puts at 8 %.  The curve is not printed, nor are the
+    model's rates and the k range; reading: nu_0 = 0.01 as in Figs. 2-4, k up to 1, and BGK
+    (all rates equal), whose largest error over that range is 8.6 % (along {1,0} at k = 1).
+    Measured on the device with the MRT kernel (FP64, 64^2 grids, two-time projection past the
+    initial layer), every point equals the shear root of the amplification matrix to 1e-4; the
+    largest error is 7-10 % for BGK and below 3 % for the quartic MRT."""
+    from oracle import symbol as S
+
+    nu0, n = 0.01, 64
+    s = O.rate_from_viscosity(nu0)
+    models = {"bgk": dict(s_xx=s, s_e=s, s_q=s, s_eps=s), "quartic": dict(s_xx=s, s_q=O.quartic_s_q(s))}
+    points = [((1, 0), m) for m in (2, 4, 6, 8, 10)] + [((2, 1), m) for m in (1, 2, 3, 4)] + \
+             [((1, 1), m) for m in (2, 4, 6, 7)]
+    worst = {}
+    for name, rates in models.items():
+        worst[name] = 0.0
+        for d, m in points:
+            mx, my = m * d[0], m * d[1]
+            kx, ky = 2 * math.pi * mx / n, 2 * math.pi * my / n
+            k2 = kx * kx + ky * ky
+            t1 = max(100, int(round(0.2 / (nu0 * k2))))
+            t2 = t1 + int(round(1.0 / (nu0 * k2)))
+            r, jx, jy = W.shear_wave(n, n, 1e-6, mx, my)
+            sim = F.FdLbm(n, n, scheme="mrt", dtype="f64", **rates)
+            sim.set_state(r, jx, jy)
+            sim.set_mode(jx, jy)
+            sim.step(t1)
+            a1 = sim.mode_projection()
+            sim.step(t2 - t1)
+            a2 = sim.mode_projection()
+            sim.close()
+            rel = -math.log(a2 / a1) / (t2 - t1) / k2 / nu0
+            want = S.nu_of_k(math.sqrt(k2), math.atan2(ky, kx), "mrt", **rates) / nu0
+            assert abs(rel / want - 1) < 1e-4, (name, d, m, rel, want)
+            worst[name] = max(worst[name], abs(rel - 1))
+        print(f"  D2Q9 {name}: largest |nu(k)/nu0 - 1| for k <= 1: {worst[name]:.4f}")
+    assert 0.07 < worst["bgk"] < 0.10
+    assert worst["quartic"] < 0.03
