@@ -3,7 +3,8 @@
 //
 // Mapping (designed for CDNA4's 64-wide wavefronts):
 //   * a block is WV wavefronts stacked in y over one strip of W = 64*CPL consecutive
-//     columns (CPL columns per lane, loaded and stored as one aligned vector per field);
+//     columns (CPL columns per lane, loaded and stored as one aligned vector per field
+//     where the grid width allows, else as element-aligned vectors or column by column);
 //     each wavefront sweeps its own R rows of the strip;
 //   * x-neighbours of a lane's outer columns come from the adjacent lanes through DPP
 //     whole-wave shifts (wave_shl:1 / wave_shr:1), so no LDS and no barrier is needed
@@ -11,8 +12,8 @@
 //     5-point differences); neighbouring strips overlap by whole halo lanes so that every
 //     access stays aligned;
 //   * y-neighbours live in a rolling window of 2h+1 input rows held in registers, with the
-//     next row prefetched; the row loop is unrolled by the window length so that the
-//     window rotates by renaming, not by register moves;
+//     next one or two rows in flight; the row loop is unrolled by the window length so
+//     that the window rotates by renaming, not by register moves;
 //   * the post-collision populations of a row are exchanged along x with the same DPP
 //     shifts and split into the parts landing on the row itself, the row above and the
 //     row below; the output row below the current one is then complete and is stored
@@ -30,8 +31,9 @@
 // in the order of fdlbm_device.hpp, so the result equals the reference path bit for bit.
 // A run without body force uses kernels built without the force additions.
 //
-// Walls (rows -1 .. -(h+1) and ny .. ny+h are ghosts): the mirror of the xi = 1/2
-// extrapolation of section 3-c is applied as a row is loaded (drho even, J odd).
+// Walls (rows -1 .. -(h+1) and ny .. ny+h are ghosts): each ghost row is formed as it is
+// loaded, by the rule of ghost_rules() for the wall distance xi (sections 3-b, 3-c: linear
+// extrapolation with zero velocity on the wall; at xi = 1/2 the mirror, drho even, J odd).
 #include "fd_sweep_body.hpp"
 #include "internal.hpp"
 

@@ -1,12 +1,14 @@
 // MRT D2Q9 stream-collide step (section 1, eqs. 1-2; equilibria and rates of the table
 // in section 1-a), the scheme the FD-LBM is compared against.
 //
-// Storage: nine planes of f_k - w_k (deviations from the rest populations).  One thread
-// per node: read its nine populations (coalesced), relax the non-conserved moments, and
-// push f*_k to x + e_k in the other buffer.  A population whose destination lies beyond a
-// wall returns to its own node with the opposite velocity (halfway bounce-back, which puts
-// the wall half-way between the last fluid row and the next one, section 3-c).
-// Algorithmic traffic: 9 values read + 9 written per node.
+// Storage: nine planes of f_k - w_k (deviations from the rest populations).  Two kernels:
+// one thread per node (mrt_kernel), and the vectorised sweep over lane groups of columns
+// (mrt_sweep_kernel, the default).  Each relaxes the non-conserved moments of a node and
+// pushes f*_k to x + e_k in the other buffer.  A population whose destination lies beyond
+// a wall returns with the opposite velocity: halfway bounce-back (the wall half-way
+// between the last fluid row and the next one, section 3-c) in both kernels, and the
+// interpolated bounce-back of Bouzidi et al. for a wall at another distance xi, in the
+// one-thread-per-node kernel.  Algorithmic traffic: 9 values read + 9 written per node.
 #include "fd_sweep_body.hpp"
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
