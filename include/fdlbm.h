@@ -43,7 +43,8 @@ extern "C" {
 
 /* FD: the FD-LBM step of section 2.  MRT: the D2Q9 MRT step of section 1.  LWACM: the
  * link-wise artificial-compressibility step of section 1-b that FD-LBM starts from
- * (periodic grids, no body force; same stored state as FD-LBM). */
+ * (periodic grids, or the disk of FDLBM_BC_DISK; no body force; same stored state as
+ * FD-LBM). */
 enum { FDLBM_SCHEME_FD = 0, FDLBM_SCHEME_MRT = 1, FDLBM_SCHEME_LWACM = 2 };
 enum { FDLBM_BC_PERIODIC = 0, FDLBM_BC_WALLS_Y = 1, FDLBM_BC_DISK = 2 };
 /* Storage dtype of the state.  F64: FP64 storage and arithmetic.  F32: FP32 storage and

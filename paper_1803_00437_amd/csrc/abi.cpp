@@ -85,7 +85,7 @@ int validate(const fdlbm_params *p)
             return FDLBM_EINVAL;  // the 9-point form is unstable on {1,1}
         if (p->scheme == FDLBM_SCHEME_LWACM &&
             (p->bc == FDLBM_BC_WALLS_Y || p->force_x != 0.0 || p->force_y != 0.0))
-            return FDLBM_EINVAL;  // section 1-b defines the step on a periodic grid without force
+            return FDLBM_EINVAL;  // section 1-b: a periodic step without force (the disk only adds ghost nodes)
         if (p->bc == FDLBM_BC_DISK) {
             DiskTable t;
             if (!disk_table(*p, &t)) return FDLBM_EINVAL;
