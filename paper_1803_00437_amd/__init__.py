@@ -369,8 +369,9 @@ def fdlbm_batch_workspace_bytes(specs, dtype="f32", max_samples=0):
 class FdLbmBatch:
     """Many independent periodic FD-LBM grids (3-point differences) advanced together.
 
-    specs: list of (nx, ny, s_xx, s_e).  Uses its own HIP stream (default priority), which
-    graph replay needs.
+    specs: list of (nx, ny, s_xx, s_e); dtype "f64", "f32" or "f16" (stochastic rounding is
+    for single grids only).  Uses its own HIP stream (default priority), which graph replay
+    needs.
     """
 
     def __init__(self, specs, dtype="f32", max_samples=0, device="cuda"):
