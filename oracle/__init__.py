@@ -8,8 +8,9 @@ Contents
   * ``fdlbm_oracle.c`` (loaded here through ctypes): the node-by-node FP64 step of the
     FD-LBM scheme (section 2), of the LW-ACM scheme it starts from (section 1-b) and of
     the MRT D2Q9 scheme (section 1, eqs. 1-2), with the
-    3-, 5- and 9-point finite differences of section 2, periodic or xi=1/2 walls
-    (section 3-c) and a Strang-split body force (section 1).
+    3-, 5- and 9-point finite differences of section 2, periodic or walls at a distance xi
+    beyond the first and last rows (section 3-c, Fig. 6) and a Strang-split body force
+    (section 1).
   * ``matrix_form``: a second, independent NumPy rendering of the same steps written as
     whole-array matrix products with ``numpy.linalg.inv`` and ``numpy.roll``.
   * ``symbol``: the linear amplification matrix H(k) of both schemes (von Neumann

@@ -15,8 +15,9 @@
  *     from the rest populations w = M^{-1} m0, m0 = (1,0,0,-2,0,0,0,0,1).  Because M is
  *     linear, working with deviations is the same algebra as the paper's, with every
  *     rest-state constant cancelled exactly instead of by rounding;
- *   - x is always periodic; y is periodic (walls = 0) or bounded by two walls at
- *     y = -1/2 and y = ny - 1/2 (walls = 1, the xi = 1/2 channel of section 3-c).
+ *   - x is always periodic; y is periodic (walls = 0) or bounded by two walls (walls = 1)
+ *     at distance xi beyond the first and last rows, y = -xi and y = ny - 1 + xi (the
+ *     channel of section 3-c and Fig. 6; xi = 1/2 puts them half-way to the next rows).
  *
  * Readings of passages that are garbled or silent in the paper:
  *   R1  the printed J_x row has +1 at e_3 and the J_y row +1 at e_4; the other rows fix
