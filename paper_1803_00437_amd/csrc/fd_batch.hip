@@ -1,6 +1,6 @@
 // Many independent FD-LBM grids (periodic, 3-point differences) of different sizes and
-// viscosities advanced together: one launch per time step covers every tile of every
-// instance, and the FP64 correlation A(t) = <J(t), J0> / <J0, J0> of each instance with its
+// viscosities advanced together: one launch per lane class (at most three) per time step
+// covers every tile of every instance, and the FP64 correlation A(t) = <J(t), J0> / <J0, J0> of each instance with its
 // initial state (section 3-a) is sampled on the device.  A chunk of steps plus one sample
 // is captured once in a HIP graph and replayed.
 //
