@@ -144,6 +144,19 @@ Layout layout(const fdlbm_params &p)
     return L;
 }
 
+// Runs an entry point's body so that no C++ exception crosses the C ABI: host allocation
+// failure (std::bad_alloc from the tables) becomes FDLBM_ENOMEM, anything else FDLBM_EINVAL.
+template <typename Body> int guarded(Body &&body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return FDLBM_ENOMEM;
+    } catch (...) {
+        return FDLBM_EINVAL;
+    }
+}
+
 }  // namespace
 
 struct fdlbm_ctx {
@@ -168,76 +181,80 @@ extern "C" {
 
 int fdlbm_workspace_bytes(const fdlbm_params *p, size_t *state_bytes, size_t *scratch_bytes)
 {
-    int rc = validate(p);
-    if (rc) return rc;
-    const size_t n = (size_t)p->nx * (size_t)p->ny;
-    if (state_bytes) *state_bytes = align256((p->scheme == FDLBM_SCHEME_MRT ? 9 : 3) * n * dtype_bytes(p->dtype));
-    if (scratch_bytes) *scratch_bytes = layout(*p).total;
-    return FDLBM_OK;
+    return guarded([&]() -> int {
+        int rc = validate(p);
+        if (rc) return rc;
+        const size_t n = (size_t)p->nx * (size_t)p->ny;
+        if (state_bytes) *state_bytes = align256((p->scheme == FDLBM_SCHEME_MRT ? 9 : 3) * n * dtype_bytes(p->dtype));
+        if (scratch_bytes) *scratch_bytes = layout(*p).total;
+        return FDLBM_OK;
+    });
 }
 
 int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scratch, size_t scratch_bytes,
                  void *hip_stream, fdlbm_ctx **out)
 {
-    int rc = validate(p);
-    if (rc) return rc;
-    if (!out || !state_a || !state_b || !scratch || state_a == state_b) return FDLBM_EINVAL;
-    if (((uintptr_t)state_a | (uintptr_t)state_b | (uintptr_t)scratch) & 255) return FDLBM_EINVAL;
-    Layout L = layout(*p);
-    if (scratch_bytes < L.total) return FDLBM_ENOMEM;
-    fdlbm_ctx *c = new (std::nothrow) fdlbm_ctx;
-    if (!c) return FDLBM_ENOMEM;
-    c->p = *p;
-    c->s_q = p->scheme == FDLBM_SCHEME_MRT && p->quartic ? quartic(p->s_xx) : p->s_q;
-    c->buf[0] = static_cast<char *>(state_a);
-    c->buf[1] = static_cast<char *>(state_b);
-    c->cur = 0;
-    c->scratch = static_cast<char *>(scratch);
-    c->L = L;
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    c->steps = 0;
-    c->mode_set = false;
-    c->disk = DiskFill{p->nx, p->ny, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
-    c->disk_full = true;
-    hipError_t e = hipGetDevice(&c->device);
-    size_t sb = 0;
-    fdlbm_workspace_bytes(p, &sb, nullptr);
-    if (e == hipSuccess) e = hipMemsetAsync(state_a, 0, sb, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(state_b, 0, sb, c->stream);
-    DiskTable t;  // outlives the uploads: the stream is synchronised below
-    if (e == hipSuccess && p->bc == FDLBM_BC_DISK) {
-        if (!disk_table(*p, &t)) {
-            delete c;
-            return FDLBM_EINVAL;
+    return guarded([&]() -> int {
+        int rc = validate(p);
+        if (rc) return rc;
+        if (!out || !state_a || !state_b || !scratch || state_a == state_b) return FDLBM_EINVAL;
+        if (((uintptr_t)state_a | (uintptr_t)state_b | (uintptr_t)scratch) & 255) return FDLBM_EINVAL;
+        Layout L = layout(*p);
+        if (scratch_bytes < L.total) return FDLBM_ENOMEM;
+        fdlbm_ctx *c = new (std::nothrow) fdlbm_ctx;
+        if (!c) return FDLBM_ENOMEM;
+        c->p = *p;
+        c->s_q = p->scheme == FDLBM_SCHEME_MRT && p->quartic ? quartic(p->s_xx) : p->s_q;
+        c->buf[0] = static_cast<char *>(state_a);
+        c->buf[1] = static_cast<char *>(state_b);
+        c->cur = 0;
+        c->scratch = static_cast<char *>(scratch);
+        c->L = L;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->steps = 0;
+        c->mode_set = false;
+        c->disk = DiskFill{p->nx, p->ny, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+        c->disk_full = true;
+        hipError_t e = hipGetDevice(&c->device);
+        size_t sb = 0;
+        fdlbm_workspace_bytes(p, &sb, nullptr);
+        if (e == hipSuccess) e = hipMemsetAsync(state_a, 0, sb, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(state_b, 0, sb, c->stream);
+        DiskTable t;  // outlives the uploads: the stream is synchronised below
+        if (e == hipSuccess && p->bc == FDLBM_BC_DISK) {
+            if (!disk_table(*p, &t)) {
+                delete c;
+                return FDLBM_EINVAL;
+            }
+            char *sc = c->scratch;
+            c->disk.nghost = int(t.dst.size());
+            c->disk.dst = reinterpret_cast<const int32_t *>(sc + L.disk_dst);
+            c->disk.src = reinterpret_cast<const int32_t *>(sc + L.disk_src);
+            c->disk.w = reinterpret_cast<const double *>(sc + L.disk_w);
+            c->disk.span = reinterpret_cast<const int32_t *>(sc + L.disk_span);
+            c->disk.nring = int(t.ring.size());
+            c->disk.ring = reinterpret_cast<const int32_t *>(sc + L.disk_ring);
+            const size_t ng = t.dst.size(), nr = t.ring.size();
+            if (ng) e = hipMemcpyAsync(sc + L.disk_dst, t.dst.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess && ng)
+                e = hipMemcpyAsync(sc + L.disk_src, t.src.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess && ng)
+                e = hipMemcpyAsync(sc + L.disk_w, t.w.data(), 3 * ng * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sc + L.disk_span, t.span.data(), t.span.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess && nr)
+                e = hipMemcpyAsync(sc + L.disk_ring, t.ring.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   c->stream);
         }
-        char *sc = c->scratch;
-        c->disk.nghost = int(t.dst.size());
-        c->disk.dst = reinterpret_cast<const int32_t *>(sc + L.disk_dst);
-        c->disk.src = reinterpret_cast<const int32_t *>(sc + L.disk_src);
-        c->disk.w = reinterpret_cast<const double *>(sc + L.disk_w);
-        c->disk.span = reinterpret_cast<const int32_t *>(sc + L.disk_span);
-        c->disk.nring = int(t.ring.size());
-        c->disk.ring = reinterpret_cast<const int32_t *>(sc + L.disk_ring);
-        const size_t ng = t.dst.size(), nr = t.ring.size();
-        if (ng) e = hipMemcpyAsync(sc + L.disk_dst, t.dst.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess && ng)
-            e = hipMemcpyAsync(sc + L.disk_src, t.src.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess && ng)
-            e = hipMemcpyAsync(sc + L.disk_w, t.w.data(), 3 * ng * sizeof(double), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sc + L.disk_span, t.span.data(), t.span.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess && nr)
-            e = hipMemcpyAsync(sc + L.disk_ring, t.ring.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice,
-                               c->stream);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        delete c;
-        return device_error(e, "fdlbm_create");
-    }
-    *out = c;
-    return FDLBM_OK;
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            delete c;
+            return device_error(e, "fdlbm_create");
+        }
+        *out = c;
+        return FDLBM_OK;
+    });
 }
 
 void fdlbm_destroy(fdlbm_ctx *c) { delete c; }
@@ -423,65 +440,67 @@ int fdlbm_mode_projection(fdlbm_ctx *c, double *out)
 
 int fdlbm_autotune(fdlbm_ctx *c, int32_t reps, int32_t *out_lane_cols, int32_t *out_tile_rows, double *out_ms)
 {
-    if (!c || reps < 1 || reps > 10000) return FDLBM_EINVAL;
-    HIPCHK(hipSetDevice(c->device), "hipSetDevice");
-    const bool fd = three_words(c->p.scheme);
-    const FdArgs fa = fd_args(c->p);
-    const bool ref = fd ? uses_reference(c->p) : c->p.kernel == FDLBM_KERNEL_REFERENCE;
-    // candidate shapes: (lane_cols, tile_rows); the reference kernels have none to choose
-    struct Shape {
-        int cols, rows;
-    };
-    std::vector<Shape> cand;
-    if (ref) {
-        cand.push_back({c->p.lane_cols, c->p.tile_rows});
-    } else if (fd) {
-        for (int cols : {1, 2, 4})
-            if (fd_sweep_supported(fa, cols))
-                for (int rows : {4, 6, 8, 12, 16, 24}) cand.push_back({cols, rows});
-    } else {
-        for (int rows : {1, 2, 4, 8, 16}) cand.push_back({0, rows});
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    // every timed launch reads the current state and writes the spare buffer, which the
-    // next step overwrites: the state does not advance
-    void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
-    auto launch = [&](const Shape &sh) -> hipError_t {
-        if (fd && ref) return launch_fd_reference(fa, src, dst, c->scratch + c->L.fstar, c->stream);
-        if (fd) return launch_fd_sweep(fa, sh.rows, sh.cols, src, dst, c->stream);
-        const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
-                         c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, sh.rows, wall_xi(c->p)};
-        return launch_mrt(ma, src, dst, c->stream);
-    };
-    Shape best{0, 0};
-    float best_ms = 0.0f;
-    for (const Shape &sh : cand) {
-        if (e == hipSuccess) e = launch(sh);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(sh);
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) break;
-        if (best_ms == 0.0f || ms < best_ms) {
-            best_ms = ms;
-            best = sh;
+    return guarded([&]() -> int {
+        if (!c || reps < 1 || reps > 10000) return FDLBM_EINVAL;
+        HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+        const bool fd = three_words(c->p.scheme);
+        const FdArgs fa = fd_args(c->p);
+        const bool ref = fd ? uses_reference(c->p) : c->p.kernel == FDLBM_KERNEL_REFERENCE;
+        // candidate shapes: (lane_cols, tile_rows); the reference kernels have none to choose
+        struct Shape {
+            int cols, rows;
+        };
+        std::vector<Shape> cand;
+        if (ref) {
+            cand.push_back({c->p.lane_cols, c->p.tile_rows});
+        } else if (fd) {
+            for (int cols : {1, 2, 4})
+                if (fd_sweep_supported(fa, cols))
+                    for (int rows : {4, 6, 8, 12, 16, 24}) cand.push_back({cols, rows});
+        } else {
+            for (int rows : {1, 2, 4, 8, 16}) cand.push_back({0, rows});
         }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return device_error(e, "fdlbm_autotune");
-    if (!ref) {
-        c->p.lane_cols = best.cols;
-        c->p.tile_rows = best.rows;
-    }
-    if (out_lane_cols) *out_lane_cols = best.cols;
-    if (out_tile_rows) *out_tile_rows = best.rows;
-    if (out_ms) *out_ms = (double)best_ms / reps;
-    return FDLBM_OK;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        // every timed launch reads the current state and writes the spare buffer, which the
+        // next step overwrites: the state does not advance
+        void *src = c->buf[c->cur], *dst = c->buf[c->cur ^ 1];
+        auto launch = [&](const Shape &sh) -> hipError_t {
+            if (fd && ref) return launch_fd_reference(fa, src, dst, c->scratch + c->L.fstar, c->stream);
+            if (fd) return launch_fd_sweep(fa, sh.rows, sh.cols, src, dst, c->stream);
+            const MrtArgs ma{c->p.nx, c->p.ny, c->p.bc == FDLBM_BC_WALLS_Y ? 1 : 0, c->p.dtype, c->p.s_e, c->p.s_xx, c->s_q,
+                             c->p.s_eps, c->p.force_x, c->p.force_y, c->p.kernel, sh.rows, wall_xi(c->p)};
+            return launch_mrt(ma, src, dst, c->stream);
+        };
+        Shape best{0, 0};
+        float best_ms = 0.0f;
+        for (const Shape &sh : cand) {
+            if (e == hipSuccess) e = launch(sh);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(sh);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (best_ms == 0.0f || ms < best_ms) {
+                best_ms = ms;
+                best = sh;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (e != hipSuccess) return device_error(e, "fdlbm_autotune");
+        if (!ref) {
+            c->p.lane_cols = best.cols;
+            c->p.tile_rows = best.rows;
+        }
+        if (out_lane_cols) *out_lane_cols = best.cols;
+        if (out_tile_rows) *out_tile_rows = best.rows;
+        if (out_ms) *out_ms = (double)best_ms / reps;
+        return FDLBM_OK;
+    });
 }
 
 int fdlbm_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream)

@@ -178,6 +178,19 @@ struct fdlbm_batch {
 
 namespace {
 
+// Runs an entry point's body so that no C++ exception crosses the C ABI: host allocation
+// failure (std::bad_alloc from the tables) becomes FDLBM_ENOMEM, anything else FDLBM_EINVAL.
+template <typename Body> int guarded(Body &&body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return FDLBM_ENOMEM;
+    } catch (...) {
+        return FDLBM_EINVAL;
+    }
+}
+
 int launch_chunk(fdlbm_batch *b, int steps, bool sample)
 {
     for (int s = 0; s < steps; ++s) {
@@ -195,71 +208,75 @@ extern "C" {
 int fdlbm_batch_workspace_bytes(const fdlbm_instance *instances, int32_t count, int32_t dtype, int32_t max_samples,
                                 size_t *state_bytes, size_t *scratch_bytes)
 {
-    int rc = validate(instances, count, dtype, max_samples);
-    if (rc) return rc;
-    Plan P = plan(instances, count, dtype, max_samples);
-    if (state_bytes) *state_bytes = al256(P.state_elems * dtype_bytes(dtype));
-    if (scratch_bytes) *scratch_bytes = P.total;
-    return FDLBM_OK;
+    return guarded([&]() -> int {
+        int rc = validate(instances, count, dtype, max_samples);
+        if (rc) return rc;
+        Plan P = plan(instances, count, dtype, max_samples);
+        if (state_bytes) *state_bytes = al256(P.state_elems * dtype_bytes(dtype));
+        if (scratch_bytes) *scratch_bytes = P.total;
+        return FDLBM_OK;
+    });
 }
 
 int fdlbm_batch_create(const fdlbm_instance *instances, int32_t count, int32_t dtype, int32_t max_samples,
                        void *state_a, void *state_b, void *scratch, size_t scratch_bytes, void *hip_stream,
                        fdlbm_batch **out)
 {
-    int rc = validate(instances, count, dtype, max_samples);
-    if (rc) return rc;
-    if (!out || !state_a || !state_b || !scratch || state_a == state_b) return FDLBM_EINVAL;
-    if (((uintptr_t)state_a | (uintptr_t)state_b | (uintptr_t)scratch) & 255) return FDLBM_EINVAL;
-    fdlbm_batch *b = new (std::nothrow) fdlbm_batch;
-    if (!b) return FDLBM_ENOMEM;
-    b->P = plan(instances, count, dtype, max_samples);
-    if (scratch_bytes < b->P.total) {
-        delete b;
-        return FDLBM_ENOMEM;
-    }
-    b->dtype = dtype;
-    b->count = count;
-    b->max_samples = max_samples;
-    b->stream = static_cast<hipStream_t>(hip_stream);
-    b->buf[0] = static_cast<char *>(state_a);
-    b->buf[1] = static_cast<char *>(state_b);
-    b->cur = 0;
-    b->scratch = static_cast<char *>(scratch);
-    b->steps = 0;
-    const Plan &P = b->P;
-    BatchLaunch &L = b->L;
-    L.dtype = dtype;
-    L.count = count;
-    use_tables(L, P, BATCH_ROWS);
-    L.nchunks = (int)P.chunks.size();
-    L.max_samples = max_samples;
-    L.inst = reinterpret_cast<const BatchInstance *>(b->scratch + P.o_inst);
-    L.blocks = reinterpret_cast<const BatchBlock *>(b->scratch + P.o_blocks);
-    L.chunks = reinterpret_cast<const BatchChunk *>(b->scratch + P.o_chunks);
-    L.mode = b->scratch + P.o_mode;
-    L.partials = reinterpret_cast<double *>(b->scratch + P.o_partials);
-    L.counter = reinterpret_cast<int *>(b->scratch + P.o_counter);
-    L.amps = reinterpret_cast<double *>(b->scratch + P.o_amps);
-    hipError_t e = hipGetDevice(&b->device);
-    const size_t sb = al256(P.state_elems * dtype_bytes(dtype));
-    if (e == hipSuccess) e = hipMemcpyAsync(b->scratch + P.o_inst, P.inst.data(), sizeof(BatchInstance) * P.inst.size(),
-                                            hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->scratch + P.o_blocks, P.blocks.data(), sizeof(BatchBlock) * P.blocks.size(),
-                                            hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->scratch + P.o_chunks, P.chunks.data(), sizeof(BatchChunk) * P.chunks.size(),
-                                            hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(state_a, 0, sb, b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(state_b, 0, sb, b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(b->scratch + P.o_counter, 0, sizeof(int), b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(b->scratch + P.o_mode, 0, dtype_bytes(dtype) * P.mode_elems, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        delete b;
-        return batch_device_error(e, "fdlbm_batch_create");
-    }
-    *out = b;
-    return FDLBM_OK;
+    return guarded([&]() -> int {
+        int rc = validate(instances, count, dtype, max_samples);
+        if (rc) return rc;
+        if (!out || !state_a || !state_b || !scratch || state_a == state_b) return FDLBM_EINVAL;
+        if (((uintptr_t)state_a | (uintptr_t)state_b | (uintptr_t)scratch) & 255) return FDLBM_EINVAL;
+        fdlbm_batch *b = new (std::nothrow) fdlbm_batch;
+        if (!b) return FDLBM_ENOMEM;
+        b->P = plan(instances, count, dtype, max_samples);
+        if (scratch_bytes < b->P.total) {
+            delete b;
+            return FDLBM_ENOMEM;
+        }
+        b->dtype = dtype;
+        b->count = count;
+        b->max_samples = max_samples;
+        b->stream = static_cast<hipStream_t>(hip_stream);
+        b->buf[0] = static_cast<char *>(state_a);
+        b->buf[1] = static_cast<char *>(state_b);
+        b->cur = 0;
+        b->scratch = static_cast<char *>(scratch);
+        b->steps = 0;
+        const Plan &P = b->P;
+        BatchLaunch &L = b->L;
+        L.dtype = dtype;
+        L.count = count;
+        use_tables(L, P, BATCH_ROWS);
+        L.nchunks = (int)P.chunks.size();
+        L.max_samples = max_samples;
+        L.inst = reinterpret_cast<const BatchInstance *>(b->scratch + P.o_inst);
+        L.blocks = reinterpret_cast<const BatchBlock *>(b->scratch + P.o_blocks);
+        L.chunks = reinterpret_cast<const BatchChunk *>(b->scratch + P.o_chunks);
+        L.mode = b->scratch + P.o_mode;
+        L.partials = reinterpret_cast<double *>(b->scratch + P.o_partials);
+        L.counter = reinterpret_cast<int *>(b->scratch + P.o_counter);
+        L.amps = reinterpret_cast<double *>(b->scratch + P.o_amps);
+        hipError_t e = hipGetDevice(&b->device);
+        const size_t sb = al256(P.state_elems * dtype_bytes(dtype));
+        if (e == hipSuccess) e = hipMemcpyAsync(b->scratch + P.o_inst, P.inst.data(), sizeof(BatchInstance) * P.inst.size(),
+                                                hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b->scratch + P.o_blocks, P.blocks.data(), sizeof(BatchBlock) * P.blocks.size(),
+                                                hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b->scratch + P.o_chunks, P.chunks.data(), sizeof(BatchChunk) * P.chunks.size(),
+                                                hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(state_a, 0, sb, b->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(state_b, 0, sb, b->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(b->scratch + P.o_counter, 0, sizeof(int), b->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(b->scratch + P.o_mode, 0, dtype_bytes(dtype) * P.mode_elems, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) {
+            delete b;
+            return batch_device_error(e, "fdlbm_batch_create");
+        }
+        *out = b;
+        return FDLBM_OK;
+    });
 }
 
 void fdlbm_batch_destroy(fdlbm_batch *b)
@@ -306,97 +323,101 @@ int fdlbm_batch_get_state(fdlbm_batch *b, int32_t i, double *drho, double *jx, d
 
 int fdlbm_batch_autotune(fdlbm_batch *b, int32_t reps, int32_t *out_rows, double *out_ms)
 {
-    if (!b || reps < 1 || reps > 10000) return FDLBM_EINVAL;
-    BHIPCHK(hipSetDevice(b->device), "hipSetDevice");
-    // upload the tile tables for `rows` rows per wavefront and point the launch at them
-    auto use_rows = [&](int rows) -> hipError_t {
-        tile_tables(b->P, rows);
-        hipError_t e = hipMemcpyAsync(b->scratch + b->P.o_inst, b->P.inst.data(),
-                                      sizeof(BatchInstance) * b->P.inst.size(), hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->scratch + b->P.o_blocks, b->P.blocks.data(), sizeof(BatchBlock) * b->P.blocks.size(),
-                               hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        use_tables(b->L, b->P, rows);
-        return e;
-    };
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    // timed launches read the current state and write the spare buffer: no step is taken
-    void *src = b->buf[b->cur], *dst = b->buf[b->cur ^ 1];
-    int best = b->L.rows;
-    float best_ms = 0.0f;
-    for (int rows : BATCH_TUNE_ROWS) {
-        if (e == hipSuccess) e = use_rows(rows);
-        if (e == hipSuccess) e = launch_batch_step(b->L, src, dst, b->stream);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch_step(b->L, src, dst, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) break;
-        if (best_ms == 0.0f || ms < best_ms) {
-            best_ms = ms;
-            best = rows;
+    return guarded([&]() -> int {
+        if (!b || reps < 1 || reps > 10000) return FDLBM_EINVAL;
+        BHIPCHK(hipSetDevice(b->device), "hipSetDevice");
+        // upload the tile tables for `rows` rows per wavefront and point the launch at them
+        auto use_rows = [&](int rows) -> hipError_t {
+            tile_tables(b->P, rows);
+            hipError_t e = hipMemcpyAsync(b->scratch + b->P.o_inst, b->P.inst.data(),
+                                          sizeof(BatchInstance) * b->P.inst.size(), hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(b->scratch + b->P.o_blocks, b->P.blocks.data(), sizeof(BatchBlock) * b->P.blocks.size(),
+                                   hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+            use_tables(b->L, b->P, rows);
+            return e;
+        };
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        // timed launches read the current state and write the spare buffer: no step is taken
+        void *src = b->buf[b->cur], *dst = b->buf[b->cur ^ 1];
+        int best = b->L.rows;
+        float best_ms = 0.0f;
+        for (int rows : BATCH_TUNE_ROWS) {
+            if (e == hipSuccess) e = use_rows(rows);
+            if (e == hipSuccess) e = launch_batch_step(b->L, src, dst, b->stream);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch_step(b->L, src, dst, b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (best_ms == 0.0f || ms < best_ms) {
+                best_ms = ms;
+                best = rows;
+            }
         }
-    }
-    if (e == hipSuccess) e = use_rows(best);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    // replays captured before hold the old grid size
-    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
-    b->graphs.clear();
-    if (e != hipSuccess) return batch_device_error(e, "fdlbm_batch_autotune");
-    if (out_rows) *out_rows = best;
-    if (out_ms) *out_ms = (double)best_ms / reps;
-    return FDLBM_OK;
+        if (e == hipSuccess) e = use_rows(best);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        // replays captured before hold the old grid size
+        for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+        b->graphs.clear();
+        if (e != hipSuccess) return batch_device_error(e, "fdlbm_batch_autotune");
+        if (out_rows) *out_rows = best;
+        if (out_ms) *out_ms = (double)best_ms / reps;
+        return FDLBM_OK;
+    });
 }
 
 int fdlbm_batch_step(fdlbm_batch *b, int64_t nsteps, int32_t sample_every, int32_t use_graph)
 {
-    if (!b || nsteps < 0 || sample_every < 0) return FDLBM_EINVAL;
-    if (sample_every > 0 && nsteps % sample_every) return FDLBM_EINVAL;
-    if (use_graph && (sample_every == 0 || !b->stream)) return FDLBM_EINVAL;  // capture needs a non-default stream
-    BHIPCHK(hipSetDevice(b->device), "hipSetDevice");
-    if (sample_every == 0) {
-        int rc = launch_chunk(b, (int)nsteps, false);
-        if (rc) return rc;
+    return guarded([&]() -> int {
+        if (!b || nsteps < 0 || sample_every < 0) return FDLBM_EINVAL;
+        if (sample_every > 0 && nsteps % sample_every) return FDLBM_EINVAL;
+        if (use_graph && (sample_every == 0 || !b->stream)) return FDLBM_EINVAL;  // capture needs a non-default stream
+        BHIPCHK(hipSetDevice(b->device), "hipSetDevice");
+        if (sample_every == 0) {
+            int rc = launch_chunk(b, (int)nsteps, false);
+            if (rc) return rc;
+            b->steps += nsteps;
+            return FDLBM_OK;
+        }
+        for (int64_t done = 0; done < nsteps; done += sample_every) {
+            if (!use_graph) {
+                int rc = launch_chunk(b, sample_every, true);
+                if (rc) return rc;
+                continue;
+            }
+            hipGraphExec_t exec = nullptr;
+            for (auto &g : b->graphs)
+                if (g.sample_every == sample_every && g.parity == b->cur) exec = g.exec;
+            if (!exec) {
+                const int cur0 = b->cur;
+                hipGraph_t graph = nullptr;
+                BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "batch graph capture");
+                int rc = launch_chunk(b, sample_every, true);
+                hipError_t e = hipStreamEndCapture(b->stream, &graph);
+                if (rc) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return rc;
+                }
+                if (e != hipSuccess) return batch_device_error(e, "batch graph capture");
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return batch_device_error(e, "batch graph instantiate");
+                b->graphs.push_back(GraphEntry{sample_every, cur0, exec});
+                b->cur = cur0;  // capture recorded the launches without running them
+            }
+            BHIPCHK(hipGraphLaunch(exec, b->stream), "batch graph launch");
+            b->cur ^= (sample_every & 1);
+        }
         b->steps += nsteps;
         return FDLBM_OK;
-    }
-    for (int64_t done = 0; done < nsteps; done += sample_every) {
-        if (!use_graph) {
-            int rc = launch_chunk(b, sample_every, true);
-            if (rc) return rc;
-            continue;
-        }
-        hipGraphExec_t exec = nullptr;
-        for (auto &g : b->graphs)
-            if (g.sample_every == sample_every && g.parity == b->cur) exec = g.exec;
-        if (!exec) {
-            const int cur0 = b->cur;
-            hipGraph_t graph = nullptr;
-            BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "batch graph capture");
-            int rc = launch_chunk(b, sample_every, true);
-            hipError_t e = hipStreamEndCapture(b->stream, &graph);
-            if (rc) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return rc;
-            }
-            if (e != hipSuccess) return batch_device_error(e, "batch graph capture");
-            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) return batch_device_error(e, "batch graph instantiate");
-            b->graphs.push_back(GraphEntry{sample_every, cur0, exec});
-            b->cur = cur0;  // capture recorded the launches without running them
-        }
-        BHIPCHK(hipGraphLaunch(exec, b->stream), "batch graph launch");
-        b->cur ^= (sample_every & 1);
-    }
-    b->steps += nsteps;
-    return FDLBM_OK;
+    });
 }
 
 int fdlbm_batch_step_per_instance(fdlbm_batch *b, int64_t nsteps)
