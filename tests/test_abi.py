@@ -217,3 +217,52 @@ def test_stochastic_rounding_storage_is_for_single_fd_grids():
                                            ctypes.byref(cb)) == F.FDLBM_EINVAL
     assert lib.fdlbm_batch_workspace_bytes(inst, 1, F.DTYPE["f16"], 4, ctypes.byref(sb),
                                            ctypes.byref(cb)) == F.FDLBM_OK
+
+
+def test_header_is_c99_and_links(tmp_path):
+    """include/fdlbm.h compiles as C99 with warnings as errors (no C++ in the declarations), every function
+    it declares links against libfdlbm.so, and a plain C caller gets the same workspace
+    sizes and error codes as the Python binding (no device is touched)."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not available")
+    names = declared_functions()
+    src = tmp_path / "caller.c"
+    refs = "\n".join(f"    (void *)&{n}," for n in names)
+    src.write_text(f"""
+#include <stdio.h>
+#include <string.h>
+#include "fdlbm.h"
+static void *const every_function[] = {{
+{refs}
+}};
+int main(void)
+{{
+    fdlbm_params p;
+    size_t sb = 0, cb = 0;
+    memset(&p, 0, sizeof p);
+    p.nx = 64; p.ny = 48; p.scheme = FDLBM_SCHEME_FD; p.stencil = 3; p.bc = FDLBM_BC_PERIODIC;
+    p.dtype = FDLBM_F32; p.s_xx = 1.5; p.s_e = 1.0;
+    int rc = fdlbm_workspace_bytes(&p, &sb, &cb);
+    p.stencil = 9;
+    int bad = fdlbm_workspace_bytes(&p, &sb, &cb);
+    printf("%d %zu %zu %d %d %s\\n", rc, sb, cb, bad, (int)(sizeof every_function / sizeof every_function[0]),
+           fdlbm_strerror(bad));
+    return 0;
+}}
+""")
+    lib_dir = os.path.dirname(F.LIB_PATH)
+    exe = tmp_path / "caller"
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", f"-I{os.path.join(ROOT, 'include')}",
+           str(src), "-o", str(exe), f"-L{lib_dir}", "-lfdlbm", f"-Wl,-rpath,{lib_dir}",
+           "-Wl,--allow-shlib-undefined"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    rc, sb, cb, bad, count = (int(x) for x in r.stdout.split()[:5])
+    want_sb, want_cb = F.fdlbm_workspace_bytes(good())
+    assert (rc, sb, cb, bad, count) == (0, want_sb, want_cb, F.FDLBM_EINVAL, len(names))
+    assert "invalid argument" in r.stdout
