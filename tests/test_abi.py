@@ -266,3 +266,21 @@ int main(void)
     want_sb, want_cb = F.fdlbm_workspace_bytes(good())
     assert (rc, sb, cb, bad, count) == (0, want_sb, want_cb, F.FDLBM_EINVAL, len(names))
     assert "invalid argument" in r.stdout
+
+
+def test_product_never_reaches_the_oracle():
+    """The library and its binding share nothing with the oracle: no source under the package
+    names it, and the oracle names nothing of the package (only tests, smoke() and the CPU
+    baseline of bench.py use the oracle)."""
+    pkg = os.path.join(ROOT, "paper_1803_00437_amd")
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath or "__pycache__" in dirpath:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text, os.path.join(dirpath, f)
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c")):
+            text = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_1803_00437_amd" not in text and "fdlbm.h" not in text, f
