@@ -189,3 +189,26 @@ def test_stokes_mode_rates_tables_2_3(F, rules, stencil, nukey):
         print(f"  FD{stencil} nu={nukey} {row['family']} l={row['l']}: error {got / g0 - 1:+.5f} "
               f"(paper {paper:+.5f})")
     print(f"  FD{stencil} nu={nukey}: worst rate ratio to the paper {worst:.4f}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16sr"])
+def test_disk_autotune_leaves_the_run_unchanged(F, dtype):
+    """fdlbm_autotune on a disk context times the step kernel on the current state without
+    advancing it; the run that follows equals an untuned one bit for bit (every tile shape
+    gives the same bits, and stochastic rounding draws from the step count, which tuning
+    does not move)."""
+    nx, ny, cx, cy, r = GEOMS["centred"]
+    init = inside_noise("centred", seed=21)
+    kw = dict(bc="disk", disk=(cx, cy, r), stencil=3, dtype=dtype, s_xx=O.rate_from_viscosity(0.05))
+    out = []
+    for tune in (False, True):
+        sim = F.FdLbm(nx, ny, **kw)
+        sim.set_state(*init)
+        sim.step(5)
+        if tune:
+            sim.autotune(reps=3)
+        sim.step(45)
+        out.append(sim.get_state())
+        sim.close()
+    for u, v in zip(*out):
+        assert np.array_equal(u, v)
