@@ -20,9 +20,9 @@ Contents
     from the fluid before each periodic step) and the decay-rate measurement of the Stokes
     modes of Tables 2 and 3.
 
-Parity unpinned: the velocity-cubic term of theta_E, taken as printed (it differs from the
-exact expansion of the defect it approximates), is checked only by the second rendering
-(``matrix_form``); everything else is pinned by tests/test_oracle_pins.py.
+Every part is pinned by tests/test_oracle_pins.py and tests/test_oracle_disk.py; the
+velocity-cubic term of theta_E (whose printed sign is read as a slip, reading R6) by the bulk
+viscosity zeta (1 - 3V^2) in a mean flow that section 2 states.
 
 Array convention: float64 arrays of shape (ny, nx), x fastest; the state is the deviation
 from rest (drho = rho - 1, jx, jy); populations are (9, ny, nx) deviations f_k - w_k.

@@ -26,7 +26,10 @@
  *   R3  every "v" inside the theta terms is the stored momentum J (rho close to 1);
  *   R4  derivatives of products (d_x v_x^2 ...) are finite differences of the product field;
  *   R5  the E and eps lines use 3(J_x^2+J_y^2)/rho as in the standard D2Q9 table;
- *   R6  the cubic term of theta_E is taken exactly as printed;
+ *   R6  the velocity-cubic term of theta_E is printed as +6|v|^2 div v; section 2 states that
+ *       with these expressions the bulk viscosity in a mean flow V is zeta (1 - 3V^2).  A term
+ *       c |v|^2 div v gives exactly zeta (1 + c V^2 / 2) in every direction of V and k, so
+ *       that statement fixes c = -6: the printed sign is taken as a slip (as in R2);
  *   R8  body force (Strang): J_a = J + F/2 enters equilibria and theta, J* = J + F;
  *   R9  walls at xi = 1/2: ghost nodes hold the linear extrapolation with zero velocity on
  *       the wall (J odd, rho even about the wall); MRT uses halfway bounce-back;
@@ -51,10 +54,10 @@
  * conservation itself: one textbook-BGK step leaves non-equilibrium moments equal to minus
  * the exact defect, whose first-order expansion for a density wave on a uniform flow is the
  * printed terms plus |J|^2 terms that the paper omits (rho close to 1).
- * PARITY UNPINNED: the velocity-cubic term of theta_E, 6 |v|^2 div v, taken as printed (R6).
- * The exact expansion of the defect has -3 |J|^2 div J - 3 J.grad |J|^2 there instead, so no
- * check of this oracle against the definition can confirm the printed term; it is guarded
- * only by the independent whole-array rendering in matrix_form.py.
+ * The velocity-cubic term of theta_E is pinned by the bulk viscosity of section 2: the
+ * acoustic damping of this oracle, linearised about a uniform flow V, has the coefficient
+ * (1 - 3V^2)/2 of zeta along axes and diagonals (and its amplification matrix equals the
+ * symbol's, which has it at every angle).
  */
 #include <math.h>
 #include <stdint.h>
@@ -247,12 +250,13 @@ int oracle_fd_derivative(int nx, int ny, int stencil, int axis, const double *in
 /*
  * Section 2: the defects of conservation at node (i, j), with v read as the stored momentum
  * J (here J_a, see R3, R8) and the derivatives estimated by finite differences (R4):
- *   theta_E  = (2 + 6|v|^2) div v - 2 v . grad rho
+ *   theta_E  = (2 - 6|v|^2) div v - 2 v . grad rho
  *   theta_XX = 2/3 (d_x v_x - d_y v_y) - 2/3 (v_x d_x rho - v_y d_y rho)
  *              - 2 [v_x (d_x v_x^2 + d_y v_x v_y) - v_y (d_x v_x v_y + d_y v_y^2)]
  *   theta_XY = 1/3 (d_x v_y + d_y v_x) - 1/3 (v_x d_y rho + v_y d_x rho)
  *              - v_x (d_x v_x v_y + d_y v_y^2) - v_y (d_x v_x^2 + d_y v_x v_y)
- * (R2: + in the linear part of theta_XY; R6: the cubic term of theta_E as printed.)
+ * (R2: + in the linear part of theta_XY; R6: the velocity-cubic term of theta_E with the
+ * sign that section 2's bulk viscosity in a mean flow fixes, see the file header.)
  */
 static void thetas(const xfield *r, const xfield *vx, const xfield *vy, const xfield *pxx, const xfield *pxy,
                    const xfield *pyy, int stencil, int i, int j, double *te, double *txx, double *txy)
@@ -263,7 +267,7 @@ static void thetas(const xfield *r, const xfield *vx, const xfield *vy, const xf
     const double uyx = ddx(vy, stencil, i, j), uxy = ddy(vx, stencil, i, j);
     const double dx_xx = ddx(pxx, stencil, i, j), dy_xy = ddy(pxy, stencil, i, j);
     const double dx_xy = ddx(pxy, stencil, i, j), dy_yy = ddy(pyy, stencil, i, j);
-    *te = (2.0 + 6.0 * (ux * ux + uy * uy)) * (uxx + uyy) - 2.0 * (ux * rx + uy * ry);
+    *te = (2.0 - 6.0 * (ux * ux + uy * uy)) * (uxx + uyy) - 2.0 * (ux * rx + uy * ry);
     *txx = (2.0 / 3.0) * (uxx - uyy) - (2.0 / 3.0) * (ux * rx - uy * ry) -
            2.0 * (ux * (dx_xx + dy_xy) - uy * (dx_xy + dy_yy));
     *txy = (1.0 / 3.0) * (uyx + uxy) - (1.0 / 3.0) * (ux * ry + uy * rx) - ux * (dx_xy + dy_yy) -

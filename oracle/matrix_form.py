@@ -75,7 +75,7 @@ def fd_step(drho, jx, jy, *, s_xx, s_e=1.0, stencil=3, walls=False, fx=0.0, fy=0
     c, d = ddx(vy, stencil), ddy(vx, stencil)
     P, Q, R = vx * vx, vy * vy, vx * vy
     Px, Qy, Rx, Ry = ddx(P, stencil), ddy(Q, stencil), ddx(R, stencil), ddy(R, stencil)
-    th_e = (2 + 6 * (P + Q)) * (a + b) - 2 * (vx * dxr + vy * dyr)
+    th_e = (2 - 6 * (P + Q)) * (a + b) - 2 * (vx * dxr + vy * dyr)
     th_xx = 2 / 3 * (a - b) - 2 / 3 * (vx * dxr - vy * dyr) - 2 * (vx * (Px + Ry) - vy * (Rx + Qy))
     th_xy = 1 / 3 * (c + d) - 1 / 3 * (vx * dyr + vy * dxr) - vx * (Rx + Qy) - vy * (Px + Ry)
     K = (P + Q) / rho

@@ -8,14 +8,16 @@ step (Phi^{n+1} = H Phi^n); the roots z of det(H - z Id) = 0 give Gamma = -log z
 Section 2 interprets the shear root as Gamma = nu_0 k^2 + nu_2 k^4 ("hyperviscosity" nu_2),
 and solves the full cubic numerically up to k = pi for linear stability.
 
-Here H is assembled numerically about the rest state rho = 1, J = 0 (LW-ACM also about a
-uniform flow, see lwacm_symbol):
+Here H is assembled numerically about a uniform state rho = 1, J = (vx, vy) (the rest state
+by default):
   FD-LBM:  H = P(k) diag(exp(-i k.e_k)) M^{-1} L(k), where L(k) maps Phi to the
-           linearised post-collision moments (the theta terms keep only their linear
-           parts, the finite differences become their Fourier symbols) and P(k) takes
-           the conserved moments of the propagated populations;
+           linearised post-collision moments (the equilibria and theta terms linearised
+           about the uniform state, the finite differences become their Fourier symbols)
+           and P(k) takes the conserved moments of the propagated populations;
   MRT:     H = diag(exp(-i k.e_k)) M^{-1} (I - S + S Q) M on the 9 populations, with Q
            the linearised equilibrium map and S the relaxation rates.
+About a uniform flow the velocity-cubic terms of theta enter H; the bulk viscosity of the
+acoustic pair then carries the factor (1 - 3 V^2) that section 2 states (tests pin this).
 """
 from __future__ import annotations
 
@@ -37,40 +39,45 @@ def _propagation(kx, ky):
     return np.diag(np.exp(-1j * (kx * E[:, 0] + ky * E[:, 1])))
 
 
-def fd_symbol(kx, ky, *, s_xx, s_e=1.0, stencil=3):
-    """3x3 amplification matrix of the FD-LBM step acting on (drho, Jx, Jy)."""
+def fd_symbol(kx, ky, *, s_xx, s_e=1.0, stencil=3, vx=0.0, vy=0.0):
+    """3x3 amplification matrix of the FD-LBM step acting on (drho, Jx, Jy), linearised about
+    rho = 1, J = (vx, vy).
+
+    Section 2's moments, with v read as J (reading R3) and the sign of the velocity-cubic
+    term of theta_E as section 2's bulk viscosity fixes it (reading R6):
+      theta_E  = (2 - 6|J|^2) div J - 2 J.grad rho
+      theta_XX = 2/3 (D_x J_x - D_y J_y) - 2/3 (J_x D_x rho - J_y D_y rho)
+                 - 2 [J_x (D_x J_x^2 + D_y J_x J_y) - J_y (D_x J_x J_y + D_y J_y^2)]
+      theta_XY = 1/3 (D_x J_y + D_y J_x) - 1/3 (J_x D_y rho + J_y D_x rho)
+                 - J_x (D_x J_x J_y + D_y J_y^2) - J_y (D_x J_x^2 + D_y J_x J_y)
+    Every derivative is of a perturbation (the base state is uniform), so each term is
+    linearised by freezing its other factors at the base state."""
     Dx, Dy = derivative_symbols(kx, ky, stencil)
     ce, cxx = 1 - 1 / s_e, 1 - 1 / s_xx
-    L = np.zeros((9, 3), dtype=complex)
-    L[0, 0] = 1
-    L[1, 1] = 1
-    L[2, 2] = 1
-    # E* = -2 rho + (1 - 1/s_e) * 2 (Dx Jx + Dy Jy)
-    L[3, 0] = -2
-    L[3, 1] = ce * 2 * Dx
-    L[3, 2] = ce * 2 * Dy
-    # XX* = (1 - 1/s_xx) * 2/3 (Dx Jx - Dy Jy)
-    L[4, 1] = cxx * 2 / 3 * Dx
-    L[4, 2] = -cxx * 2 / 3 * Dy
-    # XY* = (1 - 1/s_xx) * 1/3 (Dx Jy + Dy Jx)
-    L[5, 1] = cxx / 3 * Dy
-    L[5, 2] = cxx / 3 * Dx
-    L[6, 1] = -1
-    L[7, 2] = -1
-    L[8, 0] = 1
+    # perturbations of the stored fields and of the product fields, as rows over Phi
+    dr, djx, djy = np.eye(3)
+    dP, dQ, dR = 2 * vx * djx, 2 * vy * djy, vy * djx + vx * djy   # Jx^2, Jy^2, Jx Jy
+    v2 = vx * vx + vy * vy
+    th_e = (2 - 6 * v2) * (Dx * djx + Dy * djy) - 2 * (vx * Dx + vy * Dy) * dr
+    th_xx = (2 / 3 * (Dx * djx - Dy * djy) - 2 / 3 * (vx * Dx - vy * Dy) * dr
+             - 2 * (vx * (Dx * dP + Dy * dR) - vy * (Dx * dR + Dy * dQ)))
+    th_xy = (1 / 3 * (Dx * djy + Dy * djx) - 1 / 3 * (vx * Dy + vy * Dx) * dr
+             - vx * (Dx * dR + Dy * dQ) - vy * (Dx * dP + Dy * dR))
+    # equilibria (section 1-a table) linearised about the base state, plus the theta parts
+    L = _equilibrium_jacobian(vx, vy).astype(complex)
+    L[3] += ce * th_e
+    L[4] += cxx * th_xx
+    L[5] += cxx * th_xy
     P = M[:3]
     return P @ _propagation(kx, ky) @ MINV @ L
 
 
-def mrt_symbol(kx, ky, *, s_xx, s_e=1.0, s_q, s_eps=1.0):
-    """9x9 amplification matrix of the MRT step acting on the populations."""
+def mrt_symbol(kx, ky, *, s_xx, s_e=1.0, s_q, s_eps=1.0, vx=0.0, vy=0.0):
+    """9x9 amplification matrix of the MRT step acting on the populations, linearised about
+    the equilibrium populations of rho = 1, J = (vx, vy)."""
     S = np.diag([0, 0, 0, s_e, s_xx, s_xx, s_q, s_q, s_eps]).astype(float)
     Q = np.zeros((9, 9))
-    Q[0, 0] = Q[1, 1] = Q[2, 2] = 1
-    Q[3, 0] = -2
-    Q[6, 1] = -1
-    Q[7, 2] = -1
-    Q[8, 0] = 1
+    Q[:, :3] = _equilibrium_jacobian(vx, vy)   # m^eq depends on the conserved moments only
     C = MINV @ (np.eye(9) - S + S @ Q) @ M
     return _propagation(kx, ky) @ C
 

@@ -718,3 +718,194 @@ def test_theta_density_gradient_terms_are_the_bgk_defect(V, wave):
     e1 = _theta_error(nx, ny, mx, my, V)
     e2 = _theta_error(2 * nx if nx > 4 else nx, 2 * ny if ny > 4 else ny, mx, my, V)
     assert np.all(np.abs(2 * e2 - e1) < 1e-3), 2 * e2 - e1
+
+
+# ----------------------------- bulk viscosity in a mean flow (section 2, reading R6) ----
+#
+# Section 2 states that with its moments the viscosities in a mean flow V are nu (1 - 3V^2)
+# (shear, pinned above) and zeta (1 - 3V^2) (bulk), zeta = (1/s_e - 1/2)/3.  The bulk part is
+# the coefficient of zeta in the damping of the two sound waves, which only the velocity-cubic
+# term of theta_E reaches.  With theta_E = (2 + c|J|^2) div J - 2 J.grad rho that coefficient
+# is exactly (1 + c V^2/2)/2 per unit k^2 at every angle between V and k, so the statement
+# fixes c = -6 (the printed +6 gives (1 + 3V^2)/2, the opposite sign).
+
+def _acoustic_mean_damping(H, kx, ky, populations=False):
+    """Mean Re Gamma of the two acoustic roots (the hydrodynamic roots with more than half of
+    their weight in drho and the longitudinal momentum)."""
+    z, vec = np.linalg.eig(H)
+    k = math.hypot(kx, ky)
+    out = []
+    for i in np.argsort(-np.abs(z))[:3]:
+        m = MF.M[:3] @ vec[:, i] if populations else vec[:, i]
+        if (abs(m[0]) + abs(m[1] * kx / k + m[2] * ky / k)) / np.linalg.norm(m) > 0.5:
+            out.append(-np.log(z[i]).real)
+    assert len(out) == 2, out
+    return 0.5 * (out[0] + out[1])
+
+
+def _bulk_coefficient(damping, ks, zetas=(0.1, 0.2)):
+    """d(mean acoustic damping)/d zeta per unit k^2, extrapolated to k = 0 from two wave
+    numbers k and k/2 (Richardson: the next terms are O(k^2))."""
+    b = []
+    for k in ks:
+        g = [damping(k, z) / (k * k) for z in zetas]
+        b.append((g[1] - g[0]) / (zetas[1] - zetas[0]))
+    return (4 * b[1] - b[0]) / 3
+
+
+def _rate(zeta):
+    return 1.0 / (0.5 + 3.0 * zeta)
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("V", [0.05, 0.1, 0.2])
+@pytest.mark.parametrize("vang,kang", [(0.0, 0.0), (0.0, math.pi / 4), (math.pi / 2, 0.0),
+                                       (math.pi / 4, math.pi / 4), (0.3, 1.1)])
+def test_symbol_bulk_viscosity_in_a_mean_flow(stencil, V, vang, kang):
+    """The symbol linearised about J = V: the zeta coefficient of the sound damping is
+    (1 - 3V^2)/2 at every angle between V and k (section 2), for both stencils; and the
+    sound waves are advected at V (phase speeds V.k/|k| +- 1/sqrt 3)."""
+    s_xx = O.rate_from_viscosity(0.05)
+    vx, vy = V * math.cos(vang), V * math.sin(vang)
+
+    def damping(k, zeta):
+        kx, ky = k * math.cos(kang), k * math.sin(kang)
+        H = S.fd_symbol(kx, ky, s_xx=s_xx, s_e=_rate(zeta), stencil=stencil, vx=vx, vy=vy)
+        return _acoustic_mean_damping(H, kx, ky)
+
+    B = _bulk_coefficient(damping, (0.01, 0.005))
+    assert abs(2 * B - (1 - 3 * V * V)) < 1e-6, 2 * B
+    # advection of the acoustic pair: mean phase speed V.k/|k|, half-difference c_s
+    k = 1e-3
+    kx, ky = k * math.cos(kang), k * math.sin(kang)
+    z = np.linalg.eigvals(S.fd_symbol(kx, ky, s_xx=s_xx, s_e=1.3, stencil=stencil, vx=vx, vy=vy))
+    w = np.sort(-np.angle(z)) / k   # phase speeds of the three roots
+    vk = vx * math.cos(kang) + vy * math.sin(kang)
+    assert abs(0.5 * (w[0] + w[2]) - vk) < 1e-5 and abs(0.5 * (w[2] - w[0]) - 1 / math.sqrt(3)) < 1e-5
+
+
+@pytest.mark.parametrize("V", [0.1, 0.2])
+def test_d2q9_bulk_viscosity_averages_to_the_stated_factor(V):
+    """'As is known for D2Q9' (section 2): the MRT D2Q9 scheme, which has no theta term, damps
+    sound in a mean flow with a zeta coefficient that depends on the angle phi between V and
+    k, (1 - 3V^2 - 3/2 V^2 cos 2 phi)/2, whose average over phi is the stated (1 - 3V^2)/2."""
+    s_xx = O.rate_from_viscosity(0.05)
+    coef = []
+    for phi in (0.0, math.pi / 4, math.pi / 2, 3 * math.pi / 4):
+
+        def damping(k, zeta, phi=phi):
+            H = S.mrt_symbol(k, 0.0, s_xx=s_xx, s_e=_rate(zeta), s_q=1.0, vx=V * math.cos(phi), vy=V * math.sin(phi))
+            return _acoustic_mean_damping(H, k, 0.0, populations=True)
+
+        coef.append(2 * _bulk_coefficient(damping, (0.01, 0.005)))
+        assert abs(coef[-1] - (1 - 3 * V * V - 1.5 * V * V * math.cos(2 * phi))) < 1e-6
+    assert abs(np.mean(coef) - (1 - 3 * V * V)) < 1e-6
+
+
+def _oracle_flow_symbol(step, n, mode, V, s_e, eps=1e-6, **kw):
+    """3x3 amplification matrix of one step of the nonlinear oracle about the uniform state
+    rho = 1, J = V, by central differences: column j is the response at the wave's mode to
+    a plane wave of amplitude eps in field j (the step is translation invariant, so the mode
+    maps to itself; the conjugate mode does not reach it)."""
+    nx, ny = n if isinstance(n, tuple) else (n, n)
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    phase = 2 * np.pi * (mode[0] * x / nx + mode[1] * y / ny)
+    wave = np.cos(phase)
+    H = np.zeros((3, 3), dtype=complex)
+    for j in range(3):
+        resp = []
+        for sgn in (1.0, -1.0):
+            f = [np.zeros((ny, nx)), np.full((ny, nx), V[0]), np.full((ny, nx), V[1])]
+            f[j] = f[j] + sgn * eps * wave
+            resp.append(step(*f, s_e=s_e, **kw))
+        for i in range(3):
+            d = (resp[0][i] - resp[1][i]) / (2 * eps)
+            H[i, j] = np.sum(d * np.exp(-1j * phase)) * 2 / (nx * ny)
+    return H
+
+
+def _c_oracle_step(drho, jx, jy, *, s_e, s_xx, stencil):
+    return O.fd_run(drho, jx, jy, 1, s_xx=s_xx, s_e=s_e, stencil=stencil)
+
+
+def _oracle_bulk_error(step, V, direction, stencil=3):
+    """2 B - (1 - 3V^2) for the nonlinear oracle `step`, V along `direction`, k along x (on
+    N x 4 grids) or along the diagonal (on N x N grids), N = 64 and 128."""
+    s_xx = O.rate_from_viscosity(0.05)
+    u = np.array(direction, dtype=float) / math.hypot(*direction)
+    vel = (V * u[0], V * u[1])
+
+    out = {}
+    for kdiag in (False, True):
+        def damping(k, zeta, kdiag=kdiag):
+            n = int(round(2 * math.pi / (k / math.sqrt(2) if kdiag else k)))
+            dims, mode = ((n, n), (1, 1)) if kdiag else ((n, 4), (1, 0))
+            H = _oracle_flow_symbol(step, dims, mode, vel, _rate(zeta), s_xx=s_xx, stencil=stencil)
+            kx = 2 * math.pi / n
+            return _acoustic_mean_damping(H, kx, kx if kdiag else 0.0)
+
+        k1 = 2 * math.pi / 64 * (math.sqrt(2) if kdiag else 1.0)
+        out[kdiag] = 2 * _bulk_coefficient(damping, (k1, k1 / 2)) - (1 - 3 * V * V)
+    return out
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("mode,V", [((1, 0), (0.1, 0.0)), ((1, 1), (0.07, -0.05)), ((1, 0), (0.15, 0.1))])
+def test_oracle_linearised_in_a_mean_flow_equals_the_symbol(stencil, mode, V):
+    """The C oracle's own amplification matrix about a uniform flow (central differences of
+    one nonlinear step) equals the symbol's, at s_e != 1 where theta_E acts: every velocity
+    term of the theta expressions enters the comparison."""
+    n = 32
+    kx, ky = 2 * math.pi * mode[0] / n, 2 * math.pi * mode[1] / n
+    kw = dict(s_xx=1.6, stencil=stencil)
+    H = _oracle_flow_symbol(_c_oracle_step, n, mode, V, 1.3, **kw)
+    want = S.fd_symbol(kx, ky, s_e=1.3, vx=V[0], vy=V[1], **kw)
+    assert np.max(np.abs(H - want)) < 1e-8
+
+
+@pytest.mark.parametrize("V", [0.1, 0.2])
+def test_oracle_bulk_viscosity_in_a_mean_flow(V):
+    """The nonlinear C oracle itself, V along x and along the diagonal, sound waves along x
+    and along the diagonal: the zeta coefficient of the sound damping, extrapolated to k = 0
+    from wavelengths 64 and 128, is (1 - 3V^2)/2 (section 2).  The residue of the
+    extrapolation is O(k^4), below 1e-5 for both stencils; the printed sign would leave
+    6V^2 (6e-2 at V = 0.1)."""
+    for stencil in (3, 5):
+        for direction in ((1, 0), (1, 1)):
+            err = _oracle_bulk_error(_c_oracle_step, V, direction, stencil)
+            assert all(abs(e) < 5e-5 for e in err.values()), (stencil, direction, err)
+
+
+def test_bulk_pin_detects_a_planted_cubic_coefficient(tmp_path):
+    """The bulk pin fails for the printed sign and for other coefficients: a copy of the C
+    oracle with the velocity-cubic coefficient of theta_E replaced is compiled here, and its
+    zeta coefficient misses (1 - 3V^2)/2 by (c + 6) V^2 / 2."""
+    import ctypes
+    import subprocess
+
+    src = open(os.path.join(os.path.dirname(O.__file__), "fdlbm_oracle.c")).read()
+    term = "*te = (2.0 - 6.0 * (ux * ux + uy * uy))"
+    assert src.count(term) == 1
+    V = 0.1
+    for c in ("+6.0", "-9.0", "-3.0"):
+        path = tmp_path / f"planted{c[0] == '+'}{c[1]}.c"
+        path.write_text(src.replace(term, f"*te = (2.0 {c[0]} {c[1:]} * (ux * ux + uy * uy))"))
+        lib_path = str(path) + ".so"
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-o", lib_path,
+                        str(path), "-lm"], check=True)
+        lib = ctypes.CDLL(lib_path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_fd_step.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 5 + [dp] * 3 + [ctypes.c_int64]
+
+        def step(drho, jx, jy, *, s_e, s_xx, stencil, lib=lib):
+            a = [np.ascontiguousarray(f, dtype=np.float64).copy() for f in (drho, jx, jy)]
+            ny, nx = a[0].shape
+            rc = lib.oracle_fd_step(nx, ny, stencil, 0, 0.5, s_e, s_xx, 0.0, 0.0,
+                                    *(f.ctypes.data_as(dp) for f in a), 1)
+            assert rc == 0
+            return a
+
+        err = _oracle_bulk_error(step, V, (1, 0))
+        want = (float(c) + 6.0) * V * V / 2
+        for e in err.values():
+            assert abs(e - want) < 5e-5 and abs(e) > 100 * 5e-5, (c, err)
