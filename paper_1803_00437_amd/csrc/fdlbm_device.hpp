@@ -202,8 +202,10 @@ template <typename C> struct FdCoef {
 // Output: the nine post-collision populations as deviations f*_k - w_k.
 //
 // Section 2: theta_E, theta_XX, theta_XY (the defects of conservation at rho close to 1,
-// with v read as the stored momentum and the linear part of theta_XY as
-// (1/3)(d_x J_y + d_y J_x)); post-collision moments
+// with v read as the stored momentum, the linear part of theta_XY as
+// (1/3)(d_x J_y + d_y J_x), and theta_E = (2 - 6|J|^2) div J - 2 J.grad rho, the sign of
+// whose cubic term gives the bulk viscosity zeta (1 - 3V^2) in a mean flow that section 2
+// states); post-collision moments
 //   E = -2 rho + 3|J|^2/rho + (1 - 1/s_e) theta_E,  XX = (Jx^2 - Jy^2)/rho + (1 - 1/s_xx) theta_XX,
 //   XY = Jx Jy/rho + (1 - 1/s_xx) theta_XY,  q = -J,  eps = rho - 3|J|^2/rho;
 // then f* = M^{-1} m* written out per velocity (M^{-1} = M^T diag(1/9, 1/6, 1/6, 1/36,
@@ -218,7 +220,7 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
     const C j2 = p0 + q0;
 
     const C w = fmac(jx, rx, jy * ry);                               // J . grad rho
-    const C th_e = fmac(fmac(C(6), j2, C(2)), a + b, C(-2) * w);
+    const C th_e = fmac(fmac(C(-6), j2, C(2)), a + b, C(-2) * w);
     const C g = fmac(jx, rx, -(jy * ry));                             // Jx rx - Jy ry
     const C h = fmac(jx, sA, -(jy * sB));
     const C th_xx = fmac(C(2.0 / 3.0), (a - b) - g, C(-2) * h);

@@ -431,6 +431,64 @@ def test_sound_speed_and_damping(F, scheme, s_e):
     assert abs(gamma / k / k / ((nu + zeta) / 2) - 1) < 0.015
 
 
+def _device_flow_symbol(F, n, mode, V, s_e, stencil, s_xx=1.6, eps=1e-6):
+    """3x3 amplification matrix of one FP64 device step about the uniform flow rho = 1, J = V,
+    by central differences: column j is the response at the wave's mode to a plane wave of
+    amplitude eps in field j."""
+    nx, ny = n
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    phase = 2 * np.pi * (mode[0] * x / nx + mode[1] * y / ny)
+    H = np.zeros((3, 3), dtype=complex)
+    sim = F.FdLbm(nx, ny, scheme="fd", stencil=stencil, dtype="f64", s_xx=s_xx, s_e=s_e)
+    for j in range(3):
+        resp = []
+        for sgn in (1.0, -1.0):
+            f = [np.zeros((ny, nx)), np.full((ny, nx), V[0]), np.full((ny, nx), V[1])]
+            f[j] = f[j] + sgn * eps * np.cos(phase)
+            sim.set_state(*f)
+            sim.step(1)
+            resp.append(sim.get_state())
+        for i in range(3):
+            H[i, j] = np.sum((resp[0][i] - resp[1][i]) / (2 * eps) * np.exp(-1j * phase)) * 2 / (nx * ny)
+    sim.close()
+    return H
+
+
+def _mean_acoustic_damping(H, kx, ky):
+    z, vec = np.linalg.eig(H)
+    k = math.hypot(kx, ky)
+    g = [-np.log(z[i]).real for i in range(3)
+         if (abs(vec[0, i]) + abs(vec[1, i] * kx / k + vec[2, i] * ky / k)) / np.linalg.norm(vec[:, i]) > 0.5]
+    assert len(g) == 2, g
+    return 0.5 * (g[0] + g[1])
+
+
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("vdir", [(1, 0), (1, 1)])
+def test_bulk_viscosity_in_a_mean_flow(F, stencil, vdir):
+    """Section 2: in a mean flow V the bulk viscosity is zeta (1 - 3V^2).  The device step's
+    own amplification matrix about J = V (FP64, central differences of one step) equals the
+    oracle's symbol at s_e = 1.4, where the velocity-cubic term of theta_E acts; and the zeta
+    coefficient of its sound damping, extrapolated to k = 0 from wavelengths 64 and 128
+    (zeta = 0.1 and 0.2), is (1 - 3V^2)/2."""
+    V = 0.15
+    u = np.array(vdir, dtype=float) / math.hypot(*vdir)
+    vel = (V * u[0], V * u[1])
+    H = _device_flow_symbol(F, (32, 32), (1, 1), vel, 1.4, stencil)
+    want = S.fd_symbol(2 * math.pi / 32, 2 * math.pi / 32, s_xx=1.6, s_e=1.4, stencil=stencil, vx=vel[0], vy=vel[1])
+    dev = float(np.max(np.abs(H - want)))
+    b = []
+    for n in (64, 128):
+        k = 2 * math.pi / n
+        g = [_mean_acoustic_damping(_device_flow_symbol(F, (n, 8), (1, 0), vel, 1 / (0.5 + 3 * z), stencil), k, 0.0)
+             / (k * k) for z in (0.1, 0.2)]
+        b.append((g[1] - g[0]) / 0.1)
+    two_b = 2 * (4 * b[1] - b[0]) / 3
+    print(f"  FD{stencil} V={vel}: |H - symbol| {dev:.1e}; 2B {two_b:.6f} (1 - 3V^2 = {1 - 3 * V * V:.6f})")
+    assert dev < 1e-8
+    assert abs(two_b - (1 - 3 * V * V)) < 5e-5
+
+
 def test_d2q9_relative_viscosity_fig5(F):
     """Section 3-a, Fig. 5: nu(k)/nu_0 of the D2Q9 lattice Boltzmann model along {1,0}, {2,1},
     {1,1}, whose largest error the caption puts at 8 %.  The curve is not printed, nor are the
