@@ -1,6 +1,6 @@
 """Build libfdlbm.so (HIP, gfx950) in-tree: paper_1803_00437_amd/_build/libfdlbm.so.
 
-    python -m paper_1803_00437_amd.build [-v]
+    python -m paper_1803_00437_amd.build [-v] [--incremental]
 
 Every source under csrc/ is compiled by hipcc for gfx950 only, with FP contraction off
 (the kernels write their fused multiply-adds explicitly, so every kernel variant rounds
@@ -30,8 +30,16 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _compile(src, verbose):
+def _headers_mtime():
+    hdrs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
+    return max(os.path.getmtime(h) for h in hdrs)
+
+
+def _compile(src, verbose, incremental=False):
     obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), _headers_mtime(), os.path.getmtime(__file__)):
+        return obj
     cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
@@ -45,12 +53,14 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, incremental=False):
+    """Compile every source (incremental: only those older than their object file and the
+    headers are skipped) and link the library."""
     os.makedirs(OUT_DIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     if verbose:
@@ -61,4 +71,4 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))
