@@ -197,6 +197,38 @@ def band_errors(F, O, init, n, s_steps, rows, cases, threads, cpu_rows):
     return out, oracle_time
 
 
+def host_cpus():
+    """What the host offers: logical CPUs, those this process may run on, and the model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def oracle_single_thread(F, O, init, n, s_steps, rows):
+    """The FP64 oracle on one thread: the 3-point step on a band of `rows` rows (plus the
+    domain of dependence) of the same workload, wall clock of the step loop only."""
+    import numpy as np
+
+    m = 2 * s_steps
+    y0 = n // 3
+    band = tuple(np.ascontiguousarray(a[y0 - m:y0 + rows + m]) for a in init)
+    O.num_threads(1)
+    t0 = time.perf_counter()
+    O.fd_run(*band, s_steps, s_xx=F.fdlbm_rate_from_viscosity(NU), s_e=1.0, stencil=3)
+    dt = time.perf_counter() - t0
+    updates = band[0].size * s_steps
+    return {"value": updates / dt / 1e6, "unit": "MLUPS", "cores": O.num_threads(0),
+            "sample": f"{s_steps} steps on a {n} x {band[0].shape[0]}-row band "
+                      f"({updates / 1e6:.1f} M node updates in {dt:.1f} s)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +244,8 @@ def main():
     ap.add_argument("--err-rows", type=int, default=512)
     ap.add_argument("--cpu-rows", type=int, default=2048,
                     help="rows of the 3-point band whose FP64 oracle run is timed as the CPU baseline")
+    ap.add_argument("--cpu-rows-1t", type=int, default=512,
+                    help="rows of the band whose FP64 oracle run is timed on one thread")
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wavefront strip of the sweep kernel (0 = default)")
     ap.add_argument("--lane-cols", type=int, default=0, help="grid columns per lane of the sweep kernel (0 = default)")
     ap.add_argument("--only", default=None,
@@ -310,15 +344,21 @@ def main():
         errors, (updates, secs, band_rows) = band_errors(F, O, init, n, args.err_steps, args.err_rows, cases, threads,
                                               args.cpu_rows)
         print(f"# errors vs oracle: {errors}", file=sys.stderr, flush=True)
+        used = O.num_threads(0)
+        one = oracle_single_thread(F, O, init, n, args.err_steps, args.cpu_rows_1t)
+        O.num_threads(threads)
         cpu = {
             "value": updates / secs / 1e6,
             "unit": "MLUPS",
-            "cores": O.num_threads(0),
+            "cores": used,
             "kind": "oracle",
             "sample": f"FP64 CPU oracle, FD-LBM 3-point, {args.err_steps} steps on a {n} x "
                       f"{band_rows}-row band of the {n}x{n} decaying flow "
-                      f"({updates / 1e6:.1f} M node updates in {secs:.1f} s)",
+                      f"({updates / 1e6:.1f} M node updates in {secs:.1f} s, {used} OpenMP threads)",
+            "single_thread": one,
+            "host": host_cpus(),
         }
+        print(f"# cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
     counters = None
     if os.path.exists(COUNTERS):

@@ -66,7 +66,7 @@ typedef struct fdlbm_params {
     int32_t nx, ny;     /* grid; FD-LBM: nx >= 8; walls: ny >= 4; periodic y: ny >= 8      */
     int32_t scheme;     /* FDLBM_SCHEME_FD, FDLBM_SCHEME_MRT or FDLBM_SCHEME_LWACM          */
     int32_t stencil;    /* FD-LBM finite differences of section 2: 3 or 5 points           */
-    int32_t bc;         /* FDLBM_BC_PERIODIC or FDLBM_BC_WALLS_Y                            */
+    int32_t bc;         /* FDLBM_BC_PERIODIC, FDLBM_BC_WALLS_Y or FDLBM_BC_DISK             */
     int32_t dtype;      /* FDLBM_F64, FDLBM_F32, FDLBM_F16DEV, FDLBM_F16DEV_SR               */
     /* Relaxation rates, each in (0, 2).  Section 1-a: nu = (1/s_xx - 1/2)/3,
      * zeta = (1/s_e - 1/2)/3.  FD-LBM uses s_xx and s_e (its q and eps moments sit at
@@ -76,7 +76,7 @@ typedef struct fdlbm_params {
                          * (1/s_xx - 1/2)(1/s_q - 1/2) = 1/6 (section 3-b)                   */
     double force_x, force_y; /* uniform body force per node and step, Strang-split (section 1) */
     int32_t kernel;     /* FDLBM_KERNEL_*                                                     */
-    int32_t tile_rows;  /* sweep kernel: rows per wavefront, >= 2 (0 or 1 = choose); tuning  */
+    int32_t tile_rows;  /* sweep kernel: rows per wavefront, 2..1024 (0 or 1 = choose); tuning */
     int32_t check_every;/* > 0: fdlbm_step / mrt_step scan the state for non-finite values
                          * every check_every steps and return FDLBM_EUNSTABLE if one is found
                          * (this synchronises the stream at each check)                       */
@@ -175,8 +175,16 @@ int fdlbm_set_mode(fdlbm_ctx *c, const double *j0x, const double *j0y);
 /* A(t) for the current state (FDLBM_EINVAL if no mode was set).  Synchronises. */
 int fdlbm_mode_projection(fdlbm_ctx *c, double *out);
 
-/* Number of steps taken since the last set_state / set_populations. */
+/* Number of steps taken since the last set_state / set_populations (or since the count was
+ * set with fdlbm_set_step_count).  -1 for a NULL context. */
 int64_t fdlbm_step_count(const fdlbm_ctx *c);
+
+/* Set the step count (steps >= 0).  The count seeds the random bits of stochastic rounding
+ * (FDLBM_F16DEV_SR): step n draws bits from a hash of n.  To continue a saved run bit for bit,
+ * restore its state with fdlbm_set_state and then its count with this call; set_state
+ * alone starts the count at 0 and so replays the bits of the run's first steps.  Other
+ * dtypes ignore the count.  FDLBM_EINVAL for a NULL context or a negative count. */
+int fdlbm_set_step_count(fdlbm_ctx *c, int64_t steps);
 
 /* Tile-shape tuning (not part of the method; the results do not depend on the shape, only
  * the speed does).  Times `reps` launches (1..10000) of this context's step kernel for

@@ -31,6 +31,7 @@ EXPORTED = (
     "fdlbm_workspace_bytes", "fdlbm_create", "fdlbm_set_state", "fdlbm_get_state",
     "fdlbm_set_populations", "fdlbm_get_populations", "fdlbm_step", "mrt_step", "lwacm_step",
     "fdlbm_diagnostics", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
+    "fdlbm_set_step_count",
     "fdlbm_destroy", "fdlbm_strerror", "fdlbm_last_error", "fdlbm_rate_from_viscosity",
     "fdlbm_quartic_s_q", "fdlbm_device_copy", "fdlbm_autotune",
     "fdlbm_batch_workspace_bytes", "fdlbm_batch_create", "fdlbm_batch_set_state", "fdlbm_batch_get_state",
@@ -112,6 +113,7 @@ def load_library(path=LIB_PATH):
         "fdlbm_set_mode": (i32, [vp, dp, dp]),
         "fdlbm_mode_projection": (i32, [vp, dp]),
         "fdlbm_step_count": (i64, [vp]),
+        "fdlbm_set_step_count": (i32, [vp, i64]),
         "fdlbm_destroy": (None, [vp]),
         "fdlbm_strerror": (ctypes.c_char_p, [i32]),
         "fdlbm_last_error": (ctypes.c_char_p, []),
@@ -232,6 +234,10 @@ def fdlbm_step_count(ctx):
     return int(load_library().fdlbm_step_count(ctx))
 
 
+def fdlbm_set_step_count(ctx, steps):
+    _check(load_library().fdlbm_set_step_count(ctx, int(steps)), "fdlbm_set_step_count")
+
+
 def fdlbm_destroy(ctx):
     load_library().fdlbm_destroy(ctx)
 
@@ -321,6 +327,11 @@ class FdLbm:
     @property
     def steps(self):
         return fdlbm_step_count(self.ctx)
+
+    @steps.setter
+    def steps(self, n):
+        """Restore the step count (it seeds stochastic rounding; see fdlbm_set_step_count)."""
+        fdlbm_set_step_count(self.ctx, n)
 
     def autotune(self, reps=20):
         """Pick the fastest tile shape for this grid (fdlbm_autotune); returns

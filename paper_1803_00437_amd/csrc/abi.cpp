@@ -32,6 +32,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
 
+// rows per wavefront (FD-LBM sweep) or per tile (MRT sweep): beyond this a tile is taller
+// than any grid the kernels' index arithmetic is sized for
+constexpr int MAX_TILE_ROWS = 1024;
+
 double quartic(double s_xx) { return 1.0 / (0.5 + 1.0 / (6.0 * (1.0 / s_xx - 0.5))); }
 
 struct Layout {
@@ -79,7 +83,7 @@ int validate(const fdlbm_params *p)
     if (!std::isfinite(p->force_x) || !std::isfinite(p->force_y)) return FDLBM_EINVAL;
     if (p->bc == FDLBM_BC_WALLS_Y && !(wall_xi(*p) > 0.0 && wall_xi(*p) <= 1.0)) return FDLBM_EINVAL;
     if (p->kernel < FDLBM_KERNEL_AUTO || p->kernel > FDLBM_KERNEL_SWEEP) return FDLBM_EINVAL;
-    if (p->tile_rows < 0 || p->check_every < 0) return FDLBM_EINVAL;
+    if (p->tile_rows < 0 || p->tile_rows > MAX_TILE_ROWS || p->check_every < 0) return FDLBM_EINVAL;
     if (three_words(p->scheme)) {
         if (p->scheme == FDLBM_SCHEME_FD && p->stencil != 3 && p->stencil != 5)
             return FDLBM_EINVAL;  // the 9-point form is unstable on {1,1}
@@ -260,6 +264,13 @@ int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scra
 void fdlbm_destroy(fdlbm_ctx *c) { delete c; }
 
 int64_t fdlbm_step_count(const fdlbm_ctx *c) { return c ? c->steps : -1; }
+
+int fdlbm_set_step_count(fdlbm_ctx *c, int64_t steps)
+{
+    if (!c || steps < 0) return FDLBM_EINVAL;
+    c->steps = steps;
+    return FDLBM_OK;
+}
 
 int fdlbm_set_state(fdlbm_ctx *c, const double *drho, const double *jx, const double *jy)
 {

@@ -64,6 +64,24 @@ def test_invalid_parameters_are_rejected(bad):
     assert e.value.code == F.FDLBM_EINVAL
 
 
+@pytest.mark.parametrize("scheme", ["fd", "mrt"])
+def test_tile_rows_are_bounded(scheme):
+    """A tile taller than 1024 rows is rejected before any launch arithmetic (2^30 rows would
+    overflow the block count), for the FD-LBM and MRT sweep kernels alike."""
+    kw = dict(scheme=scheme, s_q=1.2) if scheme == "mrt" else dict(scheme=scheme)
+    F.fdlbm_workspace_bytes(good(tile_rows=1024, **kw))
+    for rows in (1025, 1 << 29, 1 << 30, (1 << 31) - 1, -1):
+        with pytest.raises(F.FdlbmError) as e:
+            F.fdlbm_workspace_bytes(good(tile_rows=rows, **kw))
+        assert e.value.code == F.FDLBM_EINVAL
+
+
+def test_set_step_count_rejects_null_and_negative():
+    lib = F.load_library()
+    assert lib.fdlbm_set_step_count(None, 5) == F.FDLBM_EINVAL
+    assert lib.fdlbm_step_count(None) == -1
+
+
 def test_wall_distance_is_checked_with_walls_only():
     """wall_xi: 0 selects 1/2, (0, 1] is accepted, other values are rejected with walls and
     ignored without them; MRT's vector sweep kernel has halfway bounce-back only."""
