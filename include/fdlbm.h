@@ -168,6 +168,30 @@ int lwacm_step(fdlbm_ctx *c, int64_t nsteps);
  * energy, max |J|, non-finite count and, if a mode was set, sum J.J0.  Synchronises. */
 int fdlbm_diagnostics(fdlbm_ctx *c, fdlbm_diag *out);
 
+/* Allocation-free diagnostics, for callers that cannot allocate device memory or hand the
+ * library a scratch buffer: work recorded under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It computes what fdlbm_diagnostics computes, with the
+ * same kernels in the same order (the results are identical bit for bit), but
+ *   - takes the state directly: `state` is a device buffer in the layout fdlbm_create's
+ *     state buffers use for `p` (scheme, dtype, nx, ny; FD-LBM and LW-ACM: the drho, Jx,
+ *     Jy planes; MRT: the nine population planes), e.g. the buffer a context's current
+ *     state is in (state_a after an even number of steps since fdlbm_create, else state_b);
+ *   - j0x, j0y: optional device FP64 planes (nx*ny each, both or neither) for the sums
+ *     <J, J0> and <J0, J0>; NULL leaves those two slots 0;
+ *   - out: caller-owned device memory for 8 doubles, written in the order mass, mom_x,
+ *     mom_y, kin_energy, max_abs_j, proj_num, proj_den, nonfinite (as a double);
+ *   - is asynchronous on hip_stream (NULL = default stream): nothing is copied to the host
+ *     and nothing synchronises, so the call can be recorded into a graph.
+ * It calls no allocation routine.  The reduction's block partials live in a static device
+ * array of 64 KiB (1024 blocks x 8 doubles) that each device holds from the first call until
+ * the process ends; every block overwrites its own partial, so nothing needs clearing.  The
+ * array's size does not depend on the grid: every p that fdlbm_workspace_bytes accepts fits,
+ * and any other returns FDLBM_EINVAL (also for a NULL state or out, or one J0 plane alone).
+ * All calls on one device share the array: calls that overlap on one device (concurrent
+ * streams or host threads) race.  FDLBM_EDEVICE if a launch fails. */
+int fdlbm_diagnostics_static(const fdlbm_params *p, const void *state, const double *j0x, const double *j0y,
+                             void *hip_stream, double *out);
+
 /* Store a reference velocity field J0 (host FP64, nx*ny each) in the scratch buffer for
  * the correlation A(t) = <J(t), J0> / <J0, J0> of section 3-a. */
 int fdlbm_set_mode(fdlbm_ctx *c, const double *j0x, const double *j0y);

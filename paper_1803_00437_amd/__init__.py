@@ -30,7 +30,7 @@ KERNEL = {"auto": 0, "reference": 1, "sweep": 2}
 EXPORTED = (
     "fdlbm_workspace_bytes", "fdlbm_create", "fdlbm_set_state", "fdlbm_get_state",
     "fdlbm_set_populations", "fdlbm_get_populations", "fdlbm_step", "mrt_step", "lwacm_step",
-    "fdlbm_diagnostics", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
+    "fdlbm_diagnostics", "fdlbm_diagnostics_static", "fdlbm_set_mode", "fdlbm_mode_projection", "fdlbm_step_count",
     "fdlbm_set_step_count",
     "fdlbm_destroy", "fdlbm_strerror", "fdlbm_last_error", "fdlbm_rate_from_viscosity",
     "fdlbm_quartic_s_q", "fdlbm_device_copy", "fdlbm_autotune",
@@ -110,6 +110,7 @@ def load_library(path=LIB_PATH):
         "mrt_step": (i32, [vp, i64]),
         "lwacm_step": (i32, [vp, i64]),
         "fdlbm_diagnostics": (i32, [vp, ctypes.POINTER(Diag)]),
+        "fdlbm_diagnostics_static": (i32, [P, vp, vp, vp, vp, vp]),
         "fdlbm_set_mode": (i32, [vp, dp, dp]),
         "fdlbm_mode_projection": (i32, [vp, dp]),
         "fdlbm_step_count": (i64, [vp]),
@@ -217,6 +218,14 @@ def fdlbm_diagnostics(ctx):
     d = Diag()
     _check(load_library().fdlbm_diagnostics(ctx, ctypes.byref(d)), "fdlbm_diagnostics")
     return {f: getattr(d, f) for f, _ in Diag._fields_}
+
+
+def fdlbm_diagnostics_static(params, state, out, j0x=0, j0y=0, stream=0):
+    """Allocation-free diagnostics of the state in device buffer `state` (int pointer, the
+    layout of `params`), written asynchronously as 8 doubles to device memory `out`; j0x, j0y
+    optional device FP64 planes.  Nothing synchronises."""
+    _check(load_library().fdlbm_diagnostics_static(ctypes.byref(params), state, j0x or None, j0y or None,
+                                                   stream or None, out), "fdlbm_diagnostics_static")
 
 
 def fdlbm_set_mode(ctx, j0x, j0y):

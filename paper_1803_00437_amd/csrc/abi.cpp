@@ -425,6 +425,20 @@ int fdlbm_diagnostics(fdlbm_ctx *c, fdlbm_diag *out)
     return FDLBM_OK;
 }
 
+int fdlbm_diagnostics_static(const fdlbm_params *p, const void *state, const double *j0x, const double *j0y,
+                             void *hip_stream, double *out)
+{
+    return guarded([&]() -> int {
+        int rc = validate(p);
+        if (rc) return rc;
+        if (!state || !out || (j0x == nullptr) != (j0y == nullptr)) return FDLBM_EINVAL;
+        const size_t n = (size_t)p->nx * (size_t)p->ny;
+        HIPCHK(launch_diag_static(p->scheme, p->dtype, state, n, j0x, j0y, out, static_cast<hipStream_t>(hip_stream)),
+               "fdlbm_diagnostics_static");
+        return FDLBM_OK;
+    });
+}
+
 int fdlbm_set_mode(fdlbm_ctx *c, const double *j0x, const double *j0y)
 {
     if (!c || !j0x || !j0y) return FDLBM_EINVAL;

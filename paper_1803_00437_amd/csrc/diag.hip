@@ -7,6 +7,8 @@
 // Quantities (section 3-a uses the correlation A(t) = <J(t), J0>/<J0, J0>):
 //   [0] sum drho, [1] sum jx, [2] sum jy, [3] 1/2 sum |J|^2/rho, [4] max |J|,
 //   [5] sum J.J0, [6] sum J0.J0, [7] count of nodes with a non-finite field.
+#include <mutex>
+
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
 
@@ -158,6 +160,49 @@ hipError_t launch_diag(int scheme, int dtype, const void *state, size_t n, const
     case FDLBM_F32: return diag_run<float>(mrt, state, n, j0x, j0y, partials, out, s);
     default: return diag_run<__half>(mrt, state, n, j0x, j0y, partials, out, s);
     }
+}
+
+// Allocation-free diagnostics (fdlbm_diagnostics_static) --------------------------------
+// The block partials of the reduction live in this file-scope array instead of a caller's
+// scratch buffer: 1024 blocks x 8 doubles = 64 KiB, held on every device the library runs
+// on until the process ends.  The reduction always uses DIAG_BLOCKS blocks, so the array
+// fits every grid.  Host code never passes the array's name to a kernel (in host code it
+// is a host-side stand-in): its device address is resolved once per device with
+// hipGetSymbolAddress, with that device current, and kept in static_ptr[].
+namespace {
+static __device__ __align__(256) double scratch[DIAG_BLOCKS * DIAG_SLOTS];
+static_assert(sizeof(double) * DIAG_BLOCKS * DIAG_SLOTS == 65536, "the static scratch is the 1024 block partials");
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex static_mu;
+double *static_ptr[STATIC_MAX_DEVICES] = {};
+
+hipError_t static_partials(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(static_mu);
+    if (!static_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        static_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = static_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_diag_static(int scheme, int dtype, const void *state, size_t n, const double *j0x,
+                              const double *j0y, double *out, hipStream_t s)
+{
+    double *partials = nullptr;
+    hipError_t e = static_partials(&partials);
+    if (e != hipSuccess) return e;
+    // every block writes its own partial, so nothing left by an earlier call is read
+    return launch_diag(scheme, dtype, state, n, j0x, j0y, partials, out, s);
 }
 
 hipError_t launch_pack(int dtype, const double *in, void *out, size_t count, hipStream_t s)

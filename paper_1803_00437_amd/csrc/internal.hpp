@@ -136,5 +136,9 @@ constexpr int DIAG_BLOCKS = 1024;
 constexpr int DIAG_SLOTS = 8;  // doubles per block partial
 hipError_t launch_diag(int scheme, int dtype, const void *state, size_t n, const double *j0x, const double *j0y,
                        double *partials, double *out, hipStream_t s);
+// The same reduction with its partials in a file-scope device array (no scratch argument);
+// out: DIAG_SLOTS doubles of device memory.  Calls that overlap on one device race.
+hipError_t launch_diag_static(int scheme, int dtype, const void *state, size_t n, const double *j0x,
+                              const double *j0y, double *out, hipStream_t s);
 
 }  // namespace fdlbm
