@@ -152,3 +152,110 @@ def disk_decay_rate(init, *, rules, nu, gamma0, **kw):
     kw.setdefault("s_xx", rate_from_viscosity(nu))
     disk_run(*init, t2, rules=rules, on_step=sample, **kw)
     return -math.log(amp[t2] / amp[t1]) / (t2 - t1)
+
+
+# ------------------------------------------------------------------ MRT D2Q9 in the disk ----
+#
+# The lattice Boltzmann columns of Tables 2 and 3 (BGK, MRT with and without the quartic
+# condition) close the disk with the linear interpolated bounce-back of Bouzidi, Firdaouss
+# and Lallemand, which section 3-b cites for its wall treatment.  Reading taken here:
+#   * fluid nodes r < R as for FD-LBM; every other node is solid and held at rest;
+#   * a boundary link joins a fluid node x and a solid node x + e_i; the wall cuts it at
+#     x + q e_i, 0 < q <= 1 (the root of |x + q e_i - c| = R);
+#   * after the periodic stream-collide step of the whole grid, the population that re-enters
+#     x from that link, along i' = -e_i, is
+#         q <  1/2:  2q f*_i(x) + (1 - 2q) f*_i(x - e_i)
+#         q >= 1/2:  f*_i(x) / (2q) + (2q - 1)/(2q) f*_i'(x)
+#     (halfway bounce-back f*_i(x) at q = 1/2); where x - e_i is solid too (a chord shorter
+#     than two links) the q < 1/2 case takes halfway bounce-back;
+#   * every post-collision value needed is still in the streamed grid: f*_i(x) sits at the
+#     solid node x + e_i, f*_i(x - e_i) at x itself, f*_i'(x) at x - e_i.
+
+def disk_links(nx, ny, cx, cy, R):
+    """Fluid mask and every boundary link (fluid node, direction i toward the wall, q), with
+    the same grid-fit rule as disk_ghost_rules.  Returns a dict: ``fluid`` (bool (ny, nx)),
+    ``j``, ``i``, ``k`` (direction 1..8 toward the wall), ``q``, ``back`` (whether x - e_k
+    is fluid)."""
+    rules = disk_ghost_rules(nx, ny, cx, cy, R)  # same fluid set and grid-fit checks
+    fluid = rules["fluid"]
+    from .matrix_form import E
+    rows = []
+    for j, i in zip(*np.nonzero(fluid)):
+        for k in range(1, 9):
+            ex, ey = E[k]
+            if fluid[j + ey, i + ex]:
+                continue
+            # |p + q e - c|^2 = R^2 with p inside: the root q in (0, 1]
+            px, py = i - cx, j - cy
+            a = ex * ex + ey * ey
+            b = 2 * (px * ex + py * ey)
+            c = px * px + py * py - R * R
+            q = (-b + math.sqrt(b * b - 4 * a * c)) / (2 * a)
+            assert 0.0 < q <= 1.0 + 1e-12, q
+            rows.append((j, i, k, min(q, 1.0), bool(fluid[j - ey, i - ex])))
+    cols = list(zip(*rows))
+    out = {"fluid": fluid}
+    for name, col, dt in zip(("j", "i", "k", "q", "back"), cols, (int, int, int, float, bool)):
+        out[name] = np.array(col, dtype=dt)
+    return out
+
+
+def interpolated_bounce_back(new, links):
+    """Apply the wall to populations `new` (9, ny, nx) just streamed by a periodic step of
+    the whole grid: every population re-entering a fluid node across a boundary link is
+    replaced by the interpolated bounce-back value.  All reads are of streamed values that
+    no replacement changes, so the links are independent of each other."""
+    from .matrix_form import E
+    opp = np.array([0, 3, 4, 1, 2, 7, 8, 5, 6])
+    j, i, k, q, back = links["j"], links["i"], links["k"], links["q"], links["back"]
+    ex, ey = E[k, 0], E[k, 1]
+    kb = opp[k]
+    fi_x = new[k, j + ey, i + ex]          # f*_k(x), streamed into the solid node x + e_k
+    fb_x = new[kb, j - ey, i - ex]         # f*_k'(x), streamed into x - e_k
+    fi_back = new[k, j, i]                 # f*_k(x - e_k), streamed into x
+    low = np.where(back, 2 * q * fi_x + (1 - 2 * q) * fi_back, fi_x)
+    high = fi_x / (2 * q) + (2 * q - 1) / (2 * q) * fb_x
+    out = np.array(new, copy=True)
+    out[kb, j, i] = np.where(q < 0.5, low, high)
+    return out
+
+
+def mrt_disk_run(df, nsteps, *, links, s_xx, s_e=1.0, s_q=None, s_eps=1.0, fx=0.0, fy=0.0, on_step=None):
+    """nsteps of the MRT D2Q9 step (eqs. 1-2) of the whole grid, then the interpolated
+    bounce-back on the disk's boundary links, then every solid node set to rest.  df:
+    population deviations (9, ny, nx); on_step(t, df) sees the populations after t steps."""
+    from . import mrt_run, quartic_s_q
+    if s_q is None:
+        s_q = quartic_s_q(s_xx)
+    solid = ~links["fluid"]
+    d = np.array(df, dtype=np.float64, copy=True)
+    d[:, solid] = 0.0
+    for t in range(nsteps):
+        if on_step is not None:
+            on_step(t, d)
+        d = mrt_run(d, 1, s_xx=s_xx, s_e=s_e, s_q=s_q, s_eps=s_eps, fx=fx, fy=fy)
+        d = interpolated_bounce_back(d, links)
+        d[:, solid] = 0.0
+    if on_step is not None:
+        on_step(nsteps, d)
+    return d
+
+
+def mrt_disk_decay_rate(init, *, links, nu, gamma0, **kw):
+    """Measured decay rate of the mode started from f = f^eq(init) (the same two-time
+    projection as disk_decay_rate), MRT with s_xx from nu unless given."""
+    from . import mrt_init, mrt_moments
+    t1, t2 = decay_times(gamma0)
+    fluid = links["fluid"]
+    j0x, j0y = np.where(fluid, init[1], 0.0), np.where(fluid, init[2], 0.0)
+    den = float(np.sum(j0x * j0x + j0y * j0y))
+    amp = {}
+
+    def sample(t, d):
+        if t in (t1, t2):
+            _, jx, jy = mrt_moments(d)
+            amp[t] = float(np.sum(jx * j0x + jy * j0y)) / den
+
+    kw.setdefault("s_xx", rate_from_viscosity(nu))
+    mrt_disk_run(mrt_init(*init), t2, links=links, on_step=sample, **kw)
+    return -math.log(amp[t2] / amp[t1]) / (t2 - t1)
