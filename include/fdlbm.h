@@ -89,9 +89,9 @@ typedef struct fdlbm_params {
                          * [1 - xi, N + xi] of Fig. 6).  FD-LBM: ghost rows by linear
                          * extrapolation with zero velocity on the wall, the expression chosen
                          * by where the wall cuts the link.  MRT: interpolated bounce-back of
-                         * Bouzidi et al. (halfway bounce-back at 1/2; other values run the
-                         * one-thread-per-node MRT kernel).  Ignored without walls.          */
-    /* FDLBM_BC_DISK (FD-LBM and LW-ACM only): a disk of radius disk_r centred at
+                         * Bouzidi et al. (halfway bounce-back at 1/2), in either MRT
+                         * kernel.  Ignored without walls.                                   */
+    /* FDLBM_BC_DISK: a disk of radius disk_r centred at
      * (disk_cx, disk_cy), in node units, inside the grid; section 3-b.  Fluid nodes lie at
      * distance r < disk_r from the centre.  Ghost nodes are the other nodes within Chebyshev
      * distance 3 of a fluid node; at r = disk_r + d on the ray of unit vector n, a ghost
@@ -105,6 +105,12 @@ typedef struct fdlbm_params {
      * node is then 3 nodes from the edges, so no periodic image enters a fluid update),
      * disk_r must exceed 3/2 (the sample at depth 3/2 then always has four fluid nodes) and
      * nx * ny must stay below 2^31.
+     * MRT D2Q9 (FP64 or FP32, either kernel, force allowed): every non-fluid node is solid
+     * and held at rest; after each periodic step of the whole grid, every population that
+     * re-enters a fluid node x across a boundary link (x + e_k solid, the wall cutting the
+     * link at x + q e_k) is the linear interpolated bounce-back of Bouzidi et al.:
+     * 2q f*_k(x) + (1 - 2q) f*_k(x - e_k) for q < 1/2 (halfway bounce-back f*_k(x) if
+     * x - e_k is solid), f*_k(x)/(2q) + (2q - 1)/(2q) f*_-k(x) for q >= 1/2.
      * Diagnostics sum over every node, ghost nodes included; give fdlbm_set_mode a J0 that
      * is zero outside the fluid to project on the fluid only.  Ignored for other bc.      */
     double disk_cx, disk_cy, disk_r;

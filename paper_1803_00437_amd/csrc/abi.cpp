@@ -41,6 +41,7 @@ double quartic(double s_xx) { return 1.0 / (0.5 + 1.0 / (6.0 * (1.0 / s_xx - 0.5
 struct Layout {
     size_t partials, out, mode, staging, fstar;
     size_t disk_dst, disk_src, disk_w, disk_span, disk_ring;  // ghost-node table (FDLBM_BC_DISK)
+    size_t mdisk_node, mdisk_kb, mdisk_q, mdisk_ring, mdisk_fspan;  // MRT boundary links (FDLBM_BC_DISK)
     size_t total;
 };
 
@@ -98,12 +99,12 @@ int validate(const fdlbm_params *p)
         if (p->lane_cols != 0 && p->lane_cols != 1 && p->lane_cols != 2 && p->lane_cols != 4) return FDLBM_EINVAL;
         if (p->kernel == FDLBM_KERNEL_SWEEP && !fd_sweep_supported(fd_args(*p), p->lane_cols)) return FDLBM_EINVAL;
     } else {
-        if (p->bc == FDLBM_BC_DISK) return FDLBM_EINVAL;  // the curved wall acts on (drho, J)
+        if (p->bc == FDLBM_BC_DISK) {
+            DiskTable t;
+            if (!disk_table(*p, &t)) return FDLBM_EINVAL;
+        }
         if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32) return FDLBM_EINVAL;
         if (!rate_ok(p->s_eps)) return FDLBM_EINVAL;
-        // interpolated bounce-back (walls away from the half-way point) runs on the
-        // one-thread-per-node kernel only
-        if (p->kernel == FDLBM_KERNEL_SWEEP && p->bc == FDLBM_BC_WALLS_Y && wall_xi(*p) != 0.5) return FDLBM_EINVAL;
         if (!p->quartic && !rate_ok(p->s_q)) return FDLBM_EINVAL;
     }
     return FDLBM_OK;
@@ -126,12 +127,15 @@ Layout layout(const fdlbm_params &p)
     L.staging = off;
     L.fstar = off;
     off += staging > fstar ? staging : fstar;
-    size_t ng = 0, nr = 0;
+    size_t ng = 0, nr = 0, nl = 0, nsr = 0;
+    const bool mrt_disk = p.bc == FDLBM_BC_DISK && !three_words(p.scheme);
     if (p.bc == FDLBM_BC_DISK) {
         DiskTable t;
         if (disk_table(p, &t)) {
-            ng = t.dst.size();
-            nr = t.ring.size();
+            ng = three_words(p.scheme) ? t.dst.size() : 0;
+            nr = three_words(p.scheme) ? t.ring.size() : 0;
+            nl = mrt_disk ? t.link_node.size() : 0;
+            nsr = mrt_disk ? t.solid_ring.size() : 0;
         }
     }
     L.disk_dst = off;
@@ -141,9 +145,19 @@ Layout layout(const fdlbm_params &p)
     L.disk_w = off;
     off += align256(sizeof(double) * 3 * ng);
     L.disk_span = off;
-    off += p.bc == FDLBM_BC_DISK ? align256(sizeof(int32_t) * 2 * size_t(p.ny)) : 0;
+    off += p.bc == FDLBM_BC_DISK && three_words(p.scheme) ? align256(sizeof(int32_t) * 2 * size_t(p.ny)) : 0;
     L.disk_ring = off;
     off += align256(sizeof(int32_t) * nr);
+    L.mdisk_node = off;
+    off += align256(sizeof(int32_t) * nl);
+    L.mdisk_kb = off;
+    off += align256(sizeof(int32_t) * nl);
+    L.mdisk_q = off;
+    off += align256(sizeof(double) * nl);
+    L.mdisk_ring = off;
+    off += align256(sizeof(int32_t) * nsr);
+    L.mdisk_fspan = off;
+    off += mrt_disk ? align256(sizeof(int32_t) * 2 * size_t(p.ny)) : 0;
     L.total = off;
     return L;
 }
@@ -175,6 +189,7 @@ struct fdlbm_ctx {
     int64_t steps;
     bool mode_set;
     DiskFill disk;   // FDLBM_BC_DISK: the ghost-node table in the scratch buffer
+    MrtDisk mdisk;   // FDLBM_BC_DISK, MRT: the boundary-link table in the scratch buffer
     bool disk_full;  // the next fill sets every rest node to rest (the state was just set)
 
     size_t n() const { return (size_t)p.nx * (size_t)p.ny; }
@@ -218,6 +233,7 @@ int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scra
         c->steps = 0;
         c->mode_set = false;
         c->disk = DiskFill{p->nx, p->ny, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
+        c->mdisk = MrtDisk{p->nx, p->ny, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr};
         c->disk_full = true;
         hipError_t e = hipGetDevice(&c->device);
         size_t sb = 0;
@@ -225,7 +241,33 @@ int fdlbm_create(const fdlbm_params *p, void *state_a, void *state_b, void *scra
         if (e == hipSuccess) e = hipMemsetAsync(state_a, 0, sb, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(state_b, 0, sb, c->stream);
         DiskTable t;  // outlives the uploads: the stream is synchronised below
-        if (e == hipSuccess && p->bc == FDLBM_BC_DISK) {
+        if (e == hipSuccess && p->bc == FDLBM_BC_DISK && !three_words(p->scheme)) {
+            if (!disk_table(*p, &t)) {
+                delete c;
+                return FDLBM_EINVAL;
+            }
+            char *sc = c->scratch;
+            const size_t nl = t.link_node.size(), nsr = t.solid_ring.size();
+            c->mdisk.nlinks = int(nl);
+            c->mdisk.nring = int(nsr);
+            c->mdisk.node = reinterpret_cast<const int32_t *>(sc + L.mdisk_node);
+            c->mdisk.kb = reinterpret_cast<const int32_t *>(sc + L.mdisk_kb);
+            c->mdisk.q = reinterpret_cast<const double *>(sc + L.mdisk_q);
+            c->mdisk.ring = reinterpret_cast<const int32_t *>(sc + L.mdisk_ring);
+            c->mdisk.fspan = reinterpret_cast<const int32_t *>(sc + L.mdisk_fspan);
+            if (nl) e = hipMemcpyAsync(sc + L.mdisk_node, t.link_node.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice,
+                                       c->stream);
+            if (e == hipSuccess && nl)
+                e = hipMemcpyAsync(sc + L.mdisk_kb, t.link_kb.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess && nl)
+                e = hipMemcpyAsync(sc + L.mdisk_q, t.link_q.data(), nl * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess && nsr)
+                e = hipMemcpyAsync(sc + L.mdisk_ring, t.solid_ring.data(), nsr * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sc + L.mdisk_fspan, t.fspan.data(), t.fspan.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, c->stream);
+        } else if (e == hipSuccess && p->bc == FDLBM_BC_DISK) {
             if (!disk_table(*p, &t)) {
                 delete c;
                 return FDLBM_EINVAL;
@@ -318,6 +360,7 @@ int fdlbm_set_populations(fdlbm_ctx *c, const double *df)
     HIPCHK(launch_pack(c->p.dtype, st, c->buf[c->cur], 9 * n, c->stream), "pack");
     HIPCHK(hipStreamSynchronize(c->stream), "set_populations");
     c->steps = 0;
+    c->disk_full = true;
     return FDLBM_OK;
 }
 
@@ -362,9 +405,9 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
         // the curved wall: ghost and rest nodes from the fluid, in place, before the step;
         // every rest node after the state was set or under a body force (which moves the
         // rest nodes too), else only the ring the previous step could reach
-        if (c->p.bc == FDLBM_BC_DISK) {
-            const bool full = c->disk_full || c->p.force_x != 0.0 || c->p.force_y != 0.0;
-            HIPCHK(launch_disk_fill(c->disk, c->p.dtype, src, full, c->stream), "disk fill launch");
+        const bool disk_full = c->disk_full || c->p.force_x != 0.0 || c->p.force_y != 0.0;
+        if (c->p.bc == FDLBM_BC_DISK && fd) {
+            HIPCHK(launch_disk_fill(c->disk, c->p.dtype, src, disk_full, c->stream), "disk fill launch");
             c->disk_full = false;
         }
         hipError_t e;
@@ -378,6 +421,13 @@ static int advance(fdlbm_ctx *c, int64_t nsteps)
             return device_error(e, c->p.scheme == FDLBM_SCHEME_FD    ? "fdlbm_step launch"
                                    : c->p.scheme == FDLBM_SCHEME_MRT ? "mrt_step launch"
                                                                       : "lwacm_step launch");
+        // MRT in the disk: the wall acts on the streamed populations, after the step; the
+        // solid nodes the links reach go back to rest (every solid node after the state was
+        // set or under a body force)
+        if (c->p.bc == FDLBM_BC_DISK && !fd) {
+            HIPCHK(launch_mrt_disk(c->mdisk, c->p.dtype, dst, disk_full, c->stream), "mrt disk launch");
+            c->disk_full = false;
+        }
         c->cur ^= 1;
         ++c->steps;
         if (c->p.check_every > 0 && c->steps % c->p.check_every == 0) {

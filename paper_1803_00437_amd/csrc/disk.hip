@@ -1,6 +1,8 @@
 // Curved no-slip wall around a disk (section 3-b): the ghost-node table, built on the host
 // once per context, and the kernel that fills ghost and rest nodes before each periodic
-// step.
+// step (FD-LBM, LW-ACM); for MRT D2Q9, the boundary-link table and the kernels that apply
+// the interpolated bounce-back of Bouzidi et al. after each periodic step and return the
+// solid nodes to rest.
 //
 // Section 3-b states the principle: the nodes just outside the fluid carry a virtual-fluid
 // state, extrapolated linearly with zero velocity on the wall, by an expression chosen from
@@ -142,6 +144,33 @@ bool build_disk_table(int nx, int ny, double cx, double cy, double r, DiskTable 
             t.ring.push_back(int32_t(long(j) * nx + i));
         }
     }
+    // MRT D2Q9: the boundary links, every (fluid node x, direction k) whose x + e_k is solid.
+    // The wall cuts the link at x + q e_k with |x + q e_k - c| = R, the root in (0, 1] of
+    // a q^2 + b q + c0 = 0 (x inside, x + e_k outside).
+    static const int EXk[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, EYk[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    t.fspan.assign(2 * size_t(ny), 0);
+    for (int j = 0; j < ny; ++j) {
+        t.fspan[2 * size_t(j)] = int32_t(flo[j]);
+        t.fspan[2 * size_t(j) + 1] = int32_t(fhi[j]);
+        for (long i = flo[j]; i <= fhi[j]; ++i)
+            for (int k = 1; k < 9; ++k) {
+                if (d.fluid(i + EXk[k], j + EYk[k])) continue;
+                const double px = double(i) - cx, py = double(j) - cy;
+                const double a = double(EXk[k] * EXk[k] + EYk[k] * EYk[k]);
+                const double b = 2.0 * (px * EXk[k] + py * EYk[k]);
+                const double c0 = px * px + py * py - r * r;
+                double q = (-b + std::sqrt(b * b - 4.0 * a * c0)) / (2.0 * a);
+                if (!(q > 0.0)) return false;
+                q = std::min(q, 1.0);
+                const bool back = d.fluid(i - EXk[k], j - EYk[k]);
+                t.link_node.push_back(int32_t(long(j) * nx + i));
+                t.link_kb.push_back(int32_t(k | (back ? 16 : 0)));
+                t.link_q.push_back(q);
+                t.solid_ring.push_back(int32_t((long(j) + EYk[k]) * nx + i + EXk[k]));
+            }
+    }
+    std::sort(t.solid_ring.begin(), t.solid_ring.end());
+    t.solid_ring.erase(std::unique(t.solid_ring.begin(), t.solid_ring.end()), t.solid_ring.end());
     *out = std::move(t);
     return true;
 }
@@ -195,7 +224,90 @@ __global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state, in
     }
 }
 
+// MRT: one thread per boundary link.  The population re-entering the fluid node x along
+// k' = -e_k is rebuilt from post-collision values still present in the streamed grid:
+// f*_k(x) at the solid node x + e_k, f*_k(x - e_k) at x itself, f*_k'(x) at x - e_k:
+//   q <  1/2:  2q f*_k(x) + (1 - 2q) f*_k(x - e_k)   (halfway bounce-back if x - e_k is solid)
+//   q >= 1/2:  f*_k(x) / (2q) + (2q - 1)/(2q) f*_k'(x)
+// No thread writes what another reads (the writes go to fluid nodes, direction k', which
+// no link reads), so the links run in any order, in place.
+template <typename T> __global__ __launch_bounds__(TPB) void mrt_disk_links_kernel(MrtDisk d, T *pop)
+{
+    using S = Storage<T>;
+    using C = typename S::C;
+    const int t = int(blockIdx.x) * TPB + int(threadIdx.x);
+    if (t >= d.nlinks) return;
+    const int kb = d.kb[t], k = kb & 15;
+    const bool back = (kb >> 4) != 0;
+    const int opp = k <= 4 ? ((k + 1) & 3) + 1 : ((k - 3) & 3) + 5;  // 1<->3, 2<->4, 5<->7, 6<->8
+    const int ex = (k == 1 || k == 5 || k == 8) - (k == 3 || k == 6 || k == 7);
+    const int ey = (k == 2 || k == 5 || k == 6) - (k == 4 || k == 7 || k == 8);
+    const size_t plane = size_t(d.nx) * size_t(d.ny);
+    const long node = d.node[t];
+    const long off = long(ex) + long(ey) * long(d.nx);
+    const C fi_x = S::load(pop[size_t(k) * plane + size_t(node + off)]);
+    const C fb_x = S::load(pop[size_t(opp) * plane + size_t(node - off)]);
+    const C fi_back = S::load(pop[size_t(k) * plane + size_t(node)]);
+    const C q = C(d.q[t]);
+    C v;
+    if (q < C(0.5))
+        v = back ? C(2) * q * fi_x + (C(1) - C(2) * q) * fi_back : fi_x;
+    else
+        v = fi_x / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * fb_x;
+    pop[size_t(opp) * plane + size_t(node)] = S::store(v);
+}
+
+// MRT: solid nodes to rest (all nine deviations zero): the ring the links reach, or, for a
+// full clearing, every node outside its row's fluid span (CLEAR_COLS columns per thread).
+template <typename T> __global__ __launch_bounds__(TPB) void mrt_disk_clear_kernel(MrtDisk d, T *pop, int full)
+{
+    using S = Storage<T>;
+    using C = typename S::C;
+    const size_t t = size_t(blockIdx.x) * TPB + threadIdx.x;
+    const size_t plane = size_t(d.nx) * size_t(d.ny);
+    if (!full) {
+        if (t >= size_t(d.nring)) return;
+        const size_t node = size_t(d.ring[t]);
+        for (int p = 0; p < 9; ++p) pop[p * plane + node] = S::store(C(0));
+        return;
+    }
+    const size_t per_row = (size_t(d.nx) + CLEAR_COLS - 1) / CLEAR_COLS;
+    if (t >= per_row * size_t(d.ny)) return;
+    const int j = int(t / per_row);
+    const int i0 = int(t - size_t(j) * per_row) * CLEAR_COLS;
+    const int a = d.fspan[2 * j], b = d.fspan[2 * j + 1];
+    for (int i = i0; i < min(i0 + CLEAR_COLS, d.nx); ++i) {
+        if (i >= a && i <= b) continue;
+        const size_t node = size_t(j) * size_t(d.nx) + size_t(i);
+        for (int p = 0; p < 9; ++p) pop[p * plane + node] = S::store(C(0));
+    }
+}
+
+template <typename T> hipError_t mrt_disk_run(const MrtDisk &d, T *pop, bool full, hipStream_t s)
+{
+    if (d.nlinks > 0) {
+        hipLaunchKernelGGL(mrt_disk_links_kernel<T>, dim3(unsigned((d.nlinks + TPB - 1) / TPB)), TPB, 0, s, d, pop);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const size_t per_row = (size_t(d.nx) + CLEAR_COLS - 1) / CLEAR_COLS;
+    const size_t threads = full ? per_row * size_t(d.ny) : size_t(d.nring);
+    if (threads == 0) return hipSuccess;
+    hipLaunchKernelGGL(mrt_disk_clear_kernel<T>, dim3(unsigned((threads + TPB - 1) / TPB)), TPB, 0, s, d, pop,
+                       full ? 1 : 0);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_mrt_disk(const MrtDisk &d, int dtype, void *pop, bool full, hipStream_t s)
+{
+    switch (dtype) {
+    case FDLBM_F64: return mrt_disk_run<double>(d, static_cast<double *>(pop), full, s);
+    case FDLBM_F32: return mrt_disk_run<float>(d, static_cast<float *>(pop), full, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, bool full, hipStream_t s)
 {

@@ -103,6 +103,13 @@ struct DiskTable {
     std::vector<int32_t> dst, src, span, ring;
     std::vector<double> w;  // 3 per ghost
     size_t nfluid = 0;
+    // MRT D2Q9 (interpolated bounce-back on the circle): per boundary link its fluid node,
+    // k | back << 4 (k: direction 1..8 toward the solid node; back: the node behind, x -
+    // e_k, is fluid) and the wall cut q in (0, 1]; the solid nodes the links reach (their
+    // streamed values are cleared after each step); per row j the fluid columns
+    // [fspan[2j], fspan[2j+1]] (empty when the first exceeds the second).
+    std::vector<int32_t> link_node, link_kb, solid_ring, fspan;
+    std::vector<double> link_q;
 };
 // Builds the table; false if the disk does not fit the grid (the fluid must stay 3 nodes
 // from every edge), holds no fluid node, or a ghost finds no fluid interpolation cell.
@@ -115,6 +122,15 @@ struct DiskFill {
 // full: set every rest node to rest (first step after the state was set, or a body force
 // acts); otherwise the ring only
 hipError_t launch_disk_fill(const DiskFill &f, int dtype, void *state, bool full, hipStream_t s);
+// MRT in the disk: after the periodic step of the whole grid (populations `pop`, in place),
+// the interpolated bounce-back of every boundary link, then the solid nodes set to rest
+// (full: every non-fluid node; otherwise the solid ring the links reach).  Two launches.
+struct MrtDisk {
+    int nx, ny, nlinks, nring;
+    const int32_t *node, *kb, *ring, *fspan;
+    const double *q;
+};
+hipError_t launch_mrt_disk(const MrtDisk &d, int dtype, void *pop, bool full, hipStream_t s);
 
 // MRT D2Q9 stream-collide (push) step.
 hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);

@@ -6,9 +6,9 @@
 // (mrt_sweep_kernel, the default).  Each relaxes the non-conserved moments of a node and
 // pushes f*_k to x + e_k in the other buffer.  A population whose destination lies beyond
 // a wall returns with the opposite velocity: halfway bounce-back (the wall half-way
-// between the last fluid row and the next one, section 3-c) in both kernels, and the
-// interpolated bounce-back of Bouzidi et al. for a wall at another distance xi, in the
-// one-thread-per-node kernel.  Algorithmic traffic: 9 values read + 9 written per node.
+// between the last fluid row and the next one, section 3-c), or the interpolated
+// bounce-back of Bouzidi et al. for a wall at another distance xi, in both kernels (they
+// agree bit for bit).  Algorithmic traffic: 9 values read + 9 written per node.
 #include "fd_sweep_body.hpp"
 #include "fdlbm_device.hpp"
 #include "internal.hpp"
@@ -136,8 +136,8 @@ template <typename C> __device__ __forceinline__ void collide(C (&f)[9], const M
 // returning population is the linear interpolation of Bouzidi, Firdaouss and Lallemand:
 //   xi <  1/2:  f_kbar(x) = 2 xi f*_k(x) + (1 - 2 xi) f*_k(x - e_k)
 //   xi >= 1/2:  f_kbar(x) = f*_k(x) / (2 xi) + (2 xi - 1) / (2 xi) f*_kbar(x)
-// which is halfway bounce-back at xi = 1/2 (the only case of the vector sweep kernel).
-// For xi < 1/2 the thread collides the node behind it, x - e_k, once more.
+// which is halfway bounce-back at xi = 1/2.  For xi < 1/2 the thread collides the node
+// behind it, x - e_k, once more.
 template <typename T, bool WALLS>
 __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
                                                   MrtCoef<typename Storage<T>::C> k, typename Storage<T>::C xi)
@@ -216,11 +216,17 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
 // stores go through range-checked buffer resources: the halo lanes' stores and the
 // prefetch past the last row use an offset beyond the row and are dropped, so every row
 // issues the same memory operations without branches.
-template <typename T, int CPL, bool WALLS>
+//
+// WALL: 0 periodic in y; 1 walls half-way between rows (halfway bounce-back); 2 walls at a
+// distance xi (interpolated bounce-back, the same expressions as mrt_kernel; for xi < 1/2
+// the row next to the wall row is loaded and collided once more for f*_k(x - e_k), the
+// populations at x - e_k coming from the neighbouring lane with the same DPP shifts).
+template <typename T, int CPL, int WALL>
 __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in, T *__restrict__ out, int nx, int ny,
                                                         int rows, int strips_x, int ntiles,
-                                                        MrtCoef<typename Storage<T>::C> k)
+                                                        MrtCoef<typename Storage<T>::C> k, typename Storage<T>::C xi)
 {
+    constexpr bool WALLS = WALL != 0;
     using C = typename Storage<T>::C;
     using namespace sweep;
     constexpr int S = 64 * CPL - 2 * CPL;  // stored columns per strip
@@ -243,6 +249,41 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
     };
     auto put = [&](int q, int y, const Group<T, CPL> &g) {
         buf_store_group<T, CPL>(row_rsrc(out + q * n, y, nx), soff, g);
+    };
+    // post-collision populations of row yy (the row next to a wall, collided once more)
+    auto collide_row = [&](int yy, C(&h)[CPL][9]) {
+        Group<T, CPL> g[9];
+        load_row(yy, true, g);
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) h[c][q] = Storage<T>::load(g[q].v[c]);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) collide<C>(h[c], k);
+    };
+    // populations returning from a wall into this row: kq leaves along (ex, ey) (ey = +1 at
+    // the top wall, -1 at the bottom one) and returns as kb; ynb is the row behind the node
+    auto bounce = [&](const C(&f)[CPL][9], int kq, int kb, int ex, int ynb, Group<T, CPL> &b) {
+        if (WALL == 1 || xi == C(0.5)) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) b.v[c] = Storage<T>::store(f[c][kq]);
+        } else if (xi > C(0.5)) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                b.v[c] = Storage<T>::store(f[c][kq] / (C(2) * xi) + (C(2) * xi - C(1)) / (C(2) * xi) * f[c][kb]);
+        } else if constexpr (WALL == 2) {
+            C h[CPL][9];
+            collide_row(ynb, h);
+            // f*_kq at x - e_kq: column - ex, i.e. from the left for ex = +1, the right for -1
+            const C edge = ex > 0 ? from_left(h[CPL - 1][kq]) : ex < 0 ? from_right(h[0][kq]) : C(0);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const C behind = ex == 0 ? h[c][kq]
+                                 : ex > 0 ? (c > 0 ? h[c > 0 ? c - 1 : 0][kq] : edge)
+                                          : (c < CPL - 1 ? h[c < CPL - 1 ? c + 1 : 0][kq] : edge);
+                b.v[c] = Storage<T>::store(C(2) * xi * f[c][kq] + (C(1) - C(2) * xi) * behind);
+            }
+        }
     };
     // collide row y (populations in `cur`) and push its post-collision populations
     auto process = [&](int y, const Group<T, CPL>(&cur)[9]) {
@@ -287,12 +328,9 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
         if (top_wall) {
             // the upward movers return into this row's downward planes, unshifted
             Group<T, CPL> b2, b5, b6;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                b2.v[c] = Storage<T>::store(f[c][2]);
-                b5.v[c] = Storage<T>::store(f[c][5]);
-                b6.v[c] = Storage<T>::store(f[c][6]);
-            }
+            bounce(f, 2, 4, 0, y - 1, b2);
+            bounce(f, 5, 7, 1, y - 1, b5);
+            bounce(f, 6, 8, -1, y - 1, b6);
             put(4, y, b2);
             put(7, y, b5);
             put(8, y, b6);
@@ -303,12 +341,9 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
         }
         if (bottom_wall) {
             Group<T, CPL> b4, b7, b8;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                b4.v[c] = Storage<T>::store(f[c][4]);
-                b7.v[c] = Storage<T>::store(f[c][7]);
-                b8.v[c] = Storage<T>::store(f[c][8]);
-            }
+            bounce(f, 4, 2, 0, y + 1, b4);
+            bounce(f, 7, 5, -1, y + 1, b7);
+            bounce(f, 8, 6, 1, y + 1, b8);
             put(2, y, b4);
             put(5, y, b7);
             put(6, y, b8);
@@ -371,12 +406,16 @@ hipError_t run_sweep(const MrtArgs &a, MrtCoef<typename Storage<T>::C> k, const 
     const int strips_x = (a.nx + S - 1) / S;
     const int ntiles = strips_x * ((a.ny + rows - 1) / rows);
     const int blocks = (ntiles + 3) / 4;
-    if (a.walls)
-        hipLaunchKernelGGL((mrt_sweep_kernel<T, CPL, true>), blocks, 256, 0, s, static_cast<const T *>(src),
-                           static_cast<T *>(dst), a.nx, a.ny, rows, strips_x, ntiles, k);
+    using C = typename Storage<T>::C;
+    if (a.walls && a.xi != 0.5)
+        hipLaunchKernelGGL((mrt_sweep_kernel<T, CPL, 2>), blocks, 256, 0, s, static_cast<const T *>(src),
+                           static_cast<T *>(dst), a.nx, a.ny, rows, strips_x, ntiles, k, C(a.xi));
+    else if (a.walls)
+        hipLaunchKernelGGL((mrt_sweep_kernel<T, CPL, 1>), blocks, 256, 0, s, static_cast<const T *>(src),
+                           static_cast<T *>(dst), a.nx, a.ny, rows, strips_x, ntiles, k, C(0.5));
     else
-        hipLaunchKernelGGL((mrt_sweep_kernel<T, CPL, false>), blocks, 256, 0, s, static_cast<const T *>(src),
-                           static_cast<T *>(dst), a.nx, a.ny, rows, strips_x, ntiles, k);
+        hipLaunchKernelGGL((mrt_sweep_kernel<T, CPL, 0>), blocks, 256, 0, s, static_cast<const T *>(src),
+                           static_cast<T *>(dst), a.nx, a.ny, rows, strips_x, ntiles, k, C(0.5));
     return hipGetLastError();
 }
 
@@ -384,7 +423,7 @@ template <typename T> hipError_t run(const MrtArgs &a, const void *src, void *ds
 {
     using C = typename Storage<T>::C;
     MrtCoef<C> k{C(a.s_e), C(a.s_xx), C(a.s_q), C(a.s_eps), C(0.5 * a.fx), C(0.5 * a.fy), C(a.fx), C(a.fy)};
-    if (a.kernel != FDLBM_KERNEL_REFERENCE && !(a.walls && a.xi != 0.5)) {
+    if (a.kernel != FDLBM_KERNEL_REFERENCE) {
         constexpr int CPL = sizeof(T) == 8 ? 2 : 4;
         if (a.nx % CPL == 0) return run_sweep<T, CPL>(a, k, src, dst, s);
         if (a.nx % 2 == 0) return run_sweep<T, 2>(a, k, src, dst, s);

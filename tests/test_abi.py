@@ -84,17 +84,17 @@ def test_set_step_count_rejects_null_and_negative():
 
 def test_wall_distance_is_checked_with_walls_only():
     """wall_xi: 0 selects 1/2, (0, 1] is accepted, other values are rejected with walls and
-    ignored without them; MRT's vector sweep kernel has halfway bounce-back only."""
+    ignored without them; both MRT kernels take any distance."""
     for xi in (0.0, 0.1, 0.5, 1.0):
         F.fdlbm_workspace_bytes(good(bc="walls", wall_xi=xi))
         F.fdlbm_workspace_bytes(good(bc="walls", wall_xi=xi, scheme="mrt", quartic=True))
     F.fdlbm_workspace_bytes(good(wall_xi=-3.0))
-    for bad in (dict(wall_xi=-0.1), dict(wall_xi=1.5), dict(wall_xi=float("nan")),
-                dict(wall_xi=0.3, scheme="mrt", quartic=True, kernel="sweep")):
+    for bad in (dict(wall_xi=-0.1), dict(wall_xi=1.5), dict(wall_xi=float("nan"))):
         with pytest.raises(F.FdlbmError) as e:
             F.fdlbm_workspace_bytes(good(bc="walls", **bad))
         assert e.value.code == F.FDLBM_EINVAL
-    F.fdlbm_workspace_bytes(good(bc="walls", wall_xi=0.5, scheme="mrt", quartic=True, kernel="sweep"))
+    for xi in (0.3, 0.5, 0.8):
+        F.fdlbm_workspace_bytes(good(bc="walls", wall_xi=xi, scheme="mrt", quartic=True, kernel="sweep"))
 
 
 def test_lwacm_is_periodic_without_force():
@@ -205,7 +205,7 @@ def test_disk_table_size_matches_the_oracle_ghost_count():
     dict(disk=(35.5, 35.5, 0.0)),
     dict(disk=(float("nan"), 35.5, 10.0)),
     dict(disk=(35.5, 35.5, float("inf"))),
-    dict(scheme="mrt", quartic=True),       # the curved wall acts on (drho, J) only
+    dict(scheme="mrt", quartic=True, dtype="f16"),  # MRT stores FP64 or FP32 populations
     dict(scheme="lwacm", force=(1e-6, 0.0)),
 ])
 def test_disk_parameters_are_checked(bad):
@@ -214,10 +214,33 @@ def test_disk_parameters_are_checked(bad):
     assert e.value.code == F.FDLBM_EINVAL
 
 
+def test_mrt_disk_table_size_matches_the_oracle_link_count():
+    """MRT in the disk: the scratch buffer grows by the boundary-link table (node, direction
+    and q per link), the solid nodes the links reach, and the fluid span of each row; the
+    link count is the oracle's (every fluid node with a solid neighbour, per direction)."""
+    import numpy as np
+    from oracle import disk as D
+
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    for (nx, ny, cx, cy, r) in ((72, 72, 35.5, 35.5, 29.9), (50, 41, 24.3, 19.8, 11.7), (12, 12, 5.5, 5.5, 1.6)):
+        links = D.disk_links(nx, ny, cx, cy, r)
+        ex, ey = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1]), np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+        nl = links["k"].size
+        nsr = len({(j + ey[k], i + ex[k]) for j, i, k in zip(links["j"], links["i"], links["k"])})
+        kw = dict(nx=nx, ny=ny, scheme="mrt", quartic=True)
+        _, base = F.fdlbm_workspace_bytes(good(**kw))
+        _, cb = F.fdlbm_workspace_bytes(good(bc="disk", disk=(cx, cy, r), **kw))
+        assert cb - base == 2 * a256(4 * nl) + a256(8 * nl) + a256(4 * nsr) + a256(8 * ny), (nx, ny, cx, cy, r)
+
+
 def test_disk_accepts_every_fd_variant():
     for kw in (dict(), dict(stencil=5), dict(dtype="f64"), dict(dtype="f16"), dict(scheme="lwacm"),
                dict(force=(1e-6, 0.0)), dict(kernel="reference"), dict(kernel="sweep", lane_cols=2),
-               dict(disk=(35.5, 35.5, 1.6)), dict(disk=(31.9, 31.9, 29.9))):
+               dict(disk=(35.5, 35.5, 1.6)), dict(disk=(31.9, 31.9, 29.9)),
+               dict(scheme="mrt", quartic=True), dict(scheme="mrt", s_q=1.3, dtype="f64", kernel="reference"),
+               dict(scheme="mrt", quartic=True, force=(1e-6, 0.0))):
         F.fdlbm_workspace_bytes(disk(**kw))
 
 

@@ -212,3 +212,123 @@ def test_disk_autotune_leaves_the_run_unchanged(F, dtype):
         sim.close()
     for u, v in zip(*out):
         assert np.array_equal(u, v)
+
+
+# ------------------------------------------------- MRT D2Q9 in the disk (Tables 2-3) ----
+
+LB_COLUMNS = {
+    "bgk_nu_0.05": ("0.05", "bgk"), "lbe_q_nu_0.05": ("0.05", "quartic"),
+    "bgk_nu_1/sqrt108": ("1/sqrt108", "bgk"), "lb_sq1.3_nu_1/sqrt108": ("1/sqrt108", 1.3),
+    "lb_q_nu_1/sqrt108": ("1/sqrt108", "quartic"),
+}
+
+
+def lb_rates(nu, kind):
+    s_xx = O.rate_from_viscosity(nu)
+    if kind == "bgk":
+        return dict(s_xx=s_xx, s_e=s_xx, s_q=s_xx, s_eps=s_xx)
+    return dict(s_xx=s_xx, s_e=1.0, s_q=O.quartic_s_q(s_xx) if kind == "quartic" else kind, s_eps=1.0)
+
+
+@pytest.fixture(scope="module")
+def links():
+    return {k: D.disk_links(*g) for k, g in GEOMS.items()}
+
+
+def run_mrt(F, geom, init, steps, **kw):
+    nx, ny, cx, cy, r = GEOMS[geom]
+    sim = F.FdLbm(nx, ny, scheme="mrt", bc="disk", disk=(cx, cy, r), **kw)
+    sim.set_state(*init)
+    sim.step(steps)
+    out = sim.get_populations()
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_mrt_disk_sweep_equals_reference_bitwise(F, geom, dtype, forced):
+    print(f"case mrt disk sweep-vs-reference geom={geom} dtype={dtype} forced={forced}", flush=True)
+    init = inside_noise(geom, seed=17)
+    kw = dict(dtype=dtype, force=(2e-6, -1e-6) if forced else (0.0, 0.0), **lb_rates(0.05, "quartic"))
+    a = run_mrt(F, geom, init, 40, kernel="reference", **kw)
+    b = run_mrt(F, geom, init, 40, kernel="sweep", **kw)
+    assert np.array_equal(a, b), float(np.max(np.abs(a - b)))
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+@pytest.mark.parametrize("kind", ["bgk", "quartic"])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_mrt_disk_matches_oracle(F, links, geom, kind, dtype, tol):
+    """A Stokes mode plus noise (noise alone when the centre is a node), 200 steps under a
+    small body force, every population of every node compared with the oracle's."""
+    nx, ny, cx, cy, r = GEOMS[geom]
+    nu, steps = 0.05, 200
+    init = inside_noise(geom, seed=5, amp=2e-4)
+    if geom != "node":
+        k = W.disk_mode_wavenumber(2, 1, r)
+        mode = W.disk_stokes_mode(nx, ny, cx, cy, r, 2, k, nu=nu)
+        init = tuple(a + b for a, b in zip(mode, init))
+    rates = lb_rates(nu, kind)
+    got = run_mrt(F, geom, init, steps, dtype=dtype, force=(1e-6, 0.0), **rates)
+    want = D.mrt_disk_run(O.mrt_init(*init), steps, links=links[geom], fx=1e-6, **rates)
+    err = math.sqrt(float(np.sum((got - want) ** 2)) / float(np.sum(want ** 2)))
+    print(f"  mrt disk {geom} {kind} {dtype}: rel L2 {err:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("geom", ["centred", "tiny"])
+@pytest.mark.parametrize("forced", [False, True])
+def test_mrt_disk_solid_nodes_set_by_the_caller_are_cleared(F, links, geom, forced):
+    """Populations on every node, the solid outside included: the first step clears every
+    solid node, later ones only the solid ring the links reach (or every solid node under a
+    body force); FP64 populations equal the oracle's, which clears every solid node at every
+    step, over 60 steps and again after a second set_populations."""
+    nx, ny, cx, cy, r = GEOMS[geom]
+    rng = np.random.default_rng(12)
+    df = O.mrt_init(*(1e-3 * rng.standard_normal((ny, nx)) for _ in range(3)))
+    force = (1e-6, -2e-6) if forced else (0.0, 0.0)
+    rates = lb_rates(0.05, "quartic")
+    sim = F.FdLbm(nx, ny, scheme="mrt", bc="disk", disk=(cx, cy, r), dtype="f64", force=force, **rates)
+    for rep in range(2):
+        sim.set_populations(df)
+        sim.step(60)
+        got = sim.get_populations()
+        want = D.mrt_disk_run(df, 60, links=links[geom], fx=force[0], fy=force[1], **rates)
+        err = math.sqrt(float(np.sum((got - want) ** 2)) / float(np.sum(want ** 2)))
+        print(f"  mrt disk {geom} forced={forced} set {rep}: rel L2 {err:.2e}")
+        assert err <= 1e-12
+        df = df[:, ::-1, ::-1].copy()
+    sim.close()
+
+
+@pytest.mark.parametrize("col", list(LB_COLUMNS))
+def test_lb_stokes_mode_rates_tables_2_3(F, links, col):
+    """FP64 device rates of the 17 modes for the BGK and MRT columns of Tables 2 and 3: equal
+    to the oracle's to 1e-8 (relative) and within 0.3 % of the paper's measured rates."""
+    key, kind = LB_COLUMNS[col]
+    nu = NUS[key]
+    rates = lb_rates(nu, kind)
+    worst = 0.0
+    for row, m, l in table_modes():
+        k = W.disk_mode_wavenumber(m, l, R)
+        init = W.disk_stokes_mode(N, N, C, C, R, m, k, nu=nu)
+        g0 = nu * k * k
+        t1, t2 = D.decay_times(g0)
+        sim = F.FdLbm(N, N, scheme="mrt", bc="disk", disk=(C, C, R), dtype="f64", **rates)
+        sim.set_state(*init)
+        sim.set_mode(np.where(links["centred"]["fluid"], init[1], 0.0), np.where(links["centred"]["fluid"], init[2], 0.0))
+        sim.step(t1)
+        a1 = sim.mode_projection()
+        sim.step(t2 - t1)
+        a2 = sim.mode_projection()
+        sim.close()
+        got = -math.log(a2 / a1) / (t2 - t1)
+        want = D.mrt_disk_decay_rate(init, links=links["centred"], nu=nu, gamma0=g0, **rates)
+        assert abs(got / want - 1) < 1e-8, (row, got, want)
+        ratio = (got / g0) / (1 + row[col]) - 1
+        worst = max(worst, abs(ratio))
+        assert abs(ratio) < 3e-3, (row, got / g0 - 1, row[col])
+        print(f"  {col} {row['family']} l={row['l']}: error {got / g0 - 1:+.5f} (paper {row[col]:+.5f})")
+    print(f"  {col}: worst rate ratio to the paper {worst:.4f}")

@@ -139,3 +139,27 @@ def test_narrowest_channel(F, scheme, xi):
         err = rel_l2(b, want)
         print(f"  {scheme} {dtype} xi={xi}: rel L2 {err:.2e}")
         assert err <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("xi", [0.2, 0.35, 0.5, 0.8, 1.0])
+@pytest.mark.parametrize("shape,tile_rows", [((296, 77), 0), ((70, 9), 2), ((523, 40), 3), ((41, 4), 16)])
+@pytest.mark.parametrize("forced", [False, True])
+def test_mrt_sweep_general_xi_equals_reference_bitwise(F, dtype, xi, shape, tile_rows, forced):
+    """The MRT vector sweep applies the interpolated bounce-back itself (for xi < 1/2 it
+    collides the row next to the wall once more and takes f*_k(x - e_k) across lanes):
+    populations equal the one-thread-per-node kernel's bit for bit, at every lane width
+    (nx a multiple of 4, even, odd), tile height and the 4-row channel."""
+    nx, ny = shape
+    print(f"case mrt walls xi={xi} dtype={dtype} shape={shape} tile_rows={tile_rows} forced={forced}", flush=True)
+    init = W.random_state(nx, ny, seed=nx + 3 * ny, amp=0.02)
+    kw = dict(scheme="mrt", dtype=dtype, s_xx=1.6, s_e=1.1, s_q=1.2, s_eps=1.3, wall_xi=xi,
+              force=(2e-5, -1e-5) if forced else (0.0, 0.0))
+    out = []
+    for kernel, rows in (("reference", 0), ("sweep", tile_rows)):
+        sim = F.FdLbm(nx, ny, bc="walls", kernel=kernel, tile_rows=rows, **kw)
+        sim.set_state(*init)
+        sim.step(9)
+        out.append(sim.get_populations())
+        sim.close()
+    assert np.array_equal(out[0], out[1]), float(np.max(np.abs(out[0] - out[1])))
