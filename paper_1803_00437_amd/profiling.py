@@ -66,6 +66,33 @@ def counter_means(d, counter):
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
 
 
+def launch_gaps(d, pattern):
+    """Idle time between the dispatches of a replayed sequence: over the window from the
+    first to the last dispatch whose kernel name contains `pattern`, the span, the time at
+    least one kernel ran (union of the dispatch intervals) and the dispatch count."""
+    rows = []
+    for p in _csvs(d, "kernel_trace.csv"):
+        for r in csv.DictReader(open(p)):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    idx = [i for i, r in enumerate(rows) if pattern in r[2]]
+    if not idx:
+        return None
+    win = rows[idx[0]:idx[-1] + 1]
+    busy, cur_s, cur_e = 0, None, None
+    for s0, e0, _ in win:
+        if cur_e is None or s0 > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = s0, e0
+        else:
+            cur_e = max(cur_e, e0)
+    busy += cur_e - cur_s
+    span = win[-1][1] - win[0][0]
+    return {"span_ns": span, "busy_ns": busy, "dispatches": len(win), "matching": len(idx),
+            "idle_frac": 1.0 - busy / span}
+
+
 def pick(table, pattern):
     hits = [k for k in table if pattern in k]
     if not hits:
@@ -116,6 +143,13 @@ def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=No
               f"{alg / avg_ns / 8000:.3f} of 8 TB/s)"]
     out = {"kernel": kname, "avg_ns": avg_ns, "calls": int(k["Calls"]), "alg_bytes_per_launch": alg, "n": n,
            "alg_gbs": alg / avg_ns}
+    if group:
+        g = launch_gaps(trace, kernel)
+        if g:
+            lines += [f"- replayed sequence (first to last `{kernel}` dispatch): {g['dispatches']} dispatches "
+                      f"({g['matching']} of them step kernels) over {g['span_ns'] / 1e6:.3f} ms, a kernel running "
+                      f"{g['busy_ns'] / 1e6:.3f} ms of it: {100 * g['idle_frac']:.2f} % idle between dispatches"]
+            out["launch_gaps"] = g
     if fetch and write:
         fm, wm = counter_means(fetch, "FETCH_SIZE"), counter_means(write, "WRITE_SIZE")
         kf, kw = fm[pick(fm, kernel)], wm[pick(wm, kernel)]
@@ -165,7 +199,7 @@ KERNELS = [
     # (the batch stem sums its per-class kernels, see summarise(group=True))
     ("fd3_f32_8192", "fd_sweep_kernel<float, 4, 3, false, false, 0>", 24 * N * N, "fd", FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP32 (3 words read + 3 written per node)"),
-    ("mrt_f32_8192", "mrt_sweep_kernel<float, 4, false>", 72 * N * N, "mrt", MRT_SOURCES,
+    ("mrt_f32_8192", "mrt_sweep_kernel<float, 4, 0>", 72 * N * N, "mrt", MRT_SOURCES,
      f"{DECAY}; MRT D2Q9, FP32 (9 words read + 9 written per node)"),
     ("fd3_f64_8192", "fd_sweep_kernel<double, 2, 3, false, false, 0>", 48 * N * N, None, FD_SOURCES,
      f"{DECAY}; FD-LBM 3-point, FP64"),
@@ -177,11 +211,11 @@ KERNELS = [
      f"{DECAY}; FD-LBM 5-point, FP32"),
     ("lwacm_f32_8192", "fd_sweep_kernel<float, 4, 1, false, false, 0>", 24 * N * N, None, FD_SOURCES,
      f"{DECAY}; LW-ACM (section 1-b), FP32, the same 3 words per node as FD-LBM"),
-    ("mrt_f64_8192", "mrt_sweep_kernel<double, 2, false>", 144 * N * N, None, MRT_SOURCES,
+    ("mrt_f64_8192", "mrt_sweep_kernel<double, 2, 0>", 144 * N * N, None, MRT_SOURCES,
      f"{DECAY}; MRT D2Q9, FP64"),
     ("fd3_f32_channel_16384x1024", "fd_sweep_kernel<float, 4, 3, true, true, 0>", 24 * CHANNEL, None, FD_SOURCES,
      "Poiseuille channel 16384 x 1024, walls at y=-1/2 and ny-1/2, body force; FD-LBM 3-point, FP32"),
-    ("mrt_f32_channel_16384x1024", "mrt_sweep_kernel<float, 4, true>", 72 * CHANNEL, None, MRT_SOURCES,
+    ("mrt_f32_channel_16384x1024", "mrt_sweep_kernel<float, 4, 1>", 72 * CHANNEL, None, MRT_SOURCES,
      "Poiseuille channel 16384 x 1024, halfway bounce-back walls, body force; MRT D2Q9, FP32"),
     ("fd3_f32_batch512", "fd_batch_kernel<float, ", 24 * BATCH_NODES, None,
      [f"{CSRC}/fd_batch.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"],

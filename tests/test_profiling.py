@@ -63,3 +63,15 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_launch_gaps_of_a_replayed_sequence(tmp_path):
+    """The idle share between dispatches is measured from the first to the last dispatch of
+    the step kernel: overlapping dispatches count once, the gaps between them count as idle."""
+    trace = str(tmp_path / "trace")
+    _write_csv(os.path.join(trace, "vm", "1_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+               [["other", 0, 50], ["fd_batch_kernel<float, 4, 0>", 100, 200], ["fd_batch_kernel<float, 4, 2>", 210, 400],
+                ["proj_partials<float>", 390, 420], ["fd_batch_kernel<float, 4, 0>", 500, 600], ["other", 700, 800]])
+    g = P.launch_gaps(trace, "fd_batch_kernel")
+    assert g["span_ns"] == 500 and g["busy_ns"] == 100 + 210 + 100 and g["dispatches"] == 4 and g["matching"] == 3
+    assert g["idle_frac"] == pytest.approx(1 - 410 / 500)
