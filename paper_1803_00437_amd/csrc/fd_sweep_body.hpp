@@ -602,7 +602,13 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nx = a.nx, ny = a.ny;
-    const int xl = sx * G::S - G::P + CPL * lane;  // first column of this lane (unwrapped)
+    // first column of this lane (unwrapped).  With element-aligned accesses the last strip of
+    // a grid wider than one strip is shifted left to end at column nx - 1: no lane's columns
+    // then cross the periodic edge (it falls between lanes), so no lane needs the per-column
+    // path.  The columns it shares with the strip before it are computed by both, from the
+    // same inputs in the same order, and both store the same bits there.
+    const bool shift_last = AM == AM_UNAL && nx > G::S && (sx + 1) * G::S >= nx;
+    const int xl = (shift_last ? nx - G::S : sx * G::S) - G::P + CPL * lane;
     const bool stored = CPL * lane >= G::P && CPL * lane < G::P + G::S;  // the strip's own columns
     static_assert(AM != AM_UNAL || sizeof(T) >= 4, "element-aligned vector accesses need 4- or 8-byte elements");
     const LaneCols<CPL, AM> lc = make_lane_cols<T, CPL, AM>(xl, nx, stored);
