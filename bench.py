@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wavefront strip of the sweep kernel (0 = default)")
     ap.add_argument("--lane-cols", type=int, default=0, help="grid columns per lane of the sweep kernel (0 = default)")
     ap.add_argument("--only", default=None,
-                    help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16, lwacm_f32")
+                    help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16, lwacm_f32, batch")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default tile shapes instead of tuning them before timing")
     ap.add_argument("--copy-probe", action="store_true",
@@ -278,6 +278,10 @@ def main():
     copy_gbs = measure_copy(F, torch, probe=args.copy_probe)
     print(f"# streaming copy (fdlbm_device_copy, 1 GiB): {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
+    if args.only == "batch":
+        batch = run_batch(F, torch, W, args.batch_steps, max(10, args.batch_steps // 4), autotune=not args.no_autotune)
+        print(json.dumps({"case": "batch", **batch}), flush=True)
+        return
     if args.only:
         name, dtype = args.only.split("_")
         scheme = name if name in ("mrt", "lwacm") else "fd"

@@ -256,8 +256,8 @@ def test_unit_rates_reduce_every_scheme_to_bgk(F, walls):
 def test_fd_in_a_mean_flow_matches_oracle(F, stencil, dtype, kernel, V):
     """A noisy state carried by a uniform flow |V| ~ 0.1 at s_e = 1.45, where theta_E acts and
     its velocity-cubic term (6|J|^2 div J, reading R6) is 6 % of its linear part: every node
-    against the oracle after 80 steps (the printed sign of that term would move the result by
-    3.5-4 %, far above the tolerances)."""
+    against the oracle after 80 steps (the printed sign of that term would move the deviation
+    from the mean flow by 3.5-4 %, the state by 0.3 %, far above the tolerances)."""
     nx, ny, steps = 83, 52, 80
     print(f"case fd mean flow stencil={stencil} dtype={dtype} kernel={kernel} V={V}", flush=True)
     r, x, y = W.random_state(nx, ny, seed=33, amp=0.01)
@@ -269,8 +269,9 @@ def test_fd_in_a_mean_flow_matches_oracle(F, stencil, dtype, kernel, V):
     got = sim.get_state()
     sim.close()
     want = O.fd_run(r, x, y, steps, stencil=stencil, **kw)
-    # compare the deviations from the mean flow, which carry the dynamics
+    # the tolerances are relative to the state; the deviation from the mean flow, which
+    # carries the dynamics (and the cubic term's effect), is about 8 % of it
+    err = rel_l2(got, want)
     dev = lambda s: (s[0], s[1] - V[0], s[2] - V[1])
-    err = rel_l2(dev(got), dev(want))
-    print(f"  rel L2 (deviation from the mean flow) = {err:.3e}")
+    print(f"  rel L2 = {err:.3e} (of the deviation from the mean flow: {rel_l2(dev(got), dev(want)):.3e})")
     assert err <= TOL[dtype]
