@@ -9,6 +9,9 @@ tests require the two oracles to agree to rounding, which guards each against sl
 transcription in the other.
 
 Same conventions as the C oracle: fields (ny, nx), x fastest, deviations from rest.
+Covered: the FD-LBM step (3-, 5-, 9-point differences, periodic or walls at any distance
+xi, body force), the MRT step (periodic or walls with interpolated bounce-back) and the
+LW-ACM step of section 1-b.
 """
 from __future__ import annotations
 
@@ -53,20 +56,44 @@ def ddy(a, stencil):
     return sum(w * _shift(a, dy, dx) for dx, dy, w in STENCILS[stencil])
 
 
-def _pad_walls(a, g, parity):
-    """g ghost rows on each side; mirror about y=-1/2 and y=ny-1/2 with the given parity."""
-    lo = parity * a[:g][::-1]
-    hi = parity * a[-g:][::-1]
-    return np.concatenate([lo, a, hi], axis=0)
+def _ghosts(rows, g, parity, xi):
+    """Ghost rows at distances 1..g beyond a wall that lies xi beyond rows[0] (rows[m] is the
+    m-th fluid row counted from the wall).  Sections 3-b and 3-c (reading R18): the ghost at
+    distance d beyond the wall holds the value at its mirror point d inside the fluid, the
+    velocity negated (parity -1; density parity +1), interpolated linearly between the fluid
+    rows around that point; a mirror point between the wall and rows[0] takes the velocity
+    interpolated between zero on the wall and rows[0], and the density of rows[0]."""
+    out = []
+    for dist in range(1, g + 1):
+        ym = dist - 2 * xi  # ghost row at -dist, wall at -xi: mirror point at -xi + (dist - xi)
+        if ym >= 0:
+            s0 = int(np.floor(ym))
+            t = ym - s0
+            v = (1 - t) * rows[s0] + (t * rows[s0 + 1] if t > 0 else 0.0)
+            out.append(parity * v)
+        elif parity > 0:
+            out.append(np.array(rows[0], copy=True))
+        else:
+            out.append(-((ym + xi) / xi) * rows[0])
+    return out
 
 
-def fd_step(drho, jx, jy, *, s_xx, s_e=1.0, stencil=3, walls=False, fx=0.0, fy=0.0):
-    """One FD-LBM step (section 2) on whole arrays."""
+def _pad_walls(a, g, parity, xi=0.5):
+    """g ghost rows on each side for walls at distance xi beyond the first and last rows
+    (xi = 1/2: the mirror about y = -1/2 and y = ny - 1/2)."""
+    lo = _ghosts(a, g, parity, xi)[::-1]          # rows -g .. -1
+    hi = _ghosts(a[::-1], g, parity, xi)          # rows ny .. ny + g - 1
+    return np.concatenate([np.array(lo), a, np.array(hi)], axis=0)
+
+
+def fd_step(drho, jx, jy, *, s_xx, s_e=1.0, stencil=3, walls=False, xi=0.5, fx=0.0, fy=0.0):
+    """One FD-LBM step (section 2) on whole arrays; walls at distance xi beyond the first and
+    last rows."""
     g = 3 if walls else 0
     if walls:
-        r = _pad_walls(drho, g, +1.0)
-        vx = _pad_walls(jx, g, -1.0) + 0.5 * fx
-        vy = _pad_walls(jy, g, -1.0) + 0.5 * fy
+        r = _pad_walls(drho, g, +1.0, xi)
+        vx = _pad_walls(jx, g, -1.0, xi) + 0.5 * fx
+        vy = _pad_walls(jy, g, -1.0, xi) + 0.5 * fy
     else:
         r, vx, vy = drho, jx + 0.5 * fx, jy + 0.5 * fy
     rho = 1.0 + r
@@ -112,8 +139,11 @@ def mrt_init(drho, jx, jy):
     return np.einsum("kl,lyx->kyx", MINV, equilibrium_moments(drho, jx, jy))
 
 
-def mrt_step(df, *, s_xx, s_e=1.0, s_q, s_eps=1.0, walls=False, fx=0.0, fy=0.0):
-    """One MRT step (eqs. 1-2) on whole arrays; halfway bounce-back on walls."""
+def mrt_step(df, *, s_xx, s_e=1.0, s_q, s_eps=1.0, walls=False, xi=0.5, fx=0.0, fy=0.0):
+    """One MRT step (eqs. 1-2) on whole arrays.  Walls at distance xi beyond the first and
+    last rows: the population that would come from beyond a wall is the linear interpolated
+    bounce-back of Bouzidi, Firdaouss and Lallemand of the one that left toward it, with the
+    wall cutting the link at q = xi (halfway bounce-back at 1/2)."""
     m = np.einsum("lk,kyx->lyx", M, df)
     meq = equilibrium_moments(m[0], m[1] + 0.5 * fx, m[2] + 0.5 * fy)
     s = np.array([0, 0, 0, s_e, s_xx, s_xx, s_q, s_q, s_eps])[:, None, None]
@@ -126,11 +156,19 @@ def mrt_step(df, *, s_xx, s_e=1.0, s_q, s_eps=1.0, walls=False, fx=0.0, fy=0.0):
         new[k] = _shift(fstar[k], -ex, -ey)
     if walls:
         opp = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+        q = xi
         for k, (ex, ey) in enumerate(E):
-            if ey == 1:  # would have come from beyond the lower wall
-                new[k][0] = fstar[opp[k]][0]
-            if ey == -1:
-                new[k][-1] = fstar[opp[k]][-1]
+            if ey == 0:
+                continue
+            row = 0 if ey == 1 else -1       # the fluid row next to the wall it came through
+            i = opp[k]                       # the population that left toward that wall
+            out_i = fstar[i][row]
+            if q < 0.5:
+                # f*_i at x - e_i, the node one row further inside
+                behind = _shift(fstar[i], -E[i][0], -E[i][1])[row]
+                new[k][row] = 2 * q * out_i + (1 - 2 * q) * behind
+            else:
+                new[k][row] = out_i / (2 * q) + (2 * q - 1) / (2 * q) * fstar[k][row]
     return new
 
 
@@ -139,6 +177,29 @@ def mrt_run(df, nsteps, **kw):
     for _ in range(nsteps):
         d = mrt_step(d, **kw)
     return d
+
+
+def lwacm_step(drho, jx, jy, *, nu):
+    """One LW-ACM step (section 1-b) on whole periodic arrays: f*_k(x) = f^eq_k(x) +
+    Theta (f^eo_k(x + e_k) - f^eo_k(x)), Theta = 1 - 6 nu, with f^eo the part of the
+    equilibrium odd in J (its J and q moments), then f_k(x + e_k) = f*_k(x)."""
+    theta = 1.0 - 6.0 * nu
+    feq = np.einsum("kl,lyx->kyx", MINV, equilibrium_moments(drho, jx, jy))
+    z = np.zeros_like(jx)
+    feo = np.einsum("kl,lyx->kyx", MINV, np.stack([z, jx, jy, z, z, z, -jx, -jy, z]))
+    new = np.empty_like(feq)
+    for k, (ex, ey) in enumerate(E):
+        fstar = feq[k] + theta * (_shift(feo[k], ex, ey) - feo[k])
+        new[k] = _shift(fstar, -ex, -ey)
+    m = np.einsum("lk,kyx->lyx", M[:3], new)
+    return m[0], m[1], m[2]
+
+
+def lwacm_run(drho, jx, jy, nsteps, **kw):
+    s = (np.array(drho, dtype=float), np.array(jx, dtype=float), np.array(jy, dtype=float))
+    for _ in range(nsteps):
+        s = lwacm_step(*s, **kw)
+    return s
 
 
 def mrt_moments(df):

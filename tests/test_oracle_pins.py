@@ -155,15 +155,38 @@ def test_c_oracle_equals_matrix_form(stencil, walls, force):
         assert np.max(np.abs(u - v)) < 1e-16
 
 
-@pytest.mark.parametrize("walls", [False, True])
-def test_mrt_c_oracle_equals_matrix_form(walls):
+@pytest.mark.parametrize("stencil", [3, 5])
+@pytest.mark.parametrize("xi", [0.15, 0.35, 0.5, 0.8, 1.0])
+def test_c_oracle_equals_matrix_form_walls_at_any_distance(stencil, xi):
+    """The ghost rows of walls at distance xi (reading R18), written independently in both
+    renderings (the C one row by row from a rule table, the NumPy one from the mirror point
+    of each ghost), give the same steps."""
+    r, x, y = W.random_state(9, 10, seed=15, amp=0.03)
+    kw = dict(s_xx=1.4, s_e=1.2, stencil=stencil, walls=True, xi=xi, fx=3e-4, fy=-1e-4)
+    a = O.fd_run(r, x, y, 8, **kw)
+    b = MF.fd_run(r, x, y, 8, **kw)
+    for u, v in zip(a, b):
+        assert np.max(np.abs(u - v)) < 1e-16
+
+
+@pytest.mark.parametrize("walls,xi", [(False, 0.5), (True, 0.5), (True, 0.2), (True, 0.7), (True, 1.0)])
+def test_mrt_c_oracle_equals_matrix_form(walls, xi):
     r, x, y = W.random_state(13, 11, seed=6, amp=0.03)
     df = O.mrt_init(r, x, y)
     assert np.max(np.abs(df - MF.mrt_init(r, x, y))) < 1e-17
-    kw = dict(s_xx=1.7, s_e=1.25, s_q=1.1, s_eps=1.35, walls=walls, fx=1e-4, fy=2e-5)
+    kw = dict(s_xx=1.7, s_e=1.25, s_q=1.1, s_eps=1.35, walls=walls, xi=xi, fx=1e-4, fy=2e-5)
     a = O.mrt_run(df, 8, **kw)
     b = MF.mrt_run(df, 8, **kw)
     assert np.max(np.abs(a - b)) < 1e-16
+
+
+@pytest.mark.parametrize("nu", [0.02, 1 / 6, 0.1])
+def test_lwacm_c_oracle_equals_matrix_form(nu):
+    r, x, y = W.random_state(13, 11, seed=7, amp=0.03)
+    a = O.lwacm_run(r, x, y, 8, nu=nu)
+    b = MF.lwacm_run(r, x, y, 8, nu=nu)
+    for u, v in zip(a, b):
+        assert np.max(np.abs(u - v)) < 1e-16
 
 
 # ----------------------------------------------- exact special case: BGK, tau = 1 ----
