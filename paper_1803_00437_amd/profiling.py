@@ -193,6 +193,23 @@ FD_COUNTER_ARGS = ["--steps", "20", "--warmup", "2", "--no-cpu", "--no-compare",
                    "--no-autotune"]
 MRT_COUNTER_ARGS = ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--copy-probe", "--no-autotune"]
 
+# VALU passes (one rocprofv3 --pmc run each): instructions issued and cycles the SIMDs spent
+# issuing them, per dispatch of the step kernel
+VALU_COUNTERS = ["SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", "SQ_WAVES"]
+VALU_PASSES = [
+    # name, bench arguments, kernel name pattern, nodes updated per dispatch (summed over the
+    # matching kernels of one step)
+    ("fd3_f32", ["--only", "fd3_f32", "--steps", "20", "--warmup", "2", "--no-autotune"],
+     "fd_sweep_kernel<float, 4, 3, false, false, 0>", N * N),
+    ("fd3_f16", ["--only", "fd3_f16", "--steps", "20", "--warmup", "2", "--no-autotune"],
+     "fd_sweep_kernel<__half, 4, 3, false, false, 0>", N * N),
+    ("mrt_f32", ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--no-autotune"],
+     "mrt_sweep_kernel<float, 4, 0>", N * N),
+    ("batch512", ["--only", "batch", "--batch-steps", "20", "--no-autotune"], "fd_batch_kernel<float, ", BATCH_NODES),
+]
+SIMDS = 1024  # 256 compute units x 4 SIMDs
+XCDS = 8
+
 DECAY = "8192 x 8192 periodic decaying flow (modes 0<|k|<=32, max|field| 0.02), nu 0.02"
 KERNELS = [
     # file stem, kernel name pattern, algorithmic bytes per launch, counter pair, sources, workload
@@ -239,6 +256,43 @@ def _run(cmd, log, limit, kill_signal):
         raise SystemExit(f"step failed with exit status {rc}: {' '.join(cmd)}")
 
 
+def valu_summary(raw, out_md, command):
+    """VALU busy of each pass: SQ_ACTIVE_INST_VALU x 4 cycles (a wave64 VALU instruction holds
+    a SIMD for 4 cycles; packed FP32 is not used) over the SIMD-cycles of the dispatch
+    (GRBM_GUI_ACTIVE is summed over the XCDs), and VALU instructions per node update
+    (SQ_INSTS_VALU x 64 lanes / nodes)."""
+    lines = ["# rocprofv3 VALU counters of the step kernels", "",
+             "Written by: `python -m paper_1803_00437_amd.profiling collect --raw <dir> --out profiles`", "",
+             "Commands (one counter pass each, nothing else collected):", ""]
+    rows = []
+    for name, args, pattern, nodes in VALU_PASSES:
+        d = os.path.join(raw, f"valu_{name}")
+        lines.append(f"    {command} -d <dir>/valu_{name} -- python3 -u {BENCH} " + " ".join(args))
+        means = {c: counter_means(d, c) for c in VALU_COUNTERS}
+        hits = sorted(k for k in means["SQ_INSTS_VALU"] if pattern in k)
+        if not hits:
+            raise SystemExit(f"no kernel matches {pattern!r} in {d}")
+        insts = sum(means["SQ_INSTS_VALU"][k][1] for k in hits)
+        active = sum(means["SQ_ACTIVE_INST_VALU"][k][1] for k in hits)
+        cycles = sum(means["GRBM_GUI_ACTIVE"][k][1] for k in hits) / XCDS
+        waves = sum(means["SQ_WAVES"][k][1] for k in hits)
+        calls = min(means["SQ_INSTS_VALU"][k][0] for k in hits)
+        busy = active * 4 / (SIMDS * cycles)
+        rows.append((pattern if len(hits) == 1 else pattern + " (" + str(len(hits)) + " kernels per step)", calls,
+                     insts, active, cycles * XCDS, waves, busy, insts * 64 / nodes))
+    lines += ["", "Per dispatch of the step kernel (per step, summed over its kernels, for the batch), averaged "
+              "over the dispatches. VALU busy = SQ_ACTIVE_INST_VALU x 4 / (1024 SIMDs x GRBM_GUI_ACTIVE / 8); "
+              "per node = SQ_INSTS_VALU x 64 / nodes updated.", "",
+              "| kernel | dispatches | SQ_INSTS_VALU | SQ_ACTIVE_INST_VALU | GRBM_GUI_ACTIVE (sum of 8 XCDs) | "
+              "SQ_WAVES | VALU busy | VALU instructions per node |", "|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{r[0]}` | {r[1]} | {r[2]:.4g} | {r[3]:.4g} | {r[4]:.4g} | {r[5]:.0f} | {100 * r[6]:.0f} % | "
+                     f"{r[7]:.1f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return rows
+
+
 def collect(raw, out, run=True):
     """run=False only rewrites the summaries from rocprofv3 output already in `raw`."""
     raw = os.path.abspath(raw)
@@ -249,7 +303,8 @@ def collect(raw, out, run=True):
     if run:
         # rocprofv3 names its files by process id: start from empty directories so that no
         # earlier run's files are summarised with this one's
-        for sub in ("trace", "fd_fetch_size", "fd_write_size", "mrt_fetch_size", "mrt_write_size"):
+        for sub in ("trace", "fd_fetch_size", "fd_write_size", "mrt_fetch_size", "mrt_write_size") + tuple(
+                f"valu_{p[0]}" for p in VALU_PASSES):
             shutil.rmtree(os.path.join(raw, sub), ignore_errors=True)
         _run(["rocprofv3"] + trace_opts + ["-d", f"{raw}/trace", "--"] + py + TRACE_ARGS, f"{raw}/trace.log", 400,
              "TERM")
@@ -263,6 +318,14 @@ def collect(raw, out, run=True):
         pmc[name] = (f"{raw}/{name}_fetch_size", f"{raw}/{name}_write_size",
                      f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv "
                      f"-d <dir> -- python3 -u {BENCH} " + " ".join(args))
+    valu_cmd = ["rocprofv3", "--pmc"] + VALU_COUNTERS + ["--output-format", "csv"]
+    if run:
+        for name, args, _, _ in VALU_PASSES:
+            d = f"{raw}/valu_{name}"
+            _run(valu_cmd + ["-d", d, "--"] + py + args, f"{d}.log", 120, "KILL")
+    valu = valu_summary(raw, os.path.join(out, "valu_busy_8192.md"), "cd /tmp && TMPDIR=/tmp " + " ".join(valu_cmd))
+    for r in valu:
+        print(f"valu {r[0]}: {r[2]:.4g} instructions, {100 * r[6]:.0f} % busy, {r[7]:.1f} per node")
     trace_str = "cd /tmp && TMPDIR=/tmp " + " ".join(["rocprofv3"] + trace_opts + ["-d", "<dir>", "--"] + py + TRACE_ARGS)
     results = {}
     for stem, pattern, alg, counters, sources, workload in KERNELS:

@@ -75,3 +75,24 @@ def test_launch_gaps_of_a_replayed_sequence(tmp_path):
     g = P.launch_gaps(trace, "fd_batch_kernel")
     assert g["span_ns"] == 500 and g["busy_ns"] == 100 + 210 + 100 and g["dispatches"] == 4 and g["matching"] == 3
     assert g["idle_frac"] == pytest.approx(1 - 410 / 500)
+
+
+def test_valu_summary_busy_and_instructions_per_node(tmp_path):
+    """VALU busy = SQ_ACTIVE_INST_VALU x 4 / (1024 SIMDs x GRBM_GUI_ACTIVE / 8), and the
+    instructions per node = SQ_INSTS_VALU x 64 / nodes; the batch sums its class kernels."""
+    raw = str(tmp_path)
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    for name, args, pattern, nodes in P.VALU_PASSES:
+        kernels = [pattern + "0>", pattern + "2>"] if name == "batch512" else [pattern]
+        rows = []
+        for k in kernels:
+            rows += [[k, "SQ_INSTS_VALU", 1e8], [k, "SQ_ACTIVE_INST_VALU", 2e8],
+                     [k, "GRBM_GUI_ACTIVE", 8e6], [k, "SQ_WAVES", 100]]
+        _write_csv(os.path.join(raw, f"valu_{name}", "vm", "1_counter_collection.csv"), hdr, rows)
+    out = P.valu_summary(raw, str(tmp_path / "v.md"), "cmd")
+    single = out[0]
+    assert single[6] == pytest.approx(2e8 * 4 / (1024 * 1e6))
+    assert single[7] == pytest.approx(1e8 * 64 / P.N ** 2)
+    batch = out[-1]
+    assert batch[2] == pytest.approx(2e8) and batch[7] == pytest.approx(2e8 * 64 / P.BATCH_NODES)
+    assert "VALU busy" in open(tmp_path / "v.md").read()
