@@ -40,7 +40,8 @@ __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = b.tile / I.strips_x;
-    sweep_tile<T, CPL, 3, false, false, AM>(t, band, b.tile - band * I.strips_x);
+    const int sx = b.tile - band * I.strips_x;
+    sweep_tile<T, CPL, 3, false, false, AM>(t, band, sx * Strip<CPL, 1>::S, sx == I.strips_x - 1);
 }
 
 // Single instance in the same tiling: the one-launch-per-grid path of the comparison.
@@ -65,7 +66,8 @@ __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict_
     t.k.kxx = C(I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = blockIdx.x / I.strips_x;
-    sweep_tile<T, CPL, 3, false, false, AM>(t, band, blockIdx.x - band * I.strips_x);
+    const int sx = blockIdx.x - band * I.strips_x;
+    sweep_tile<T, CPL, 3, false, false, AM>(t, band, sx * Strip<CPL, 1>::S, sx == I.strips_x - 1);
 }
 
 __device__ __forceinline__ double wave_sum(double v)

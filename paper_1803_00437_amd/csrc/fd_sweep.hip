@@ -51,7 +51,8 @@ __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 {
     // blocks dealt out row band after row band
     const int band = blockIdx.x / a.strips_x;
-    sweep_tile<T, CPL, ST, WALLS, FORCE, AM>(a.t, band, blockIdx.x - band * a.strips_x);
+    const int sx = blockIdx.x - band * a.strips_x;
+    sweep_tile<T, CPL, ST, WALLS, FORCE, AM>(a.t, band, sx * Strip<CPL, Stencil<ST>::H>::S, sx == a.strips_x - 1);
 }
 
 // Rows per wavefront when the caller leaves the choice open (fastest at 8192^2): FP32

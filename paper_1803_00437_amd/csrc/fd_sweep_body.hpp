@@ -589,10 +589,11 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     }
 }
 
-// One tile: the block's WV wavefronts over column strip sx and row band `band` of one
-// grid.  Called by every wavefront of the block (it contains a block barrier).
+// One tile: the block's WV wavefronts over row band `band` of the column strip that stores
+// columns [x0, x0 + S) of one grid (`last`: the grid's last strip, reaching column nx - 1).
+// Called by every wavefront of the block (it contains a block barrier).
 template <typename T, int CPL, int ST, bool WALLS, bool FORCE, int AM>
-__device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int sx)
+__device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int x0, bool last)
 {
     using C = typename Storage<T>::C;
     using G = Strip<CPL, Stencil<ST>::H>;
@@ -607,8 +608,8 @@ __device__ __forceinline__ void sweep_tile(const TileArgs<T> &a, int band, int s
     // then cross the periodic edge (it falls between lanes), so no lane needs the per-column
     // path.  The columns it shares with the strip before it are computed by both, from the
     // same inputs in the same order, and both store the same bits there.
-    const bool shift_last = AM == AM_UNAL && nx > G::S && (sx + 1) * G::S >= nx;
-    const int xl = (shift_last ? nx - G::S : sx * G::S) - G::P + CPL * lane;
+    const bool shift_last = AM == AM_UNAL && last && nx > G::S;
+    const int xl = (shift_last ? nx - G::S : x0) - G::P + CPL * lane;
     const bool stored = CPL * lane >= G::P && CPL * lane < G::P + G::S;  // the strip's own columns
     static_assert(AM != AM_UNAL || sizeof(T) >= 4, "element-aligned vector accesses need 4- or 8-byte elements");
     const LaneCols<CPL, AM> lc = make_lane_cols<T, CPL, AM>(xl, nx, stored);
