@@ -16,12 +16,15 @@ Contents
   * ``symbol``: the linear amplification matrix H(k) of both schemes (von Neumann
     analysis of section 1-b, dispersion equation of section 2) and the transport
     coefficients extracted from its eigenvalues.
+  * ``d3q19``: the FD-LBM step carried over to the D3Q19 lattice (``fd3d_oracle.c``), which
+    the Conclusion says was analysed without printing it, and its linear symbol.
   * ``disk``: the curved no-slip wall of section 3-b around a disk (FD-LBM and LW-ACM:
     ghost nodes filled from the fluid before each periodic step; MRT D2Q9: interpolated
     bounce-back on the boundary links after it) and the decay-rate measurement of the
     Stokes modes of Tables 2 and 3.
 
-Every part is pinned by tests/test_oracle_pins.py and tests/test_oracle_disk.py; the
+Every part is pinned by tests/test_oracle_pins.py, tests/test_oracle_disk.py and
+tests/test_oracle_d3q19.py; the
 velocity-cubic term of theta_E (whose printed sign is read as a slip, reading R6) by the bulk
 viscosity zeta (1 - 3V^2) in a mean flow that section 2 states.
 

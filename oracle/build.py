@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "fdlbm_oracle.c")
+SRCS = [os.path.join(HERE, "fdlbm_oracle.c"), os.path.join(HERE, "fd3d_oracle.c")]
 OUT_DIR = os.path.join(HERE, "_build")
 OUT = os.path.join(OUT_DIR, "liboracle.so")
 
@@ -18,7 +18,7 @@ def build(verbose=False):
     os.makedirs(OUT_DIR, exist_ok=True)
     tmp = OUT + ".tmp"
     cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-           "-std=c11", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+           "-std=c11", "-Wall", "-Wextra", "-o", tmp, *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

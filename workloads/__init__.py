@@ -181,3 +181,43 @@ def disk_stokes_mode(nx, ny, cx, cy, R, m, k, amp=1e-3, nu=None):
     if nu is not None and m > 0:
         drho = np.where(inside, 3.0 * nu * k * k * scale * b * r ** m * s, 0.0)
     return drho, jx, jy
+
+
+# ------------------------------------------------------------- three dimensions (D3Q19) ----
+
+def random_state3(nx, ny, nz, seed, amp=1e-2):
+    """Uniform white noise of amplitude amp in each of (drho, jx, jy, jz), shape (nz, ny, nx)."""
+    rng = np.random.default_rng(seed)
+    return tuple(amp * (2.0 * rng.random((nz, ny, nx)) - 1.0) for _ in range(4))
+
+
+def decaying_flow3(n, seed=6, kmax=8, amp=0.02, dtype=np.float64):
+    """Band-limited random state on an n^3 periodic grid: per field (drho, jx, jy, jz), every
+    Fourier mode with 0 < |k| <= kmax (integer wave numbers) with a random complex amplitude,
+    scaled to max|field| = amp.  The three-dimensional counterpart of decaying_flow."""
+    rng = np.random.default_rng(seed)
+    kk = np.fft.fftfreq(n, 1.0 / n)
+    kr = np.arange(n // 2 + 1)
+    k2 = kk[:, None, None] ** 2 + kk[None, :, None] ** 2 + kr[None, None, :] ** 2
+    mask = (k2 > 0) & (k2 <= kmax * kmax)
+    out = []
+    for _ in range(4):
+        spec = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+        cnt = int(mask.sum())
+        spec[mask] = rng.standard_normal(cnt) + 1j * rng.standard_normal(cnt)
+        f = np.fft.irfftn(spec, s=(n, n, n))
+        f *= amp / np.max(np.abs(f))
+        out.append(np.ascontiguousarray(f.astype(dtype)))
+        del spec
+    return tuple(out)
+
+
+def plane_wave3(shape, m, field, amp=1e-6, V=(0.0, 0.0, 0.0)):
+    """cos(k.x) of amplitude amp in one field (0 = drho, 1-3 = J components) on the uniform
+    state rho = 1, J = V; k = 2 pi (mx/nx, my/ny, mz/nz), shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ph = 2 * np.pi * (m[0] * x / nx + m[1] * y / ny + m[2] * z / nz)
+    st = [np.zeros(shape)] + [np.full(shape, float(v)) for v in V]
+    st[field] = st[field] + amp * np.cos(ph)
+    return tuple(st)
