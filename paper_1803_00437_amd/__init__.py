@@ -1,11 +1,14 @@
-"""MI355X (gfx950) FD-LBM, LW-ACM and MRT D2Q9 steps -- thin Python binding of libfdlbm.so.
+"""MI355X (gfx950) FD-LBM, LW-ACM and MRT D2Q9 steps, and the FD-LBM step on D3Q19 -- thin
+Python binding of libfdlbm.so.
 
 The binding only marshals arguments: every step of the computation runs in the HIP
-kernels of ``csrc/``, behind the C ABI declared in ``include/fdlbm.h``.  PyTorch is used
+kernels of ``csrc/``, behind the C ABI declared in ``include/fdlbm.h`` and
+``include/fdlbm3d.h``.  PyTorch is used
 to allocate the caller-owned device buffers and to supply the HIP stream.
 
 Module-level functions carry the C names (``fdlbm_create``, ``fdlbm_step``, ``mrt_step``, ``lwacm_step``,
-``fdlbm_diagnostics`` ...); :class:`FdLbm` owns the buffers of one simulation.
+``fdlbm_diagnostics``, ``fdlbm3d_step`` ...); :class:`FdLbm` and :class:`FdLbm3D` own the
+buffers of one simulation.
 
 There is no fallback: if ``_build/libfdlbm.so`` is missing, importing the binding's entry
 points raises.
@@ -37,6 +40,8 @@ EXPORTED = (
     "fdlbm_batch_workspace_bytes", "fdlbm_batch_create", "fdlbm_batch_set_state", "fdlbm_batch_get_state",
     "fdlbm_batch_step", "fdlbm_batch_step_per_instance", "fdlbm_batch_amplitudes", "fdlbm_batch_step_count",
     "fdlbm_batch_destroy", "fdlbm_batch_last_error", "fdlbm_batch_autotune",
+    "fdlbm3d_workspace_bytes", "fdlbm3d_create", "fdlbm3d_set_state", "fdlbm3d_get_state", "fdlbm3d_step",
+    "fdlbm3d_diagnostics", "fdlbm3d_step_count", "fdlbm3d_destroy", "fdlbm3d_last_error",
 )
 
 
@@ -61,6 +66,22 @@ class Diag(ctypes.Structure):
     ]
 
 
+class Params3D(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("s_nu", ctypes.c_double), ("s_e", ctypes.c_double), ("kernel", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("tile_planes", ctypes.c_int32),
+    ]
+
+
+class Diag3D(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double),
+        ("mom_z", ctypes.c_double), ("kin_energy", ctypes.c_double), ("max_abs_j", ctypes.c_double),
+        ("nonfinite", ctypes.c_int64),
+    ]
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("s_xx", ctypes.c_double), ("s_e", ctypes.c_double)]
 
@@ -70,7 +91,8 @@ class FdlbmError(RuntimeError):
         lib = _lib_or_none()
         msg = lib.fdlbm_strerror(code).decode() if lib else str(code)
         if code == FDLBM_EDEVICE and lib:
-            msg += ": " + lib.fdlbm_last_error().decode()
+            last = lib.fdlbm3d_last_error if what.startswith("fdlbm3d") else lib.fdlbm_last_error
+            msg += ": " + last().decode()
         super().__init__(f"{what}: {msg}")
         self.code = code
 
@@ -135,6 +157,16 @@ def load_library(path=LIB_PATH):
         "fdlbm_batch_destroy": (None, [vp]),
         "fdlbm_batch_last_error": (ctypes.c_char_p, []),
         "fdlbm_batch_autotune": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), dp]),
+        "fdlbm3d_workspace_bytes": (i32, [ctypes.POINTER(Params3D), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+        "fdlbm3d_create": (i32, [ctypes.POINTER(Params3D), vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "fdlbm3d_set_state": (i32, [vp, dp, dp, dp, dp]),
+        "fdlbm3d_get_state": (i32, [vp, dp, dp, dp, dp]),
+        "fdlbm3d_step": (i32, [vp, i64]),
+        "fdlbm3d_diagnostics": (i32, [vp, ctypes.POINTER(Diag3D)]),
+        "fdlbm3d_step_count": (i64, [vp]),
+        "fdlbm3d_destroy": (None, [vp]),
+        "fdlbm3d_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -458,6 +490,114 @@ class FdLbmBatch:
     def close(self):
         if getattr(self, "ctx", None):
             load_library().fdlbm_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ D3Q19 (3D) ----
+
+def make_params3d(nx, ny, nz, dtype="f32", s_nu=1.0, s_e=1.0, kernel="auto", tile_rows=0, tile_planes=0):
+    if dtype not in ("f64", "f32"):
+        raise ValueError("the D3Q19 step stores FP64 or FP32")
+    return Params3D(int(nx), int(ny), int(nz), DTYPE[dtype], float(s_nu), float(s_e), KERNEL[kernel],
+                    int(tile_rows), int(tile_planes))
+
+
+def fdlbm3d_workspace_bytes(params):
+    sb, cb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().fdlbm3d_workspace_bytes(ctypes.byref(params), ctypes.byref(sb), ctypes.byref(cb)),
+           "fdlbm3d_workspace_bytes")
+    return sb.value, cb.value
+
+
+def fdlbm3d_create(params, state_a, state_b, scratch, scratch_bytes, stream):
+    ctx = ctypes.c_void_p()
+    _check(load_library().fdlbm3d_create(ctypes.byref(params), state_a, state_b, scratch, scratch_bytes, stream,
+                                         ctypes.byref(ctx)), "fdlbm3d_create")
+    return ctx
+
+
+def fdlbm3d_set_state(ctx, drho, jx, jy, jz):
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (drho, jx, jy, jz)]
+    _check(load_library().fdlbm3d_set_state(ctx, *(_dptr(x) for x in a)), "fdlbm3d_set_state")
+
+
+def fdlbm3d_get_state(ctx, shape):
+    out = [np.empty(shape, dtype=np.float64) for _ in range(4)]
+    _check(load_library().fdlbm3d_get_state(ctx, *(_dptr(x) for x in out)), "fdlbm3d_get_state")
+    return tuple(out)
+
+
+def fdlbm3d_step(ctx, nsteps):
+    _check(load_library().fdlbm3d_step(ctx, int(nsteps)), "fdlbm3d_step")
+
+
+def fdlbm3d_diagnostics(ctx):
+    d = Diag3D()
+    _check(load_library().fdlbm3d_diagnostics(ctx, ctypes.byref(d)), "fdlbm3d_diagnostics")
+    return {k: getattr(d, k) for k, _ in Diag3D._fields_}
+
+
+def fdlbm3d_step_count(ctx):
+    return int(load_library().fdlbm3d_step_count(ctx))
+
+
+def fdlbm3d_destroy(ctx):
+    load_library().fdlbm3d_destroy(ctx)
+
+
+def fdlbm3d_last_error():
+    return load_library().fdlbm3d_last_error().decode()
+
+
+class FdLbm3D:
+    """One D3Q19 FD-LBM simulation on a periodic nx * ny * nz grid: owns its torch device
+    buffers and its library context.  Keyword arguments follow ``fdlbm3d_params``
+    (include/fdlbm3d.h): ``dtype`` "f64" or "f32", ``s_nu``, ``s_e``, ``kernel`` "auto",
+    "reference" or "sweep", ``tile_rows`` (8 or 16), ``tile_planes``.  Host arrays have shape
+    (nz, ny, nx)."""
+
+    def __init__(self, nx, ny, nz, device="cuda", stream=None, **kw):
+        import torch
+
+        load_library()
+        self.shape = (int(nz), int(ny), int(nx))
+        self.params = make_params3d(nx, ny, nz, **kw)
+        sb, cb = fdlbm3d_workspace_bytes(self.params)
+        dev = torch.device(device)
+        self.buffers = Buffers(*(torch.empty(b, dtype=torch.uint8, device=dev) for b in (sb, sb, cb)))
+        for t in (self.buffers.state_a, self.buffers.state_b, self.buffers.scratch):
+            if t.data_ptr() % 256:
+                raise RuntimeError("torch returned a device buffer that is not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.ctx = fdlbm3d_create(self.params, self.buffers.state_a.data_ptr(), self.buffers.state_b.data_ptr(),
+                                  self.buffers.scratch.data_ptr(), cb, self.stream.cuda_stream)
+        self.state_bytes, self.scratch_bytes = sb, cb
+
+    def set_state(self, drho, jx, jy, jz):
+        fdlbm3d_set_state(self.ctx, drho, jx, jy, jz)
+
+    def get_state(self):
+        return fdlbm3d_get_state(self.ctx, self.shape)
+
+    def step(self, nsteps=1):
+        fdlbm3d_step(self.ctx, nsteps)
+
+    @property
+    def steps(self):
+        return fdlbm3d_step_count(self.ctx)
+
+    def diagnostics(self):
+        return fdlbm3d_diagnostics(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            fdlbm3d_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

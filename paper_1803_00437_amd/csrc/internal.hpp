@@ -157,4 +157,20 @@ hipError_t launch_diag(int scheme, int dtype, const void *state, size_t n, const
 hipError_t launch_diag_static(int scheme, int dtype, const void *state, size_t n, const double *j0x,
                               const double *j0y, double *out, hipStream_t s);
 
+// ---- FD-LBM on the D3Q19 lattice (fd3d.hip) -------------------------------------------
+struct Dim3Grid {
+    int x, y, z;
+};
+// reference path: 18 post-collision planes in fstar (18 * nx*ny*nz elements), then gather
+hipError_t launch_d3_reference(int dtype, const void *in, void *out, void *fstar, int nx, int ny, int nz, double s_nu,
+                               double s_e, hipStream_t s);
+// sweep path: wy wavefronts (8 or 16) per block along y, tz planes per block along z
+Dim3Grid d3_sweep_grid(int nx, int ny, int nz, int wy, int tz);
+hipError_t launch_d3_sweep(int dtype, const void *in, void *out, int nx, int ny, int nz, double s_nu, double s_e,
+                           int wy, int tz, hipStream_t s);
+// FP64 reduction: out[0..6] = mass, momentum x, y, z, kinetic energy, max |J|, non-finite
+// count; partials: 8 doubles per block of d3_diag_blocks(n)
+int d3_diag_blocks(size_t n);
+hipError_t launch_d3_diagnostics(int dtype, const void *state, size_t n, double *partials, double *out, hipStream_t s);
+
 }  // namespace fdlbm

@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI (no GPU): the library loads, exports every function that
-include/fdlbm.h declares, and rejects invalid parameters before touching a device."""
+include/fdlbm.h and include/fdlbm3d.h declare, and rejects invalid parameters before touching
+a device."""
 import ctypes
 import os
 import re
@@ -9,20 +10,26 @@ import pytest
 import paper_1803_00437_amd as F
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "fdlbm.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("fdlbm.h", "fdlbm3d.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    names = []
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
     return sorted(set(names))
+
+
+def test_every_header_is_covered():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == sorted(os.path.basename(h) for h in HEADERS)
 
 
 def test_library_loads_and_exports_every_declared_function():
     lib = F.load_library()
     names = declared_functions()
     assert "fdlbm_step" in names and "mrt_step" in names and "fdlbm_diagnostics" in names
+    assert "fdlbm3d_step" in names and "fdlbm3d_create" in names
     for name in names:
         assert hasattr(lib, name), name
     assert sorted(F.EXPORTED) == names
@@ -276,6 +283,7 @@ def test_header_is_c99_and_links(tmp_path):
 #include <stdio.h>
 #include <string.h>
 #include "fdlbm.h"
+#include "fdlbm3d.h"
 static void *const every_function[] = {{
 {refs}
 }};
@@ -307,6 +315,51 @@ int main(void)
     want_sb, want_cb = F.fdlbm_workspace_bytes(good())
     assert (rc, sb, cb, bad, count) == (0, want_sb, want_cb, F.FDLBM_EINVAL, len(names))
     assert "invalid argument" in r.stdout
+
+
+def test_params3d_struct_layout_matches_header():
+    # 4 int32, 2 doubles, 3 int32 (+pad)
+    assert ctypes.sizeof(F.Params3D) == 4 * 4 + 2 * 8 + 3 * 4 + 4
+    assert F.Params3D.s_nu.offset == 16 and F.Params3D.kernel.offset == 32
+    assert ctypes.sizeof(F.Diag3D) == 7 * 8
+
+
+def good3(**kw):
+    base = dict(nx=64, ny=40, nz=24, dtype="f32", s_nu=1.5, s_e=1.2)
+    base.update(kw)
+    return F.make_params3d(**base)
+
+
+def test_workspace_bytes_3d():
+    n = 64 * 40 * 24
+    sb, cb = F.fdlbm3d_workspace_bytes(good3())
+    assert sb >= 4 * n * 4 and sb % 256 == 0 and cb >= 4 * n * 8
+    sb64, _ = F.fdlbm3d_workspace_bytes(good3(dtype="f64"))
+    assert sb64 >= 4 * n * 8
+    _, cref = F.fdlbm3d_workspace_bytes(good3(kernel="reference"))
+    assert cref >= cb + 18 * n * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=2), dict(ny=2), dict(nz=2), dict(nx=(1 << 20) + 1), dict(s_nu=2.0), dict(s_nu=0.0), dict(s_e=-1.0),
+    dict(s_e=float("nan")), dict(tile_rows=4), dict(tile_rows=12), dict(tile_rows=-1), dict(tile_planes=-1),
+    dict(tile_planes=4097), dict(nx=1 << 20, ny=1 << 20, nz=3),
+])
+def test_invalid_parameters_3d_are_rejected(bad):
+    with pytest.raises(F.FdlbmError) as e:
+        F.fdlbm3d_workspace_bytes(good3(**bad))
+    assert e.value.code == F.FDLBM_EINVAL
+
+
+def test_params3d_rejects_other_dtypes():
+    for d in ("f16", "f16sr"):
+        with pytest.raises(ValueError):
+            good3(dtype=d)
+    lib = F.load_library()
+    p = good3()
+    p.dtype = F.DTYPE["f16"]
+    sb, cb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fdlbm3d_workspace_bytes(ctypes.byref(p), ctypes.byref(sb), ctypes.byref(cb)) == F.FDLBM_EINVAL
 
 
 def test_product_never_reaches_the_oracle():

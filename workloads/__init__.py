@@ -205,7 +205,7 @@ def decaying_flow3(n, seed=6, kmax=8, amp=0.02, dtype=np.float64):
         spec = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
         cnt = int(mask.sum())
         spec[mask] = rng.standard_normal(cnt) + 1j * rng.standard_normal(cnt)
-        f = np.fft.irfftn(spec, s=(n, n, n))
+        f = np.fft.irfftn(spec, s=(n, n, n), axes=(0, 1, 2))
         f *= amp / np.max(np.abs(f))
         out.append(np.ascontiguousarray(f.astype(dtype)))
         del spec
