@@ -10,7 +10,9 @@ Prints ONE JSON line: value = FD-LBM FP32 MLUPS (million lattice-node updates pe
 second), the HBM roofline of the step kernel (algorithmic bytes: 3 FP32 words read and 3
 written per node), the CPU oracle timed on a bounded band of the same workload, the
 relative L2 error of each GPU dtype against that oracle band, and the same measurements
-for the MRT step, the FP64 and FP16-storage FD-LBM steps and the 5-point stencil.
+for the MRT step, the FP64 and FP16-storage FD-LBM steps and the 5-point stencil.  The
+FD-LBM step on the D3Q19 lattice is timed beside them on a 512^3 periodic decaying flow
+(object "d3q19").
 
     python bench.py [--steps K] [--warmup W] [--n 8192] [--no-compare] [--no-cpu]
 """
@@ -94,6 +96,67 @@ def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with
         "nonfinite": diag["nonfinite"],
         "tile": {"lane_cols": shape[0], "tile_rows": shape[1]} if shape else None,
     }
+
+
+D3_N = 512
+D3_WORKLOAD = ("{n}^3 periodic decaying flow, random Fourier modes 0<|k|<=8 per field, max|field|=0.02, seed 6; "
+               "FD-LBM D3Q19 3-point finite differences, nu=0.02, s_e=1")
+
+
+def d3_bytes_per_node(dtype):
+    return 2 * 4 * {"f64": 8, "f32": 4}[dtype]
+
+
+def run_d3(F, torch, init, dtype, steps, warmup):
+    """The FD-LBM step on the D3Q19 lattice (fused sweep kernel, default tile), timed with HIP
+    events on the library's stream; whole-step time with FP64 diagnostics every 100 steps."""
+    nz, ny, nx = init[0].shape
+    sim = F.FdLbm3D(nx, ny, nz, dtype=dtype, s_nu=F.fdlbm_rate_from_viscosity(NU), s_e=1.0)
+    sim.set_state(*init)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    e1.synchronize()
+    kernel_ms = e0.elapsed_time(e1) / steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(DIAG_EVERY, steps - done)
+        sim.step(k)
+        done += k
+        sim.diagnostics()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    diag = sim.diagnostics()
+    sim.close()
+    nodes = nx * ny * nz
+    alg = d3_bytes_per_node(dtype) * nodes / (kernel_ms * 1e6)
+    return {
+        "ms_per_step": wall_ms,
+        "kernel_ms": kernel_ms,
+        "mlups": nodes / (wall_ms * 1e3),
+        "kernel_mlups": nodes / (kernel_ms * 1e3),
+        "alg_gbs": alg,
+        "hbm_frac": alg / HBM_PEAK_GBS,
+        "nonfinite": diag["nonfinite"],
+    }
+
+
+def d3_oracle_baseline(O3, n=160, steps=3):
+    """The FP64 D3Q19 oracle timed on an n^3 periodic sample of the same kind of flow."""
+    import workloads as W
+
+    init = W.decaying_flow3(n, seed=6, amp=0.02)
+    t0 = time.perf_counter()
+    O3.fd3d_run(*init, steps, s_nu=1.0 / (0.5 + 3 * NU), s_e=1.0)
+    secs = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / secs / 1e6, "unit": "MLUPS", "kind": "oracle",
+            "sample": f"FP64 CPU oracle of the D3Q19 step, {steps} steps of a {n}^3 periodic decaying flow "
+                      f"({secs:.1f} s)"}
 
 
 def measure_copy(F, torch, probe=False, nbytes=1 << 30, reps=10):
@@ -239,6 +302,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip MRT / FP64 / FP16 / 5-point lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error bands")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch line")
+    ap.add_argument("--no-d3", action="store_true", help="skip the D3Q19 lines")
+    ap.add_argument("--d3-steps", type=int, default=100)
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--err-steps", type=int, default=12)
     ap.add_argument("--err-rows", type=int, default=512)
@@ -249,7 +314,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per wavefront strip of the sweep kernel (0 = default)")
     ap.add_argument("--lane-cols", type=int, default=0, help="grid columns per lane of the sweep kernel (0 = default)")
     ap.add_argument("--only", default=None,
-                    help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16, lwacm_f32, batch")
+                    help="time only this case instead of FD3 FP32, e.g. mrt_f32, fd3_f16, lwacm_f32, batch, "
+                         "d3_f32 (D3Q19)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default tile shapes instead of tuning them before timing")
     ap.add_argument("--copy-probe", action="store_true",
@@ -270,6 +336,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     F.load_library()
+    if args.only in ("d3_f32", "d3_f64"):
+        copy_gbs = measure_copy(F, torch, probe=args.copy_probe)
+        init3 = W.decaying_flow3(D3_N, seed=6, amp=0.02)
+        case = run_d3(F, torch, init3, args.only.split("_")[1], args.d3_steps, 5)
+        print(json.dumps({"case": args.only, "workload": D3_WORKLOAD.format(n=D3_N), "copy_gbs": copy_gbs, **case}),
+              flush=True)
+        return
     n = args.n
     t0 = time.perf_counter()
     init = W.decaying_flow(n=n, seed=4, kmax=32, amp=0.02)
@@ -335,6 +408,22 @@ def main():
     if not args.no_batch:
         batch = run_batch(F, torch, W, args.batch_steps, max(10, args.batch_steps // 4), autotune=not args.no_autotune)
         print(f"# batch: {batch}", file=sys.stderr, flush=True)
+
+    d3 = None
+    if not args.no_d3:
+        t0 = time.perf_counter()
+        init3 = W.decaying_flow3(D3_N, seed=6, amp=0.02)
+        print(f"# input {D3_N}^3 generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        d3 = {"workload": D3_WORKLOAD.format(n=D3_N), "bytes_per_node": {"f32": 32, "f64": 64}}
+        for dtype in ("f32", "f64"):
+            d3[dtype] = run_d3(F, torch, init3, dtype, args.d3_steps, 5)
+            print(f"# d3q19 {dtype}: {d3[dtype]}", file=sys.stderr, flush=True)
+        del init3
+        if not args.no_cpu:
+            from oracle import d3q19 as O3
+
+            d3["cpu_oracle"] = d3_oracle_baseline(O3)
+            print(f"# d3q19 cpu oracle: {d3['cpu_oracle']}", file=sys.stderr, flush=True)
 
     cpu = None
     errors = None
@@ -409,6 +498,8 @@ def main():
         "cpu_baseline": cpu,
         "err_vs_oracle": errors,
         "batch_512": batch,
+        "d3q19": ({k: ({kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                       if isinstance(v, dict) else v) for k, v in d3.items()} if d3 else None),
         "compare": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in compare.items()},
     }

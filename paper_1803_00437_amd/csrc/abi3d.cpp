@@ -34,9 +34,10 @@ struct Layout3 {
     size_t staging, partials, out, fstar, total;
 };
 
-// default rows per block: 16 in FP32 (76 VGPRs); FP64 needs more registers than 16 wavefronts leave
-int tile_rows(const fdlbm3d_params &p) { return p.tile_rows != 0 ? p.tile_rows : p.dtype == FDLBM_F64 ? 8 : 16; }
-int tile_planes(const fdlbm3d_params &p) { return p.tile_planes == 0 ? 32 : p.tile_planes; }
+// default tile (measured at 512^3): FP32 12 rows x 64 planes, FP64 8 rows x 32 planes (its
+// registers leave no room for taller blocks)
+int tile_rows(const fdlbm3d_params &p) { return p.tile_rows != 0 ? p.tile_rows : p.dtype == FDLBM_F64 ? 8 : 12; }
+int tile_planes(const fdlbm3d_params &p) { return p.tile_planes != 0 ? p.tile_planes : p.dtype == FDLBM_F64 ? 32 : 64; }
 size_t nodes(const fdlbm3d_params &p) { return (size_t)p.nx * (size_t)p.ny * (size_t)p.nz; }
 size_t elem(const fdlbm3d_params &p) { return p.dtype == FDLBM_F64 ? 8 : 4; }
 
@@ -50,7 +51,7 @@ int validate3(const fdlbm3d_params *p)
     if (!rate_ok(p->s_nu) || !rate_ok(p->s_e)) return FDLBM_EINVAL;
     if (p->kernel != FDLBM_KERNEL_AUTO && p->kernel != FDLBM_KERNEL_REFERENCE && p->kernel != FDLBM_KERNEL_SWEEP)
         return FDLBM_EINVAL;
-    if (p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 16) return FDLBM_EINVAL;
+    if (p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16) return FDLBM_EINVAL;
     if (p->tile_planes < 0 || p->tile_planes > 4096) return FDLBM_EINVAL;
     const Dim3Grid g = d3_sweep_grid(p->nx, p->ny, p->nz, tile_rows(*p), tile_planes(*p));
     if (g.y > 65535 || g.z > 65535) return FDLBM_EINVAL;

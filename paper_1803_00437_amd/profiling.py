@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = "paper_1803_00437_amd/csrc"
 FD_SOURCES = [f"{CSRC}/fd_sweep.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"]
 MRT_SOURCES = [f"{CSRC}/mrt.hip", f"{CSRC}/fdlbm_device.hpp"]
+D3_SOURCES = [f"{CSRC}/fd3d.hip", f"{CSRC}/fd3d_device.hpp", f"{CSRC}/fdlbm_device.hpp", f"{CSRC}/fd_sweep_body.hpp"]
+N3 = 512
 COPY_BYTES = 1 << 30
 N = 8192
 CHANNEL = 16384 * 1024
@@ -192,6 +194,7 @@ TRACE_ARGS = ["--steps", "100", "--warmup", "10", "--no-cpu", "--copy-probe", "-
 FD_COUNTER_ARGS = ["--steps", "20", "--warmup", "2", "--no-cpu", "--no-compare", "--no-batch", "--copy-probe",
                    "--no-autotune"]
 MRT_COUNTER_ARGS = ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--copy-probe", "--no-autotune"]
+D3_COUNTER_ARGS = ["--only", "d3_f32", "--d3-steps", "20", "--copy-probe"]
 
 # VALU passes (one rocprofv3 --pmc run each): instructions issued and cycles the SIMDs spent
 # issuing them, per dispatch of the step kernel
@@ -206,6 +209,7 @@ VALU_PASSES = [
     ("mrt_f32", ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--no-autotune"],
      "mrt_sweep_kernel<float, 4, 0>", N * N),
     ("batch512", ["--only", "batch", "--batch-steps", "20", "--no-autotune"], "fd_batch_kernel<float, ", BATCH_NODES),
+    ("d3_f32", ["--only", "d3_f32", "--d3-steps", "20"], "d3_sweep_kernel<float, 12>", N3 ** 3),
 ]
 SIMDS = 1024  # 256 compute units x 4 SIMDs
 XCDS = 8
@@ -237,6 +241,11 @@ KERNELS = [
     ("fd3_f32_batch512", "fd_batch_kernel<float, ", 24 * BATCH_NODES, None,
      [f"{CSRC}/fd_batch.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"],
      "512 periodic shear-wave instances N x N, N ~ U{32..1024}, one launch per step for all; FP32"),
+    ("fd3d_f32_512", "d3_sweep_kernel<float, 12>", 32 * N3 ** 3, "d3", D3_SOURCES,
+     "512^3 periodic decaying flow (modes 0<|k|<=8, max|field| 0.02), nu 0.02; FD-LBM D3Q19 sweep kernel, FP32 "
+     "(4 words read + 4 written per node)"),
+    ("fd3d_f64_512", "d3_sweep_kernel<double, 8>", 64 * N3 ** 3, None, D3_SOURCES,
+     "512^3 periodic decaying flow (modes 0<|k|<=8, max|field| 0.02), nu 0.02; FD-LBM D3Q19 sweep kernel, FP64"),
     ("disk_fill_f32_8192", "disk_fill_kernel<float>", DISK_FILL_BYTES, None, [f"{CSRC}/disk.hip"],
      "disk of radius 4090 in the 8192 x 8192 grid (section 3-b curved wall): ghost nodes and the ring of rest "
      "nodes set before each FD-LBM 3-point FP32 step (the first fill after the state is set clears every rest "
@@ -303,13 +312,14 @@ def collect(raw, out, run=True):
     if run:
         # rocprofv3 names its files by process id: start from empty directories so that no
         # earlier run's files are summarised with this one's
-        for sub in ("trace", "fd_fetch_size", "fd_write_size", "mrt_fetch_size", "mrt_write_size") + tuple(
+        for sub in ("trace", "fd_fetch_size", "fd_write_size", "mrt_fetch_size", "mrt_write_size", "d3_fetch_size",
+                    "d3_write_size") + tuple(
                 f"valu_{p[0]}" for p in VALU_PASSES):
             shutil.rmtree(os.path.join(raw, sub), ignore_errors=True)
         _run(["rocprofv3"] + trace_opts + ["-d", f"{raw}/trace", "--"] + py + TRACE_ARGS, f"{raw}/trace.log", 400,
              "TERM")
     pmc = {}
-    for name, args in (("fd", FD_COUNTER_ARGS), ("mrt", MRT_COUNTER_ARGS)):
+    for name, args in (("fd", FD_COUNTER_ARGS), ("mrt", MRT_COUNTER_ARGS), ("d3", D3_COUNTER_ARGS)):
         for counter in ("FETCH_SIZE", "WRITE_SIZE"):
             d = f"{raw}/{name}_{counter.lower()}"
             if run:
@@ -335,6 +345,7 @@ def collect(raw, out, run=True):
             kw = dict(fetch=f, write=w, counter_command=cc, json_out=os.path.join(out, f"{stem}_counters.json"))
         results[stem] = summarise(f"{raw}/trace", pattern, alg, os.path.join(out, f"{stem}.md"), sources=sources,
                                   command=trace_str, workload=workload, group=stem.endswith("batch512"),
+                                  n=N3 if stem.startswith("fd3d") else N,
                                   generator="python -m paper_1803_00437_amd.profiling collect --raw <dir> --out profiles",
                                   **kw)
         r = results[stem]

@@ -60,7 +60,7 @@ def test_reference_matches_oracle(F, dtype, shape):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("tile", [(0, 0), (8, 5), (16, 1), (8, 64)])
+@pytest.mark.parametrize("tile", [(0, 0), (8, 5), (12, 3), (16, 1), (8, 64)])
 def test_sweep_equals_reference_bitwise(F, dtype, shape, tile):
     rows, planes = tile
     print(f"case d3 sweep-vs-reference dtype={dtype} shape={shape} tile_rows={rows} tile_planes={planes}",

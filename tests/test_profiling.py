@@ -93,6 +93,8 @@ def test_valu_summary_busy_and_instructions_per_node(tmp_path):
     single = out[0]
     assert single[6] == pytest.approx(2e8 * 4 / (1024 * 1e6))
     assert single[7] == pytest.approx(1e8 * 64 / P.N ** 2)
-    batch = out[-1]
+    batch = out[[p[0] for p in P.VALU_PASSES].index("batch512")]
     assert batch[2] == pytest.approx(2e8) and batch[7] == pytest.approx(2e8 * 64 / P.BATCH_NODES)
+    d3 = out[[p[0] for p in P.VALU_PASSES].index("d3_f32")]
+    assert d3[7] == pytest.approx(1e8 * 64 / P.N3 ** 3)
     assert "VALU busy" in open(tmp_path / "v.md").read()
