@@ -39,8 +39,8 @@ typedef struct fdlbm3d_params {
     double s_nu, s_e;    /* relaxation rates in (0, 2): shear (five traceless moments), energy    */
     int32_t kernel;      /* FDLBM_KERNEL_AUTO or _SWEEP: the fused sweep kernel; _REFERENCE: the
                             post-collision planes then a gather (needs the larger scratch)        */
-    int32_t tile_rows;   /* sweep: wavefronts per block along y, 8, 12 or 16 (0 = 12 in FP32, 8
-                            in FP64), two of which hold halo rows                                 */
+    int32_t tile_rows;   /* sweep: wavefronts per block along y, 8, 12 or 16 (0 = 12), two of which
+                            hold halo rows                                                        */
     int32_t tile_planes; /* sweep: planes per block along z, 1 .. 4096 (0 = 64 in FP32, 32 in FP64) */
 } fdlbm3d_params;
 

@@ -17,10 +17,11 @@
 //   * the block sweeps TZ planes along z; each lane keeps its column's fields of three
 //     planes in registers (plus one loaded ahead), and the partial update of the plane below
 //     until the plane above has been formed;
-//   * measured at 512^3 (FP32): 12 rows per block and 64 planes run fastest (78 000 MLUPS);
-//     16 rows leave one block per compute unit (65 000), 8 rows spend a third of the work on
-//     halo rows (75 000); unrolling the plane loop to rename the window instead of copying it
-//     raised the registers past six wavefronts per SIMD and ran 5-17 % slower;
+//   * measured at 512^3 (FP32): 12 rows per block and 64 planes run fastest (86 000 MLUPS);
+//     16 rows leave one block per compute unit (68 000), 8 rows spend a third of the work on
+//     halo rows (83 000), 14 rows split 4/4/3/3 over the SIMDs so that a second block does not
+//     fit (69 000); unrolling the plane loop to rename the window instead of copying it raised
+//     the registers past six wavefronts per SIMD and ran 5-17 % slower;
 //   * every index wraps (periodic grid), so a grid narrower than a tile is covered by lanes,
 //     rows or planes that repeat: they compute and store the same bits.  The last strip, row
 //     band and plane band are shifted back to end at the grid's edge, so tiles overlap there
@@ -63,8 +64,12 @@ __global__ __launch_bounds__(256) void d3_ref_fstar(const T *__restrict__ st, T 
         for (int a = 0; a < 3; ++a) {
             gr[a] = nb[a][0][0] - nb[a][1][0];
             for (int b = 0; b < 3; ++b) dj[a][b] = nb[a][0][1 + b] - nb[a][1][1 + b];
-            // D_a of the products J_b J_a (b = x, y, z) at the two neighbours along a
-            for (int b = 0; b < 3; ++b) dpa[a][b] = nb[a][0][1 + b] * nb[a][0][1 + a] - nb[a][1][1 + b] * nb[a][1][1 + a];
+            // D_a of the products J_b J_a (b = x, y, z) at the two neighbours along a: along x the
+            // difference of the two rounded products (the sweep forms each column's products once
+            // and shifts them between lanes), along y and z one product fused into the difference
+            for (int b = 0; b < 3; ++b)
+                dpa[a][b] = a == 0 ? nb[a][0][1 + b] * nb[a][0][1 + a] - nb[a][1][1 + b] * nb[a][1][1 + a]
+                                   : d3_pdiff(nb[a][0][1 + b], nb[a][0][1 + a], nb[a][1][1 + b], nb[a][1][1 + a]);
         }
         const C dp[3] = {d3_flux(dpa[0][0], dpa[1][0], dpa[2][0]), d3_flux(dpa[0][1], dpa[1][1], dpa[2][1]),
                          d3_flux(dpa[0][2], dpa[1][2], dpa[2][2])};
@@ -142,23 +147,38 @@ __global__ __launch_bounds__(LANES *WY) void d3_sweep_kernel(const T *__restrict
     if (z0 + tz > nz) z0 = nz > tz ? nz - tz : 0;
 
     const int col = wrapi(x0 - 2 + lane, nx);
-    const size_t rowoff = (size_t)wrapi(y0 - 1 + w, ny) * nx + col;
     const bool halo_lo = w == 0, halo_hi = w == WY - 1;
-    const size_t outoff = (size_t)wrapi(halo_lo ? y0 - 2 : y0 + WY - 1, ny) * nx + col;  // outer row of a halo wave
     const bool store_lane = lane >= 2 && lane < LANES - 2 && !halo_lo && !halo_hi;
-
-    auto load4 = [&](size_t off, int pz, C (&d)[4]) {
-        const size_t a = (size_t)wrapi(pz, nz) * plane + off;
-        for (int f = 0; f < 4; ++f) d[f] = st[f * n + a];
+    // Accesses go through one buffer resource per field plane (scalar base and size), so the
+    // per-lane part of every address is a 32-bit byte offset fixed for the whole sweep: this
+    // row, the outer row of a halo wave, and this row for the stores (beyond the plane, where
+    // the hardware drops the store, for the halo lanes and rows).
+    const unsigned off_row = (unsigned)(((size_t)wrapi(y0 - 1 + w, ny) * nx + col) * sizeof(T));
+    const unsigned off_out = (unsigned)(((size_t)wrapi(halo_lo ? y0 - 2 : y0 + WY - 1, ny) * nx + col) * sizeof(T));
+    const unsigned off_st = store_lane ? off_row : sweep::OFF_NONE;
+    using Ops = sweep::BufOps<sizeof(T)>;
+    auto rsrc = [&](const T *base, int f, int pz) {
+        const unsigned long long r = reinterpret_cast<unsigned long long>(base + (size_t)f * n + (size_t)pz * plane);
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)r);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(r >> 32));
+        void *b = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+        return __builtin_amdgcn_make_buffer_rsrc(b, 0, (int)(plane * sizeof(T)), sweep::RSRC_WORD3);
+    };
+    auto load4 = [&](unsigned off, int pz, C (&d)[4]) {  // pz wrapped by the caller
+        for (int f = 0; f < 4; ++f) d[f] = __builtin_bit_cast(T, Ops::load(rsrc(st, f, pz), off));
     };
 
     // window: planes p-1, p, p+1 of this row; nxt: plane p+2; outer row (halo waves): plane p
     C win[3][4], nxt[4], orow[4], onxt[4];
-    load4(rowoff, z0 - 2, win[0]);
-    load4(rowoff, z0 - 1, win[1]);
-    load4(rowoff, z0, win[2]);
+    load4(off_row, wrapi(z0 - 2, nz), win[0]);
+    load4(off_row, wrapi(z0 - 1, nz), win[1]);
+    load4(off_row, wrapi(z0, nz), win[2]);
     for (int f = 0; f < 4; ++f) orow[f] = onxt[f] = C(0);
-    if (halo_lo || halo_hi) load4(outoff, z0 - 1, orow);
+    if (halo_lo || halo_hi) load4(off_out, wrapi(z0 - 1, nz), orow);
+    auto next_plane = [&](int z) { return z + 1 == nz ? 0 : z + 1; };
+    int zn = wrapi(z0 + 1, nz);  // plane p+2: this row's next load
+    int zo = wrapi(z0, nz);      // plane p+1: the outer row's next load
+    int zs = wrapi(z0 - 2, nz);  // plane p-1: completed in this iteration
 
     // carried between planes: arrivals for the plane above (group (0,1) and f15, f18 from the
     // neighbouring rows) and, for the plane below, its partial update and own sums of the
@@ -168,9 +188,8 @@ __global__ __launch_bounds__(LANES *WY) void d3_sweep_kernel(const T *__restrict
     C o0m1s = 0, o0m1x = 0, o17 = 0, o16 = 0;
 
     for (int it = 0; it < tz + 2; ++it) {
-        const int p = z0 - 1 + it;  // the plane whose post-collision populations are formed
-        load4(rowoff, p + 2, nxt);
-        if (halo_lo || halo_hi) load4(outoff, p + 1, onxt);
+        load4(off_row, zn, nxt);  // plane p + 2 (p = z0 - 1 + it: the plane formed now)
+        if (halo_lo || halo_hi) load4(off_out, zo, onxt);
 
         for (int f = 0; f < 4; ++f) lds_f[w][f][lane] = win[1][f];
         __syncthreads();
@@ -196,8 +215,8 @@ __global__ __launch_bounds__(LANES *WY) void d3_sweep_kernel(const T *__restrict
         for (int b = 0; b < 3; ++b) {
             const C px = c[1 + b] * c[1];  // J_b J_x of this column, for the neighbours' x-differences
             const C dx = from_right(px) - from_left(px);
-            const C dy = up[1 + b] * up[2] - dn[1 + b] * dn[2];
-            const C dz = win[2][1 + b] * win[2][3] - win[0][1 + b] * win[0][3];
+            const C dy = d3_pdiff(up[1 + b], up[2], dn[1 + b], dn[2]);
+            const C dz = d3_pdiff(win[2][1 + b], win[2][3], win[0][1 + b], win[0][3]);
             dp[b] = d3_flux(dx, dy, dz);
         }
         C f[Q];
@@ -214,44 +233,53 @@ __global__ __launch_bounds__(LANES *WY) void d3_sweep_kernel(const T *__restrict
         lds_g[w][5][lane] = l9 - r8;
         lds_g[w][6][lane] = f[16];  // (-1,-1): row below, plane below
         lds_g[w][7][lane] = f[18];  // (-1,1): row below, plane above
-        const C l11 = from_left(f[11]), r14 = from_right(f[14]);
-        const C l13 = from_left(f[13]), r12 = from_right(f[12]);
-        const C s01 = d3_sum(f[5], l11, r14), x01 = l11 - r14;   // (0,1): this row, plane above
-        const C s0m1 = d3_sum(f[6], l13, r12), x0m1 = l13 - r12; // (0,-1): this row, plane below
-        const C e1 = from_left(f[1]) - f[1], e2 = from_right(f[2]) - f[2];
-        __syncthreads();
-        const int wb = halo_lo ? w : w - 1, wa = halo_hi ? w : w + 1;
-        const C in10s = lds_g[wb][0][lane], in10x = lds_g[wb][1][lane];
-        const C in15 = lds_g[wb][2][lane], in17 = lds_g[wb][3][lane];
-        const C inm10s = lds_g[wa][4][lane], inm10x = lds_g[wa][5][lane];
-        const C in16 = lds_g[wa][6][lane], in18 = lds_g[wa][7][lane];
-
-        // the plane below (p - 1) is complete: its arrivals from plane p are in
-        if (it >= 2) {
-            C r, x, y, z;
-            d3_finish(part, s0m1 - o0m1s, x0m1 - o0m1x, in17 - o17, in16 - o16, win[0][0], win[0][1], win[0][2],
-                      win[0][3], r, x, y, z);
-            if (store_lane) {
-                const size_t a = (size_t)wrapi(p - 1, nz) * plane + rowoff;
-                out[a] = r;
-                out[n + a] = x;
-                out[2 * n + a] = y;
-                out[3 * n + a] = z;
-            }
+        // A halo row only sends: its own update is never stored, so it skips it (the branch is
+        // uniform in each wavefront; every wavefront still meets both barriers).
+        const bool inner = !halo_lo && !halo_hi;
+        C s01 = 0, x01 = 0, s0m1 = 0, x0m1 = 0, e1 = 0, e2 = 0;
+        if (inner) {
+            const C l11 = from_left(f[11]), r14 = from_right(f[14]);
+            const C l13 = from_left(f[13]), r12 = from_right(f[12]);
+            s01 = d3_sum(f[5], l11, r14);  // (0,1): this row, plane above
+            x01 = l11 - r14;
+            s0m1 = d3_sum(f[6], l13, r12);  // (0,-1): this row, plane below
+            x0m1 = l13 - r12;
+            e1 = from_left(f[1]) - f[1];
+            e2 = from_right(f[2]) - f[2];
         }
-        // this plane: arrivals from the plane below (carried) and from this plane
-        const D3Part<C> lo = d3_lo(a01s - d3_sum(f[5], f[11], f[14]), a01x - (f[11] - f[14]), a15 - f[15], a18 - f[18]);
-        part = d3_lo_mid(lo, e1, e2, in10s - d3_sum(f[3], f[7], f[10]), in10x - (f[7] - f[10]),
-                         inm10s - d3_sum(f[4], f[9], f[8]), inm10x - (f[9] - f[8]));
-        o0m1s = d3_sum(f[6], f[13], f[12]);
-        o0m1x = f[13] - f[12];
-        o17 = f[17];
-        o16 = f[16];
-        a01s = s01;
-        a01x = x01;
-        a15 = in15;
-        a18 = in18;
+        __syncthreads();
+        if (inner) {
+            const C in10s = lds_g[w - 1][0][lane], in10x = lds_g[w - 1][1][lane];
+            const C in15 = lds_g[w - 1][2][lane], in17 = lds_g[w - 1][3][lane];
+            const C inm10s = lds_g[w + 1][4][lane], inm10x = lds_g[w + 1][5][lane];
+            const C in16 = lds_g[w + 1][6][lane], in18 = lds_g[w + 1][7][lane];
 
+            // the plane below (p - 1) is complete: its arrivals from plane p are in
+            if (it >= 2) {
+                C r, x, y, z;
+                d3_finish(part, s0m1 - o0m1s, x0m1 - o0m1x, in17 - o17, in16 - o16, win[0][0], win[0][1], win[0][2],
+                          win[0][3], r, x, y, z);
+                const C v[4] = {r, x, y, z};
+                for (int f = 0; f < 4; ++f)
+                    Ops::store(__builtin_bit_cast(typename Ops::W, v[f]), rsrc(out, f, zs), off_st);
+            }
+            // this plane: arrivals from the plane below (carried) and from this plane
+            const D3Part<C> lo =
+                d3_lo(a01s - d3_sum(f[5], f[11], f[14]), a01x - (f[11] - f[14]), a15 - f[15], a18 - f[18]);
+            part = d3_lo_mid(lo, e1, e2, in10s - d3_sum(f[3], f[7], f[10]), in10x - (f[7] - f[10]),
+                             inm10s - d3_sum(f[4], f[9], f[8]), inm10x - (f[9] - f[8]));
+            o0m1s = d3_sum(f[6], f[13], f[12]);
+            o0m1x = f[13] - f[12];
+            o17 = f[17];
+            o16 = f[16];
+            a01s = s01;
+            a01x = x01;
+            a15 = in15;
+            a18 = in18;
+        }
+        zn = next_plane(zn);
+        zo = next_plane(zo);
+        zs = next_plane(zs);
         for (int q = 0; q < 4; ++q) {
             win[0][q] = win[1][q];
             win[1][q] = win[2][q];

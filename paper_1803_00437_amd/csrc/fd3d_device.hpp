@@ -19,20 +19,26 @@ namespace d3 {
 constexpr int Q = 19;
 
 // Per-step constants.  The differences are unscaled (g(+1) - g(-1), twice the derivative) and
-// the factor 1/2 is folded in here, as are the norms of the moment rows:
-//   energy e = 19|c|^2 - 30, |e|^2 = 2394; 3p_xx = 3c_x^2 - |c|^2, |.|^2 = 36;
-//   p_ww = c_y^2 - c_z^2, |.|^2 = 12; p_xy, p_yz, p_xz, |.|^2 = 4.
+// the factor 1/2 is folded in here, as are the norms of the moment rows and the weights the
+// corrections enter the populations with:
+//   energy e = 19|c|^2 - 30, |e|^2 = 2394, weight -11 on faces and 8 on edges;
+//   3p_xx = 3c_x^2 - |c|^2, |.|^2 = 36; p_ww = c_y^2 - c_z^2, |.|^2 = 12;
+//   p_xy, p_yz, p_xz, |.|^2 = 4.
 template <typename C> struct Coef3 {
-    C ke;  // (1 - 1/s_e) / 252  = (1 - 1/s_e) * 19 / (2 * 2394)
-    C kp;  // (1 - 1/s_nu) / 72  = (1 - 1/s_nu) / (2 * 36)
-    C kw;  // (1 - 1/s_nu) / 24
-    C ko;  // (1 - 1/s_nu) / 8
+    C kf;  // -11 (1 - 1/s_e) / 252 = -11 (1 - 1/s_e) 19 / (2 * 2394): energy, faces
+    C kd;  //   8 (1 - 1/s_e) / 252: energy, edges
+    C kp;  // (1 - 1/s_nu) / 36: 3p_xx per unit of the half diagonal defects h_aa = u_aa / 2
+    C kw;  // (1 - 1/s_nu) / 12: p_ww per unit of h_aa
+    C ko;  // (1 - 1/s_nu) / 8 : p_xy, p_yz, p_xz per unit of u_ab
 };
 template <typename C> inline Coef3<C> coef3(double s_nu, double s_e)
 {
     const double a = 1.0 - 1.0 / s_e, b = 1.0 - 1.0 / s_nu;
-    return Coef3<C>{C(a / 252.0), C(b / 72.0), C(b / 24.0), C(b / 8.0)};
+    return Coef3<C>{C(-11.0 * a / 252.0), C(8.0 * a / 252.0), C(b / 36.0), C(b / 12.0), C(b / 8.0)};
 }
+
+// a b - c d, the difference of a product between the two neighbours along an axis
+template <typename C> __device__ __forceinline__ C d3_pdiff(C a, C b, C c, C d) { return fmac(a, b, -(c * d)); }
 
 // Inputs of one node: the stored deviations and the unscaled differences
 //   gr[a] = D_a drho,  dj[a][b] = D_a J_b,  dp[a] = (D_x(J_a J_x) + D_y(J_a J_y)) + D_z(J_a J_z).
@@ -41,10 +47,11 @@ template <typename C> inline Coef3<C> coef3(double s_nu, double s_e)
 // Defects (unscaled, u = 2 theta):
 //   u_ab = 1/3 [(D_a J_b + D_b J_a) - (J_a D_b rho + J_b D_a rho)] - (J_a dp_b + J_b dp_a)
 //   te   = (2/3 - 2|J|^2) div J - 2/3 J.grad rho    (the energy's trace term)
-// Corrections of the second-order moments, per population (columns of M^{-1} = M^T / norms):
-//   pe = ke te, pp = kp (2u_xx - u_yy - u_zz), pw = kw (u_yy - u_zz), p_ab = ko u_ab
-//   face x: -11pe + 2pp      face y: -11pe - pp + pw     face z: -11pe - pp - pw
-//   edge xy: 8pe + pp + pw +- p_xy   edge xz: 8pe + pp - pw +- p_xz   edge yz: 8pe - 2pp +- p_yz
+// Corrections of the second-order moments, per population (columns of M^{-1} = M^T / norms),
+// with h_aa = u_aa / 2:
+//   fe = kf te, ee = kd te, pp = kp (2h_xx - h_yy - h_zz), pw = kw (h_yy - h_zz), p_ab = ko u_ab
+//   face x: fe + 2pp         face y: fe - pp + pw        face z: fe - pp - pw
+//   edge xy: ee + pp + pw +- p_xy    edge xz: ee + pp - pw +- p_xz    edge yz: ee - 2pp +- p_yz
 // Equilibrium (deviations), with T = drho - 3/2 |J|^2/rho and Q_ab = J_a J_b / rho:
 //   face +-a: T/18 + Q_aa/4 +- J_a/6
 //   edge (s_a, s_b): T/36 + (Q_aa + Q_bb)/8 + s_a s_b Q_ab/4 + (s_a J_a + s_b J_b)/12
@@ -53,10 +60,10 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
                                          const Coef3<C> &k, C (&f)[Q])
 {
     const C third = C(1.0 / 3.0);
-    // diagonal defects u_aa = 2 [1/3 (D_a J_a - J_a D_a rho) - J_a dp_a]
-    C uxx = C(2) * fmac(third, fmac(-j[0], gr[0], dj[0][0]), -(j[0] * dp[0]));
-    C uyy = C(2) * fmac(third, fmac(-j[1], gr[1], dj[1][1]), -(j[1] * dp[1]));
-    C uzz = C(2) * fmac(third, fmac(-j[2], gr[2], dj[2][2]), -(j[2] * dp[2]));
+    // half diagonal defects h_aa = u_aa / 2 = 1/3 (D_a J_a - J_a D_a rho) - J_a dp_a
+    const C hxx = fmac(third, fmac(-j[0], gr[0], dj[0][0]), -(j[0] * dp[0]));
+    const C hyy = fmac(third, fmac(-j[1], gr[1], dj[1][1]), -(j[1] * dp[1]));
+    const C hzz = fmac(third, fmac(-j[2], gr[2], dj[2][2]), -(j[2] * dp[2]));
     // off-diagonal defects
     const C uxy = fmac(third, (dj[0][1] + dj[1][0]) - fmac(j[0], gr[1], j[1] * gr[0]), -fmac(j[0], dp[1], j[1] * dp[0]));
     const C uxz = fmac(third, (dj[0][2] + dj[2][0]) - fmac(j[0], gr[2], j[2] * gr[0]), -fmac(j[0], dp[2], j[2] * dp[0]));
@@ -67,16 +74,15 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
     const C jg = fmac(j[0], gr[0], fmac(j[1], gr[1], j[2] * gr[2]));
     const C te = fmac(fmac(C(-2), j2, C(2.0 / 3.0)), div, C(-2.0 / 3.0) * jg);
 
-    const C pe = k.ke * te;
-    const C pp = k.kp * ((C(2) * uxx - uyy) - uzz);
-    const C pw = k.kw * (uyy - uzz);
+    const C fe = k.kf * te, ee = k.kd * te;
+    const C pp = k.kp * fmac(C(2), hxx, -hyy - hzz);
+    const C pw = k.kw * (hyy - hzz);
     const C cxy = k.ko * uxy, cxz = k.ko * uxz, cyz = k.ko * uyz;
 
     const C rinv = recip(C(1) + dr);
     const C qxx = pxx * rinv, qyy = pyy * rinv, qzz = pzz * rinv;
     const C T = fmac(C(-1.5), (qxx + qyy) + qzz, dr);
     const C t18 = T * C(1.0 / 18.0), t36 = T * C(1.0 / 36.0);
-    const C fe = C(-11) * pe, ee = C(8) * pe;
 
     // faces
     const C Fx = fmac(qxx, C(0.25), t18) + fmac(C(2), pp, fe);

@@ -244,7 +244,7 @@ KERNELS = [
     ("fd3d_f32_512", "d3_sweep_kernel<float, 12>", 32 * N3 ** 3, "d3", D3_SOURCES,
      "512^3 periodic decaying flow (modes 0<|k|<=8, max|field| 0.02), nu 0.02; FD-LBM D3Q19 sweep kernel, FP32 "
      "(4 words read + 4 written per node)"),
-    ("fd3d_f64_512", "d3_sweep_kernel<double, 8>", 64 * N3 ** 3, None, D3_SOURCES,
+    ("fd3d_f64_512", "d3_sweep_kernel<double, 12>", 64 * N3 ** 3, None, D3_SOURCES,
      "512^3 periodic decaying flow (modes 0<|k|<=8, max|field| 0.02), nu 0.02; FD-LBM D3Q19 sweep kernel, FP64"),
     ("disk_fill_f32_8192", "disk_fill_kernel<float>", DISK_FILL_BYTES, None, [f"{CSRC}/disk.hip"],
      "disk of radius 4090 in the 8192 x 8192 grid (section 3-b curved wall): ghost nodes and the ring of rest "

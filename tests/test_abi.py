@@ -342,7 +342,7 @@ def test_workspace_bytes_3d():
 
 @pytest.mark.parametrize("bad", [
     dict(nx=2), dict(ny=2), dict(nz=2), dict(nx=(1 << 20) + 1), dict(s_nu=2.0), dict(s_nu=0.0), dict(s_e=-1.0),
-    dict(s_e=float("nan")), dict(tile_rows=4), dict(tile_rows=10), dict(tile_rows=-1), dict(tile_planes=-1),
+    dict(s_e=float("nan")), dict(tile_rows=4), dict(tile_rows=14), dict(tile_rows=-1), dict(tile_planes=-1),
     dict(tile_planes=4097), dict(nx=1 << 20, ny=1 << 20, nz=3),
 ])
 def test_invalid_parameters_3d_are_rejected(bad):
