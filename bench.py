@@ -99,6 +99,27 @@ def run_case(F, torch, init, scheme, dtype, stencil, steps, warmup, kernel, with
 
 
 D3_N = 512
+VALU_JSON = os.path.join(ROOT, "profiles", "valu_busy_8192.json")
+# issue rate of FP32 vector instructions without packed math: 256 compute units x 4 SIMDs x
+# 16 lanes per cycle (a wave64 instruction holds a SIMD for 4 cycles) x 2.4 GHz
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def d3_alu_roofline(kernel_ms, nodes):
+    """The D3Q19 sweep is bound by instruction issue: VALU lane-instructions per second against
+    the chip's issue rate, with the instructions per node the rocprofv3 VALU pass measured on
+    the same kernel sources (None when the counters were taken on other sources)."""
+    if not os.path.exists(VALU_JSON):
+        return None
+    from paper_1803_00437_amd.profiling import VALU_SOURCES, sources_sha
+
+    with open(VALU_JSON) as f:
+        v = json.load(f).get("d3_f32")
+    if not v or v.get("kernel_source_sha") != sources_sha(VALU_SOURCES["d3_f32"], ROOT):
+        return None
+    achieved = v["insts_per_node"] * nodes / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK, "unit": "VALU lane-instructions/s",
+            "frac": achieved / VALU_PEAK, "insts_per_node": v["insts_per_node"], "valu_busy_counter": v["busy"]}
 D3_WORKLOAD = ("{n}^3 periodic decaying flow, random Fourier modes 0<|k|<=8 per field, max|field|=0.02, seed 6; "
                "FD-LBM D3Q19 3-point finite differences, nu=0.02, s_e=1")
 
@@ -418,6 +439,7 @@ def main():
         for dtype in ("f32", "f64"):
             d3[dtype] = run_d3(F, torch, init3, dtype, args.d3_steps, 5)
             print(f"# d3q19 {dtype}: {d3[dtype]}", file=sys.stderr, flush=True)
+        d3["roofline_f32"] = d3_alu_roofline(d3["f32"]["kernel_ms"], D3_N ** 3)
         del init3
         if not args.no_cpu:
             from oracle import d3q19 as O3

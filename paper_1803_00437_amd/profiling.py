@@ -199,6 +199,9 @@ D3_COUNTER_ARGS = ["--only", "d3_f32", "--d3-steps", "20", "--copy-probe"]
 # VALU passes (one rocprofv3 --pmc run each): instructions issued and cycles the SIMDs spent
 # issuing them, per dispatch of the step kernel
 VALU_COUNTERS = ["SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", "SQ_WAVES"]
+VALU_SOURCES = {"fd3_f32": FD_SOURCES, "fd3_f16": FD_SOURCES, "mrt_f32": MRT_SOURCES,
+                "batch512": [f"{CSRC}/fd_batch.hip", f"{CSRC}/fd_sweep_body.hpp", f"{CSRC}/fdlbm_device.hpp"],
+                "d3_f32": D3_SOURCES}
 VALU_PASSES = [
     # name, bench arguments, kernel name pattern, nodes updated per dispatch (summed over the
     # matching kernels of one step)
@@ -299,6 +302,11 @@ def valu_summary(raw, out_md, command):
                      f"{r[7]:.1f} |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
+    summary = {name: {"kernel": r[0], "valu_insts": r[2], "busy": r[6], "insts_per_node": r[7],
+                      "kernel_source_sha": sources_sha(VALU_SOURCES[name])}
+               for (name, _, _, _), r in zip(VALU_PASSES, rows)}
+    with open(os.path.splitext(out_md)[0] + ".json", "w") as f:
+        json.dump(summary, f, indent=1)
     return rows
 
 

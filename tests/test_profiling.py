@@ -1,6 +1,7 @@
 """Host checks of the rocprofv3 summariser: the scaling of the HBM byte counters by the
 copy kernel of known traffic, and the constants it uses for the bench workloads."""
 import csv
+import json
 import os
 
 import pytest
@@ -98,3 +99,6 @@ def test_valu_summary_busy_and_instructions_per_node(tmp_path):
     d3 = out[[p[0] for p in P.VALU_PASSES].index("d3_f32")]
     assert d3[7] == pytest.approx(1e8 * 64 / P.N3 ** 3)
     assert "VALU busy" in open(tmp_path / "v.md").read()
+    js = json.load(open(tmp_path / "v.json"))
+    assert js["d3_f32"]["insts_per_node"] == pytest.approx(1e8 * 64 / P.N3 ** 3)
+    assert js["d3_f32"]["kernel_source_sha"] == P.sources_sha(P.D3_SOURCES)
