@@ -239,19 +239,21 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
     const C A_ax = fmac(dr, C(1.0 / 9.0), fmac(te, C(-1.0 / 36.0), k12));
     const C A_dg = fmac(dr, C(1.0 / 36.0), fmac(te, C(1.0 / 18.0), k12));
     f[0] = fmac(dr, C(4.0 / 9.0), fmac(K, C(-2.0 / 3.0), te * C(-1.0 / 9.0)));
+    // the odd parts (J/3 on the axes, (+-Jx +-Jy)/12 on the diagonals) enter through fused
+    // multiply-adds with the constant: one instruction per population
     const C axp = fmac(XX, C(0.25), A_ax), axm = fmac(XX, C(-0.25), A_ax);
-    const C ux = plus_force<FORCE>(jx, k.qfx) * C(1.0 / 3.0), uy = plus_force<FORCE>(jy, k.qfy) * C(1.0 / 3.0);
-    f[1] = axp + ux;
-    f[3] = axp - ux;
-    f[2] = axm + uy;
-    f[4] = axm - uy;
+    const C ux = plus_force<FORCE>(jx, k.qfx), uy = plus_force<FORCE>(jy, k.qfy);
+    f[1] = fmac(ux, C(1.0 / 3.0), axp);
+    f[3] = fmac(ux, C(-1.0 / 3.0), axp);
+    f[2] = fmac(uy, C(1.0 / 3.0), axm);
+    f[4] = fmac(uy, C(-1.0 / 3.0), axm);
     const C dgp = fmac(XY, C(0.25), A_dg), dgm = fmac(XY, C(-0.25), A_dg);
-    const C vx = plus_force<FORCE>(jx, k.dfx) * C(1.0 / 12.0), vy = plus_force<FORCE>(jy, k.dfy) * C(1.0 / 12.0);
+    const C vx = plus_force<FORCE>(jx, k.dfx), vy = plus_force<FORCE>(jy, k.dfy);
     const C s = vx + vy, t = vy - vx;
-    f[5] = dgp + s;
-    f[7] = dgp - s;
-    f[6] = dgm + t;
-    f[8] = dgm - t;
+    f[5] = fmac(s, C(1.0 / 12.0), dgp);
+    f[7] = fmac(s, C(-1.0 / 12.0), dgp);
+    f[6] = fmac(t, C(1.0 / 12.0), dgm);
+    f[8] = fmac(t, C(-1.0 / 12.0), dgm);
 }
 
 // LW-ACM (section 1-b): f*_k(x) = f^eq_k(x) + Theta (f^eo_k(x + e_k) - f^eo_k(x)) with
@@ -274,18 +276,17 @@ template <typename C> __device__ __forceinline__ void lw_node_g(C dr, C jx, C jy
     const C A_dg = fmac(dr, C(1.0 / 36.0), k12);
     f[0] = fmac(dr, C(4.0 / 9.0), K * C(-2.0 / 3.0));
     const C axp = fmac(XX, C(0.25), A_ax), axm = fmac(XX, C(-0.25), A_ax);
-    const C ux = lin * jx * C(1.0 / 3.0), uy = lin * jy * C(1.0 / 3.0);
-    f[1] = axp + ux;
-    f[3] = axp - ux;
-    f[2] = axm + uy;
-    f[4] = axm - uy;
+    const C ux = lin * jx, uy = lin * jy;
+    f[1] = fmac(ux, C(1.0 / 3.0), axp);
+    f[3] = fmac(ux, C(-1.0 / 3.0), axp);
+    f[2] = fmac(uy, C(1.0 / 3.0), axm);
+    f[4] = fmac(uy, C(-1.0 / 3.0), axm);
     const C dgp = fmac(XY, C(0.25), A_dg), dgm = fmac(XY, C(-0.25), A_dg);
-    const C vx = lin * jx * C(1.0 / 12.0), vy = lin * jy * C(1.0 / 12.0);
-    const C s = vx + vy, t = vy - vx;
-    f[5] = dgp + s;
-    f[7] = dgp - s;
-    f[6] = dgm + t;
-    f[8] = dgm - t;
+    const C s = ux + uy, t = uy - ux;
+    f[5] = fmac(s, C(1.0 / 12.0), dgp);
+    f[7] = fmac(s, C(-1.0 / 12.0), dgp);
+    f[6] = fmac(t, C(1.0 / 12.0), dgm);
+    f[8] = fmac(t, C(-1.0 / 12.0), dgm);
 }
 
 // Propagation (eq. 2) in increment form.  The new state at x sums f*_k(x - e_k); the
