@@ -79,6 +79,14 @@ int fdlbm3d_step(fdlbm3d_ctx *c, int64_t nsteps);
 /* FP64 reduction over the current state.  Synchronises the stream. */
 int fdlbm3d_diagnostics(fdlbm3d_ctx *c, fdlbm3d_diag *out);
 
+/* Time every sweep tile shape (rows per block 8, 12, 16 x planes per block 16, 32, 64, 128)
+ * on this grid, reps steps each after one warm-up, and keep the fastest for later steps.  The
+ * timed steps read the current state and write the spare buffer, so the state does not
+ * advance; all shapes give the same bits.  The reference kernels have no shape (their time is
+ * reported).  Chosen rows, planes and ms per step go to the out pointers (each may be NULL).
+ * Synchronises the stream.  FDLBM_EINVAL for a NULL context or reps outside 1..10000. */
+int fdlbm3d_autotune(fdlbm3d_ctx *c, int32_t reps, int32_t *out_rows, int32_t *out_planes, double *out_ms);
+
 int64_t fdlbm3d_step_count(const fdlbm3d_ctx *c);
 void fdlbm3d_destroy(fdlbm3d_ctx *c);
 const char *fdlbm3d_last_error(void);

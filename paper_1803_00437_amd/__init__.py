@@ -41,7 +41,7 @@ EXPORTED = (
     "fdlbm_batch_step", "fdlbm_batch_step_per_instance", "fdlbm_batch_amplitudes", "fdlbm_batch_step_count",
     "fdlbm_batch_destroy", "fdlbm_batch_last_error", "fdlbm_batch_autotune",
     "fdlbm3d_workspace_bytes", "fdlbm3d_create", "fdlbm3d_set_state", "fdlbm3d_get_state", "fdlbm3d_step",
-    "fdlbm3d_diagnostics", "fdlbm3d_step_count", "fdlbm3d_destroy", "fdlbm3d_last_error",
+    "fdlbm3d_diagnostics", "fdlbm3d_step_count", "fdlbm3d_destroy", "fdlbm3d_last_error", "fdlbm3d_autotune",
 )
 
 
@@ -167,6 +167,7 @@ def load_library(path=LIB_PATH):
         "fdlbm3d_step_count": (i64, [vp]),
         "fdlbm3d_destroy": (None, [vp]),
         "fdlbm3d_last_error": (ctypes.c_char_p, []),
+        "fdlbm3d_autotune": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -555,6 +556,13 @@ def fdlbm3d_last_error():
     return load_library().fdlbm3d_last_error().decode()
 
 
+def fdlbm3d_autotune(ctx, reps=10):
+    rows, planes, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load_library().fdlbm3d_autotune(ctx, int(reps), ctypes.byref(rows), ctypes.byref(planes),
+                                           ctypes.byref(ms)), "fdlbm3d_autotune")
+    return rows.value, planes.value, ms.value
+
+
 class FdLbm3D:
     """One D3Q19 FD-LBM simulation on a periodic nx * ny * nz grid: owns its torch device
     buffers and its library context.  Keyword arguments follow ``fdlbm3d_params``
@@ -594,6 +602,11 @@ class FdLbm3D:
 
     def diagnostics(self):
         return fdlbm3d_diagnostics(self.ctx)
+
+    def autotune(self, reps=10):
+        """Pick the fastest sweep tile shape for this grid (fdlbm3d_autotune); returns
+        (tile_rows, tile_planes, ms_per_step)."""
+        return fdlbm3d_autotune(self.ctx, reps)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

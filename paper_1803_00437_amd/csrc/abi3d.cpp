@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <new>
+#include <vector>
 
 #include "fdlbm3d.h"
 #include "internal.hpp"
@@ -203,6 +204,66 @@ int fdlbm3d_diagnostics(fdlbm3d_ctx *c, fdlbm3d_diag *out)
     out->kin_energy = h[4];
     out->max_abs_j = h[5];
     out->nonfinite = (int64_t)h[6];
+    return FDLBM_OK;
+}
+
+int fdlbm3d_autotune(fdlbm3d_ctx *c, int32_t reps, int32_t *out_rows, int32_t *out_planes, double *out_ms)
+{
+    if (!c || reps < 1 || reps > 10000) return FDLBM_EINVAL;
+    HIPCHK3(hipSetDevice(c->device), "hipSetDevice");
+    fdlbm3d_params &p = c->p;
+    struct Shape {
+        int rows, planes;
+    };
+    std::vector<Shape> cand;
+    if (p.kernel == FDLBM_KERNEL_REFERENCE) {
+        cand.push_back({p.tile_rows, p.tile_planes});
+    } else {
+        for (int rows : {8, 12, 16})
+            for (int planes : {16, 32, 64, 128}) {
+                const Dim3Grid g = d3_sweep_grid(p.nx, p.ny, p.nz, rows, planes);
+                if (g.y <= 65535 && g.z <= 65535) cand.push_back({rows, planes});
+            }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // every timed launch reads the current state and writes the spare buffer, which the next
+    // step overwrites: the state does not advance
+    const void *src = c->buf[c->cur];
+    void *dst = c->buf[1 - c->cur];
+    auto launch = [&](const Shape &sh) -> hipError_t {
+        if (p.kernel == FDLBM_KERNEL_REFERENCE)
+            return launch_d3_reference(p.dtype, src, dst, c->scratch + c->L.fstar, p.nx, p.ny, p.nz, p.s_nu, p.s_e,
+                                       c->stream);
+        return launch_d3_sweep(p.dtype, src, dst, p.nx, p.ny, p.nz, p.s_nu, p.s_e, sh.rows, sh.planes, c->stream);
+    };
+    Shape best{0, 0};
+    float best_ms = 0.0f;
+    for (const Shape &sh : cand) {
+        if (e == hipSuccess) e = launch(sh);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(sh);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return device_error3(e, "fdlbm3d_autotune");
+    if (p.kernel != FDLBM_KERNEL_REFERENCE) {
+        p.tile_rows = best.rows;
+        p.tile_planes = best.planes;
+    }
+    if (out_rows) *out_rows = tile_rows(p);
+    if (out_planes) *out_planes = tile_planes(p);
+    if (out_ms) *out_ms = (double)best_ms / reps;
     return FDLBM_OK;
 }
 

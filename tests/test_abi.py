@@ -29,7 +29,7 @@ def test_library_loads_and_exports_every_declared_function():
     lib = F.load_library()
     names = declared_functions()
     assert "fdlbm_step" in names and "mrt_step" in names and "fdlbm_diagnostics" in names
-    assert "fdlbm3d_step" in names and "fdlbm3d_create" in names
+    assert "fdlbm3d_step" in names and "fdlbm3d_create" in names and "fdlbm3d_autotune" in names
     for name in names:
         assert hasattr(lib, name), name
     assert sorted(F.EXPORTED) == names

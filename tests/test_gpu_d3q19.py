@@ -182,3 +182,41 @@ def test_full_size_sweep_equals_reference(F):
     b = run3(F, (n, n, n), 3, init, kernel="sweep", **kw)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
+
+
+def test_autotune_keeps_the_state_and_the_bits(F):
+    """fdlbm3d_autotune times every tile shape out of place: the state and the step count are
+    unchanged, and the tuned run gives the same bits as an untuned one."""
+    shape = (40, 37, 130)
+    print(f"case d3 autotune shape={shape}", flush=True)
+    nz, ny, nx = shape
+    init = W.random_state3(nx, ny, nz, seed=21, amp=0.02)
+    sim = F.FdLbm3D(nx, ny, nz, dtype="f32", s_nu=1.5, s_e=1.1)
+    sim.set_state(*init)
+    before = sim.get_state()
+    rows, planes, ms = sim.autotune(reps=2)
+    assert rows in (8, 12, 16) and planes in (16, 32, 64, 128) and ms > 0
+    assert sim.steps == 0
+    for u, v in zip(before, sim.get_state()):
+        assert np.array_equal(u, v)
+    sim.step(7)
+    tuned = sim.get_state()
+    sim.close()
+    plain = run3(F, shape, 7, init, dtype="f32", s_nu=1.5, s_e=1.1)
+    for u, v in zip(tuned, plain):
+        assert np.array_equal(u, v)
+
+
+def test_fp32_long_run_against_fp64(F):
+    """Over 1000 steps of the 128^3 decaying flow the FP32 state stays within 2e-6 (relative
+    L2) of the FP64 run, whose kernels equal the oracle to 1e-13 above: the increment-form
+    update keeps the rounding at the scale of the increments."""
+    n, steps = 128, 1000
+    print(f"case d3 fp32-vs-fp64 n={n} steps={steps}", flush=True)
+    init = W.decaying_flow3(n, seed=6, amp=0.02)
+    kw = dict(s_nu=1.0 / (0.5 + 3 * 0.02), s_e=1.0)
+    a = run3(F, (n, n, n), steps, init, dtype="f64", **kw)
+    b = run3(F, (n, n, n), steps, init, dtype="f32", **kw)
+    err = rel(b, a)
+    print(f"d3 fp32 vs fp64 after {steps} steps: {err:.3e}", flush=True)
+    assert err < 2e-6, err
