@@ -34,7 +34,8 @@ extern "C" {
 #endif
 
 typedef struct fdlbm3d_params {
-    int32_t nx, ny, nz;  /* periodic grid, each 3 .. 2^20, nx*ny*nz < 2^40                      */
+    int32_t nx, ny, nz;  /* periodic grid, each 3 .. 2^20, nx*ny*nz < 2^40, one x-y plane below
+                            2^31 bytes (nx*ny < 2^29 in FP32, 2^28 in FP64)                       */
     int32_t dtype;       /* FDLBM_F64 or FDLBM_F32: storage and arithmetic                        */
     double s_nu, s_e;    /* relaxation rates in (0, 2): shear (five traceless moments), energy    */
     int32_t kernel;      /* FDLBM_KERNEL_AUTO or _SWEEP: the fused sweep kernel; _REFERENCE: the

@@ -49,6 +49,9 @@ int validate3(const fdlbm3d_params *p)
         if (v < 3 || v > (1 << 20)) return FDLBM_EINVAL;
     if (nodes(*p) >= (size_t(1) << 40)) return FDLBM_EINVAL;
     if (p->dtype != FDLBM_F64 && p->dtype != FDLBM_F32) return FDLBM_EINVAL;
+    // the sweep kernel addresses a field plane through a buffer resource whose size and
+    // per-lane offsets are 32-bit byte counts: one plane must stay below 2^31 bytes
+    if ((size_t)p->nx * (size_t)p->ny * elem(*p) >= (size_t(1) << 31)) return FDLBM_EINVAL;
     if (!rate_ok(p->s_nu) || !rate_ok(p->s_e)) return FDLBM_EINVAL;
     if (p->kernel != FDLBM_KERNEL_AUTO && p->kernel != FDLBM_KERNEL_REFERENCE && p->kernel != FDLBM_KERNEL_SWEEP)
         return FDLBM_EINVAL;

@@ -343,12 +343,19 @@ def test_workspace_bytes_3d():
 @pytest.mark.parametrize("bad", [
     dict(nx=2), dict(ny=2), dict(nz=2), dict(nx=(1 << 20) + 1), dict(s_nu=2.0), dict(s_nu=0.0), dict(s_e=-1.0),
     dict(s_e=float("nan")), dict(tile_rows=4), dict(tile_rows=14), dict(tile_rows=-1), dict(tile_planes=-1),
-    dict(tile_planes=4097), dict(nx=1 << 20, ny=1 << 20, nz=3),
+    dict(tile_planes=4097), dict(nx=1 << 20, ny=1 << 20, nz=3), dict(nx=1 << 15, ny=1 << 14, nz=3),
+    dict(nx=1 << 14, ny=1 << 14, nz=3, dtype="f64"),
 ])
 def test_invalid_parameters_3d_are_rejected(bad):
     with pytest.raises(F.FdlbmError) as e:
         F.fdlbm3d_workspace_bytes(good3(**bad))
     assert e.value.code == F.FDLBM_EINVAL
+
+
+def test_largest_3d_plane_is_accepted():
+    """One plane just below 2^31 bytes is accepted (2^29 - 2^14 FP32 nodes, half of that in FP64)."""
+    F.fdlbm3d_workspace_bytes(good3(nx=1 << 15, ny=(1 << 14) - 1, nz=3))
+    F.fdlbm3d_workspace_bytes(good3(nx=1 << 14, ny=(1 << 14) - 1, nz=3, dtype="f64"))
 
 
 def test_params3d_rejects_other_dtypes():
