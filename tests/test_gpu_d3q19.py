@@ -220,3 +220,42 @@ def test_fp32_long_run_against_fp64(F):
     err = rel(b, a)
     print(f"d3 fp32 vs fp64 after {steps} steps: {err:.3e}", flush=True)
     assert err < 2e-6, err
+
+
+def test_state_beyond_2_31_values(F):
+    """832 x 832 x 800 nodes: the four planes hold 2.2e9 values, more than 2^31, so every offset
+    past the first plane needs 64-bit arithmetic.  A transverse wave along z plus a density wave
+    along x; one step is checked on sampled nodes against the oracle (periodic 9^3 windows), and
+    the FP64 momentum sums are conserved."""
+    nx, ny, nz = 832, 832, 800
+    print(f"case d3 beyond 2^31 values shape=({nz}, {ny}, {nx})", flush=True)
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    shape = (nz, ny, nx)
+    dr = np.ascontiguousarray(np.broadcast_to(1e-3 * np.cos(2 * np.pi * x / nx), shape))
+    jx = np.ascontiguousarray(np.broadcast_to(2e-3 * np.sin(2 * np.pi * z / nz), shape))
+    jy = np.zeros(shape)
+    jz = np.ascontiguousarray(np.broadcast_to(1e-3 * np.cos(4 * np.pi * z / nz), shape))
+    init = (dr, jx, jy, jz)
+    kw = dict(s_nu=1.0 / (0.5 + 3 * 0.02), s_e=1.3)
+    sim = F.FdLbm3D(nx, ny, nz, dtype="f32", **kw)
+    sim.set_state(*init)
+    d0 = sim.diagnostics()
+    sim.step(1)
+    d1 = sim.diagnostics()
+    out = sim.get_state()
+    sim.close()
+    held = tuple(a.astype(np.float32).astype(np.float64) for a in init)
+    rng = np.random.default_rng(3)
+    pts = rng.integers(0, [nz, ny, nx], size=(60, 3))
+    pts[0] = (nz - 1, ny - 1, nx - 1)
+    worst = 0.0
+    for (k, j, i) in pts:
+        idx = np.ix_(np.arange(k - 4, k + 5) % nz, np.arange(j - 4, j + 5) % ny, np.arange(i - 4, i + 5) % nx)
+        res = D.fd3d_run(*(a[idx] for a in held), 1, **kw)
+        for q in range(4):
+            worst = max(worst, abs(res[q][4, 4, 4] - out[q][k, j, i]) / 2e-3)
+    assert worst < 1e-6, worst
+    for key in ("mom_x", "mom_z"):
+        assert abs(d1[key] - d0[key]) < 1e-6 * nx * ny * nz * 1e-3, (key, d0[key], d1[key])
+    assert d1["nonfinite"] == 0
