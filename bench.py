@@ -346,7 +346,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the FD-LBM path of this "
-              "library has no multi-GPU build; see the sharding notes in DESIGN.md", file=sys.stderr)
+              "library has no multi-GPU build (it would split the grid into row bands, each GPU exchanging its edge "
+              "rows with its neighbours every step: two for 3-point differences, three for 5-point)", file=sys.stderr)
         sys.exit(2)
 
     import torch
