@@ -324,7 +324,7 @@ int fdlbm_set_state(fdlbm_ctx *c, const double *drho, const double *jx, const do
     HIPCHK(hipMemcpyAsync(st + n, jx, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
     HIPCHK(hipMemcpyAsync(st + 2 * n, jy, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
     if (three_words(c->p.scheme))
-        HIPCHK(launch_pack(c->p.dtype, st, c->buf[c->cur], 3 * n, c->stream), "pack");
+        HIPCHK(launch_pack3(c->p.dtype, st, c->buf[c->cur], c->p.nx, c->p.ny, c->stream), "pack");
     else
         HIPCHK(launch_mrt_init(c->p.dtype, st, st + n, st + 2 * n, c->buf[c->cur], n, c->stream), "mrt_init");
     HIPCHK(hipStreamSynchronize(c->stream), "set_state");
@@ -340,7 +340,7 @@ int fdlbm_get_state(fdlbm_ctx *c, double *drho, double *jx, double *jy)
     const size_t n = c->n(), nb = n * sizeof(double);
     double *st = c->sd(c->L.staging);
     if (three_words(c->p.scheme))
-        HIPCHK(launch_unpack(c->p.dtype, c->buf[c->cur], st, 3 * n, c->stream), "unpack");
+        HIPCHK(launch_unpack3(c->p.dtype, c->buf[c->cur], st, c->p.nx, c->p.ny, c->stream), "unpack");
     else
         HIPCHK(launch_mrt_moments(c->p.dtype, c->buf[c->cur], st, st + n, st + 2 * n, n, c->stream), "mrt_moments");
     HIPCHK(hipMemcpyAsync(drho, st, nb, hipMemcpyDeviceToHost, c->stream), "get_state download");
@@ -381,8 +381,8 @@ static int run_diag(fdlbm_ctx *c, double out[DIAG_SLOTS])
     HIPCHK(hipSetDevice(c->device), "hipSetDevice");
     const size_t n = c->n();
     const double *m = c->mode_set ? c->sd(c->L.mode) : nullptr;
-    HIPCHK(launch_diag(c->p.scheme, c->p.dtype, c->buf[c->cur], n, m, m ? m + n : nullptr, c->sd(c->L.partials),
-                       c->sd(c->L.out), c->stream),
+    HIPCHK(launch_diag(c->p.scheme, c->p.dtype, c->buf[c->cur], c->p.nx, c->p.ny, m, m ? m + n : nullptr,
+                       c->sd(c->L.partials), c->sd(c->L.out), c->stream),
            "diagnostics");
     HIPCHK(hipMemcpyAsync(out, c->sd(c->L.out), DIAG_SLOTS * sizeof(double), hipMemcpyDeviceToHost, c->stream),
            "diagnostics download");
@@ -482,8 +482,8 @@ int fdlbm_diagnostics_static(const fdlbm_params *p, const void *state, const dou
         int rc = validate(p);
         if (rc) return rc;
         if (!state || !out || (j0x == nullptr) != (j0y == nullptr)) return FDLBM_EINVAL;
-        const size_t n = (size_t)p->nx * (size_t)p->ny;
-        HIPCHK(launch_diag_static(p->scheme, p->dtype, state, n, j0x, j0y, out, static_cast<hipStream_t>(hip_stream)),
+        HIPCHK(launch_diag_static(p->scheme, p->dtype, state, p->nx, p->ny, j0x, j0y, out,
+                                  static_cast<hipStream_t>(hip_stream)),
                "fdlbm_diagnostics_static");
         return FDLBM_OK;
     });

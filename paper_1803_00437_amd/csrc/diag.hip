@@ -49,41 +49,55 @@ __device__ void block_reduce(double (&acc)[DIAG_SLOTS])
     }
 }
 
+__device__ __forceinline__ void diag_add(double (&acc)[DIAG_SLOTS], double r, double x, double y,
+                                         const double *__restrict__ j0x, const double *__restrict__ j0y, size_t p)
+{
+    const bool finite = isfinite(r) && isfinite(x) && isfinite(y);
+    if (!finite) {
+        acc[7] += 1.0;
+        return;
+    }
+    const double j2 = x * x + y * y;
+    acc[0] += r;
+    acc[1] += x;
+    acc[2] += y;
+    acc[3] += 0.5 * j2 / (1.0 + r);
+    acc[4] = fmax(acc[4], sqrt(j2));
+    if (j0x) {
+        const double ax = j0x[p], ay = j0y[p];
+        acc[5] += x * ax + y * ay;
+        acc[6] += ax * ax + ay * ay;
+    }
+}
+
+// MRT: nine population planes, node by node.  FD-LBM / LW-ACM: the row-interleaved state
+// (fd_elem), row by row (rows over the blocks, columns over the threads).  The mode (j0x,
+// j0y) is two planes in both cases.
 template <typename T, bool MRT>
-__global__ void __launch_bounds__(TPB) diag_partials(const T *__restrict__ st, size_t n, const double *__restrict__ j0x,
-                                                     const double *__restrict__ j0y, double *__restrict__ partials)
+__global__ void __launch_bounds__(TPB) diag_partials(const T *__restrict__ st, int nx, int ny,
+                                                     const double *__restrict__ j0x, const double *__restrict__ j0y,
+                                                     double *__restrict__ partials)
 {
     double acc[DIAG_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (size_t p = blockIdx.x * (size_t)TPB + threadIdx.x; p < n; p += (size_t)gridDim.x * TPB) {
-        double r, x, y;
-        if (MRT) {
+    const size_t n = (size_t)nx * (size_t)ny;
+    if (MRT) {
+        for (size_t p = blockIdx.x * (size_t)TPB + threadIdx.x; p < n; p += (size_t)gridDim.x * TPB) {
             double f[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) f[q] = double(Storage<T>::load(st[q * n + p]));
-            r = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
-            x = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
-            y = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
-        } else {
-            r = double(Storage<T>::load(st[p]));
-            x = double(Storage<T>::load(st[n + p]));
-            y = double(Storage<T>::load(st[2 * n + p]));
+            const double r = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
+            const double x = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+            const double y = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+            diag_add(acc, r, x, y, j0x, j0y, p);
         }
-        const bool finite = isfinite(r) && isfinite(x) && isfinite(y);
-        if (!finite) {
-            acc[7] += 1.0;
-            continue;
-        }
-        const double j2 = x * x + y * y;
-        acc[0] += r;
-        acc[1] += x;
-        acc[2] += y;
-        acc[3] += 0.5 * j2 / (1.0 + r);
-        acc[4] = fmax(acc[4], sqrt(j2));
-        if (j0x) {
-            const double ax = j0x[p], ay = j0y[p];
-            acc[5] += x * ax + y * ay;
-            acc[6] += ax * ax + ay * ay;
-        }
+    } else {
+        for (int j = blockIdx.x; j < ny; j += gridDim.x)
+            for (int i = threadIdx.x; i < nx; i += TPB) {
+                const double r = double(Storage<T>::load(st[fd_elem(i, j, 0, nx)]));
+                const double x = double(Storage<T>::load(st[fd_elem(i, j, 1, nx)]));
+                const double y = double(Storage<T>::load(st[fd_elem(i, j, 2, nx)]));
+                diag_add(acc, r, x, y, j0x, j0y, (size_t)j * (size_t)nx + (size_t)i);
+            }
     }
     block_reduce(acc);
     if (threadIdx.x == 0)
@@ -135,14 +149,14 @@ inline unsigned grid_for(size_t n)
 }
 
 template <typename T>
-hipError_t diag_run(bool mrt, const void *state, size_t n, const double *j0x, const double *j0y, double *partials,
-                    double *out, hipStream_t s)
+hipError_t diag_run(bool mrt, const void *state, int nx, int ny, const double *j0x, const double *j0y,
+                    double *partials, double *out, hipStream_t s)
 {
     const T *st = static_cast<const T *>(state);
     if (mrt)
-        hipLaunchKernelGGL((diag_partials<T, true>), DIAG_BLOCKS, TPB, 0, s, st, n, j0x, j0y, partials);
+        hipLaunchKernelGGL((diag_partials<T, true>), DIAG_BLOCKS, TPB, 0, s, st, nx, ny, j0x, j0y, partials);
     else
-        hipLaunchKernelGGL((diag_partials<T, false>), DIAG_BLOCKS, TPB, 0, s, st, n, j0x, j0y, partials);
+        hipLaunchKernelGGL((diag_partials<T, false>), DIAG_BLOCKS, TPB, 0, s, st, nx, ny, j0x, j0y, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(diag_final, 1, TPB, 0, s, partials, DIAG_BLOCKS, out);
@@ -151,14 +165,14 @@ hipError_t diag_run(bool mrt, const void *state, size_t n, const double *j0x, co
 
 }  // namespace
 
-hipError_t launch_diag(int scheme, int dtype, const void *state, size_t n, const double *j0x, const double *j0y,
+hipError_t launch_diag(int scheme, int dtype, const void *state, int nx, int ny, const double *j0x, const double *j0y,
                        double *partials, double *out, hipStream_t s)
 {
     const bool mrt = scheme == FDLBM_SCHEME_MRT;
     switch (dtype) {
-    case FDLBM_F64: return diag_run<double>(mrt, state, n, j0x, j0y, partials, out, s);
-    case FDLBM_F32: return diag_run<float>(mrt, state, n, j0x, j0y, partials, out, s);
-    default: return diag_run<__half>(mrt, state, n, j0x, j0y, partials, out, s);
+    case FDLBM_F64: return diag_run<double>(mrt, state, nx, ny, j0x, j0y, partials, out, s);
+    case FDLBM_F32: return diag_run<float>(mrt, state, nx, ny, j0x, j0y, partials, out, s);
+    default: return diag_run<__half>(mrt, state, nx, ny, j0x, j0y, partials, out, s);
     }
 }
 
@@ -195,14 +209,56 @@ hipError_t static_partials(double **out)
 }
 }  // namespace
 
-hipError_t launch_diag_static(int scheme, int dtype, const void *state, size_t n, const double *j0x,
+hipError_t launch_diag_static(int scheme, int dtype, const void *state, int nx, int ny, const double *j0x,
                               const double *j0y, double *out, hipStream_t s)
 {
     double *partials = nullptr;
     hipError_t e = static_partials(&partials);
     if (e != hipSuccess) return e;
     // every block writes its own partial, so nothing left by an earlier call is read
-    return launch_diag(scheme, dtype, state, n, j0x, j0y, partials, out, s);
+    return launch_diag(scheme, dtype, state, nx, ny, j0x, j0y, partials, out, s);
+}
+
+// Three-word state: host order (three planes of nx*ny FP64 values) to and from the
+// row-interleaved storage (fd_elem); one block row of columns per grid row.
+template <typename T>
+__global__ void __launch_bounds__(TPB) pack3_kernel(const double *__restrict__ in, T *__restrict__ out, int nx, int ny)
+{
+    const size_t n = (size_t)nx * (size_t)ny;
+    for (int j = blockIdx.x; j < ny; j += gridDim.x)
+        for (int i = threadIdx.x; i < nx; i += TPB)
+            for (int f = 0; f < 3; ++f)
+                out[fd_elem(i, j, f, nx)] = Storage<T>::store(typename Storage<T>::C(in[f * n + (size_t)j * nx + i]));
+}
+template <typename T>
+__global__ void __launch_bounds__(TPB) unpack3_kernel(const T *__restrict__ in, double *__restrict__ out, int nx, int ny)
+{
+    const size_t n = (size_t)nx * (size_t)ny;
+    for (int j = blockIdx.x; j < ny; j += gridDim.x)
+        for (int i = threadIdx.x; i < nx; i += TPB)
+            for (int f = 0; f < 3; ++f) out[f * n + (size_t)j * nx + i] = double(Storage<T>::load(in[fd_elem(i, j, f, nx)]));
+}
+
+hipError_t launch_pack3(int dtype, const double *in, void *out, int nx, int ny, hipStream_t s)
+{
+    const unsigned g = (unsigned)(ny < 65536 ? ny : 65536);
+    switch (dtype) {
+    case FDLBM_F64: hipLaunchKernelGGL(pack3_kernel<double>, g, TPB, 0, s, in, (double *)out, nx, ny); break;
+    case FDLBM_F32: hipLaunchKernelGGL(pack3_kernel<float>, g, TPB, 0, s, in, (float *)out, nx, ny); break;
+    default: hipLaunchKernelGGL(pack3_kernel<__half>, g, TPB, 0, s, in, (__half *)out, nx, ny); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack3(int dtype, const void *in, double *out, int nx, int ny, hipStream_t s)
+{
+    const unsigned g = (unsigned)(ny < 65536 ? ny : 65536);
+    switch (dtype) {
+    case FDLBM_F64: hipLaunchKernelGGL(unpack3_kernel<double>, g, TPB, 0, s, (const double *)in, out, nx, ny); break;
+    case FDLBM_F32: hipLaunchKernelGGL(unpack3_kernel<float>, g, TPB, 0, s, (const float *)in, out, nx, ny); break;
+    default: hipLaunchKernelGGL(unpack3_kernel<__half>, g, TPB, 0, s, (const __half *)in, out, nx, ny); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_pack(int dtype, const double *in, void *out, size_t count, hipStream_t s)

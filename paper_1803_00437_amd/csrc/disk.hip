@@ -191,17 +191,19 @@ __global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state, in
     using S = Storage<T>;
     using C = typename S::C;
     const size_t t = size_t(blockIdx.x) * TPB + threadIdx.x;
-    const size_t plane = size_t(f.nx) * size_t(f.ny);
+    const size_t nx = size_t(f.nx);
+    // element of field p at a node index (j nx + i) of the row-interleaved state (fd_elem)
+    auto elem = [&](size_t node, int p) { return fd_elem(node % nx, node / nx, p, nx); };
     if (t < size_t(f.nghost)) {
         const size_t s = size_t(f.src[t]), dst = size_t(f.dst[t]);
         const C wx = C(f.w[3 * t]), wy = C(f.w[3 * t + 1]), sj = C(f.w[3 * t + 2]);
         const C ux = C(1) - wx, uy = C(1) - wy;
         for (int p = 0; p < 3; ++p) {
-            const T *a = state + p * plane + s;
+            const T *a = state + elem(s, p);  // the cell's corners: +1 the next column, +3 nx the next row
             const C lower = ux * S::load(a[0]) + wx * S::load(a[1]);
-            const C upper = ux * S::load(a[f.nx]) + wx * S::load(a[f.nx + 1]);
+            const C upper = ux * S::load(a[3 * nx]) + wx * S::load(a[3 * nx + 1]);
             const C v = uy * lower + wy * upper;
-            state[p * plane + dst] = S::store(p == 0 ? v : sj * v);
+            state[elem(dst, p)] = S::store(p == 0 ? v : sj * v);
         }
         return;
     }
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state, in
     if (!full) {
         if (u >= size_t(f.nring)) return;
         const size_t node = size_t(f.ring[u]);
-        for (int p = 0; p < 3; ++p) state[p * plane + node] = S::store(C(0));
+        for (int p = 0; p < 3; ++p) state[elem(node, p)] = S::store(C(0));
         return;
     }
     const size_t per_row = (size_t(f.nx) + CLEAR_COLS - 1) / CLEAR_COLS;
@@ -219,8 +221,7 @@ __global__ __launch_bounds__(TPB) void disk_fill_kernel(DiskFill f, T *state, in
     const int a = f.span[2 * j], b = f.span[2 * j + 1];
     for (int i = i0; i < min(i0 + CLEAR_COLS, f.nx); ++i) {
         if (i >= a && i <= b) continue;
-        const size_t node = size_t(j) * size_t(f.nx) + size_t(i);
-        for (int p = 0; p < 3; ++p) state[p * plane + node] = S::store(C(0));
+        for (int p = 0; p < 3; ++p) state[fd_elem(i, j, p, nx)] = S::store(C(0));
     }
 }
 

@@ -25,14 +25,13 @@ __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__
     using C = typename Storage<T>::C;
     const BatchBlock b = blocks[blockIdx.x];
     const BatchInstance I = inst[b.instance];
-    const size_t n = (size_t)I.nx * (size_t)I.ny;
     TileArgs<T> t;
     t.dr = in + I.offset;
-    t.jx = t.dr + n;
-    t.jy = t.dr + 2 * n;
+    t.jx = t.dr + I.nx;  // row-interleaved fields (fd_elem)
+    t.jy = t.dr + 2 * (size_t)I.nx;
     t.odr = out + I.offset;
-    t.ojx = t.odr + n;
-    t.ojy = t.odr + 2 * n;
+    t.ojx = t.odr + I.nx;
+    t.ojy = t.odr + 2 * (size_t)I.nx;
     t.nx = I.nx;
     t.ny = I.ny;
     t.rows = rows;
@@ -51,14 +50,13 @@ __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict_
 {
     using C = typename Storage<T>::C;
     const BatchInstance I = inst[i];
-    const size_t n = (size_t)I.nx * (size_t)I.ny;
     TileArgs<T> t;
     t.dr = in + I.offset;
-    t.jx = t.dr + n;
-    t.jy = t.dr + 2 * n;
+    t.jx = t.dr + I.nx;  // row-interleaved fields (fd_elem)
+    t.jy = t.dr + 2 * (size_t)I.nx;
     t.odr = out + I.offset;
-    t.ojx = t.odr + n;
-    t.ojy = t.odr + 2 * n;
+    t.ojx = t.odr + I.nx;
+    t.ojy = t.odr + 2 * (size_t)I.nx;
     t.nx = I.nx;
     t.ny = I.ny;
     t.rows = rows;
@@ -89,12 +87,14 @@ __global__ void __launch_bounds__(PROJ_TPB) proj_partials(const T *__restrict__ 
     const BatchInstance I = inst[ch.instance];
     const size_t n = (size_t)I.nx * (size_t)I.ny;
     const size_t p0 = (size_t)ch.chunk * BATCH_CHUNK, p1 = p0 + BATCH_CHUNK < n ? p0 + BATCH_CHUNK : n;
-    const T *jx = state + I.offset + n, *jy = jx + n;
-    const T *mx = mode + I.mode_offset, *my = mx + n;
+    const T *st = state + I.offset;
+    const T *mx = mode + I.mode_offset, *my = mx + n;  // the mode: two planes
+    const unsigned nx = (unsigned)I.nx;
     double num = 0.0, den = 0.0;
     for (size_t p = p0 + threadIdx.x; p < p1; p += PROJ_TPB) {
+        const unsigned j = (unsigned)p / nx, i = (unsigned)p - j * nx;  // an instance has < 2^32 nodes
         const double ax = double(Storage<T>::load(mx[p])), ay = double(Storage<T>::load(my[p]));
-        num += double(Storage<T>::load(jx[p])) * ax + double(Storage<T>::load(jy[p])) * ay;
+        num += double(Storage<T>::load(st[fd_elem(i, j, 1, nx)])) * ax + double(Storage<T>::load(st[fd_elem(i, j, 2, nx)])) * ay;
         den += ax * ax + ay * ay;
     }
     num = wave_sum(num);

@@ -21,33 +21,38 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 // wall, drho even and J odd).
 template <typename T, bool WALLS> struct View {
     using C = typename Storage<T>::C;
-    const T *dr, *jx, *jy;
+    const T *st;  // row-interleaved state (fd_elem)
     int nx, ny;
     GhostRules<C> gr;
+    __device__ __forceinline__ void load3(int i, int j, C &r, C &x, C &y) const
+    {
+        r = Storage<T>::load(st[fd_elem(i, j, 0, nx)]);
+        x = Storage<T>::load(st[fd_elem(i, j, 1, nx)]);
+        y = Storage<T>::load(st[fd_elem(i, j, 2, nx)]);
+    }
     __device__ __forceinline__ void at(int i, int j, C &r, C &x, C &y) const
     {
         i = wrap(wrap(i, nx), nx);
         if (WALLS && (j < 0 || j >= ny)) {
             const GhostRule<C> q = ghost_rule(gr, j < 0 ? -j : j - ny + 1);
             const int ja = j < 0 ? q.sa : ny - 1 - q.sa;
-            const size_t pa = (size_t)ja * (size_t)nx + (size_t)i;
-            r = q.car * Storage<T>::load(dr[pa]);
-            x = q.caj * Storage<T>::load(jx[pa]);
-            y = q.caj * Storage<T>::load(jy[pa]);
+            C ra, xa, ya;
+            load3(i, ja, ra, xa, ya);
+            r = q.car * ra;
+            x = q.caj * xa;
+            y = q.caj * ya;
             if (q.sb >= 0) {
                 const int jb = j < 0 ? q.sb : ny - 1 - q.sb;
-                const size_t pb = (size_t)jb * (size_t)nx + (size_t)i;
-                r = r + q.cbr * Storage<T>::load(dr[pb]);
-                x = x + q.cbj * Storage<T>::load(jx[pb]);
-                y = y + q.cbj * Storage<T>::load(jy[pb]);
+                C rb, xb, yb;
+                load3(i, jb, rb, xb, yb);
+                r = r + q.cbr * rb;
+                x = x + q.cbj * xb;
+                y = y + q.cbj * yb;
             }
             return;
         }
         if (!WALLS) j = wrap(wrap(j, ny), ny);
-        const size_t p = (size_t)j * (size_t)nx + (size_t)i;
-        r = Storage<T>::load(dr[p]);
-        x = Storage<T>::load(jx[p]);
-        y = Storage<T>::load(jy[p]);
+        load3(i, j, r, x, y);
     }
 };
 
@@ -116,8 +121,8 @@ __global__ void __launch_bounds__(256) fd_ref_fstar(View<T, WALLS> v, FdCoef<typ
 template <typename T, bool WALLS, bool FORCE>
 __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::C *__restrict__ fstar,
                                                      const T *__restrict__ in, FdCoef<typename Storage<T>::C> k,
-                                                     int nx, int ny, int row0, int nrows, T *__restrict__ odr,
-                                                     T *__restrict__ ojx, T *__restrict__ ojy, uint32_t seed)
+                                                     int nx, int ny, int row0, int nrows, T *__restrict__ out,
+                                                     uint32_t seed)
 {
     using C = typename Storage<T>::C;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,17 +143,17 @@ __global__ void __launch_bounds__(256) fd_ref_gather(const typename Storage<T>::
     const C pux = (F(5, -1, -1) - F(6, 1, -1)) - (F(5, 0, 0) - F(6, 0, 0));
     const C pd = row_sum(F(4, 0, 1), F(8, -1, 1), F(7, 1, 1)) - row_sum(F(4, 0, 0), F(8, 0, 0), F(7, 0, 0));
     const C pdx = (F(8, -1, 1) - F(7, 1, 1)) - (F(8, 0, 0) - F(7, 0, 0));
-    const size_t n = (size_t)nx * (size_t)ny;
-    const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+    const size_t p = (size_t)j * (size_t)nx + (size_t)i;  // node index
     C r, x, y;
-    fd_finish<C, FORCE>(fd_partial<C>(pc, pcx, pu, pux), pd, pdx, Storage<T>::load(in[p]), Storage<T>::load(in[n + p]),
-                 Storage<T>::load(in[2 * n + p]), k.dfx, k.dfy, r, x, y);
+    fd_finish<C, FORCE>(fd_partial<C>(pc, pcx, pu, pux), pd, pdx, Storage<T>::load(in[fd_elem(i, j, 0, nx)]),
+                        Storage<T>::load(in[fd_elem(i, j, 1, nx)]), Storage<T>::load(in[fd_elem(i, j, 2, nx)]), k.dfx,
+                        k.dfy, r, x, y);
     // rounded for storage (stochastically for HalfSR: the same bits as the sweep kernel)
     uint32_t rb[3] = {0u, 0u, 0u};
     if constexpr (Storage<T>::STOCHASTIC) sr_draw(uint32_t(p), seed, rb);
-    odr[p] = Storage<T>::store_r(r, rb[0]);
-    ojx[p] = Storage<T>::store_r(x, rb[1]);
-    ojy[p] = Storage<T>::store_r(y, rb[2]);
+    out[fd_elem(i, j, 0, nx)] = Storage<T>::store_r(r, rb[0]);
+    out[fd_elem(i, j, 1, nx)] = Storage<T>::store_r(x, rb[1]);
+    out[fd_elem(i, j, 2, nx)] = Storage<T>::store_r(y, rb[2]);
 }
 
 template <typename T> FdCoef<typename Storage<T>::C> make_coef(const FdArgs &a)
@@ -172,11 +177,10 @@ template <typename T, int ST, bool WALLS, bool FORCE>
 hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStream_t s)
 {
     using C = typename Storage<T>::C;
-    const size_t n = (size_t)a.nx * (size_t)a.ny;
     const T *in = static_cast<const T *>(src);
     T *out = static_cast<T *>(dst);
     auto k = make_coef<T>(a);
-    View<T, WALLS> v{in, in + n, in + 2 * n, a.nx, a.ny, ghost_rules<C>(a.xi)};
+    View<T, WALLS> v{in, a.nx, a.ny, ghost_rules<C>(a.xi)};
     const int row0 = WALLS ? -1 : 0, nrows = WALLS ? a.ny + 2 : a.ny;
     dim3 blk(64, 4);
     dim3 g1((a.nx + 63) / 64, (nrows + 3) / 4);
@@ -185,7 +189,7 @@ hipError_t run(const FdArgs &a, const void *src, void *dst, void *fstar, hipStre
     if (e != hipSuccess) return e;
     dim3 g2((a.nx + 63) / 64, (a.ny + 3) / 4);
     hipLaunchKernelGGL((fd_ref_gather<T, WALLS, FORCE>), g2, blk, 0, s, static_cast<const C *>(fstar), in, k, a.nx, a.ny,
-                       row0, nrows, out, out + n, out + 2 * n, a.seed);
+                       row0, nrows, out, a.seed);
     return hipGetLastError();
 }
 

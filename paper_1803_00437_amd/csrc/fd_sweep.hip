@@ -69,16 +69,15 @@ hipError_t run(const FdArgs &fa, int tile_rows, const void *src, void *dst, hipS
 {
     using C = typename Storage<T>::C;
     using G = Strip<CPL, Stencil<ST>::H>;
-    const size_t n = (size_t)fa.nx * (size_t)fa.ny;
     SweepArgs<T> a;
     const T *in = static_cast<const T *>(src);
     T *out = static_cast<T *>(dst);
-    a.t.dr = in;
-    a.t.jx = in + n;
-    a.t.jy = in + 2 * n;
-    a.t.odr = out;
-    a.t.ojx = out + n;
-    a.t.ojy = out + 2 * n;
+    a.t.dr = in + fd_elem(0, 0, 0, fa.nx);
+    a.t.jx = in + fd_elem(0, 0, 1, fa.nx);
+    a.t.jy = in + fd_elem(0, 0, 2, fa.nx);
+    a.t.odr = out + fd_elem(0, 0, 0, fa.nx);
+    a.t.ojx = out + fd_elem(0, 0, 1, fa.nx);
+    a.t.ojy = out + fd_elem(0, 0, 2, fa.nx);
     a.t.nx = fa.nx;
     a.t.ny = fa.ny;
     // rows per wavefront (>= 2, see the tile body)

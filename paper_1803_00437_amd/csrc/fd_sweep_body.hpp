@@ -56,9 +56,12 @@ constexpr unsigned OFF_NONE = 0x80000000u;
 constexpr int RSRC_WORD3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
 constexpr int NT_HINT = 2;              // non-temporal store (written once, read next step)
 
-template <typename T> __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T *plane, int row, int nx)
+// Buffer resource of one row of a field: the field's first row at `field`, rows `stride`
+// elements apart (3 nx in the row-interleaved state), nx elements long.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T *field, int row, int stride, int nx)
 {
-    const unsigned long long r = reinterpret_cast<unsigned long long>(plane + (size_t)(unsigned)row * (size_t)(unsigned)nx);
+    const unsigned long long r = reinterpret_cast<unsigned long long>(field + (size_t)(unsigned)row * (size_t)(unsigned)stride);
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)r);
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(r >> 32));
     void *base = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
@@ -222,7 +225,8 @@ template <int CPL, int H> struct Strip {
     static constexpr int S = W - 2 * P;
 };
 
-// One grid as a tile sees it: input and output planes, size, rows per wavefront and the
+// One grid as a tile sees it: the first rows of the input and output fields (rows of a field
+// 3 nx apart, see fd_elem), size, rows per wavefront and the
 // reconstruction constants.
 template <typename T> struct TileArgs {
     const T *dr, *jx, *jy;
@@ -322,9 +326,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         }
         src = min(max(src, 0), ny - 1);
         const int r = slot % RAW;
-        pr[r] = row_load<T, CPL, AM>(row_rsrc(a.dr, src, nx), lc, use);
-        px[r] = row_load<T, CPL, AM>(row_rsrc(a.jx, src, nx), lc, use);
-        py[r] = row_load<T, CPL, AM>(row_rsrc(a.jy, src, nx), lc, use);
+        pr[r] = row_load<T, CPL, AM>(row_rsrc(a.dr, src, 3 * nx, nx), lc, use);
+        px[r] = row_load<T, CPL, AM>(row_rsrc(a.jx, src, 3 * nx, nx), lc, use);
+        py[r] = row_load<T, CPL, AM>(row_rsrc(a.jy, src, 3 * nx, nx), lc, use);
         pca[r] = ca;
         pcj[r] = cj;
         pbr[r] = br;
@@ -342,9 +346,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
         if (WALLS && psb[r] >= 0) {
             // ghost row between two fluid rows (walls at a general distance): the second
             // row is read here, a few times per sweep at most
-            const Group<T, CPL> br_ = row_load<T, CPL, AM>(row_rsrc(a.dr, psb[r], nx), lc, true);
-            const Group<T, CPL> bx_ = row_load<T, CPL, AM>(row_rsrc(a.jx, psb[r], nx), lc, true);
-            const Group<T, CPL> by_ = row_load<T, CPL, AM>(row_rsrc(a.jy, psb[r], nx), lc, true);
+            const Group<T, CPL> br_ = row_load<T, CPL, AM>(row_rsrc(a.dr, psb[r], 3 * nx, nx), lc, true);
+            const Group<T, CPL> bx_ = row_load<T, CPL, AM>(row_rsrc(a.jx, psb[r], 3 * nx, nx), lc, true);
+            const Group<T, CPL> by_ = row_load<T, CPL, AM>(row_rsrc(a.jy, psb[r], 3 * nx, nx), lc, true);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 w[0][slot][c] = w[0][slot][c] + pbr[r] * Storage<T>::load(br_.v[c]);
@@ -516,9 +520,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
             // output row b is complete once f* of the rows on both sides of it are known
             {
                 const int orow = min(max(first + DIR * (it - 1), 0), ny - 1);
-                row_store<T, CPL, AM>(row_rsrc(a.odr, orow, nx), lc, it >= 2, gr);
-                row_store<T, CPL, AM>(row_rsrc(a.ojx, orow, nx), lc, it >= 2, gx);
-                row_store<T, CPL, AM>(row_rsrc(a.ojy, orow, nx), lc, it >= 2, gy);
+                row_store<T, CPL, AM>(row_rsrc(a.odr, orow, 3 * nx, nx), lc, it >= 2, gr);
+                row_store<T, CPL, AM>(row_rsrc(a.ojx, orow, 3 * nx, nx), lc, it >= 2, gx);
+                row_store<T, CPL, AM>(row_rsrc(a.ojy, orow, 3 * nx, nx), lc, it >= 2, gy);
             }
         }
     }
@@ -527,9 +531,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
     const int last = first + DIR * (nf - 1);
     Group<T, CPL> o1r, o1x, o1y;
     if (!empty && !end_edge) {
-        o1r = row_load<T, CPL, AM>(row_rsrc(a.dr, last, nx), lc, true);
-        o1x = row_load<T, CPL, AM>(row_rsrc(a.jx, last, nx), lc, true);
-        o1y = row_load<T, CPL, AM>(row_rsrc(a.jy, last, nx), lc, true);
+        o1r = row_load<T, CPL, AM>(row_rsrc(a.dr, last, 3 * nx, nx), lc, true);
+        o1x = row_load<T, CPL, AM>(row_rsrc(a.jx, last, 3 * nx, nx), lc, true);
+        o1y = row_load<T, CPL, AM>(row_rsrc(a.jy, last, 3 * nx, nx), lc, true);
         // the forward sums of the last f* row complete the last output row of the
         // neighbour across the end side
 #pragma unroll
@@ -561,9 +565,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
                                     nxv, nyv);
             round_out(first, c, nr, nxv, nyv, gr.v[c], gx.v[c], gy.v[c]);
         }
-        row_store<T, CPL, AM>(row_rsrc(a.odr, first, nx), lc, true, gr);
-        row_store<T, CPL, AM>(row_rsrc(a.ojx, first, nx), lc, true, gx);
-        row_store<T, CPL, AM>(row_rsrc(a.ojy, first, nx), lc, true, gy);
+        row_store<T, CPL, AM>(row_rsrc(a.odr, first, 3 * nx, nx), lc, true, gr);
+        row_store<T, CPL, AM>(row_rsrc(a.ojx, first, 3 * nx, nx), lc, true, gx);
+        row_store<T, CPL, AM>(row_rsrc(a.ojy, first, 3 * nx, nx), lc, true, gy);
     }
     if (!end_edge) {
         // last output row: carried parts and the sums sent across the end side
@@ -583,9 +587,9 @@ __device__ __forceinline__ void sweep_wave(const TileArgs<T> &a, typename Storag
                                     nxv, nyv);
             round_out(last, c, nr, nxv, nyv, gr.v[c], gx.v[c], gy.v[c]);
         }
-        row_store<T, CPL, AM>(row_rsrc(a.odr, last, nx), lc, true, gr);
-        row_store<T, CPL, AM>(row_rsrc(a.ojx, last, nx), lc, true, gx);
-        row_store<T, CPL, AM>(row_rsrc(a.ojy, last, nx), lc, true, gy);
+        row_store<T, CPL, AM>(row_rsrc(a.odr, last, 3 * nx, nx), lc, true, gr);
+        row_store<T, CPL, AM>(row_rsrc(a.ojx, last, 3 * nx, nx), lc, true, gx);
+        row_store<T, CPL, AM>(row_rsrc(a.ojy, last, 3 * nx, nx), lc, true, gy);
     }
 }
 

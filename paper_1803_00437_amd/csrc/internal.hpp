@@ -135,9 +135,13 @@ hipError_t launch_mrt_disk(const MrtDisk &d, int dtype, void *pop, bool full, hi
 // MRT D2Q9 stream-collide (push) step.
 hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);
 
-// Conversions between host-staged FP64 planes and device storage.
+// Conversions between host-staged FP64 planes and device storage: element by element (MRT
+// populations, the D3Q19 state, the batch modes), and for a three-word state between three
+// FP64 planes and its row-interleaved storage (fd_elem).
 hipError_t launch_pack(int dtype, const double *in, void *out, size_t count, hipStream_t s);
 hipError_t launch_unpack(int dtype, const void *in, double *out, size_t count, hipStream_t s);
+hipError_t launch_pack3(int dtype, const double *in, void *out, int nx, int ny, hipStream_t s);
+hipError_t launch_unpack3(int dtype, const void *in, double *out, int nx, int ny, hipStream_t s);
 // MRT: populations f^eq(rho, J) from FP64 (drho, jx, jy) planes, and the conserved moments back.
 hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const double *jy, void *pop, size_t n,
                            hipStream_t s);
@@ -150,11 +154,11 @@ hipError_t launch_device_copy(void *dst, const void *src, size_t bytes, hipStrea
 // FP64 diagnostics: totals, kinetic energy, max |J|, non-finite count and sum J.J0.
 constexpr int DIAG_BLOCKS = 1024;
 constexpr int DIAG_SLOTS = 8;  // doubles per block partial
-hipError_t launch_diag(int scheme, int dtype, const void *state, size_t n, const double *j0x, const double *j0y,
+hipError_t launch_diag(int scheme, int dtype, const void *state, int nx, int ny, const double *j0x, const double *j0y,
                        double *partials, double *out, hipStream_t s);
 // The same reduction with its partials in a file-scope device array (no scratch argument);
 // out: DIAG_SLOTS doubles of device memory.  Calls that overlap on one device race.
-hipError_t launch_diag_static(int scheme, int dtype, const void *state, size_t n, const double *j0x,
+hipError_t launch_diag_static(int scheme, int dtype, const void *state, int nx, int ny, const double *j0x,
                               const double *j0y, double *out, hipStream_t s);
 
 // ---- FD-LBM on the D3Q19 lattice (fd3d.hip) -------------------------------------------

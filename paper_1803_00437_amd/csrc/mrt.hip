@@ -245,10 +245,10 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
     auto load_row = [&](int y, bool use, Group<T, CPL>(&g)[9]) {
         const int yy = min(y, ny - 1);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) g[q] = buf_load_group<T, CPL>(row_rsrc(in + q * n, yy, nx), use ? voff : OFF_NONE);
+        for (int q = 0; q < 9; ++q) g[q] = buf_load_group<T, CPL>(row_rsrc(in + q * n, yy, nx, nx), use ? voff : OFF_NONE);
     };
     auto put = [&](int q, int y, const Group<T, CPL> &g) {
-        buf_store_group<T, CPL>(row_rsrc(out + q * n, y, nx), soff, g);
+        buf_store_group<T, CPL>(row_rsrc(out + q * n, y, nx, nx), soff, g);
     };
     // post-collision populations of row yy (the row next to a wall, collided once more)
     auto collide_row = [&](int yy, C(&h)[CPL][9]) {
