@@ -12,12 +12,12 @@
  *     holds a disk closed by a curved no-slip wall (FDLBM_BC_DISK, the Stokes-mode test of
  *     section 3-b; see fdlbm_params.disk_r).
  *   - The state is stored as deviations from the rest state rho = 1, J = 0, in the storage
- *     dtype with no padding.  FD-LBM and LW-ACM: the three fields drho = rho - 1, jx, jy,
- *     row-interleaved: row y of field f (0 = drho, 1 = jx, 2 = jy) starts at element
- *     (3y + f)*nx, so node (x, y) of field f is element (3y + f)*nx + x (the three rows a
- *     step reads and writes together are adjacent in memory).  MRT: nine population planes
- *     f_k - w_k, plane after plane, each nx*ny elements.  The host arrays of set_state and
- *     get_state are plain nx*ny planes in every case.
+ *     dtype with no padding, row-interleaved: with F fields, row y of field f starts at
+ *     element (F*y + f)*nx, so node (x, y) of field f is element (F*y + f)*nx + x (the rows
+ *     a step reads and writes together are adjacent in memory).  FD-LBM and LW-ACM: F = 3,
+ *     fields drho = rho - 1, jx, jy.  MRT: F = 9, fields f_k - w_k in velocity order.  The
+ *     host arrays of set_state, get_state, set_populations and get_populations are plain
+ *     planes of nx*ny values (x fastest) in every case.
  *   - Velocity order of the populations (section 1): e_0 = (0,0), e_1..e_4 = (1,0), (0,1),
  *     (-1,0), (0,-1), e_5..e_8 = (1,1), (-1,1), (-1,-1), (1,-1).
  *   - Device buffers are owned by the caller (allocated e.g. by PyTorch) and must stay
@@ -184,7 +184,7 @@ int fdlbm_diagnostics(fdlbm_ctx *c, fdlbm_diag *out);
  * same kernels in the same order (the results are identical bit for bit), but
  *   - takes the state directly: `state` is a device buffer in the layout fdlbm_create's
  *     state buffers use for `p` (scheme, dtype, nx, ny; FD-LBM and LW-ACM: the
- *     row-interleaved drho, Jx, Jy fields; MRT: the nine population planes), e.g. the
+ *     row-interleaved drho, Jx, Jy fields; MRT: the nine row-interleaved populations), e.g. the
  *     buffer a context's current state is in (state_a after an even number of steps
  *     since fdlbm_create, else state_b);
  *   - j0x, j0y: optional device FP64 planes (nx*ny each, both or neither) for the sums

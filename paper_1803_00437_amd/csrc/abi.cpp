@@ -324,9 +324,9 @@ int fdlbm_set_state(fdlbm_ctx *c, const double *drho, const double *jx, const do
     HIPCHK(hipMemcpyAsync(st + n, jx, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
     HIPCHK(hipMemcpyAsync(st + 2 * n, jy, nb, hipMemcpyHostToDevice, c->stream), "set_state upload");
     if (three_words(c->p.scheme))
-        HIPCHK(launch_pack3(c->p.dtype, st, c->buf[c->cur], c->p.nx, c->p.ny, c->stream), "pack");
+        HIPCHK(launch_pack_rows(c->p.dtype, 3, st, c->buf[c->cur], c->p.nx, c->p.ny, c->stream), "pack");
     else
-        HIPCHK(launch_mrt_init(c->p.dtype, st, st + n, st + 2 * n, c->buf[c->cur], n, c->stream), "mrt_init");
+        HIPCHK(launch_mrt_init(c->p.dtype, st, st + n, st + 2 * n, c->buf[c->cur], c->p.nx, c->p.ny, c->stream), "mrt_init");
     HIPCHK(hipStreamSynchronize(c->stream), "set_state");
     c->steps = 0;
     c->disk_full = true;
@@ -340,9 +340,9 @@ int fdlbm_get_state(fdlbm_ctx *c, double *drho, double *jx, double *jy)
     const size_t n = c->n(), nb = n * sizeof(double);
     double *st = c->sd(c->L.staging);
     if (three_words(c->p.scheme))
-        HIPCHK(launch_unpack3(c->p.dtype, c->buf[c->cur], st, c->p.nx, c->p.ny, c->stream), "unpack");
+        HIPCHK(launch_unpack_rows(c->p.dtype, 3, c->buf[c->cur], st, c->p.nx, c->p.ny, c->stream), "unpack");
     else
-        HIPCHK(launch_mrt_moments(c->p.dtype, c->buf[c->cur], st, st + n, st + 2 * n, n, c->stream), "mrt_moments");
+        HIPCHK(launch_mrt_moments(c->p.dtype, c->buf[c->cur], st, st + n, st + 2 * n, c->p.nx, c->p.ny, c->stream), "mrt_moments");
     HIPCHK(hipMemcpyAsync(drho, st, nb, hipMemcpyDeviceToHost, c->stream), "get_state download");
     HIPCHK(hipMemcpyAsync(jx, st + n, nb, hipMemcpyDeviceToHost, c->stream), "get_state download");
     HIPCHK(hipMemcpyAsync(jy, st + 2 * n, nb, hipMemcpyDeviceToHost, c->stream), "get_state download");
@@ -357,7 +357,7 @@ int fdlbm_set_populations(fdlbm_ctx *c, const double *df)
     const size_t n = c->n();
     double *st = c->sd(c->L.staging);
     HIPCHK(hipMemcpyAsync(st, df, 9 * n * sizeof(double), hipMemcpyHostToDevice, c->stream), "set_populations");
-    HIPCHK(launch_pack(c->p.dtype, st, c->buf[c->cur], 9 * n, c->stream), "pack");
+    HIPCHK(launch_pack_rows(c->p.dtype, 9, st, c->buf[c->cur], c->p.nx, c->p.ny, c->stream), "pack");
     HIPCHK(hipStreamSynchronize(c->stream), "set_populations");
     c->steps = 0;
     c->disk_full = true;
@@ -370,7 +370,7 @@ int fdlbm_get_populations(fdlbm_ctx *c, double *df)
     HIPCHK(hipSetDevice(c->device), "hipSetDevice");
     const size_t n = c->n();
     double *st = c->sd(c->L.staging);
-    HIPCHK(launch_unpack(c->p.dtype, c->buf[c->cur], st, 9 * n, c->stream), "unpack");
+    HIPCHK(launch_unpack_rows(c->p.dtype, 9, c->buf[c->cur], st, c->p.nx, c->p.ny, c->stream), "unpack");
     HIPCHK(hipMemcpyAsync(df, st, 9 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "get_populations");
     HIPCHK(hipStreamSynchronize(c->stream), "get_populations");
     return FDLBM_OK;

@@ -296,7 +296,7 @@ int fdlbm_batch_set_state(fdlbm_batch *b, int32_t i, const double *drho, const d
     BHIPCHK(hipMemcpyAsync(st, drho, nb, hipMemcpyHostToDevice, b->stream), "batch set_state upload");
     BHIPCHK(hipMemcpyAsync(st + n, jx, nb, hipMemcpyHostToDevice, b->stream), "batch set_state upload");
     BHIPCHK(hipMemcpyAsync(st + 2 * n, jy, nb, hipMemcpyHostToDevice, b->stream), "batch set_state upload");
-    BHIPCHK(launch_pack3(b->dtype, st, b->buf[b->cur] + I.offset * db, I.nx, I.ny, b->stream), "batch pack");
+    BHIPCHK(launch_pack_rows(b->dtype, 3, st, b->buf[b->cur] + I.offset * db, I.nx, I.ny, b->stream), "batch pack");
     // the correlation reference J0 is this state's momentum, as stored
     BHIPCHK(launch_pack(b->dtype, st + n, b->scratch + b->P.o_mode + I.mode_offset * db, 2 * n, b->stream),
             "batch pack mode");
@@ -313,7 +313,7 @@ int fdlbm_batch_get_state(fdlbm_batch *b, int32_t i, double *drho, double *jx, d
     const BatchInstance &I = b->P.inst[i];
     const size_t n = (size_t)I.nx * (size_t)I.ny, nb = n * sizeof(double), db = dtype_bytes(b->dtype);
     double *st = reinterpret_cast<double *>(b->scratch + b->P.o_staging);
-    BHIPCHK(launch_unpack3(b->dtype, b->buf[b->cur] + I.offset * db, st, I.nx, I.ny, b->stream), "batch unpack");
+    BHIPCHK(launch_unpack_rows(b->dtype, 3, b->buf[b->cur] + I.offset * db, st, I.nx, I.ny, b->stream), "batch unpack");
     BHIPCHK(hipMemcpyAsync(drho, st, nb, hipMemcpyDeviceToHost, b->stream), "batch get_state download");
     BHIPCHK(hipMemcpyAsync(jx, st + n, nb, hipMemcpyDeviceToHost, b->stream), "batch get_state download");
     BHIPCHK(hipMemcpyAsync(jy, st + 2 * n, nb, hipMemcpyDeviceToHost, b->stream), "batch get_state download");

@@ -70,35 +70,32 @@ __device__ __forceinline__ void diag_add(double (&acc)[DIAG_SLOTS], double r, do
     }
 }
 
-// MRT: nine population planes, node by node.  FD-LBM / LW-ACM: the row-interleaved state
-// (fd_elem), row by row (rows over the blocks, columns over the threads).  The mode (j0x,
-// j0y) is two planes in both cases.
+// The row-interleaved state, row by row (rows over the blocks, columns over the threads):
+// MRT nine populations (pop_elem), FD-LBM / LW-ACM drho, Jx, Jy (fd_elem).  The mode (j0x,
+// j0y) is two planes of nx*ny values.
 template <typename T, bool MRT>
 __global__ void __launch_bounds__(TPB) diag_partials(const T *__restrict__ st, int nx, int ny,
                                                      const double *__restrict__ j0x, const double *__restrict__ j0y,
                                                      double *__restrict__ partials)
 {
     double acc[DIAG_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const size_t n = (size_t)nx * (size_t)ny;
-    if (MRT) {
-        for (size_t p = blockIdx.x * (size_t)TPB + threadIdx.x; p < n; p += (size_t)gridDim.x * TPB) {
-            double f[9];
+    for (int j = blockIdx.x; j < ny; j += gridDim.x)
+        for (int i = threadIdx.x; i < nx; i += TPB) {
+            double r, x, y;
+            if (MRT) {
+                double f[9];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) f[q] = double(Storage<T>::load(st[q * n + p]));
-            const double r = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
-            const double x = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
-            const double y = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
-            diag_add(acc, r, x, y, j0x, j0y, p);
-        }
-    } else {
-        for (int j = blockIdx.x; j < ny; j += gridDim.x)
-            for (int i = threadIdx.x; i < nx; i += TPB) {
-                const double r = double(Storage<T>::load(st[fd_elem(i, j, 0, nx)]));
-                const double x = double(Storage<T>::load(st[fd_elem(i, j, 1, nx)]));
-                const double y = double(Storage<T>::load(st[fd_elem(i, j, 2, nx)]));
-                diag_add(acc, r, x, y, j0x, j0y, (size_t)j * (size_t)nx + (size_t)i);
+                for (int q = 0; q < 9; ++q) f[q] = double(Storage<T>::load(st[pop_elem(i, j, q, nx)]));
+                r = (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
+                x = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+                y = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+            } else {
+                r = double(Storage<T>::load(st[fd_elem(i, j, 0, nx)]));
+                x = double(Storage<T>::load(st[fd_elem(i, j, 1, nx)]));
+                y = double(Storage<T>::load(st[fd_elem(i, j, 2, nx)]));
             }
-    }
+            diag_add(acc, r, x, y, j0x, j0y, (size_t)j * (size_t)nx + (size_t)i);
+        }
     block_reduce(acc);
     if (threadIdx.x == 0)
         for (int q = 0; q < DIAG_SLOTS; ++q) partials[blockIdx.x * DIAG_SLOTS + q] = acc[q];
@@ -219,45 +216,63 @@ hipError_t launch_diag_static(int scheme, int dtype, const void *state, int nx, 
     return launch_diag(scheme, dtype, state, nx, ny, j0x, j0y, partials, out, s);
 }
 
-// Three-word state: host order (three planes of nx*ny FP64 values) to and from the
-// row-interleaved storage (fd_elem); one block row of columns per grid row.
-template <typename T>
-__global__ void __launch_bounds__(TPB) pack3_kernel(const double *__restrict__ in, T *__restrict__ out, int nx, int ny)
+// State of NF fields (3: drho, Jx, Jy; 9: the MRT populations): host order (NF planes of
+// nx*ny FP64 values) to and from the row-interleaved storage (row_elem); one block row of
+// columns per grid row.
+template <typename T, int NF>
+__global__ void __launch_bounds__(TPB) pack_rows_kernel(const double *__restrict__ in, T *__restrict__ out, int nx,
+                                                        int ny)
 {
     const size_t n = (size_t)nx * (size_t)ny;
     for (int j = blockIdx.x; j < ny; j += gridDim.x)
         for (int i = threadIdx.x; i < nx; i += TPB)
-            for (int f = 0; f < 3; ++f)
-                out[fd_elem(i, j, f, nx)] = Storage<T>::store(typename Storage<T>::C(in[f * n + (size_t)j * nx + i]));
+            for (int f = 0; f < NF; ++f)
+                out[row_elem<NF>(i, j, f, nx)] =
+                    Storage<T>::store(typename Storage<T>::C(in[f * n + (size_t)j * nx + i]));
 }
-template <typename T>
-__global__ void __launch_bounds__(TPB) unpack3_kernel(const T *__restrict__ in, double *__restrict__ out, int nx, int ny)
+template <typename T, int NF>
+__global__ void __launch_bounds__(TPB) unpack_rows_kernel(const T *__restrict__ in, double *__restrict__ out, int nx,
+                                                          int ny)
 {
     const size_t n = (size_t)nx * (size_t)ny;
     for (int j = blockIdx.x; j < ny; j += gridDim.x)
         for (int i = threadIdx.x; i < nx; i += TPB)
-            for (int f = 0; f < 3; ++f) out[f * n + (size_t)j * nx + i] = double(Storage<T>::load(in[fd_elem(i, j, f, nx)]));
+            for (int f = 0; f < NF; ++f)
+                out[f * n + (size_t)j * nx + i] = double(Storage<T>::load(in[row_elem<NF>(i, j, f, nx)]));
 }
 
-hipError_t launch_pack3(int dtype, const double *in, void *out, int nx, int ny, hipStream_t s)
+template <typename T, int NF> void pack_rows_t(bool to_device, const void *in, void *out, int nx, int ny, hipStream_t s)
 {
     const unsigned g = (unsigned)(ny < 65536 ? ny : 65536);
+    if (to_device)
+        hipLaunchKernelGGL((pack_rows_kernel<T, NF>), g, TPB, 0, s, (const double *)in, (T *)out, nx, ny);
+    else
+        hipLaunchKernelGGL((unpack_rows_kernel<T, NF>), g, TPB, 0, s, (const T *)in, (double *)out, nx, ny);
+}
+template <int NF> void pack_rows_nf(int dtype, bool to_device, const void *in, void *out, int nx, int ny, hipStream_t s)
+{
     switch (dtype) {
-    case FDLBM_F64: hipLaunchKernelGGL(pack3_kernel<double>, g, TPB, 0, s, in, (double *)out, nx, ny); break;
-    case FDLBM_F32: hipLaunchKernelGGL(pack3_kernel<float>, g, TPB, 0, s, in, (float *)out, nx, ny); break;
-    default: hipLaunchKernelGGL(pack3_kernel<__half>, g, TPB, 0, s, in, (__half *)out, nx, ny); break;
+    case FDLBM_F64: pack_rows_t<double, NF>(to_device, in, out, nx, ny, s); break;
+    case FDLBM_F32: pack_rows_t<float, NF>(to_device, in, out, nx, ny, s); break;
+    default: pack_rows_t<__half, NF>(to_device, in, out, nx, ny, s); break;
     }
+}
+
+hipError_t launch_pack_rows(int dtype, int nf, const double *in, void *out, int nx, int ny, hipStream_t s)
+{
+    if (nf == 9)
+        pack_rows_nf<9>(dtype, true, in, out, nx, ny, s);
+    else
+        pack_rows_nf<3>(dtype, true, in, out, nx, ny, s);
     return hipGetLastError();
 }
 
-hipError_t launch_unpack3(int dtype, const void *in, double *out, int nx, int ny, hipStream_t s)
+hipError_t launch_unpack_rows(int dtype, int nf, const void *in, double *out, int nx, int ny, hipStream_t s)
 {
-    const unsigned g = (unsigned)(ny < 65536 ? ny : 65536);
-    switch (dtype) {
-    case FDLBM_F64: hipLaunchKernelGGL(unpack3_kernel<double>, g, TPB, 0, s, (const double *)in, out, nx, ny); break;
-    case FDLBM_F32: hipLaunchKernelGGL(unpack3_kernel<float>, g, TPB, 0, s, (const float *)in, out, nx, ny); break;
-    default: hipLaunchKernelGGL(unpack3_kernel<__half>, g, TPB, 0, s, (const __half *)in, out, nx, ny); break;
-    }
+    if (nf == 9)
+        pack_rows_nf<9>(dtype, false, in, out, nx, ny, s);
+    else
+        pack_rows_nf<3>(dtype, false, in, out, nx, ny, s);
     return hipGetLastError();
 }
 

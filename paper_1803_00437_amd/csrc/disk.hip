@@ -243,19 +243,21 @@ template <typename T> __global__ __launch_bounds__(TPB) void mrt_disk_links_kern
     const int opp = k <= 4 ? ((k + 1) & 3) + 1 : ((k - 3) & 3) + 5;  // 1<->3, 2<->4, 5<->7, 6<->8
     const int ex = (k == 1 || k == 5 || k == 8) - (k == 3 || k == 6 || k == 7);
     const int ey = (k == 2 || k == 5 || k == 6) - (k == 4 || k == 7 || k == 8);
-    const size_t plane = size_t(d.nx) * size_t(d.ny);
+    const size_t nx = size_t(d.nx);
+    // element of population p at a node index (j nx + i) of the row-interleaved state
+    auto at = [&](long node, int p) { return pop_elem(size_t(node) % nx, size_t(node) / nx, p, nx); };
     const long node = d.node[t];
     const long off = long(ex) + long(ey) * long(d.nx);
-    const C fi_x = S::load(pop[size_t(k) * plane + size_t(node + off)]);
-    const C fb_x = S::load(pop[size_t(opp) * plane + size_t(node - off)]);
-    const C fi_back = S::load(pop[size_t(k) * plane + size_t(node)]);
+    const C fi_x = S::load(pop[at(node + off, k)]);
+    const C fb_x = S::load(pop[at(node - off, opp)]);
+    const C fi_back = S::load(pop[at(node, k)]);
     const C q = C(d.q[t]);
     C v;
     if (q < C(0.5))
         v = back ? C(2) * q * fi_x + (C(1) - C(2) * q) * fi_back : fi_x;
     else
         v = fi_x / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * fb_x;
-    pop[size_t(opp) * plane + size_t(node)] = S::store(v);
+    pop[at(node, opp)] = S::store(v);
 }
 
 // MRT: solid nodes to rest (all nine deviations zero): the ring the links reach, or, for a
@@ -265,11 +267,11 @@ template <typename T> __global__ __launch_bounds__(TPB) void mrt_disk_clear_kern
     using S = Storage<T>;
     using C = typename S::C;
     const size_t t = size_t(blockIdx.x) * TPB + threadIdx.x;
-    const size_t plane = size_t(d.nx) * size_t(d.ny);
+    const size_t nx = size_t(d.nx);
     if (!full) {
         if (t >= size_t(d.nring)) return;
         const size_t node = size_t(d.ring[t]);
-        for (int p = 0; p < 9; ++p) pop[p * plane + node] = S::store(C(0));
+        for (int p = 0; p < 9; ++p) pop[pop_elem(node % nx, node / nx, p, nx)] = S::store(C(0));
         return;
     }
     const size_t per_row = (size_t(d.nx) + CLEAR_COLS - 1) / CLEAR_COLS;
@@ -279,8 +281,7 @@ template <typename T> __global__ __launch_bounds__(TPB) void mrt_disk_clear_kern
     const int a = d.fspan[2 * j], b = d.fspan[2 * j + 1];
     for (int i = i0; i < min(i0 + CLEAR_COLS, d.nx); ++i) {
         if (i >= a && i <= b) continue;
-        const size_t node = size_t(j) * size_t(d.nx) + size_t(i);
-        for (int p = 0; p < 9; ++p) pop[p * plane + node] = S::store(C(0));
+        for (int p = 0; p < 9; ++p) pop[pop_elem(i, j, p, nx)] = S::store(C(0));
     }
 }
 

@@ -140,12 +140,13 @@ hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t 
 // FP64 planes and its row-interleaved storage (fd_elem).
 hipError_t launch_pack(int dtype, const double *in, void *out, size_t count, hipStream_t s);
 hipError_t launch_unpack(int dtype, const void *in, double *out, size_t count, hipStream_t s);
-hipError_t launch_pack3(int dtype, const double *in, void *out, int nx, int ny, hipStream_t s);
-hipError_t launch_unpack3(int dtype, const void *in, double *out, int nx, int ny, hipStream_t s);
+// nf (3 or 9) host-order FP64 planes of nx*ny values to and from the row-interleaved storage
+hipError_t launch_pack_rows(int dtype, int nf, const double *in, void *out, int nx, int ny, hipStream_t s);
+hipError_t launch_unpack_rows(int dtype, int nf, const void *in, double *out, int nx, int ny, hipStream_t s);
 // MRT: populations f^eq(rho, J) from FP64 (drho, jx, jy) planes, and the conserved moments back.
-hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const double *jy, void *pop, size_t n,
+hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const double *jy, void *pop, int nx, int ny,
                            hipStream_t s);
-hipError_t launch_mrt_moments(int dtype, const void *pop, double *dr, double *jx, double *jy, size_t n,
+hipError_t launch_mrt_moments(int dtype, const void *pop, double *dr, double *jx, double *jy, int nx, int ny,
                               hipStream_t s);
 
 // Streaming device-to-device copy (bytes a multiple of 16, 16-byte aligned pointers).

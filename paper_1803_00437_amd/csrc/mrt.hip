@@ -1,7 +1,9 @@
 // MRT D2Q9 stream-collide step (section 1, eqs. 1-2; equilibria and rates of the table
 // in section 1-a), the scheme the FD-LBM is compared against.
 //
-// Storage: nine planes of f_k - w_k (deviations from the rest populations).  Two kernels:
+// Storage: the nine deviations f_k - w_k from the rest populations, row-interleaved (row j
+// of population k at element (9 j + k) nx, pop_elem): the nine rows a node row reads are
+// adjacent in memory, and so are the rows it writes.  Two kernels:
 // one thread per node (mrt_kernel), and the vectorised sweep over lane groups of columns
 // (mrt_sweep_kernel, the default).  Each relaxes the non-conserved moments of a node and
 // pushes f*_k to x + e_k in the other buffer.  A population whose destination lies beyond
@@ -146,11 +148,9 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nx || j >= ny) return;
-    const size_t n = (size_t)nx * (size_t)ny;
-    const size_t p = (size_t)j * (size_t)nx + (size_t)i;
     C f[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = Storage<T>::load(in[q * n + p]);
+    for (int q = 0; q < 9; ++q) f[q] = Storage<T>::load(in[pop_elem(i, j, q, nx)]);
     collide<C>(f, k);
     // propagation, eq. 2 (push)
     const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
@@ -159,14 +159,12 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
         if (jp == ny) jp = 0;
         if (jm < 0) jm = ny - 1;
     }
-    const size_t row = (size_t)j * nx, rowp = (size_t)jp * nx, rowm = (size_t)jm * nx;
     // post-collision population q at node (ii, jj), collided again (interpolated bounce-back)
     auto post_at = [&](int ii, int jj, int q) -> C {
         ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
-        const size_t pp = (size_t)jj * (size_t)nx + (size_t)ii;
         C g[9];
 #pragma unroll
-        for (int r = 0; r < 9; ++r) g[r] = Storage<T>::load(in[r * n + pp]);
+        for (int r = 0; r < 9; ++r) g[r] = Storage<T>::load(in[pop_elem(ii, jj, r, nx)]);
         collide<C>(g, k);
         C v = g[0];
 #pragma unroll
@@ -180,38 +178,38 @@ __global__ void __launch_bounds__(256) mrt_kernel(const T *__restrict__ in, T *_
         if (xi > C(0.5)) return f[kq] / (C(2) * xi) + (C(2) * xi - C(1)) / (C(2) * xi) * f[kb];
         return C(2) * xi * f[kq] + (C(1) - C(2) * xi) * post_at(i - ex, j - ey, kq);
     };
-    out[0 * n + p] = Storage<T>::store(f[0]);
-    out[1 * n + row + ip] = Storage<T>::store(f[1]);
-    out[3 * n + row + im] = Storage<T>::store(f[3]);
+    out[pop_elem(i, j, 0, nx)] = Storage<T>::store(f[0]);
+    out[pop_elem(ip, j, 1, nx)] = Storage<T>::store(f[1]);
+    out[pop_elem(im, j, 3, nx)] = Storage<T>::store(f[3]);
     if (!WALLS || jp < ny) {
-        out[2 * n + rowp + i] = Storage<T>::store(f[2]);
-        out[5 * n + rowp + ip] = Storage<T>::store(f[5]);
-        out[6 * n + rowp + im] = Storage<T>::store(f[6]);
+        out[pop_elem(i, jp, 2, nx)] = Storage<T>::store(f[2]);
+        out[pop_elem(ip, jp, 5, nx)] = Storage<T>::store(f[5]);
+        out[pop_elem(im, jp, 6, nx)] = Storage<T>::store(f[6]);
     } else {  // bounce-back at the upper wall
-        out[4 * n + p] = Storage<T>::store(back(2, 4, 0, 1));
-        out[7 * n + p] = Storage<T>::store(back(5, 7, 1, 1));
-        out[8 * n + p] = Storage<T>::store(back(6, 8, -1, 1));
+        out[pop_elem(i, j, 4, nx)] = Storage<T>::store(back(2, 4, 0, 1));
+        out[pop_elem(i, j, 7, nx)] = Storage<T>::store(back(5, 7, 1, 1));
+        out[pop_elem(i, j, 8, nx)] = Storage<T>::store(back(6, 8, -1, 1));
     }
     if (!WALLS || jm >= 0) {
-        out[4 * n + rowm + i] = Storage<T>::store(f[4]);
-        out[7 * n + rowm + im] = Storage<T>::store(f[7]);
-        out[8 * n + rowm + ip] = Storage<T>::store(f[8]);
+        out[pop_elem(i, jm, 4, nx)] = Storage<T>::store(f[4]);
+        out[pop_elem(im, jm, 7, nx)] = Storage<T>::store(f[7]);
+        out[pop_elem(ip, jm, 8, nx)] = Storage<T>::store(f[8]);
     } else {  // bounce-back at the lower wall
-        out[2 * n + p] = Storage<T>::store(back(4, 2, 0, -1));
-        out[5 * n + p] = Storage<T>::store(back(7, 5, -1, -1));
-        out[6 * n + p] = Storage<T>::store(back(8, 6, 1, -1));
+        out[pop_elem(i, j, 2, nx)] = Storage<T>::store(back(4, 2, 0, -1));
+        out[pop_elem(i, j, 5, nx)] = Storage<T>::store(back(7, 5, -1, -1));
+        out[pop_elem(i, j, 6, nx)] = Storage<T>::store(back(8, 6, 1, -1));
     }
 }
 
 // Vectorised MRT step.  A wavefront owns 64*CPL consecutive columns (CPL per lane, one
-// aligned vector access per population plane) of R rows.  After the collision, the
+// aligned vector access per population row) of R rows.  After the collision, the
 // populations moving along +x / -x are shifted by one column across lanes with DPP
 // whole-wave shifts, so every store is an aligned vector too; the outermost lane on each
 // side has no neighbour to take from and only feeds its neighbour, so strips overlap by
 // one lane on each side.  Populations moving along y go to the row above or below (or
 // bounce back at a wall).  Wavefronts are dealt out row band after row band.
 //
-// The nine planes of the next row are loaded while the current one is collided (two row
+// The nine population rows of the next grid row are loaded while the current one is collided (two row
 // buffers, the loop unrolled by two so that they alternate without copies).  Loads and
 // stores go through range-checked buffer resources: the halo lanes' stores and the
 // prefetch past the last row use an offset beyond the row and are dropped, so every row
@@ -239,16 +237,16 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
     const bool store_ok = lane >= 1 && lane <= 62 && xl < nx;
     const unsigned voff = col * (unsigned)sizeof(T);
     const unsigned soff = store_ok ? voff : OFF_NONE;  // halo lanes do not store
-    const size_t n = (size_t)nx * (size_t)ny;
     const int y0 = band * rows, y1 = min(y0 + rows, ny);
 
     auto load_row = [&](int y, bool use, Group<T, CPL>(&g)[9]) {
         const int yy = min(y, ny - 1);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) g[q] = buf_load_group<T, CPL>(row_rsrc(in + q * n, yy, nx, nx), use ? voff : OFF_NONE);
+        for (int q = 0; q < 9; ++q)
+            g[q] = buf_load_group<T, CPL>(row_rsrc(in + pop_elem(0, 0, q, nx), yy, 9 * nx, nx), use ? voff : OFF_NONE);
     };
     auto put = [&](int q, int y, const Group<T, CPL> &g) {
-        buf_store_group<T, CPL>(row_rsrc(out + q * n, y, nx, nx), soff, g);
+        buf_store_group<T, CPL>(row_rsrc(out + pop_elem(0, 0, q, nx), y, 9 * nx, nx), soff, g);
     };
     // post-collision populations of row yy (the row next to a wall, collided once more)
     auto collide_row = [&](int yy, C(&h)[CPL][9]) {
@@ -326,7 +324,7 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
         put(1, y, g[1]);
         put(3, y, g[3]);
         if (top_wall) {
-            // the upward movers return into this row's downward planes, unshifted
+            // the upward movers return into this row's downward populations, unshifted
             Group<T, CPL> b2, b5, b6;
             bounce(f, 2, 4, 0, y - 1, b2);
             bounce(f, 5, 7, 1, y - 1, b5);
@@ -365,37 +363,45 @@ __global__ void __launch_bounds__(256) mrt_sweep_kernel(const T *__restrict__ in
     }
 }
 
+// Equilibrium populations of host-order FP64 planes (drho, Jx, Jy; node (i, j) at j nx + i),
+// stored row-interleaved; one block row of columns per grid row.
 template <typename T>
 __global__ void __launch_bounds__(256) mrt_init_kernel(const double *__restrict__ dr, const double *__restrict__ jx,
-                                                       const double *__restrict__ jy, T *__restrict__ pop, size_t n)
+                                                       const double *__restrict__ jy, T *__restrict__ pop, int nx, int ny)
 {
     using C = typename Storage<T>::C;
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
-        C m[9], f[9];
-        m[0] = C(dr[p]);
-        m[1] = C(jx[p]);
-        m[2] = C(jy[p]);
-        equilibrium<C>(m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8]);
-        populations<C>(m, f);
+    for (int j = blockIdx.x; j < ny; j += gridDim.x)
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+            const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+            C m[9], f[9];
+            m[0] = C(dr[p]);
+            m[1] = C(jx[p]);
+            m[2] = C(jy[p]);
+            equilibrium<C>(m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8]);
+            populations<C>(m, f);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) pop[q * n + p] = Storage<T>::store(f[q]);
-    }
+            for (int q = 0; q < 9; ++q) pop[pop_elem(i, j, q, nx)] = Storage<T>::store(f[q]);
+        }
 }
 
-// Conserved moments of the stored populations, summed in FP64 whatever the storage dtype.
+// Conserved moments of the stored populations, summed in FP64 whatever the storage dtype,
+// into host-order planes.
 template <typename T>
 __global__ void __launch_bounds__(256) mrt_moments_kernel(const T *__restrict__ pop, double *__restrict__ dr,
-                                                          double *__restrict__ jx, double *__restrict__ jy, size_t n)
+                                                          double *__restrict__ jx, double *__restrict__ jy, int nx,
+                                                          int ny)
 {
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
-        double f[9], m[9];
+    for (int j = blockIdx.x; j < ny; j += gridDim.x)
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+            const size_t p = (size_t)j * (size_t)nx + (size_t)i;
+            double f[9], m[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = double(Storage<T>::load(pop[q * n + p]));
-        moments<double>(f, m);
-        dr[p] = m[0];
-        jx[p] = m[1];
-        jy[p] = m[2];
-    }
+            for (int q = 0; q < 9; ++q) f[q] = double(Storage<T>::load(pop[pop_elem(i, j, q, nx)]));
+            moments<double>(f, m);
+            dr[p] = m[0];
+            jx[p] = m[1];
+            jy[p] = m[2];
+        }
 }
 
 template <typename T, int CPL>
@@ -439,11 +445,7 @@ template <typename T> hipError_t run(const MrtArgs &a, const void *src, void *ds
     return hipGetLastError();
 }
 
-inline unsigned grid_for(size_t n)
-{
-    size_t b = (n + 255) / 256;
-    return (unsigned)(b < 8192 ? (b == 0 ? 1 : b) : 8192);
-}
+inline unsigned rows_grid(int ny) { return (unsigned)(ny < 65536 ? ny : 65536); }
 
 }  // namespace
 
@@ -452,24 +454,27 @@ hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t 
     return a.dtype == FDLBM_F64 ? run<double>(a, src, dst, s) : run<float>(a, src, dst, s);
 }
 
-hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const double *jy, void *pop, size_t n,
+hipError_t launch_mrt_init(int dtype, const double *dr, const double *jx, const double *jy, void *pop, int nx, int ny,
                            hipStream_t s)
 {
     if (dtype == FDLBM_F64)
-        hipLaunchKernelGGL(mrt_init_kernel<double>, grid_for(n), 256, 0, s, dr, jx, jy, static_cast<double *>(pop), n);
+        hipLaunchKernelGGL(mrt_init_kernel<double>, rows_grid(ny), 256, 0, s, dr, jx, jy, static_cast<double *>(pop), nx,
+                           ny);
     else
-        hipLaunchKernelGGL(mrt_init_kernel<float>, grid_for(n), 256, 0, s, dr, jx, jy, static_cast<float *>(pop), n);
+        hipLaunchKernelGGL(mrt_init_kernel<float>, rows_grid(ny), 256, 0, s, dr, jx, jy, static_cast<float *>(pop), nx,
+                           ny);
     return hipGetLastError();
 }
 
-hipError_t launch_mrt_moments(int dtype, const void *pop, double *dr, double *jx, double *jy, size_t n, hipStream_t s)
+hipError_t launch_mrt_moments(int dtype, const void *pop, double *dr, double *jx, double *jy, int nx, int ny,
+                              hipStream_t s)
 {
     if (dtype == FDLBM_F64)
-        hipLaunchKernelGGL(mrt_moments_kernel<double>, grid_for(n), 256, 0, s, static_cast<const double *>(pop), dr,
-                           jx, jy, n);
+        hipLaunchKernelGGL(mrt_moments_kernel<double>, rows_grid(ny), 256, 0, s, static_cast<const double *>(pop), dr,
+                           jx, jy, nx, ny);
     else
-        hipLaunchKernelGGL(mrt_moments_kernel<float>, grid_for(n), 256, 0, s, static_cast<const float *>(pop), dr, jx,
-                           jy, n);
+        hipLaunchKernelGGL(mrt_moments_kernel<float>, rows_grid(ny), 256, 0, s, static_cast<const float *>(pop), dr,
+                           jx, jy, nx, ny);
     return hipGetLastError();
 }
 
