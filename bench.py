@@ -397,7 +397,7 @@ def main():
         for scheme, dtype, stencil in (("mrt", "f32", 0), ("fd", "f64", 3), ("fd", "f16", 3), ("fd", "f16sr", 3),
                                        ("fd", "f32", 5), ("mrt", "f64", 0), ("lwacm", "f32", 0)):
             key = f"{scheme}{stencil if scheme == 'fd' else ''}_{dtype}"
-            compare[key] = run_case(F, torch, init, scheme, dtype, stencil, short, 10, args.kernel, False,
+            compare[key] = run_case(F, torch, init, scheme, dtype, stencil, short, args.warmup, args.kernel, False,
                                     autotune=not args.no_autotune)
             print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
         # the 16384 x 1024 Poiseuille channel: walls at y = -1/2 and ny - 1/2, body force along x
@@ -405,8 +405,8 @@ def main():
         r, x, y, fx = W.poiseuille_profile(16384, 1024, nu_ch, 0.05)
         for scheme, stencil in (("fd", 3), ("mrt", 0)):
             key = f"poiseuille_16384x1024_{scheme}{stencil if scheme == 'fd' else ''}_f32"
-            compare[key] = run_case(F, torch, (r, x, y), scheme, "f32", stencil, short, 10, args.kernel, False,
-                                    bc="walls", nu=nu_ch, force=(fx, 0.0), autotune=not args.no_autotune)
+            compare[key] = run_case(F, torch, (r, x, y), scheme, "f32", stencil, short, args.warmup, args.kernel,
+                                    False, bc="walls", nu=nu_ch, force=(fx, 0.0), autotune=not args.no_autotune)
             print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)
         del r, x, y
         # a disk of radius n/2 - 6 closed by the curved wall (section 3-b): the ghost fill
@@ -420,7 +420,7 @@ def main():
         dinit = tuple(np.where(inside, a, 0.0) for a in init)
         del inside
         key = f"disk_r{rad:g}_fd3_f32"
-        compare[key] = run_case(F, torch, dinit, "fd", "f32", 3, short, 10, args.kernel, False, bc="disk",
+        compare[key] = run_case(F, torch, dinit, "fd", "f32", 3, short, args.warmup, args.kernel, False, bc="disk",
                                 disk=(c, c, rad), autotune=not args.no_autotune)
         compare[key]["vs_periodic"] = round(compare[key]["kernel_ms"] / main_case["kernel_ms"], 4)
         print(f"# {key}: {compare[key]}", file=sys.stderr, flush=True)

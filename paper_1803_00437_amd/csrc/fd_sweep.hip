@@ -56,11 +56,13 @@ __global__ void __launch_bounds__(64 * WV) fd_sweep_kernel(SweepArgs<T> a)
 }
 
 // Rows per wavefront when the caller leaves the choice open (fastest at 8192^2): FP32
-// 3-point 8, FP32 5-point 16, FP16 storage 16, FP64 8 (LW-ACM as 3-point).  fdlbm_autotune measures instead.
+// 3-point 8, FP32 5-point 16, LW-ACM 4, FP16 storage 16, FP64 6.  fdlbm_autotune measures
+// instead.
 int default_rows(const FdArgs &a)
 {
-    if (a.dtype == FDLBM_F64) return 8;
+    if (a.dtype == FDLBM_F64) return 6;
     if (is_f16(a.dtype)) return 16;
+    if (a.stencil == 1) return 4;
     return a.stencil == 5 ? 16 : 8;
 }
 

@@ -190,7 +190,9 @@ def summarise(trace, kernel, alg, out_md, *, fetch=None, write=None, json_out=No
 
 BENCH = "/root/repo/bench.py"
 # default tile shapes (no tuning launches mixed into the averages)
-TRACE_ARGS = ["--steps", "100", "--warmup", "10", "--no-cpu", "--copy-probe", "--no-autotune"]
+# the bench's own step counts: the first few dozen launches after a pause run up to 25 % slower
+# (clock ramp), so a short trace overstates the steady kernel time
+TRACE_ARGS = ["--steps", "1000", "--warmup", "50", "--no-cpu", "--copy-probe", "--no-autotune"]
 FD_COUNTER_ARGS = ["--steps", "20", "--warmup", "2", "--no-cpu", "--no-compare", "--no-batch", "--copy-probe",
                    "--no-autotune"]
 MRT_COUNTER_ARGS = ["--only", "mrt_f32", "--steps", "20", "--warmup", "2", "--copy-probe", "--no-autotune"]
