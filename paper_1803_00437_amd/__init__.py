@@ -567,7 +567,7 @@ class FdLbm3D:
     """One D3Q19 FD-LBM simulation on a periodic nx * ny * nz grid: owns its torch device
     buffers and its library context.  Keyword arguments follow ``fdlbm3d_params``
     (include/fdlbm3d.h): ``dtype`` "f64" or "f32", ``s_nu``, ``s_e``, ``kernel`` "auto",
-    "reference" or "sweep", ``tile_rows`` (8 or 16), ``tile_planes``.  Host arrays have shape
+    "reference" or "sweep", ``tile_rows`` (8, 12 or 16), ``tile_planes``.  Host arrays have shape
     (nz, ny, nx)."""
 
     def __init__(self, nx, ny, nz, device="cuda", stream=None, **kw):

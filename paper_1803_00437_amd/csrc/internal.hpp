@@ -51,7 +51,7 @@ bool fd_sweep_supported(const FdArgs &a, int lane_cols);
 // Batch of independent periodic FD-LBM grids (3-point differences) -------------------
 constexpr int BATCH_CHUNK = 65536;  // nodes per block of the A(t) reduction
 struct BatchInstance {
-    size_t offset;       // element offset of the instance's drho plane in the state buffers
+    size_t offset;       // element offset of the instance's state (row-interleaved) in the state buffers
     size_t mode_offset;  // element offset of its J0 planes (jx, jy) in the mode buffer
     int nx, ny, strips_x, nbands;
     int cls;             // lane class of its tiles (BATCH_CLASSES)
@@ -135,9 +135,9 @@ hipError_t launch_mrt_disk(const MrtDisk &d, int dtype, void *pop, bool full, hi
 // MRT D2Q9 stream-collide (push) step.
 hipError_t launch_mrt(const MrtArgs &a, const void *src, void *dst, hipStream_t s);
 
-// Conversions between host-staged FP64 planes and device storage: element by element (MRT
-// populations, the D3Q19 state, the batch modes), and for a three-word state between three
-// FP64 planes and its row-interleaved storage (fd_elem).
+// Conversions between host-staged FP64 planes and device storage: element by element (the
+// D3Q19 state, the batch modes), and row by row between nf FP64 planes and the
+// row-interleaved storage of the two-dimensional states (row_elem).
 hipError_t launch_pack(int dtype, const double *in, void *out, size_t count, hipStream_t s);
 hipError_t launch_unpack(int dtype, const void *in, double *out, size_t count, hipStream_t s);
 // nf (3 or 9) host-order FP64 planes of nx*ny values to and from the row-interleaved storage
@@ -169,7 +169,7 @@ struct Dim3Grid {
 // reference path: 18 post-collision planes in fstar (18 * nx*ny*nz elements), then gather
 hipError_t launch_d3_reference(int dtype, const void *in, void *out, void *fstar, int nx, int ny, int nz, double s_nu,
                                double s_e, hipStream_t s);
-// sweep path: wy wavefronts (8 or 16) per block along y, tz planes per block along z
+// sweep path: wy wavefronts (8, 12 or 16) per block along y, tz planes per block along z
 Dim3Grid d3_sweep_grid(int nx, int ny, int nz, int wy, int tz);
 hipError_t launch_d3_sweep(int dtype, const void *in, void *out, int nx, int ny, int nz, double s_nu, double s_e,
                            int wy, int tz, hipStream_t s);
