@@ -349,6 +349,45 @@ def test_largest_grids_beyond_2_31_nodes(F, dtype):
     assert abs(d["kin_energy"] / (0.5 * n * (jx * jx + jy * jy)) - 1) < 1e-12
 
 
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f64", 1e-13)])
+def test_mrt_state_beyond_2_31_values(F, dtype, tol):
+    """MRT on 16384 x 16384: the nine row-interleaved populations hold 2.4e9 values, so the
+    element offsets of the upper rows pass 2^31 (past 2^34 bytes in FP64).  A uniform state at
+    rest (fdlbm_create clears it) under a body force stays uniform, since propagation moves
+    equal populations between equal nodes; after k steps every node must hold what one node
+    of the FP64 oracle's 4 x 4 run holds (section 1, eqs. 1-2, Strang force).  Nodes in the
+    first, middle and last rows are read straight from the state buffer at the documented
+    element (9y + k) nx + x: equal to each other bit for bit, and to the oracle's node within
+    `tol` of its largest population; the FP64 diagnostics equal n times the node's moments."""
+    import torch
+
+    nx = ny = 16384
+    steps, fx, fy, s_xx = 6, 2.0 ** -10, -(2.0 ** -11), 1.5
+    n = nx * ny
+    print(f"case MRT {nx}x{ny} dtype={dtype} ({9 * n} values per state)", flush=True)
+    sim = F.FdLbm(nx, ny, scheme="mrt", dtype=dtype, s_xx=s_xx, quartic=True, force=(fx, fy))
+    sim.step(steps)
+    d = sim.diagnostics()
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    buf = (sim.buffers.state_a if steps % 2 == 0 else sim.buffers.state_b).view(tdt)
+    nodes = [(0, 0), (nx - 1, ny // 2), (nx // 2, ny - 1), (nx - 1, ny - 1)]
+    vals = np.array([[buf[(9 * y + k) * nx + x].item() for k in range(9)] for x, y in nodes])
+    sim.close()
+    del sim, buf
+    torch.cuda.empty_cache()
+    want = O.mrt_run(np.zeros((9, 4, 4)), steps, s_xx=s_xx, s_q=O.quartic_s_q(s_xx), fx=fx, fy=fy)[:, 0, 0]
+    scale = np.abs(want).max()
+    print(f"  node populations {vals[0]}, oracle {want}")
+    assert np.array_equal(vals, np.broadcast_to(vals[0], vals.shape))
+    assert np.abs(vals[0] - want).max() <= tol * scale
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.float64)
+    node = vals[0].astype(np.float64)
+    assert d["nonfinite"] == 0
+    for key, v in (("mass", node.sum()), ("mom_x", ex @ node), ("mom_y", ey @ node)):
+        assert abs(d[key] - n * v) <= 1e-12 * n * scale, (key, d[key], n * v)
+
+
 @pytest.mark.parametrize("stencil", [3, 5])
 def test_relative_viscosity_curves_figs_2_3(F, stencil):
     """Section 3-a, Figs. 2 and 3: nu(k)/nu_0 at nu_0 = 0.01 for wave vectors along {1,0},
