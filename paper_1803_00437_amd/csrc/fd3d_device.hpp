@@ -60,14 +60,16 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
                                          const Coef3<C> &k, C (&f)[Q])
 {
     const C third = C(1.0 / 3.0);
-    // half diagonal defects h_aa = u_aa / 2 = 1/3 (D_a J_a - J_a D_a rho) - J_a dp_a
-    const C hxx = fmac(third, fmac(-j[0], gr[0], dj[0][0]), -(j[0] * dp[0]));
-    const C hyy = fmac(third, fmac(-j[1], gr[1], dj[1][1]), -(j[1] * dp[1]));
-    const C hzz = fmac(third, fmac(-j[2], gr[2], dj[2][2]), -(j[2] * dp[2]));
-    // off-diagonal defects
-    const C uxy = fmac(third, (dj[0][1] + dj[1][0]) - fmac(j[0], gr[1], j[1] * gr[0]), -fmac(j[0], dp[1], j[1] * dp[0]));
-    const C uxz = fmac(third, (dj[0][2] + dj[2][0]) - fmac(j[0], gr[2], j[2] * gr[0]), -fmac(j[0], dp[2], j[2] * dp[0]));
-    const C uyz = fmac(third, (dj[1][2] + dj[2][1]) - fmac(j[1], gr[2], j[2] * gr[1]), -fmac(j[1], dp[2], j[2] * dp[1]));
+    // J_b multiplies D_b rho / 3 + dp_b wherever it appears in the defects: w_b
+    const C w0 = fmac(gr[0], third, dp[0]), w1 = fmac(gr[1], third, dp[1]), w2 = fmac(gr[2], third, dp[2]);
+    // half diagonal defects h_aa = u_aa / 2 = 1/3 D_a J_a - J_a w_a
+    const C hxx = fmac(third, dj[0][0], -(j[0] * w0));
+    const C hyy = fmac(third, dj[1][1], -(j[1] * w1));
+    const C hzz = fmac(third, dj[2][2], -(j[2] * w2));
+    // off-diagonal defects u_ab = 1/3 (D_a J_b + D_b J_a) - (J_a w_b + J_b w_a)
+    const C uxy = fmac(third, dj[0][1] + dj[1][0], -fmac(j[0], w1, j[1] * w0));
+    const C uxz = fmac(third, dj[0][2] + dj[2][0], -fmac(j[0], w2, j[2] * w0));
+    const C uyz = fmac(third, dj[1][2] + dj[2][1], -fmac(j[1], w2, j[2] * w1));
     const C pxx = j[0] * j[0], pyy = j[1] * j[1], pzz = j[2] * j[2];
     const C j2 = (pxx + pyy) + pzz;
     const C div = (dj[0][0] + dj[1][1]) + dj[2][2];
