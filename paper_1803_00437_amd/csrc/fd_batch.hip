@@ -37,6 +37,7 @@ __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__
     t.rows = rows;
     t.k.ke = C(I.ke);
     t.k.kxx = C(I.kxx);
+    t.k.kxx2 = C(2.0 * I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = b.tile / I.strips_x;
     const int sx = b.tile - band * I.strips_x;
@@ -62,6 +63,7 @@ __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict_
     t.rows = rows;
     t.k.ke = C(I.ke);
     t.k.kxx = C(I.kxx);
+    t.k.kxx2 = C(2.0 * I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
     const int band = blockIdx.x / I.strips_x;
     const int sx = blockIdx.x - band * I.strips_x;

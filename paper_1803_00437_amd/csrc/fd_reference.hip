@@ -163,6 +163,7 @@ template <typename T> FdCoef<typename Storage<T>::C> make_coef(const FdArgs &a)
     FdCoef<C> k;
     k.ke = C(scale * (1.0 - 1.0 / a.s_e));
     k.kxx = C(scale * (1.0 - 1.0 / a.s_xx));
+    k.kxx2 = C(2.0 * scale * (1.0 - 1.0 / a.s_xx));
     k.hfx = C(0.5 * a.fx);
     k.hfy = C(0.5 * a.fy);
     k.qfx = C(0.25 * a.fx);

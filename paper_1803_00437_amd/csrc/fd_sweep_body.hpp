@@ -644,6 +644,7 @@ template <typename C> inline FdCoef<C> make_coef(int stencil, double s_xx, doubl
     FdCoef<C> k;
     k.ke = C(scale * (1.0 - 1.0 / s_e));
     k.kxx = C(scale * (1.0 - 1.0 / s_xx));
+    k.kxx2 = C(2.0 * scale * (1.0 - 1.0 / s_xx));
     k.hfx = C(0.5 * fx);
     k.hfy = C(0.5 * fy);
     k.qfx = C(0.25 * fx);

@@ -202,7 +202,8 @@ template <bool FORCE, typename C> __device__ __forceinline__ C plus_force(C x, C
 // Per-step constants of the reconstruction.
 template <typename C> struct FdCoef {
     C ke;     // SCALE * (1 - 1/s_e)   multiplies theta_E (unscaled derivatives)
-    C kxx;    // SCALE * (1 - 1/s_xx)  multiplies theta_XX and theta_XY
+    C kxx;    // SCALE * (1 - 1/s_xx)  multiplies theta_XY
+    C kxx2;   // 2 kxx                 multiplies theta_XX / 2
     C hfx, hfy;  // F/2: J_a = J + F/2 (Strang splitting, section 1)
     C qfx, qfy;  // F/4: axis populations carry (J_a + F/4)/3
     C dfx, dfy;  // F  : diagonal populations carry (J_a + F)/12
@@ -235,17 +236,17 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
 
     const C w = fmac(jx, rx, jy * ry);                               // J . grad rho
     const C th_e = fmac(fmac(C(-6), j2, C(2)), a + b, C(-2) * w);
-    const C g = fmac(jx, rx, -(jy * ry));                             // Jx rx - Jy ry
-    const C h = fmac(jx, sA, -(jy * sB));
-    const C th_xx = fmac(C(2.0 / 3.0), (a - b) - g, C(-2) * h);
-    const C g2 = fmac(jx, ry, jy * rx);                               // Jx ry + Jy rx
-    const C h2 = fmac(jx, sB, jy * sA);
-    const C th_xy = fmac(C(1.0 / 3.0), (c + dd) - g2, -h2);
+    // Jx and Jy enter theta_XX and theta_XY only through rx / 3 + sA and ry / 3 + sB:
+    //   theta_XX / 2 = 1/3 (D_x Jx - D_y Jy) - (Jx wx - Jy wy)
+    //   theta_XY     = 1/3 (D_x Jy + D_y Jx) - (Jx wy + Jy wx)
+    const C wx = fmac(rx, C(1.0 / 3.0), sA), wy = fmac(ry, C(1.0 / 3.0), sB);
+    const C th_xx_h = fmac(C(1.0 / 3.0), a - b, -fmac(jx, wx, -(jy * wy)));
+    const C th_xy = fmac(C(1.0 / 3.0), c + dd, -fmac(jx, wy, jy * wx));
 
     const C rinv = recip(C(1) + dr);
     const C K = j2 * rinv;
     const C te = k.ke * th_e;                                         // (1 - 1/s_e) theta_E
-    const C XX = fmac(p0 - q0, rinv, k.kxx * th_xx);
+    const C XX = fmac(p0 - q0, rinv, k.kxx2 * th_xx_h);
     const C XY = fmac(r0, rinv, k.kxx * th_xy);
 
     // deviation populations (rest moments m0 = (1,0,0,-2,0,0,0,0,1) removed)
