@@ -35,7 +35,9 @@ __global__ void __launch_bounds__(64 * WV) fd_batch_kernel(const T *__restrict__
     t.nx = I.nx;
     t.ny = I.ny;
     t.rows = rows;
-    t.k.ke = C(I.ke);
+    t.k.eax = C(-2.0 * I.ke / 36.0);
+    t.k.edg = C(2.0 * I.ke / 18.0);
+    t.k.e0 = C(-2.0 * I.ke / 9.0);
     t.k.kxx = C(I.kxx);
     t.k.kxx2 = C(2.0 * I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);
@@ -61,7 +63,9 @@ __global__ void __launch_bounds__(64 * WV) fd_single_kernel(const T *__restrict_
     t.nx = I.nx;
     t.ny = I.ny;
     t.rows = rows;
-    t.k.ke = C(I.ke);
+    t.k.eax = C(-2.0 * I.ke / 36.0);
+    t.k.edg = C(2.0 * I.ke / 18.0);
+    t.k.e0 = C(-2.0 * I.ke / 9.0);
     t.k.kxx = C(I.kxx);
     t.k.kxx2 = C(2.0 * I.kxx);
     t.k.hfx = t.k.hfy = t.k.qfx = t.k.qfy = t.k.dfx = t.k.dfy = C(0);

@@ -161,7 +161,10 @@ template <typename T> FdCoef<typename Storage<T>::C> make_coef(const FdArgs &a)
     using C = typename Storage<T>::C;
     const double scale = a.stencil == 3 ? Stencil<3>::SCALE : Stencil<5>::SCALE;
     FdCoef<C> k;
-    k.ke = C(scale * (1.0 - 1.0 / a.s_e));
+    const double ke = 2.0 * scale * (1.0 - 1.0 / a.s_e);
+    k.eax = C(-ke / 36.0);
+    k.edg = C(ke / 18.0);
+    k.e0 = C(-ke / 9.0);
     k.kxx = C(scale * (1.0 - 1.0 / a.s_xx));
     k.kxx2 = C(2.0 * scale * (1.0 - 1.0 / a.s_xx));
     k.hfx = C(0.5 * a.fx);

@@ -642,7 +642,10 @@ template <typename C> inline FdCoef<C> make_coef(int stencil, double s_xx, doubl
 {
     const double scale = stencil == 3 ? Stencil<3>::SCALE : Stencil<5>::SCALE;
     FdCoef<C> k;
-    k.ke = C(scale * (1.0 - 1.0 / s_e));
+    const double ke = 2.0 * scale * (1.0 - 1.0 / s_e);
+    k.eax = C(-ke / 36.0);
+    k.edg = C(ke / 18.0);
+    k.e0 = C(-ke / 9.0);
     k.kxx = C(scale * (1.0 - 1.0 / s_xx));
     k.kxx2 = C(2.0 * scale * (1.0 - 1.0 / s_xx));
     k.hfx = C(0.5 * fx);

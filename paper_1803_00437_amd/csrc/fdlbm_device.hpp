@@ -201,7 +201,11 @@ template <bool FORCE, typename C> __device__ __forceinline__ C plus_force(C x, C
 
 // Per-step constants of the reconstruction.
 template <typename C> struct FdCoef {
-    C ke;     // SCALE * (1 - 1/s_e)   multiplies theta_E (unscaled derivatives)
+    // (1 - 1/s_e) theta_E enters the populations with the weights -1/36 (axes), 1/18
+    // (diagonals) and -1/9 (rest); with the derivative scale, per unit of theta_E / 2:
+    C eax;    // -2 SCALE (1 - 1/s_e) / 36
+    C edg;    //  2 SCALE (1 - 1/s_e) / 18
+    C e0;     // -2 SCALE (1 - 1/s_e) / 9
     C kxx;    // SCALE * (1 - 1/s_xx)  multiplies theta_XY
     C kxx2;   // 2 kxx                 multiplies theta_XX / 2
     C hfx, hfy;  // F/2: J_a = J + F/2 (Strang splitting, section 1)
@@ -235,7 +239,7 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
     const C j2 = p0 + q0;
 
     const C w = fmac(jx, rx, jy * ry);                               // J . grad rho
-    const C th_e = fmac(fmac(C(-6), j2, C(2)), a + b, C(-2) * w);
+    const C th_e_h = fmac(fmac(C(-3), j2, C(1)), a + b, -w);        // theta_E / 2
     // Jx and Jy enter theta_XX and theta_XY only through rx / 3 + sA and ry / 3 + sB:
     //   theta_XX / 2 = 1/3 (D_x Jx - D_y Jy) - (Jx wx - Jy wy)
     //   theta_XY     = 1/3 (D_x Jy + D_y Jx) - (Jx wy + Jy wx)
@@ -245,15 +249,14 @@ __device__ __forceinline__ void fd_node_fstar(C dr, C jx, C jy, const C (&d)[10]
 
     const C rinv = recip(C(1) + dr);
     const C K = j2 * rinv;
-    const C te = k.ke * th_e;                                         // (1 - 1/s_e) theta_E
     const C XX = fmac(p0 - q0, rinv, k.kxx2 * th_xx_h);
     const C XY = fmac(r0, rinv, k.kxx * th_xy);
 
     // deviation populations (rest moments m0 = (1,0,0,-2,0,0,0,0,1) removed)
     const C k12 = K * C(1.0 / 12.0);
-    const C A_ax = fmac(dr, C(1.0 / 9.0), fmac(te, C(-1.0 / 36.0), k12));
-    const C A_dg = fmac(dr, C(1.0 / 36.0), fmac(te, C(1.0 / 18.0), k12));
-    f[0] = fmac(dr, C(4.0 / 9.0), fmac(K, C(-2.0 / 3.0), te * C(-1.0 / 9.0)));
+    const C A_ax = fmac(dr, C(1.0 / 9.0), fmac(th_e_h, k.eax, k12));
+    const C A_dg = fmac(dr, C(1.0 / 36.0), fmac(th_e_h, k.edg, k12));
+    f[0] = fmac(dr, C(4.0 / 9.0), fmac(K, C(-2.0 / 3.0), th_e_h * k.e0));
     // the odd parts (J/3 on the axes, (+-Jx +-Jy)/12 on the diagonals) enter through fused
     // multiply-adds with the constant: one instruction per population
     const C axp = fmac(XX, C(0.25), A_ax), axm = fmac(XX, C(-0.25), A_ax);
