@@ -14,7 +14,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-NP = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
+NP = {"f64": np.float64, "f32": np.float32, "f16": np.float16, "f16sr": np.float16}
 # D2Q9 velocities in the order of section 1 (e_0 .. e_8)
 EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)
 EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.float64)
@@ -46,11 +46,12 @@ def _interleaved(planes):
 def _buffer(sim, dtype, count):
     import torch
 
-    tdt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[dtype]
+    tdt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "f16sr": torch.float16}[dtype]
     return sim.buffers.state_a.view(tdt)[:count]
 
 
-CASES_2D = [("fd", "f64"), ("fd", "f32"), ("fd", "f16"), ("lwacm", "f32"), ("mrt", "f64"), ("mrt", "f32")]
+CASES_2D = [("fd", "f64"), ("fd", "f32"), ("fd", "f16"), ("fd", "f16sr"), ("lwacm", "f32"), ("mrt", "f64"),
+            ("mrt", "f32")]
 
 
 @pytest.mark.parametrize("scheme,dtype", CASES_2D)
