@@ -25,16 +25,19 @@ constexpr int Q = 19;
 //   3p_xx = 3c_x^2 - |c|^2, |.|^2 = 36; p_ww = c_y^2 - c_z^2, |.|^2 = 12;
 //   p_xy, p_yz, p_xz, |.|^2 = 4.
 template <typename C> struct Coef3 {
-    C kf;  // -11 (1 - 1/s_e) / 252 = -11 (1 - 1/s_e) 19 / (2 * 2394): energy, faces
-    C kd;  //   8 (1 - 1/s_e) / 252: energy, edges
-    C kp;  // (1 - 1/s_nu) / 36: 3p_xx per unit of the half diagonal defects h_aa = u_aa / 2
-    C kw;  // (1 - 1/s_nu) / 12: p_ww per unit of h_aa
-    C ko;  // (1 - 1/s_nu) / 8 : p_xy, p_yz, p_xz per unit of u_ab
+    C kf;   // -11 (1 - 1/s_e) / 252 = -11 (1 - 1/s_e) 19 / (2 * 2394): energy, faces, times 2/3
+            // (per unit of te_h = 3/2 te, below)
+    C kd;   //   8 (1 - 1/s_e) / 252 times 2/3: energy, edges
+    C kp;   // (1 - 1/s_nu) / 36: 3p_xx per unit of the half diagonal defects h_aa = u_aa / 2
+    C k2p;  // 2 kp
+    C kw;   // (1 - 1/s_nu) / 12: p_ww per unit of h_aa
+    C ko;   // (1 - 1/s_nu) / 8 : p_xy, p_yz, p_xz per unit of u_ab
 };
 template <typename C> inline Coef3<C> coef3(double s_nu, double s_e)
 {
     const double a = 1.0 - 1.0 / s_e, b = 1.0 - 1.0 / s_nu;
-    return Coef3<C>{C(-11.0 * a / 252.0), C(8.0 * a / 252.0), C(b / 36.0), C(b / 12.0), C(b / 8.0)};
+    return Coef3<C>{C(-11.0 * a / 252.0 * (2.0 / 3.0)), C(8.0 * a / 252.0 * (2.0 / 3.0)), C(b / 36.0), C(b / 18.0),
+                    C(b / 12.0), C(b / 8.0)};
 }
 
 // a b - c d, the difference of a product between the two neighbours along an axis
@@ -50,6 +53,8 @@ template <typename C> __device__ __forceinline__ C d3_pdiff(C a, C b, C c, C d) 
 // Corrections of the second-order moments, per population (columns of M^{-1} = M^T / norms),
 // with h_aa = u_aa / 2:
 //   fe = kf te, ee = kd te, pp = kp (2h_xx - h_yy - h_zz), pw = kw (h_yy - h_zz), p_ab = ko u_ab
+// (te is formed as te_h = 3/2 te, with kf and kd scaled to match; kp and kw are applied where
+// pp and pw enter the populations)
 //   face x: fe + 2pp         face y: fe - pp + pw        face z: fe - pp - pw
 //   edge xy: ee + pp + pw +- p_xy    edge xz: ee + pp - pw +- p_xz    edge yz: ee - 2pp +- p_yz
 // Equilibrium (deviations), with T = drho - 3/2 |J|^2/rho and Q_ab = J_a J_b / rho:
@@ -74,11 +79,11 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
     const C j2 = (pxx + pyy) + pzz;
     const C div = (dj[0][0] + dj[1][1]) + dj[2][2];
     const C jg = fmac(j[0], gr[0], fmac(j[1], gr[1], j[2] * gr[2]));
-    const C te = fmac(fmac(C(-2), j2, C(2.0 / 3.0)), div, C(-2.0 / 3.0) * jg);
+    const C te_h = fmac(fmac(C(-3), j2, C(1)), div, -jg);  // 3/2 te
 
-    const C fe = k.kf * te, ee = k.kd * te;
-    const C pp = k.kp * fmac(C(2), hxx, -hyy - hzz);
-    const C pw = k.kw * (hyy - hzz);
+    const C fe = k.kf * te_h, ee = k.kd * te_h;
+    const C pq = fmac(C(2), hxx, -hyy - hzz);  // pp / kp
+    const C wq = hyy - hzz;                    // pw / kw
     const C cxy = k.ko * uxy, cxz = k.ko * uxz, cyz = k.ko * uyz;
 
     const C rinv = recip(C(1) + dr);
@@ -87,9 +92,10 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
     const C t18 = T * C(1.0 / 18.0), t36 = T * C(1.0 / 36.0);
 
     // faces
-    const C Fx = fmac(qxx, C(0.25), t18) + fmac(C(2), pp, fe);
-    const C Fy = fmac(qyy, C(0.25), t18) + ((fe - pp) + pw);
-    const C Fz = fmac(qzz, C(0.25), t18) + ((fe - pp) - pw);
+    const C fmp = fmac(-pq, k.kp, fe);  // fe - pp
+    const C Fx = fmac(qxx, C(0.25), t18) + fmac(pq, k.k2p, fe);
+    const C Fy = fmac(qyy, C(0.25), t18) + fmac(wq, k.kw, fmp);
+    const C Fz = fmac(qzz, C(0.25), t18) + fmac(-wq, k.kw, fmp);
     f[1] = fmac(j[0], C(1.0 / 6.0), Fx);
     f[2] = fmac(j[0], C(-1.0 / 6.0), Fx);
     f[3] = fmac(j[1], C(1.0 / 6.0), Fy);
@@ -99,8 +105,9 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
 
     // edges
     const C hx = j[0] * C(1.0 / 12.0), hy = j[1] * C(1.0 / 12.0), hz = j[2] * C(1.0 / 12.0);
+    const C epp = fmac(pq, k.kp, ee);  // ee + pp
     {
-        const C B = fmac(qxx + qyy, C(0.125), t36) + ((ee + pp) + pw);
+        const C B = fmac(qxx + qyy, C(0.125), t36) + fmac(wq, k.kw, epp);
         const C Cc = fmac(j[0] * j[1], C(0.25) * rinv, cxy);
         const C bp = B + Cc, bm = B - Cc, s = hx + hy, t = hx - hy;
         f[7] = bp + s;
@@ -109,7 +116,7 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
         f[10] = bm - t;
     }
     {
-        const C B = fmac(qxx + qzz, C(0.125), t36) + ((ee + pp) - pw);
+        const C B = fmac(qxx + qzz, C(0.125), t36) + fmac(-wq, k.kw, epp);
         const C Cc = fmac(j[0] * j[2], C(0.25) * rinv, cxz);
         const C bp = B + Cc, bm = B - Cc, s = hx + hz, t = hx - hz;
         f[11] = bp + s;
@@ -118,7 +125,7 @@ __device__ __forceinline__ void d3_fstar(C dr, const C (&j)[3], const C (&gr)[3]
         f[14] = bm - t;
     }
     {
-        const C B = fmac(qyy + qzz, C(0.125), t36) + fmac(C(-2), pp, ee);
+        const C B = fmac(qyy + qzz, C(0.125), t36) + fmac(-pq, k.k2p, ee);
         const C Cc = fmac(j[1] * j[2], C(0.25) * rinv, cyz);
         const C bp = B + Cc, bm = B - Cc, s = hy + hz, t = hy - hz;
         f[15] = bp + s;
